@@ -1,0 +1,47 @@
+"""Staggered-grid finite-difference coefficients, derived exactly.
+
+Test infrastructure (the oracle): only ``tests/``, ``__graft_entry__.smoke()``
+and the ``cpu_baseline`` leg of ``bench.py`` may import anything under
+``oracle/``.  The product path shares no code with it.
+
+The paper (Sec. 3.3, "Simulation implementation details") discretises the
+stretched pressure-velocity system on a staggered grid with an operator of
+order 2M in space and M = 4.  The coefficient values themselves are not printed
+(they come from Tan & Huang 2014, which is not available), so the oracle takes
+the textbook Taylor construction of a 2M-th order staggered first derivative:
+
+    f'(0) ~ (1/h) * sum_{m=1..M} c_m * ( f((m-1/2)h) - f(-(m-1/2)h) )
+
+is exact for every odd monomial x^(2k-1), k = 1..M, which gives the linear
+system  sum_m c_m (2m-1)^(2k-1) = delta_{k,1}.  Even monomials cancel by
+symmetry, so the operator is exact for all polynomials of degree <= 2M-1.
+The system is solved here in exact rational arithmetic.
+"""
+from fractions import Fraction
+
+
+def staggered_coefficients_exact(M=4):
+    """Return [c_1..c_M] as Fractions solving sum_m c_m (2m-1)^(2k-1) = [k==1]."""
+    A = [[Fraction((2 * m - 1) ** (2 * k - 1)) for m in range(1, M + 1)]
+         for k in range(1, M + 1)]
+    rhs = [Fraction(1 if k == 1 else 0) for k in range(1, M + 1)]
+    # Gauss-Jordan elimination with exact rationals.
+    n = M
+    for col in range(n):
+        piv = next(r for r in range(col, n) if A[r][col] != 0)
+        A[col], A[piv] = A[piv], A[col]
+        rhs[col], rhs[piv] = rhs[piv], rhs[col]
+        inv = 1 / A[col][col]
+        A[col] = [x * inv for x in A[col]]
+        rhs[col] = rhs[col] * inv
+        for r in range(n):
+            if r != col and A[r][col] != 0:
+                f = A[r][col]
+                A[r] = [x - f * y for x, y in zip(A[r], A[col])]
+                rhs[r] = rhs[r] - f * rhs[col]
+    return rhs
+
+
+def staggered_coefficients(M=4):
+    """FP64 values of the exact coefficients."""
+    return [float(c) for c in staggered_coefficients_exact(M)]

@@ -1,0 +1,176 @@
+"""Relaxation-parameter calibration (host, FP64): the paper's Sec. 3.
+
+For one tissue class (c, alpha0, y) and N mechanisms this fits the 2 + 4N
+parameters (kappa_1, kappa_2, d_i^nu, alpha_i^nu; Sec. 2.1) so that the
+model wavenumber of Eq. (dispersion_relations) matches the power law of
+Eq. (power_law_attenuation) and the Kramers-Kronig phase velocity of
+Eq. (kk_relation):
+
+* objective J = mean |k'_GT - k'_pred|^2 over log-spaced frequencies in the
+  band (Sec. 3.2), each wavenumber normalised by the ranges of the real and
+  imaginary parts of k_GT and weighted by (1 - w) and w;
+* adaptive Nelder-Mead (SciPy ``minimize``), maximum 5e4 iterations,
+  absolute tolerances 1e-25 (Sec. 3.2);
+* variables and bounds of Table 2: kappa in [0.98, 1] (linear, start 1),
+  d in [1e2, 1e10] and alpha in [1e5, 1e12] optimised as log10 (start 1e6
+  and 1e9), which keeps d >= 0 and alpha > 0;
+* w swept over {0.1, 0.3, 0.5, 0.7, 0.9}; the winner has the lowest
+  attenuation NRMSE (Sec. 4.1 definition) at the eight measurement
+  frequencies 1 + 2.714 k MHz, ties broken by the dispersion error.  A fit is
+  flagged failed above 10 % NRMSE or 5 m/s dispersion error (Sec. 3.2).
+
+Conventions: e^{+iwt} time dependence, so attenuation is -Im k_pred and the
+comparison uses conj(k_pred); alpha0 in dB/(MHz^y cm) converted with
+20 log10(e) dB per neper; phase velocity referenced to c at f_ref = 1 MHz.
+"""
+import json
+import math
+import os
+
+import numpy as np
+
+NEPER_DB = 20.0 / math.log(10.0)
+WEIGHTS = (0.1, 0.3, 0.5, 0.7, 0.9)
+MEASURE_FREQS = 1e6 + 2.714e6 * np.arange(8)
+
+
+def _alpha_np(f_hz, alpha0_db, y):
+    return alpha0_db * 100.0 / NEPER_DB * (np.asarray(f_hz) / 1e6) ** y
+
+
+def target_wavenumber(f_hz, c0, alpha0_db, y, f_ref=1e6):
+    """k_GT = w / c(w) + i alpha(w) with the Kramers-Kronig c(w)."""
+    w = 2.0 * np.pi * np.asarray(f_hz, dtype=np.float64)
+    w0 = 2.0 * np.pi * f_ref
+    a0 = alpha0_db * 100.0 / NEPER_DB / (2.0 * np.pi * 1e6) ** y
+    if abs(y - 1.0) < 1e-12:
+        inv_c = 1.0 / c0 - 2.0 / np.pi * a0 * np.log(w / w0)
+    else:
+        inv_c = 1.0 / c0 + a0 * math.tan(math.pi * y / 2.0) * (w ** (y - 1.0) - w0 ** (y - 1.0))
+    return w * inv_c + 1j * a0 * w ** y
+
+
+def model_wavenumber(f_hz, c, kappa, d, alpha):
+    """k_pred of Eq. (dispersion_relations); kappa [2], d and alpha [2][N]."""
+    w = 2.0 * np.pi * np.asarray(f_hz, dtype=np.float64)
+    S = []
+    for i in range(2):
+        g = np.zeros_like(w, dtype=np.complex128)
+        for dn, an in zip(d[i], alpha[i]):
+            g += dn / kappa[i] ** 2 / (dn / kappa[i] + an + 1j * w)
+        S.append(1.0 / kappa[i] - g)
+    return w / c / np.sqrt(S[0] * S[1])
+
+
+def _unpack(x, N):
+    kappa = np.array([x[0], x[1]])
+    d = 10.0 ** np.asarray(x[2:2 + 2 * N]).reshape(2, N)
+    al = 10.0 ** np.asarray(x[2 + 2 * N:2 + 4 * N]).reshape(2, N)
+    return kappa, d, al
+
+
+def _objective_factory(f, kgt, w, c, N):
+    rr = np.ptp(kgt.real)
+    ri = np.ptp(kgt.imag)
+    gt = (1.0 - w) * kgt.real / rr + 1j * w * kgt.imag / ri
+
+    def J(x):
+        kappa, d, al = _unpack(x, N)
+        kp = np.conj(model_wavenumber(f, c, kappa, d, al))
+        pr = (1.0 - w) * kp.real / rr + 1j * w * kp.imag / ri
+        val = np.mean(np.abs(gt - pr) ** 2)
+        return val if np.isfinite(val) else 1e30
+    return J
+
+
+def model_errors(c, alpha0_db, y, kappa, d, alpha, f_ref=1e6):
+    """(attenuation NRMSE, dispersion RMSE in m/s) of the closed-form model at
+    the eight measurement frequencies."""
+    f = MEASURE_FREQS
+    kp = model_wavenumber(f, c, kappa, d, alpha)
+    kt = target_wavenumber(f, c, alpha0_db, y, f_ref)
+    at = kt.imag
+    am = -kp.imag
+    nr = math.sqrt(np.mean((am - at) ** 2)) / (at.max() - at.min())
+    w = 2.0 * np.pi * f
+    disp = math.sqrt(np.mean((w / kp.real - w / kt.real) ** 2))
+    return nr, disp
+
+
+def fit_class(c, alpha0_db, y, nmech=2, weights=WEIGHTS, n_freq=64, band=(1e6, 20e6),
+              f_ref=1e6, maxiter=50000, tol=1e-25):
+    """Fit one class; returns a dict with kappa [2], d [2][N], alpha [2][N],
+    the chosen weight and the model errors."""
+    from scipy.optimize import minimize
+    N = int(nmech)
+    f = np.logspace(math.log10(band[0]), math.log10(band[1]), n_freq)
+    kgt = target_wavenumber(f, c, alpha0_db, y, f_ref)
+    x0 = np.array([1.0, 1.0] + [6.0] * (2 * N) + [9.0] * (2 * N))
+    bounds = [(0.98, 1.0)] * 2 + [(2.0, 10.0)] * (2 * N) + [(5.0, 12.0)] * (2 * N)
+    best = None
+    for w in weights:
+        J = _objective_factory(f, kgt, w, c, N)
+        res = minimize(J, x0, method="Nelder-Mead", bounds=bounds,
+                       options=dict(adaptive=True, maxiter=int(maxiter), maxfev=int(maxiter) * 4,
+                                    xatol=tol, fatol=tol))
+        kappa, d, al = _unpack(res.x, N)
+        nr, disp = model_errors(c, alpha0_db, y, kappa, d, al, f_ref)
+        cand = dict(kappa=kappa.tolist(), d=d.tolist(), alpha=al.tolist(), w=w, J=float(res.fun),
+                    nrmse=nr, disp=disp)
+        if best is None or (nr, disp, w) < (best["nrmse"], best["disp"], best["w"]):
+            best = cand
+    best.update(c=float(c), alpha0=float(alpha0_db), y=float(y), nmech=N,
+                failed=bool(best["nrmse"] > 0.10 or best["disp"] > 5.0))
+    return best
+
+
+# ------------------------------------------------------------ table cache --
+CACHE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "relax_tables.json")
+
+
+def _key(c, alpha0_db, y, nmech, maxiter):
+    return "c=%.6f|a0=%.8g|y=%.6f|N=%d|it=%d" % (c, alpha0_db, y, nmech, maxiter)
+
+
+def _fit_job(args):
+    c, a0, y, N, maxiter = args
+    return _key(c, a0, y, N, maxiter), fit_class(c, a0, y, N, maxiter=maxiter)
+
+
+def load_cache(path=CACHE_PATH):
+    if os.path.exists(path):
+        with open(path) as fh:
+            return json.load(fh)
+    return {}
+
+
+def tables_for(classes, nmech, maxiter=50000, allow_fit=True, processes=None, path=CACHE_PATH):
+    """Return (kappa [C][2], d [C][2][N], alpha [C][2][N], fits) for classes =
+    dict(c=[...], alpha0=[...], y=[...]).  Rows come from the cache when
+    present; otherwise they are fitted (in parallel) and the cache is updated."""
+    cache = load_cache(path)
+    items = list(zip(classes["c"], classes["alpha0"], classes["y"]))
+    keys = [_key(c, a0, y, nmech, maxiter) for c, a0, y in items]
+    todo = sorted({k: (c, a0, y, nmech, maxiter) for k, (c, a0, y) in zip(keys, items) if k not in cache}.items())
+    if todo:
+        if not allow_fit:
+            raise KeyError("relaxation tables missing from cache: %d classes" % len(todo))
+        jobs = [v for _, v in todo]
+        if len(jobs) > 1:
+            import multiprocessing as mp
+            with mp.get_context("fork").Pool(processes or min(8, os.cpu_count() or 1)) as pool:
+                out = pool.map(_fit_job, jobs)
+        else:
+            out = [_fit_job(jobs[0])]
+        cache = load_cache(path)
+        cache.update(dict(out))
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp%d" % os.getpid()
+        with open(tmp, "w") as fh:
+            json.dump(cache, fh, indent=0, sort_keys=True)
+        os.replace(tmp, path)
+    fits = [cache[k] for k in keys]
+    kappa = np.array([f["kappa"] for f in fits], dtype=np.float64)
+    d = np.array([f["d"] for f in fits], dtype=np.float64)
+    al = np.array([f["alpha"] for f in fits], dtype=np.float64)
+    return kappa, d, al, fits
