@@ -1,0 +1,184 @@
+"""Benchmark of the FDTD step on one MI355X.
+
+Workload: the 3D heterogeneous case -- 960 x 960 x 720 cells, dx = 0.1 mm,
+8 tissue classes from a seeded smoothed label field, +-1 % per-voxel speed
+perturbation, N = 4 relaxation mechanisms, 24-cell CPML, nonlinear, focused
+64-element source (synthetic data; relaxation tables from the FP64
+calibration).  A "step" is one full time step: velocity update, pressure
+update, sources and receivers.
+
+Prints one JSON line: Gcell-updates/s of the whole job, the HBM roofline
+fraction of the dominant kernel (velocity update) and of the whole step,
+and the FP64 oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(case):
+    """Algorithmic bytes per cell-update (FP32 state read once and written
+    once, uint8 class index, CPML variables inside the slabs):
+      velocity kernel: p (4) + class (1) + v r/w (8 ndim) + psi1 r/w (8 N ndim)
+                       + CPML face variable r/w (8) per slab axis
+      pressure kernel: v (4 ndim) + p r/w (8) + psi2 r/w (8 N) + class (1)
+                       + CPML cell variable r/w (8) per slab axis
+      whole step (minimum of any schedule): every state float read and written
+                       once, class read once: (1 + ndim + N (ndim + 1)) 8 + 1
+                       + 16 per slab axis."""
+    nd, N, P = case.ndim, case.nmech, case.pml_cells
+    cells = case.cells()
+    slab = 0.0
+    for shp in case.shapes:
+        c = float(np.prod(shp))
+        for a in range(nd):
+            slab += c * min(1.0, 2.0 * P / shp[a])
+    slab_frac = slab / cells           # sum over axes of the slab fraction
+    vel = 4 + 1 + 8 * nd + 8 * N * nd + 8 * slab_frac
+    prs = 4 * nd + 8 + 8 * N + 1 + 8 * slab_frac
+    step = (1 + nd + N * (nd + 1)) * 8 + 1 + 16 * slab_frac
+    return vel, prs, step
+
+
+def bench_case(full=True):
+    from workloads import configs
+    shape = (960, 960, 720) if full else (192, 160, 128)
+    return configs.heterogeneous_3d(shape=shape, steps=2000)
+
+
+def fill_tables(case, allow_fit=True):
+    from paper_2606_11103_amd import relax
+    classes = dict(c=case.c, alpha0=case.alpha0, y=case.y)
+    kappa, d, al, fits = relax.tables_for(classes, case.nmech, allow_fit=allow_fit)
+    case.kappa, case.d, case.alpha = kappa, d, al
+    return fits
+
+
+def cpu_baseline(seconds_target=20.0):
+    """The FP64 oracle as it stands, on a 128 x 128 x 96 crop-sized instance of
+    the same recipe (same classes, tables, noise, source), timed on the host."""
+    from workloads import configs
+    from workloads.adapters import to_oracle
+    case = configs.heterogeneous_3d(shape=(128, 128, 96), steps=2000, n_elem=16)
+    fill_tables(case)
+    sim = to_oracle(case)
+    waves = case.waves.astype(np.float64)[case.src_wave]
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        sim.run(10, case.src_cell, waves, case.rec_cell)
+        steps += 10
+        el = time.perf_counter() - t0
+        if el >= seconds_target or steps >= 2000:
+            break
+    cells = case.cells()
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cores = min(cores, os.cpu_count() or cores)
+    return dict(value=cells * steps / el / 1e9, unit="Gcell-updates/s", cores=cores, kind="oracle",
+                sample="FP64 oracle, 128x128x96 instance of the 3D heterogeneous recipe (N=4, CPML 24, "
+                       "noise, nonlinear), %d steps in %.1f s" % (steps, el))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--small", action="store_true", help="reduced grid for quick checks (not the benchmark)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--march-chunk", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (got --gpus %d)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2606_11103_amd.native import FW_OPT_MARCH_CHUNK, FW_OPT_TILE_ROWS
+    from workloads.adapters import to_simulation
+
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    case = bench_case(full=not args.small)
+    fill_tables(case)
+    print("# workload %s built in %.1f s" % (case.name, time.time() - t0), file=sys.stderr, flush=True)
+    sim = to_simulation(case)
+    if args.tile_rows:
+        sim.set_option(FW_OPT_TILE_ROWS, args.tile_rows)
+    if args.march_chunk:
+        sim.set_option(FW_OPT_MARCH_CHUNK, args.march_chunk)
+    print("# simulation ready (%.1f GB workspace)" % (sim.workspace.numel() / 1e9), file=sys.stderr, flush=True)
+
+    stream = torch.cuda.current_stream()
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+    print("# warmup done", file=sys.stderr, flush=True)
+
+    # timed region: K full steps, each kernel bracketed by HIP events on the
+    # stream it runs on
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    wall0 = time.perf_counter()
+    kern_ms = sim.time_kernels(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_total = ev0.elapsed_time(ev1)
+    ms_step = ms_total / args.steps
+    cells = case.cells()
+    value = cells * args.steps / (ms_total / 1e3) / 1e9
+
+    traces = sim.read_receivers()
+    finite = bool(np.all(np.isfinite(traces[: args.warmup + args.steps])))
+
+    b_vel, b_prs, b_step = algorithmic_bytes(case)
+    ach_vel = b_vel * cells / (kern_ms[0] / 1e3) / 1e9
+    ach_step = b_step * cells / (ms_step / 1e3) / 1e9
+    out = {
+        "metric": "Gcell-updates/s (3D heterogeneous, 4 mechanisms)",
+        "value": round(value, 4),
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": case.name if not args.small else case.name + " (reduced, not the benchmark)",
+                   "cells": cells, "nmech": case.nmech, "pml_cells": case.pml_cells, "classes": case.n_classes,
+                   "steps_of_full_run": case.n_steps, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": "velocity update",
+                     "achieved": round(ach_vel, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach_vel / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_cell": round(b_vel, 2), "avg_ms": round(kern_ms[0], 4)},
+        "step_roofline": {"achieved": round(ach_step, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": round(ach_step / HBM_PEAK_GBS, 4), "bytes_per_cell": round(b_step, 2)},
+        "kernels_ms": {"velocity": round(kern_ms[0], 4), "pressure": round(kern_ms[1], 4),
+                       "sources_receivers": round(kern_ms[2], 4)},
+        "traces_finite": finite,
+        "wall_s": round(wall, 3),
+    }
+    if not args.no_cpu_baseline:
+        print("# cpu baseline ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,202 @@
+/*
+ * fw25.h -- C ABI of the MI355X (gfx950) FDTD step for attenuating, nonlinear
+ * acoustic waves with multiple relaxation mechanisms.
+ *
+ * The method (Sode & Pinton, "Spatially heterogeneous power-law attenuation
+ * with multiple relaxation mechanisms for ultrasound modeling"):
+ *   - Sec. 2.1, Eqs. (wave1)/(wave2): staggered pressure p and particle
+ *     velocity v, rho dv/dt = -grad~ p, kappa dp/dt = -div~ v (K = 1/kappa).
+ *   - Sec. 2.1, Eq. (relaxation4): every derivative is stretched,
+ *     d/dx~ = (1/kappa_i) d/dx + sum_nu psi_i^nu, i = 1 (gradient) or 2
+ *     (divergence), nu = 1..N relaxation mechanisms.
+ *   - Sec. 2.1, Eqs. (relaxation_psi), (relaxation_a), (relaxation_b): the
+ *     memory variables follow psi <- b psi + a D with
+ *     b = exp(-(d/kappa + alpha) dt), a = d / (kappa (d + kappa alpha)) (b - 1).
+ *   - Sec. 2.1 / abstract: the CPML boundary reuses the same recursion form.
+ *   - Sec. 3.3: staggered finite differences of order 2M in space, M = 4.
+ *   - Sec. 1 names pressure-dependent nonlinearity; here K -> K + 2 beta p.
+ *
+ * Conventions for every call:
+ *   - Return value: FW_OK (0) or a negative fw_status.  No C++ exception
+ *     crosses this boundary.  fw_last_error() returns a thread-local text.
+ *   - Grids: cell (i, j, k) of a domain with shape (nx, ny, nz) has the
+ *     domain-local linear index (k*ny + j)*nx + i (x fastest).  Unused
+ *     trailing dimensions are 1.  The face i+1/2 of an axis is stored at the
+ *     index of cell i.  Field values beyond the grid are zero.
+ *   - Several domains ("shots", ragged sizes) can share one object; they all
+ *     advance together with the same dx, dt, N and CPML width.
+ *   - Memory: device state lives in a caller-owned workspace (for example a
+ *     torch uint8 tensor) bound with fw_bind_workspace; the library borrows
+ *     it and never frees it.  The library allocates only small device tables
+ *     (class coefficients, CPML profiles, tile lists, sources, receivers,
+ *     counters).  Host arrays passed to setters are copied before return.
+ *   - Streams: hip_stream is a hipStream_t (NULL = default stream).  Work is
+ *     enqueued asynchronously unless stated otherwise.
+ *   - Call order: create -> bind_workspace -> set_media ->
+ *     set_relaxation_table -> [set_sources] -> [set_receivers] -> step.
+ *     A call made too early returns FW_ESTATE.
+ */
+#ifndef FW25_H
+#define FW25_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fw_sim fw_sim;
+
+typedef enum fw_status {
+    FW_OK = 0,
+    FW_EINVAL = -1,        /* bad argument (shape, index, count, pointer) */
+    FW_ESTATE = -2,        /* call out of order                          */
+    FW_EUNSTABLE = -3,     /* time step violates the stability bound     */
+    FW_EHIP = -4,          /* HIP runtime error (text has the HIP error) */
+    FW_ENOMEM = -5,        /* workspace too small / allocation failed    */
+    FW_ENONFINITE = -6,    /* non-finite value detected                  */
+    FW_EUNSUPPORTED = -7   /* valid request this build does not support  */
+} fw_status;
+
+/* Thread-local text of the last failure on this thread ("" if none). */
+const char *fw_last_error(void);
+
+/* ABI version, incremented on every incompatible change. */
+int fw_abi_version(void);
+
+/*
+ * Create a grid object (host only, no device work).
+ *   ndim       1, 2 or 3.
+ *   n_domains  >= 1.
+ *   shape      [n_domains][3] = (nx, ny, nz); dims beyond ndim must be 1;
+ *              every used dim must exceed 2*pml_cells + 8.
+ *   dx, dt     grid step (m) and time step (s), both > 0.
+ *   n_mech     relaxation mechanisms N per operator, 1..4 (Sec. 2.1).
+ *   pml_cells  CPML width P in cells on every face of every domain (>= 0).
+ *   pml_params NULL for defaults, else [3] = (R0, f_alpha_hz, c_ref):
+ *              d(delta) = d0 delta^2 with d0 = 3 c_ref ln(1/R0) / (2 P dx),
+ *              alpha(delta) = pi f_alpha (1 - delta), kappa = 1, delta the
+ *              depth into the slab measured from its inner edge at positions
+ *              P - 1/2 and n - P - 1/2 (defaults 1e-4, 1e6, 0; c_ref = 0 takes
+ *              the largest class speed given to fw_set_media).
+ * On success *out holds a new object owned by the caller (fw_destroy).
+ */
+int fw_create_grid(fw_sim **out, int ndim, int n_domains, const int64_t *shape,
+                   double dx, double dt, int n_mech, int pml_cells, const double *pml_params);
+
+/* Release the object and the small tables the library allocated.  The bound
+ * workspace is not freed. */
+int fw_destroy(fw_sim *sim);
+
+/* Device bytes the workspace must provide: pressure, velocity, the memory
+ * variables (3N face variables and N cell variables summed over axes per
+ * cell), CPML memory variables and the uint8 class map.  -1 on a NULL sim. */
+int64_t fw_workspace_bytes(const fw_sim *sim);
+
+/* Bind a caller-owned device buffer of at least fw_workspace_bytes bytes,
+ * 256-byte aligned.  The state is zeroed (synchronously on the default
+ * stream) and the step counter reset. */
+int fw_bind_workspace(fw_sim *sim, void *d_ptr, int64_t bytes);
+
+/*
+ * Tissue classes and their map (Sec. 2.1: material maps rho(x), kappa(x)).
+ *   h_class     host uint8, all domains concatenated in domain order, each in
+ *               its own linear order; value = class index local to its domain.
+ *   class_base  host [n_domains]: global class = class_base[d] + local index;
+ *               every local index must be < 256 and the global < n_classes.
+ *   c, rho      host [n_classes] sound speed (m/s) and density (kg/m^3), > 0.
+ *   beta        host [n_classes] nonlinearity coefficient (K -> K + 2 beta p);
+ *               0 is the linear medium, a tissue with parameter B/A has
+ *               beta = 1 + B/(2A).
+ *   c_noise_amp per-voxel speed perturbation c (1 + eps), eps = amp (2u - 1),
+ *               u = (SplitMix64(noise_seed ^ local_index) >> 40) * 2^-24;
+ *               0 disables it.  0 <= amp < 0.5.
+ * Checks the stability bound c_max (1 + amp) dt/dx sqrt(ndim) sum|c_m| < 1
+ * (FW_EUNSTABLE).  Uploads the map into the workspace (synchronous).
+ */
+int fw_set_media(fw_sim *sim, const uint8_t *h_class, const int32_t *class_base, int n_classes,
+                 const double *c, const double *rho, const double *beta,
+                 double c_noise_amp, uint64_t noise_seed);
+
+/*
+ * Relaxation parameters per class (Sec. 2.1, Table 2 variables), FP64 in:
+ *   kappa [n_classes][2], d [n_classes][2][N], alpha [n_classes][2][N]
+ *   (index 0: gradient operator nabla_1, index 1: divergence nabla_2).
+ * Requires kappa > 0, d >= 0, alpha >= 0, d + kappa alpha > 0.  The per-step
+ * coefficients a, b of Eqs. (relaxation_a)/(relaxation_b) are computed in
+ * FP64 on the host and rounded to FP32 for the device.  Re-checks the
+ * stability bound with 1/sqrt(min kappa_1 kappa_2).
+ */
+int fw_set_relaxation_table(fw_sim *sim, int n_classes, const double *kappa,
+                            const double *d, const double *alpha);
+
+/*
+ * Additive pressure sources: after the pressure update of step t (0-based,
+ * counted from the last reset), p[domain[s], cell[s]] += waves[wave_idx[s]][t]
+ * for t < n_t.  cell = domain-local linear index.  Each (domain, cell) pair
+ * may appear once.  waves is host float [n_wave][n_t].  n_src = 0 clears.
+ */
+int fw_set_sources(fw_sim *sim, int64_t n_src, const int32_t *domain, const int64_t *cell,
+                   const int32_t *wave_idx, int n_wave, const float *waves, int n_t);
+
+/*
+ * Receivers: after step t's sources, trace[t][r] = p[domain[r], cell[r]]
+ * for t < n_t_max (later steps are not recorded).  Allocates the device
+ * trace buffer [n_t_max][n_rec] (zeroed).  n_rec = 0 clears.
+ */
+int fw_set_receivers(fw_sim *sim, int64_t n_rec, const int32_t *domain, const int64_t *cell,
+                     int n_t_max);
+
+/*
+ * Advance every domain by n_steps time steps on hip_stream (asynchronous).
+ * One step = velocity update (gradient, N memory variables per axis, CPML)
+ * -> pressure update (divergence, N memory variables, CPML, nonlinearity)
+ * -> sources -> receivers -> device step counter + 1.  Replays captured HIP
+ * graphs of the configured length, with eager launches for the remainder.
+ */
+int fw_step(fw_sim *sim, int n_steps, void *hip_stream);
+
+/*
+ * Copy n_elems floats of the trace buffer ([n_t_max][n_rec], row-major) to
+ * dst (device memory if dst_is_device, else host).  Synchronises the stream.
+ */
+int fw_read_receivers(fw_sim *sim, float *dst, int64_t n_elems, int dst_is_device, void *hip_stream);
+
+/* Zero every state field, the traces and the step counter (asynchronous). */
+int fw_reset_state(fw_sim *sim, void *hip_stream);
+
+/* Host view of the number of steps enqueued since the last reset. */
+int fw_get_step(const fw_sim *sim, int64_t *step);
+
+/* Bytes of a full state snapshot (fields, memory variables, CPML variables
+ * and the step counter); -1 on a NULL sim. */
+int64_t fw_state_bytes(const fw_sim *sim);
+
+/* Copy the full state into / out of a caller-owned device buffer of
+ * fw_state_bytes bytes (asynchronous, device-to-device).  Resuming from a
+ * saved state reproduces the uninterrupted run bit for bit. */
+int fw_save_state(fw_sim *sim, void *d_dst, void *hip_stream);
+int fw_load_state(fw_sim *sim, const void *d_src, void *hip_stream);
+
+/*
+ * Advance n_steps steps like fw_step, but launch every kernel eagerly with a
+ * HIP event before and after it on hip_stream, wait for completion, and
+ * return the average duration in milliseconds of each kernel kind:
+ * avg_ms[0] velocity update, avg_ms[1] pressure update, avg_ms[2] sources and
+ * receivers.  Used for per-kernel roofline figures; the state advances.
+ */
+int fw_time_kernels(fw_sim *sim, int n_steps, void *hip_stream, double *avg_ms);
+
+/*
+ * Tuning and behaviour options (host only):
+ *   FW_OPT_GRAPH_STEPS   steps per captured HIP graph (0 = eager only); default 16.
+ *   FW_OPT_MARCH_CHUNK   cells of the marching axis per tile (>= 8); default auto.
+ *   FW_OPT_TILE_ROWS     3D tile rows along y per block: 8 or 16; default 16.
+ */
+enum { FW_OPT_GRAPH_STEPS = 1, FW_OPT_MARCH_CHUNK = 2, FW_OPT_TILE_ROWS = 3 };
+int fw_set_option(fw_sim *sim, int key, int64_t value);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FW25_H */

@@ -1,0 +1,83 @@
+// Internal types shared by the host runtime and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace fw {
+
+constexpr int kMaxMech = 4;
+constexpr int kMaxLocalClasses = 256;   // class indices are uint8 within a domain
+
+// FP32 per-class coefficients, produced on the host in FP64 and rounded once.
+struct ClassCoef {
+    float ik1;        // 1 / kappa_1 (gradient operator)
+    float ik2;        // 1 / kappa_2 (divergence operator)
+    float rho;        // density
+    float K;          // bulk modulus rho c^2 (without the per-voxel perturbation)
+    float twobeta;    // 2 beta of the pressure-dependent modulus K + 2 beta p
+    float pad[3];
+    float a1[kMaxMech], b1[kMaxMech];   // recursion coefficients, gradient operator
+    float a2[kMaxMech], b2[kMaxMech];   // recursion coefficients, divergence operator
+};
+
+struct DomainDesc {
+    int64_t n[3];          // nx, ny, nz
+    int64_t cell_off;      // first cell of the domain in the concatenated arrays
+    int32_t class_base;    // first global class of the domain
+    int32_t n_classes;     // number of local classes
+    int32_t pml_off[3];    // offset of the per-axis CPML tables [aF|bF|aC|bC] x n[a]
+    int32_t pad;
+    uint64_t noise_seed;
+};
+
+// A tile: a block of cells along x (and y in 3D) marched over [z0, z1) of
+// the marching axis (z in 3D, y in 2D, a single row in 1D).
+struct Tile {
+    int32_t dom, x0, y0, z0, z1, pad0, pad1, pad2;
+};
+
+struct Fields {
+    float *p, *vx, *vy, *vz;
+    float *psi1x, *psi1y, *psi1z;   // [cell][N] gradient-operator memory variables per axis
+    float *psi2;                    // [cell][N] divergence-operator memory variables, summed over axes
+    float *pP1[3], *pP2[3];         // CPML memory variables per axis (touched inside slabs only)
+    uint8_t *cls;
+};
+
+struct StepArgs {
+    Fields f;
+    const DomainDesc *doms;
+    const Tile *tiles;
+    const ClassCoef *classes;
+    const float *pml_tab;
+    int32_t n_tiles;
+    int32_t tiles_per_xcd;     // ceil(n_tiles / 8): block b runs tile (b % 8) * tiles_per_xcd + b / 8
+    int32_t pml;               // CPML width P
+    float fd[4];               // staggered coefficients c_m / dx
+    float dt;
+    float noise_amp;
+};
+
+struct SrcRecArgs {
+    float *p;
+    const int64_t *src_cell;   // global cell index
+    const int32_t *src_wave;
+    const float *waves;        // [n_wave][n_t]
+    int64_t n_src;
+    int32_t n_t;
+    const int64_t *rec_cell;
+    float *traces;             // [n_t_max][n_rec]
+    int64_t n_rec;
+    int32_t n_t_max;
+    int64_t *step;             // device step counter
+};
+
+// Launchers (kernels.hip).  Return hipSuccess or the launch error.
+hipError_t launch_velocity(int ndim, int nmech, int tile_rows, const StepArgs &a, hipStream_t s);
+hipError_t launch_pressure(int ndim, int nmech, int tile_rows, const StepArgs &a, hipStream_t s);
+hipError_t launch_src_rec(const SrcRecArgs &a, hipStream_t s);
+// Tile footprint of a launch configuration: cells per tile along x and y.
+void tile_shape(int ndim, int tile_rows, int *tx, int *ty);
+
+}  // namespace fw

@@ -1,0 +1,776 @@
+// Host runtime behind the C ABI of include/fw25.h: validation, FP64 set-up of
+// the per-step coefficients, workspace layout, tile lists and HIP-graph replay.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fw25.h"
+#include "fw_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_OR_FAIL(expr)                                                                          \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) return fail(FW_EHIP, "%s: %s", #expr, hipGetErrorString(e_));        \
+    } while (0)
+
+// Staggered first-derivative coefficients of order 8 (Taylor construction:
+// exact for odd monomials up to x^7 on the half-integer stencil).
+constexpr double kFD[4] = {1225.0 / 1024.0, -245.0 / 3072.0, 49.0 / 5120.0, -5.0 / 7168.0};
+
+double fd_abs_sum() { return std::fabs(kFD[0]) + std::fabs(kFD[1]) + std::fabs(kFD[2]) + std::fabs(kFD[3]); }
+
+constexpr int64_t kAlignCells = 64;
+constexpr int64_t kAlignBytes = 256;
+
+int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+// Device buffer owned by the library (small tables only).
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    ~DevBuf() { release(); }
+    void release()
+    {
+        if (ptr) (void)hipFree(ptr);
+        ptr = nullptr;
+        bytes = 0;
+    }
+    hipError_t ensure(size_t n)
+    {
+        if (n <= bytes && ptr) return hipSuccess;
+        release();
+        hipError_t e = hipMalloc(&ptr, std::max<size_t>(n, 256));
+        if (e == hipSuccess) bytes = std::max<size_t>(n, 256);
+        return e;
+    }
+    template <class T> T *as() const { return static_cast<T *>(ptr); }
+};
+
+}  // namespace
+
+struct fw_sim {
+    // grid
+    int ndim = 0, n_domains = 0, nmech = 0, pml = 0;
+    double dx = 0, dt = 0;
+    double pml_R0 = 1e-4, pml_falpha = 1e6, pml_cref = 0;
+    std::vector<fw::DomainDesc> doms;
+    int64_t total_cells = 0;
+    // workspace layout (byte offsets)
+    int64_t off_p = 0, off_v[3] = {0, 0, 0}, off_psi1[3] = {0, 0, 0}, off_psi2 = 0;
+    int64_t off_pP1[3] = {0, 0, 0}, off_pP2[3] = {0, 0, 0}, state_end = 0, off_cls = 0, ws_bytes = 0;
+    bool have_v[3] = {false, false, false};
+    char *ws = nullptr;
+    // media
+    bool media_set = false, table_set = false;
+    int n_classes = 0;
+    std::vector<double> c, rho, beta;
+    double noise_amp = 0;
+    uint64_t noise_seed = 0;
+    std::vector<double> kappa, dcoef, alpha;
+    // device tables
+    DevBuf d_doms, d_classes, d_pml, d_tiles, d_src_cell, d_src_wave, d_waves, d_rec_cell, d_traces, d_step;
+    int n_tiles = 0, tiles_per_xcd = 0;
+    int64_t n_src = 0, n_rec = 0;
+    int n_t = 0, n_t_max = 0;
+    // options
+    int graph_steps = 16, march_chunk = 0, tile_rows = 16;
+    // stepping
+    int64_t host_step = 0;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    int graph_len = 0;
+    bool tiles_dirty = true;
+
+    ~fw_sim()
+    {
+        drop_graph();
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    }
+    void drop_graph()
+    {
+        if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+        graph_exec = nullptr;
+        graph_len = 0;
+    }
+    int64_t cells(int d) const { return doms[d].n[0] * doms[d].n[1] * doms[d].n[2]; }
+};
+
+namespace {
+
+void layout(fw_sim *s)
+{
+    int64_t off = 0;
+    const int64_t fbytes = s->total_cells * 4;
+    const int64_t vbytes = s->total_cells * 4 * s->nmech;
+    auto take = [&](int64_t bytes) {
+        const int64_t o = off;
+        off = align_up(off + bytes, kAlignBytes);
+        return o;
+    };
+    s->off_p = take(fbytes);
+    for (int a = 0; a < 3; ++a) {
+        s->have_v[a] = a < s->ndim;
+        s->off_v[a] = take(s->have_v[a] ? fbytes : 0);
+    }
+    for (int a = 0; a < 3; ++a) s->off_psi1[a] = take(a < s->ndim ? vbytes : 0);
+    s->off_psi2 = take(vbytes);
+    for (int a = 0; a < 3; ++a) s->off_pP1[a] = take(s->pml > 0 && a < s->ndim ? fbytes : 0);
+    for (int a = 0; a < 3; ++a) s->off_pP2[a] = take(s->pml > 0 && a < s->ndim ? fbytes : 0);
+    s->state_end = off;
+    s->off_cls = take(s->total_cells);
+    s->ws_bytes = off;
+}
+
+fw::Fields fields_of(const fw_sim *s)
+{
+    fw::Fields f{};
+    char *w = s->ws;
+    f.p = reinterpret_cast<float *>(w + s->off_p);
+    f.vx = reinterpret_cast<float *>(w + s->off_v[0]);
+    f.vy = reinterpret_cast<float *>(w + s->off_v[1]);
+    f.vz = reinterpret_cast<float *>(w + s->off_v[2]);
+    f.psi1x = reinterpret_cast<float *>(w + s->off_psi1[0]);
+    f.psi1y = reinterpret_cast<float *>(w + s->off_psi1[1]);
+    f.psi1z = reinterpret_cast<float *>(w + s->off_psi1[2]);
+    f.psi2 = reinterpret_cast<float *>(w + s->off_psi2);
+    for (int a = 0; a < 3; ++a) {
+        f.pP1[a] = reinterpret_cast<float *>(w + s->off_pP1[a]);
+        f.pP2[a] = reinterpret_cast<float *>(w + s->off_pP2[a]);
+    }
+    f.cls = reinterpret_cast<uint8_t *>(w + s->off_cls);
+    return f;
+}
+
+// CPML recursion coefficients along one axis of n points (kappa = 1):
+// d = d0 delta^2, alpha = pi f_alpha (1 - delta), b = exp(-(d + alpha) dt),
+// a = d / (d + alpha) (b - 1); delta = depth from the slab's inner edge.
+void pml_axis(const fw_sim *s, int64_t n, double cref, bool faces, double *a, double *b)
+{
+    const int P = s->pml;
+    const double d0 = P > 0 ? 3.0 * cref * std::log(1.0 / s->pml_R0) / (2.0 * P * s->dx) : 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const double x = (double)i + (faces ? 0.5 : 0.0);
+        double delta = 0.0;
+        if (P > 0) {
+            delta = std::max(0.0, std::max((P - 0.5 - x) / P, (x - ((double)n - P - 0.5)) / P));
+            delta = std::min(delta, 1.0);
+        }
+        const double d = d0 * delta * delta;
+        const double al = M_PI * s->pml_falpha * (1.0 - delta);
+        const double bb = std::exp(-(d + al) * s->dt);
+        b[i] = bb;
+        a[i] = d > 0.0 ? d / (d + al) * (bb - 1.0) : 0.0;
+    }
+}
+
+int stability_check(const fw_sim *s, double min_kappa_prod)
+{
+    double cmax = 0;
+    for (double v : s->c) cmax = std::max(cmax, v);
+    const double courant = cmax * (1.0 + s->noise_amp) * s->dt / s->dx * std::sqrt((double)s->ndim) * fd_abs_sum() /
+                           std::sqrt(min_kappa_prod);
+    if (!(courant < 1.0))
+        return fail(FW_EUNSTABLE, "time step too large: c_max dt/dx sqrt(ndim) sum|c_m| / sqrt(kappa1 kappa2) = %.6f >= 1",
+                    courant);
+    return FW_OK;
+}
+
+int build_tiles(fw_sim *s)
+{
+    int tx, ty;
+    fw::tile_shape(s->ndim, s->tile_rows, &tx, &ty);
+    std::vector<fw::Tile> tiles;
+    for (int d = 0; d < s->n_domains; ++d) {
+        const int64_t nx = s->doms[d].n[0], ny = s->doms[d].n[1], nz = s->doms[d].n[2];
+        const int64_t nmarch = s->ndim == 3 ? nz : (s->ndim == 2 ? ny : 1);
+        const int64_t nytile = s->ndim == 3 ? (ny + ty - 1) / ty : 1;
+        const int64_t nxtile = (nx + tx - 1) / tx;
+        int64_t chunk = s->march_chunk;
+        if (chunk <= 0) {
+            // aim for a few thousand tiles over all domains, chunks of >= 32 planes
+            const int64_t cols = nxtile * nytile;
+            chunk = nmarch;
+            while (chunk > 64 && cols * ((nmarch + chunk - 1) / chunk) < 4096) chunk = (chunk + 1) / 2;
+        }
+        chunk = std::max<int64_t>(1, std::min<int64_t>(chunk, nmarch));
+        for (int64_t z0 = 0; z0 < nmarch; z0 += chunk)
+            for (int64_t yt = 0; yt < nytile; ++yt)
+                for (int64_t xt = 0; xt < nxtile; ++xt) {
+                    fw::Tile t{};
+                    t.dom = d;
+                    t.x0 = (int32_t)(xt * tx);
+                    t.y0 = (int32_t)(yt * ty);
+                    t.z0 = (int32_t)z0;
+                    t.z1 = (int32_t)std::min(nmarch, z0 + chunk);
+                    tiles.push_back(t);
+                }
+    }
+    s->n_tiles = (int)tiles.size();
+    s->tiles_per_xcd = (s->n_tiles + 7) / 8;
+    HIP_OR_FAIL(s->d_tiles.ensure(tiles.size() * sizeof(fw::Tile)));
+    HIP_OR_FAIL(hipMemcpy(s->d_tiles.ptr, tiles.data(), tiles.size() * sizeof(fw::Tile), hipMemcpyHostToDevice));
+    s->tiles_dirty = false;
+    s->drop_graph();
+    return FW_OK;
+}
+
+fw::StepArgs step_args(const fw_sim *s)
+{
+    fw::StepArgs a{};
+    a.f = fields_of(s);
+    a.doms = s->d_doms.as<fw::DomainDesc>();
+    a.tiles = s->d_tiles.as<fw::Tile>();
+    a.classes = s->d_classes.as<fw::ClassCoef>();
+    a.pml_tab = s->d_pml.as<float>();
+    a.n_tiles = s->n_tiles;
+    a.tiles_per_xcd = s->tiles_per_xcd;
+    a.pml = s->pml;
+    for (int m = 0; m < 4; ++m) a.fd[m] = (float)(kFD[m] / s->dx);
+    a.dt = (float)s->dt;
+    a.noise_amp = (float)s->noise_amp;
+    return a;
+}
+
+fw::SrcRecArgs srcrec_args(const fw_sim *s)
+{
+    fw::SrcRecArgs a{};
+    a.p = fields_of(s).p;
+    a.src_cell = s->d_src_cell.as<int64_t>();
+    a.src_wave = s->d_src_wave.as<int32_t>();
+    a.waves = s->d_waves.as<float>();
+    a.n_src = s->n_src;
+    a.n_t = s->n_t;
+    a.rec_cell = s->d_rec_cell.as<int64_t>();
+    a.traces = s->d_traces.as<float>();
+    a.n_rec = s->n_rec;
+    a.n_t_max = s->n_t_max;
+    a.step = s->d_step.as<int64_t>();
+    return a;
+}
+
+int enqueue_steps(fw_sim *s, int n, hipStream_t st)
+{
+    const fw::StepArgs a = step_args(s);
+    const fw::SrcRecArgs r = srcrec_args(s);
+    for (int i = 0; i < n; ++i) {
+        HIP_OR_FAIL(fw::launch_velocity(s->ndim, s->nmech, s->tile_rows, a, st));
+        HIP_OR_FAIL(fw::launch_pressure(s->ndim, s->nmech, s->tile_rows, a, st));
+        HIP_OR_FAIL(fw::launch_src_rec(r, st));
+    }
+    return FW_OK;
+}
+
+int ensure_graph(fw_sim *s, int len)
+{
+    if (s->graph_exec && s->graph_len == len) return FW_OK;
+    s->drop_graph();
+    if (!s->cap_stream) HIP_OR_FAIL(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+    HIP_OR_FAIL(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+    const int rc = enqueue_steps(s, len, s->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s->cap_stream, &g);
+    if (rc != FW_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(FW_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e2 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e2 != hipSuccess) return fail(FW_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e2));
+    s->graph_exec = ex;
+    s->graph_len = len;
+    return FW_OK;
+}
+
+bool check_ptr(const void *p) { return p != nullptr; }
+
+}  // namespace
+
+extern "C" {
+
+const char *fw_last_error(void) { return g_err.c_str(); }
+
+int fw_abi_version(void) { return 1; }
+
+int fw_create_grid(fw_sim **out, int ndim, int n_domains, const int64_t *shape, double dx, double dt, int n_mech,
+                   int pml_cells, const double *pml_params)
+{
+    g_err.clear();
+    if (!out) return fail(FW_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (ndim < 1 || ndim > 3) return fail(FW_EINVAL, "ndim must be 1, 2 or 3 (got %d)", ndim);
+    if (n_domains < 1) return fail(FW_EINVAL, "n_domains must be >= 1 (got %d)", n_domains);
+    if (!shape) return fail(FW_EINVAL, "shape is NULL");
+    if (!(dx > 0) || !(dt > 0) || !std::isfinite(dx) || !std::isfinite(dt))
+        return fail(FW_EINVAL, "dx and dt must be finite and > 0");
+    if (n_mech < 1 || n_mech > fw::kMaxMech) return fail(FW_EINVAL, "n_mech must be in 1..4 (got %d)", n_mech);
+    if (pml_cells < 0) return fail(FW_EINVAL, "pml_cells must be >= 0");
+    fw_sim *s = new (std::nothrow) fw_sim();
+    if (!s) return fail(FW_ENOMEM, "out of host memory");
+    s->ndim = ndim;
+    s->n_domains = n_domains;
+    s->nmech = n_mech;
+    s->pml = pml_cells;
+    s->dx = dx;
+    s->dt = dt;
+    if (pml_params) {
+        s->pml_R0 = pml_params[0];
+        s->pml_falpha = pml_params[1];
+        s->pml_cref = pml_params[2];
+        if (!(s->pml_R0 > 0 && s->pml_R0 < 1) || !(s->pml_falpha >= 0) || !(s->pml_cref >= 0)) {
+            delete s;
+            return fail(FW_EINVAL, "pml_params: need 0 < R0 < 1, f_alpha >= 0, c_ref >= 0");
+        }
+    }
+    int64_t off = 0;
+    for (int d = 0; d < n_domains; ++d) {
+        fw::DomainDesc D{};
+        for (int a = 0; a < 3; ++a) {
+            const int64_t n = shape[3 * d + a];
+            if (a < ndim) {
+                if (n <= 2 * (int64_t)pml_cells + 8 || n > (int64_t)INT32_MAX) {
+                    delete s;
+                    return fail(FW_EINVAL, "domain %d axis %d: size %lld must exceed 2*pml_cells+8 = %d", d, a,
+                                (long long)n, 2 * pml_cells + 8);
+                }
+            } else if (n != 1) {
+                delete s;
+                return fail(FW_EINVAL, "domain %d axis %d: unused dimension must be 1 (got %lld)", d, a, (long long)n);
+            }
+            D.n[a] = n;
+        }
+        D.cell_off = off;
+        off = align_up(off + D.n[0] * D.n[1] * D.n[2], kAlignCells);
+        s->doms.push_back(D);
+    }
+    s->total_cells = off;
+    layout(s);
+    *out = s;
+    return FW_OK;
+}
+
+int fw_destroy(fw_sim *sim)
+{
+    delete sim;
+    return FW_OK;
+}
+
+int64_t fw_workspace_bytes(const fw_sim *sim) { return sim ? sim->ws_bytes : -1; }
+
+int fw_bind_workspace(fw_sim *sim, void *d_ptr, int64_t bytes)
+{
+    g_err.clear();
+    if (!sim) return fail(FW_EINVAL, "sim is NULL");
+    if (!d_ptr) return fail(FW_EINVAL, "workspace pointer is NULL");
+    if ((reinterpret_cast<uintptr_t>(d_ptr) % kAlignBytes) != 0) return fail(FW_EINVAL, "workspace must be 256-byte aligned");
+    if (bytes < sim->ws_bytes)
+        return fail(FW_ENOMEM, "workspace too small: %lld < %lld bytes", (long long)bytes, (long long)sim->ws_bytes);
+    sim->ws = static_cast<char *>(d_ptr);
+    HIP_OR_FAIL(hipMemset(sim->ws, 0, (size_t)sim->ws_bytes));
+    HIP_OR_FAIL(sim->d_step.ensure(sizeof(int64_t)));
+    HIP_OR_FAIL(hipMemset(sim->d_step.ptr, 0, sizeof(int64_t)));
+    sim->host_step = 0;
+    sim->media_set = sim->table_set = false;
+    sim->drop_graph();
+    return FW_OK;
+}
+
+int fw_set_media(fw_sim *sim, const uint8_t *h_class, const int32_t *class_base, int n_classes, const double *c,
+                 const double *rho, const double *beta, double c_noise_amp, uint64_t noise_seed)
+{
+    g_err.clear();
+    if (!sim) return fail(FW_EINVAL, "sim is NULL");
+    if (!check_ptr(h_class) || !check_ptr(class_base) || !check_ptr(c) || !check_ptr(rho) || !check_ptr(beta))
+        return fail(FW_EINVAL, "NULL array argument");
+    if (n_classes < 1) return fail(FW_EINVAL, "n_classes must be >= 1");
+    if (!(c_noise_amp >= 0 && c_noise_amp < 0.5)) return fail(FW_EINVAL, "c_noise_amp must be in [0, 0.5)");
+    for (int k = 0; k < n_classes; ++k) {
+        if (!(c[k] > 0) || !(rho[k] > 0) || !std::isfinite(c[k]) || !std::isfinite(rho[k]))
+            return fail(FW_EINVAL, "class %d: c and rho must be finite and > 0", k);
+        if (!std::isfinite(beta[k])) return fail(FW_EINVAL, "class %d: beta must be finite", k);
+    }
+    // class indices: local < 256 (uint8) and base + local < n_classes
+    int64_t pos = 0;
+    std::vector<int> ncls(sim->n_domains, 0);
+    for (int d = 0; d < sim->n_domains; ++d) {
+        const int32_t b = class_base[d];
+        if (b < 0 || b >= n_classes) return fail(FW_EINVAL, "domain %d: class_base %d out of range", d, b);
+        const int64_t nc = sim->cells(d);
+        int mx = 0;
+        for (int64_t i = 0; i < nc; ++i) mx = std::max<int>(mx, h_class[pos + i]);
+        if (b + mx >= n_classes)
+            return fail(FW_EINVAL, "domain %d: class index %d + base %d >= n_classes %d", d, mx, b, n_classes);
+        ncls[d] = mx + 1;
+        pos += nc;
+    }
+    sim->c.assign(c, c + n_classes);
+    sim->rho.assign(rho, rho + n_classes);
+    sim->beta.assign(beta, beta + n_classes);
+    sim->n_classes = n_classes;
+    sim->noise_amp = c_noise_amp;
+    sim->noise_seed = noise_seed;
+    int rc = stability_check(sim, 1.0);
+    if (rc != FW_OK) return rc;
+    if (!sim->ws) return fail(FW_ESTATE, "fw_bind_workspace must come first");
+    // upload the map
+    pos = 0;
+    char *dcls = sim->ws + sim->off_cls;
+    for (int d = 0; d < sim->n_domains; ++d) {
+        const int64_t nc = sim->cells(d);
+        HIP_OR_FAIL(hipMemcpy(dcls + sim->doms[d].cell_off, h_class + pos, (size_t)nc, hipMemcpyHostToDevice));
+        pos += nc;
+        sim->doms[d].class_base = class_base[d];
+        sim->doms[d].n_classes = ncls[d];
+        sim->doms[d].noise_seed = noise_seed;
+    }
+    // CPML profiles, per domain and axis: [aF | bF | aC | bC] x n
+    double cref = sim->pml_cref;
+    if (cref <= 0) {
+        for (double v : sim->c) cref = std::max(cref, v);
+    }
+    std::vector<float> tab;
+    std::vector<double> a, b;
+    for (int d = 0; d < sim->n_domains; ++d) {
+        for (int ax = 0; ax < 3; ++ax) {
+            const int64_t n = sim->doms[d].n[ax];
+            sim->doms[d].pml_off[ax] = (int32_t)tab.size();
+            if (ax >= sim->ndim) continue;
+            a.resize(n);
+            b.resize(n);
+            for (int stag = 0; stag < 2; ++stag) {
+                pml_axis(sim, n, cref, stag == 0, a.data(), b.data());
+                for (int64_t i = 0; i < n; ++i) tab.push_back((float)a[i]);
+                for (int64_t i = 0; i < n; ++i) tab.push_back((float)b[i]);
+            }
+        }
+    }
+    if (tab.size() > (size_t)INT32_MAX) return fail(FW_EINVAL, "CPML tables too large");
+    HIP_OR_FAIL(sim->d_pml.ensure(std::max<size_t>(tab.size(), 1) * sizeof(float)));
+    if (!tab.empty()) HIP_OR_FAIL(hipMemcpy(sim->d_pml.ptr, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice));
+    HIP_OR_FAIL(sim->d_doms.ensure(sim->doms.size() * sizeof(fw::DomainDesc)));
+    HIP_OR_FAIL(hipMemcpy(sim->d_doms.ptr, sim->doms.data(), sim->doms.size() * sizeof(fw::DomainDesc),
+                          hipMemcpyHostToDevice));
+    sim->media_set = true;
+    sim->table_set = false;
+    sim->tiles_dirty = true;
+    sim->drop_graph();
+    return FW_OK;
+}
+
+int fw_set_relaxation_table(fw_sim *sim, int n_classes, const double *kappa, const double *d, const double *alpha)
+{
+    g_err.clear();
+    if (!sim) return fail(FW_EINVAL, "sim is NULL");
+    if (!sim->media_set) return fail(FW_ESTATE, "fw_set_media must come first");
+    if (n_classes != sim->n_classes)
+        return fail(FW_EINVAL, "n_classes %d differs from fw_set_media (%d)", n_classes, sim->n_classes);
+    if (!kappa || !d || !alpha) return fail(FW_EINVAL, "NULL array argument");
+    const int N = sim->nmech;
+    double min_kk = 1e300;
+    std::vector<fw::ClassCoef> cc(n_classes);
+    for (int k = 0; k < n_classes; ++k) {
+        fw::ClassCoef &o = cc[k];
+        std::memset(&o, 0, sizeof o);
+        const double k1 = kappa[2 * k], k2 = kappa[2 * k + 1];
+        if (!(k1 > 0) || !(k2 > 0) || !std::isfinite(k1) || !std::isfinite(k2))
+            return fail(FW_EINVAL, "class %d: kappa must be finite and > 0", k);
+        min_kk = std::min(min_kk, k1 * k2);
+        o.ik1 = (float)(1.0 / k1);
+        o.ik2 = (float)(1.0 / k2);
+        o.rho = (float)sim->rho[k];
+        o.K = (float)(sim->rho[k] * sim->c[k] * sim->c[k]);
+        o.twobeta = (float)(2.0 * sim->beta[k]);
+        for (int i = 0; i < 2; ++i) {
+            const double kap = i == 0 ? k1 : k2;
+            for (int nu = 0; nu < N; ++nu) {
+                const double dd = d[(k * 2 + i) * N + nu], al = alpha[(k * 2 + i) * N + nu];
+                if (!(dd >= 0) || !(al >= 0) || !std::isfinite(dd) || !std::isfinite(al) || !(dd + kap * al > 0))
+                    return fail(FW_EINVAL, "class %d operator %d mechanism %d: need d >= 0, alpha >= 0, d + kappa alpha > 0",
+                                k, i + 1, nu);
+                // Eqs. (relaxation_b) and (relaxation_a), FP64
+                const double bb = std::exp(-(dd / kap + al) * sim->dt);
+                const double aa = dd / (kap * (dd + kap * al)) * (bb - 1.0);
+                (i == 0 ? o.a1 : o.a2)[nu] = (float)aa;
+                (i == 0 ? o.b1 : o.b2)[nu] = (float)bb;
+            }
+        }
+    }
+    int rc = stability_check(sim, min_kk);
+    if (rc != FW_OK) return rc;
+    sim->kappa.assign(kappa, kappa + 2 * n_classes);
+    sim->dcoef.assign(d, d + 2 * N * n_classes);
+    sim->alpha.assign(alpha, alpha + 2 * N * n_classes);
+    HIP_OR_FAIL(sim->d_classes.ensure(cc.size() * sizeof(fw::ClassCoef)));
+    HIP_OR_FAIL(hipMemcpy(sim->d_classes.ptr, cc.data(), cc.size() * sizeof(fw::ClassCoef), hipMemcpyHostToDevice));
+    sim->table_set = true;
+    sim->drop_graph();
+    return FW_OK;
+}
+
+static int check_cells(const fw_sim *sim, int64_t n, const int32_t *domain, const int64_t *cell,
+                       std::vector<int64_t> &global, const char *what)
+{
+    global.resize(n);
+    for (int64_t i = 0; i < n; ++i) {
+        const int32_t d = domain[i];
+        if (d < 0 || d >= sim->n_domains) return fail(FW_EINVAL, "%s %lld: domain %d out of range", what, (long long)i, d);
+        if (cell[i] < 0 || cell[i] >= sim->cells(d))
+            return fail(FW_EINVAL, "%s %lld: cell %lld outside domain %d", what, (long long)i, (long long)cell[i], d);
+        global[i] = sim->doms[d].cell_off + cell[i];
+    }
+    return FW_OK;
+}
+
+int fw_set_sources(fw_sim *sim, int64_t n_src, const int32_t *domain, const int64_t *cell, const int32_t *wave_idx,
+                   int n_wave, const float *waves, int n_t)
+{
+    g_err.clear();
+    if (!sim) return fail(FW_EINVAL, "sim is NULL");
+    if (n_src < 0) return fail(FW_EINVAL, "n_src must be >= 0");
+    if (n_src > 0) {
+        if (!domain || !cell || !wave_idx || !waves) return fail(FW_EINVAL, "NULL array argument");
+        if (n_wave < 1 || n_t < 1) return fail(FW_EINVAL, "n_wave and n_t must be >= 1");
+    }
+    std::vector<int64_t> g;
+    int rc = check_cells(sim, n_src, domain, cell, g, "source");
+    if (rc != FW_OK) return rc;
+    for (int64_t i = 0; i < n_src; ++i)
+        if (wave_idx[i] < 0 || wave_idx[i] >= n_wave)
+            return fail(FW_EINVAL, "source %lld: wave index %d out of range", (long long)i, wave_idx[i]);
+    {
+        std::vector<int64_t> sorted(g);
+        std::sort(sorted.begin(), sorted.end());
+        if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+            return fail(FW_EINVAL, "a source cell appears more than once");
+    }
+    for (int64_t i = 0; i < (int64_t)n_wave * (n_src > 0 ? n_t : 0); ++i)
+        if (!std::isfinite(waves[i])) return fail(FW_ENONFINITE, "source waveform sample %lld is not finite", (long long)i);
+    if (!sim->ws) return fail(FW_ESTATE, "fw_bind_workspace must come first");
+    sim->n_src = n_src;
+    sim->n_t = n_src > 0 ? n_t : 0;
+    if (n_src > 0) {
+        HIP_OR_FAIL(sim->d_src_cell.ensure(n_src * sizeof(int64_t)));
+        HIP_OR_FAIL(sim->d_src_wave.ensure(n_src * sizeof(int32_t)));
+        HIP_OR_FAIL(sim->d_waves.ensure((size_t)n_wave * n_t * sizeof(float)));
+        HIP_OR_FAIL(hipMemcpy(sim->d_src_cell.ptr, g.data(), n_src * sizeof(int64_t), hipMemcpyHostToDevice));
+        HIP_OR_FAIL(hipMemcpy(sim->d_src_wave.ptr, wave_idx, n_src * sizeof(int32_t), hipMemcpyHostToDevice));
+        HIP_OR_FAIL(hipMemcpy(sim->d_waves.ptr, waves, (size_t)n_wave * n_t * sizeof(float), hipMemcpyHostToDevice));
+    }
+    sim->drop_graph();
+    return FW_OK;
+}
+
+int fw_set_receivers(fw_sim *sim, int64_t n_rec, const int32_t *domain, const int64_t *cell, int n_t_max)
+{
+    g_err.clear();
+    if (!sim) return fail(FW_EINVAL, "sim is NULL");
+    if (n_rec < 0 || n_t_max < 0) return fail(FW_EINVAL, "n_rec and n_t_max must be >= 0");
+    if (n_rec > 0 && (!domain || !cell)) return fail(FW_EINVAL, "NULL array argument");
+    std::vector<int64_t> g;
+    int rc = check_cells(sim, n_rec, domain, cell, g, "receiver");
+    if (rc != FW_OK) return rc;
+    if (!sim->ws) return fail(FW_ESTATE, "fw_bind_workspace must come first");
+    sim->n_rec = n_rec;
+    sim->n_t_max = n_rec > 0 ? n_t_max : 0;
+    if (n_rec > 0) {
+        HIP_OR_FAIL(sim->d_rec_cell.ensure(n_rec * sizeof(int64_t)));
+        HIP_OR_FAIL(hipMemcpy(sim->d_rec_cell.ptr, g.data(), n_rec * sizeof(int64_t), hipMemcpyHostToDevice));
+        const size_t tb = (size_t)n_rec * std::max(n_t_max, 1) * sizeof(float);
+        HIP_OR_FAIL(sim->d_traces.ensure(tb));
+        HIP_OR_FAIL(hipMemset(sim->d_traces.ptr, 0, tb));
+    }
+    sim->drop_graph();
+    return FW_OK;
+}
+
+int fw_step(fw_sim *sim, int n_steps, void *hip_stream)
+{
+    g_err.clear();
+    if (!sim) return fail(FW_EINVAL, "sim is NULL");
+    if (n_steps < 0) return fail(FW_EINVAL, "n_steps must be >= 0");
+    if (!sim->ws || !sim->media_set || !sim->table_set)
+        return fail(FW_ESTATE, "bind the workspace, then set media and the relaxation table before stepping");
+    if (n_steps == 0) return FW_OK;
+    if (sim->tiles_dirty) {
+        int rc = build_tiles(sim);
+        if (rc != FW_OK) return rc;
+    }
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    int left = n_steps;
+    if (sim->graph_steps > 0 && left >= sim->graph_steps) {
+        int rc = ensure_graph(sim, sim->graph_steps);
+        if (rc != FW_OK) return rc;
+        while (left >= sim->graph_steps) {
+            HIP_OR_FAIL(hipGraphLaunch(sim->graph_exec, st));
+            left -= sim->graph_steps;
+        }
+    }
+    int rc = enqueue_steps(sim, left, st);
+    if (rc != FW_OK) return rc;
+    sim->host_step += n_steps;
+    return FW_OK;
+}
+
+int fw_read_receivers(fw_sim *sim, float *dst, int64_t n_elems, int dst_is_device, void *hip_stream)
+{
+    g_err.clear();
+    if (!sim) return fail(FW_EINVAL, "sim is NULL");
+    if (!dst) return fail(FW_EINVAL, "dst is NULL");
+    if (n_elems < 0 || n_elems > sim->n_rec * (int64_t)sim->n_t_max)
+        return fail(FW_EINVAL, "n_elems %lld exceeds the trace buffer (%lld)", (long long)n_elems,
+                    (long long)(sim->n_rec * (int64_t)sim->n_t_max));
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if (n_elems > 0)
+        HIP_OR_FAIL(hipMemcpyAsync(dst, sim->d_traces.ptr, (size_t)n_elems * sizeof(float),
+                                   dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+    HIP_OR_FAIL(hipStreamSynchronize(st));
+    return FW_OK;
+}
+
+int fw_reset_state(fw_sim *sim, void *hip_stream)
+{
+    g_err.clear();
+    if (!sim) return fail(FW_EINVAL, "sim is NULL");
+    if (!sim->ws) return fail(FW_ESTATE, "no workspace bound");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    HIP_OR_FAIL(hipMemsetAsync(sim->ws, 0, (size_t)sim->state_end, st));
+    HIP_OR_FAIL(hipMemsetAsync(sim->d_step.ptr, 0, sizeof(int64_t), st));
+    if (sim->n_rec > 0)
+        HIP_OR_FAIL(hipMemsetAsync(sim->d_traces.ptr, 0, (size_t)sim->n_rec * std::max(sim->n_t_max, 1) * sizeof(float), st));
+    sim->host_step = 0;
+    return FW_OK;
+}
+
+int fw_get_step(const fw_sim *sim, int64_t *step)
+{
+    if (!sim || !step) return fail(FW_EINVAL, "NULL argument");
+    *step = sim->host_step;
+    return FW_OK;
+}
+
+int64_t fw_state_bytes(const fw_sim *sim) { return sim ? sim->state_end + kAlignBytes : -1; }
+
+int fw_save_state(fw_sim *sim, void *d_dst, void *hip_stream)
+{
+    g_err.clear();
+    if (!sim || !d_dst) return fail(FW_EINVAL, "NULL argument");
+    if (!sim->ws) return fail(FW_ESTATE, "no workspace bound");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    char *dst = static_cast<char *>(d_dst);
+    HIP_OR_FAIL(hipMemcpyAsync(dst, sim->ws, (size_t)sim->state_end, hipMemcpyDeviceToDevice, st));
+    HIP_OR_FAIL(hipMemcpyAsync(dst + sim->state_end, sim->d_step.ptr, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+    return FW_OK;
+}
+
+int fw_load_state(fw_sim *sim, const void *d_src, void *hip_stream)
+{
+    g_err.clear();
+    if (!sim || !d_src) return fail(FW_EINVAL, "NULL argument");
+    if (!sim->ws) return fail(FW_ESTATE, "no workspace bound");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const char *src = static_cast<const char *>(d_src);
+    HIP_OR_FAIL(hipMemcpyAsync(sim->ws, src, (size_t)sim->state_end, hipMemcpyDeviceToDevice, st));
+    HIP_OR_FAIL(hipMemcpyAsync(sim->d_step.ptr, src + sim->state_end, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+    int64_t step = 0;
+    HIP_OR_FAIL(hipMemcpyAsync(&step, src + sim->state_end, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_OR_FAIL(hipStreamSynchronize(st));
+    sim->host_step = step;
+    return FW_OK;
+}
+
+int fw_time_kernels(fw_sim *sim, int n_steps, void *hip_stream, double *avg_ms)
+{
+    g_err.clear();
+    if (!sim || !avg_ms) return fail(FW_EINVAL, "NULL argument");
+    if (n_steps < 1) return fail(FW_EINVAL, "n_steps must be >= 1");
+    if (!sim->ws || !sim->media_set || !sim->table_set) return fail(FW_ESTATE, "set up the simulation first");
+    if (sim->tiles_dirty) {
+        int rc = build_tiles(sim);
+        if (rc != FW_OK) return rc;
+    }
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const fw::StepArgs a = step_args(sim);
+    const fw::SrcRecArgs r = srcrec_args(sim);
+    std::vector<hipEvent_t> ev((size_t)n_steps * 4, nullptr);
+    for (auto &e : ev) HIP_OR_FAIL(hipEventCreate(&e));
+    int rc = FW_OK;
+    for (int i = 0; i < n_steps && rc == FW_OK; ++i) {
+        hipEvent_t *e = &ev[(size_t)i * 4];
+        hipError_t err = hipEventRecord(e[0], st);
+        if (err == hipSuccess) err = fw::launch_velocity(sim->ndim, sim->nmech, sim->tile_rows, a, st);
+        if (err == hipSuccess) err = hipEventRecord(e[1], st);
+        if (err == hipSuccess) err = fw::launch_pressure(sim->ndim, sim->nmech, sim->tile_rows, a, st);
+        if (err == hipSuccess) err = hipEventRecord(e[2], st);
+        if (err == hipSuccess) err = fw::launch_src_rec(r, st);
+        if (err == hipSuccess) err = hipEventRecord(e[3], st);
+        if (err != hipSuccess) rc = fail(FW_EHIP, "timed launch: %s", hipGetErrorString(err));
+    }
+    double tot[3] = {0, 0, 0};
+    if (rc == FW_OK) {
+        hipError_t err = hipStreamSynchronize(st);
+        if (err != hipSuccess) rc = fail(FW_EHIP, "hipStreamSynchronize: %s", hipGetErrorString(err));
+        for (int i = 0; i < n_steps && rc == FW_OK; ++i)
+            for (int k = 0; k < 3; ++k) {
+                float ms = 0;
+                err = hipEventElapsedTime(&ms, ev[(size_t)i * 4 + k], ev[(size_t)i * 4 + k + 1]);
+                if (err != hipSuccess) rc = fail(FW_EHIP, "hipEventElapsedTime: %s", hipGetErrorString(err));
+                tot[k] += ms;
+            }
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    if (rc != FW_OK) return rc;
+    for (int k = 0; k < 3; ++k) avg_ms[k] = tot[k] / n_steps;
+    sim->host_step += n_steps;
+    return FW_OK;
+}
+
+int fw_set_option(fw_sim *sim, int key, int64_t value)
+{
+    g_err.clear();
+    if (!sim) return fail(FW_EINVAL, "sim is NULL");
+    switch (key) {
+    case FW_OPT_GRAPH_STEPS:
+        if (value < 0 || value > 4096) return fail(FW_EINVAL, "graph steps must be in 0..4096");
+        sim->graph_steps = (int)value;
+        sim->drop_graph();
+        return FW_OK;
+    case FW_OPT_MARCH_CHUNK:
+        if (value != 0 && value < 8) return fail(FW_EINVAL, "march chunk must be 0 (auto) or >= 8");
+        sim->march_chunk = (int)value;
+        sim->tiles_dirty = true;
+        return FW_OK;
+    case FW_OPT_TILE_ROWS:
+        if (value != 8 && value != 16) return fail(FW_EINVAL, "tile rows must be 8 or 16");
+        sim->tile_rows = (int)value;
+        sim->tiles_dirty = true;
+        return FW_OK;
+    default:
+        return fail(FW_EINVAL, "unknown option %d", key);
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,71 @@
+"""ctypes binding of libfw25.so (declarations in include/fw25.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+Importing this module loads the library and fails loudly when it is missing;
+there is no fallback.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfw25.so")
+
+FW_OK, FW_EINVAL, FW_ESTATE, FW_EUNSTABLE, FW_EHIP, FW_ENOMEM, FW_ENONFINITE, FW_EUNSUPPORTED = \
+    0, -1, -2, -3, -4, -5, -6, -7
+FW_OPT_GRAPH_STEPS, FW_OPT_MARCH_CHUNK, FW_OPT_TILE_ROWS = 1, 2, 3
+
+_NAMES = {0: "FW_OK", -1: "FW_EINVAL", -2: "FW_ESTATE", -3: "FW_EUNSTABLE", -4: "FW_EHIP",
+          -5: "FW_ENOMEM", -6: "FW_ENONFINITE", -7: "FW_EUNSUPPORTED"}
+
+# exported symbol -> (restype, argtypes)
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_L = ctypes.c_int64
+_D = ctypes.c_double
+SIGNATURES = {
+    "fw_last_error": (ctypes.c_char_p, []),
+    "fw_abi_version": (_I, []),
+    "fw_create_grid": (_I, [ctypes.POINTER(_P), _I, _I, _P, _D, _D, _I, _I, _P]),
+    "fw_destroy": (_I, [_P]),
+    "fw_workspace_bytes": (_L, [_P]),
+    "fw_bind_workspace": (_I, [_P, _P, _L]),
+    "fw_set_media": (_I, [_P, _P, _P, _I, _P, _P, _P, _D, ctypes.c_uint64]),
+    "fw_set_relaxation_table": (_I, [_P, _I, _P, _P, _P]),
+    "fw_set_sources": (_I, [_P, _L, _P, _P, _P, _I, _P, _I]),
+    "fw_set_receivers": (_I, [_P, _L, _P, _P, _I]),
+    "fw_step": (_I, [_P, _I, _P]),
+    "fw_read_receivers": (_I, [_P, _P, _L, _I, _P]),
+    "fw_reset_state": (_I, [_P, _P]),
+    "fw_get_step": (_I, [_P, ctypes.POINTER(_L)]),
+    "fw_state_bytes": (_L, [_P]),
+    "fw_save_state": (_I, [_P, _P, _P]),
+    "fw_load_state": (_I, [_P, _P, _P]),
+    "fw_set_option": (_I, [_P, _I, _L]),
+    "fw_time_kernels": (_I, [_P, _I, _P, _P]),
+}
+
+
+class FWError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (_NAMES.get(code, "?"), code, msg))
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libfw25.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def check(rc):
+    if rc != FW_OK:
+        raise FWError(rc, lib.fw_last_error().decode(errors="replace"))
+    return rc

@@ -1,0 +1,26 @@
+"""Fill the relaxation-table cache (data/relax_tables.json) for the named
+workloads by running the FP64 calibration (relax.fit_class) on every class
+that is not cached yet.  Usage: python -m paper_2606_11103_amd.relax_cache"""
+import sys
+import time
+
+from . import relax
+
+
+def main():
+    sys.path.insert(0, __file__.rsplit("/paper_2606_11103_amd/", 1)[0])
+    from workloads import configs
+    jobs = [
+        ("2d_homogeneous", configs.homogeneous_2d(64, 10), 2),
+        ("2d_two_layer", configs.two_layer_2d(64, 10, n_rec=2), 4),
+        ("3d_heterogeneous", configs.heterogeneous_3d(shape=(64, 64, 64), steps=10, n_elem=4), 4),
+    ]
+    for name, case, N in jobs:
+        t = time.time()
+        _, _, _, fits = relax.tables_for(dict(c=case.c, alpha0=case.alpha0, y=case.y), N)
+        print("%-18s N=%d classes=%d  %.1f s  model NRMSE %s" % (
+            name, N, len(fits), time.time() - t, ["%.4f" % f["nrmse"] for f in fits]), flush=True)
+
+
+if __name__ == "__main__":
+    main()

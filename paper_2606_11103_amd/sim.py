@@ -1,0 +1,142 @@
+"""Python view of one fw_sim object: torch supplies the device workspace and
+the stream, the HIP library does the work (include/fw25.h)."""
+import ctypes
+
+import numpy as np
+
+from . import native
+from .native import check, lib
+
+
+def _ptr(arr):
+    return ctypes.c_void_p(arr.ctypes.data)
+
+
+def beta_from_b_over_a(b_over_a):
+    """Nonlinearity coefficient of a fluid with parameter B/A: 1 + B/(2A)."""
+    return 1.0 + np.asarray(b_over_a, dtype=np.float64) / 2.0
+
+
+class Simulation:
+    """Grid of one or more domains advancing together.
+
+    shapes: [(nx, ny, nz), ...] with unused trailing dims 1.
+    """
+
+    def __init__(self, ndim, shapes, dx, dt, n_mech, pml_cells=0, pml_params=None, device=None):
+        import torch
+        self.torch = torch
+        self.ndim = int(ndim)
+        self.shapes = [tuple(int(v) for v in s) for s in shapes]
+        self.n_domains = len(self.shapes)
+        self.dx, self.dt, self.n_mech = float(dx), float(dt), int(n_mech)
+        shp = np.ascontiguousarray(np.array(self.shapes, dtype=np.int64).reshape(-1, 3))
+        self._h = ctypes.c_void_p()
+        pp = None
+        if pml_params is not None:
+            self._pml_params = np.ascontiguousarray(np.asarray(pml_params, dtype=np.float64))
+            pp = _ptr(self._pml_params)
+        check(lib.fw_create_grid(ctypes.byref(self._h), self.ndim, self.n_domains, _ptr(shp), self.dx, self.dt,
+                                 self.n_mech, int(pml_cells), pp))
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        nbytes = lib.fw_workspace_bytes(self._h)
+        self.workspace = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        check(lib.fw_bind_workspace(self._h, ctypes.c_void_p(base + off), int(nbytes)))
+        self.n_rec = 0
+        self.n_t_max = 0
+
+    # --------------------------------------------------------------- api --
+    def _stream(self, stream=None):
+        s = self.torch.cuda.current_stream(self.device) if stream is None else stream
+        return ctypes.c_void_p(s.cuda_stream)
+
+    def set_media(self, class_maps, class_base, c, rho, beta, c_noise_amp=0.0, noise_seed=0):
+        cls = np.ascontiguousarray(np.concatenate([np.asarray(m, dtype=np.uint8).reshape(-1) for m in class_maps]))
+        base = np.ascontiguousarray(np.asarray(class_base, dtype=np.int32))
+        c = np.ascontiguousarray(np.asarray(c, dtype=np.float64))
+        rho = np.ascontiguousarray(np.asarray(rho, dtype=np.float64))
+        beta = np.ascontiguousarray(np.asarray(beta, dtype=np.float64))
+        check(lib.fw_set_media(self._h, _ptr(cls), _ptr(base), int(c.size), _ptr(c), _ptr(rho), _ptr(beta),
+                               float(c_noise_amp), ctypes.c_uint64(int(noise_seed))))
+
+    def set_relaxation_table(self, kappa, d, alpha):
+        kappa = np.ascontiguousarray(np.asarray(kappa, dtype=np.float64))
+        d = np.ascontiguousarray(np.asarray(d, dtype=np.float64))
+        alpha = np.ascontiguousarray(np.asarray(alpha, dtype=np.float64))
+        check(lib.fw_set_relaxation_table(self._h, int(kappa.shape[0]), _ptr(kappa), _ptr(d), _ptr(alpha)))
+
+    def set_sources(self, domain, cell, wave_idx, waves):
+        domain = np.ascontiguousarray(np.asarray(domain, dtype=np.int32).reshape(-1))
+        cell = np.ascontiguousarray(np.asarray(cell, dtype=np.int64).reshape(-1))
+        wave_idx = np.ascontiguousarray(np.asarray(wave_idx, dtype=np.int32).reshape(-1))
+        waves = np.ascontiguousarray(np.asarray(waves, dtype=np.float32))
+        if waves.ndim == 1:
+            waves = waves[None, :]
+        check(lib.fw_set_sources(self._h, int(cell.size), _ptr(domain), _ptr(cell), _ptr(wave_idx),
+                                 int(waves.shape[0]), _ptr(waves), int(waves.shape[1])))
+
+    def set_receivers(self, domain, cell, n_t_max):
+        domain = np.ascontiguousarray(np.asarray(domain, dtype=np.int32).reshape(-1))
+        cell = np.ascontiguousarray(np.asarray(cell, dtype=np.int64).reshape(-1))
+        check(lib.fw_set_receivers(self._h, int(cell.size), _ptr(domain), _ptr(cell), int(n_t_max)))
+        self.n_rec = int(cell.size)
+        self.n_t_max = int(n_t_max)
+
+    def step(self, n_steps, stream=None):
+        check(lib.fw_step(self._h, int(n_steps), self._stream(stream)))
+
+    def read_receivers(self, stream=None):
+        out = np.zeros((self.n_t_max, self.n_rec), dtype=np.float32)
+        if out.size:
+            check(lib.fw_read_receivers(self._h, _ptr(out), int(out.size), 0, self._stream(stream)))
+        return out
+
+    def read_receivers_device(self, stream=None):
+        out = self.torch.zeros((self.n_t_max, self.n_rec), dtype=self.torch.float32, device=self.device)
+        if out.numel():
+            check(lib.fw_read_receivers(self._h, ctypes.c_void_p(out.data_ptr()), int(out.numel()), 1,
+                                        self._stream(stream)))
+        return out
+
+    def reset(self, stream=None):
+        check(lib.fw_reset_state(self._h, self._stream(stream)))
+
+    def get_step(self):
+        v = ctypes.c_int64()
+        check(lib.fw_get_step(self._h, ctypes.byref(v)))
+        return v.value
+
+    def state_bytes(self):
+        return int(lib.fw_state_bytes(self._h))
+
+    def save_state(self, buf=None, stream=None):
+        if buf is None:
+            buf = self.torch.empty(self.state_bytes(), dtype=self.torch.uint8, device=self.device)
+        check(lib.fw_save_state(self._h, ctypes.c_void_p(buf.data_ptr()), self._stream(stream)))
+        return buf
+
+    def load_state(self, buf, stream=None):
+        check(lib.fw_load_state(self._h, ctypes.c_void_p(buf.data_ptr()), self._stream(stream)))
+
+    def time_kernels(self, n_steps, stream=None):
+        """Advance n_steps with per-kernel HIP events; returns the average
+        milliseconds of (velocity, pressure, sources+receivers)."""
+        out = np.zeros(3, dtype=np.float64)
+        check(lib.fw_time_kernels(self._h, int(n_steps), self._stream(stream), _ptr(out)))
+        return out
+
+    def set_option(self, key, value):
+        check(lib.fw_set_option(self._h, int(key), int(value)))
+
+    def close(self):
+        if self._h:
+            lib.fw_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

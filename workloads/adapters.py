@@ -1,0 +1,53 @@
+"""Hand a Case to the product library or to the oracle.
+
+Pure argument passing: each side converts B/A to its nonlinearity coefficient
+with its own code.  Imports are lazy so that neither side is loaded unless
+asked for; this module is used by the tests, the smoke check and the
+benchmark (whose oracle leg is the CPU baseline).
+"""
+import numpy as np
+
+
+def to_simulation(case, **kw):
+    """Build and configure a product Simulation (HIP library) for the case."""
+    from paper_2606_11103_amd.sim import Simulation, beta_from_b_over_a
+    sim = Simulation(case.ndim, case.shapes, case.dx, case.dt, case.nmech, case.pml_cells,
+                     pml_params=case.pml_params, **kw)
+    beta = beta_from_b_over_a(case.b_over_a) if case.nonlinear else np.zeros(case.n_classes)
+    sim.set_media(case.class_maps, case.class_base, case.c, case.rho, beta, case.noise_amp, case.noise_seed)
+    sim.set_relaxation_table(case.kappa, case.d, case.alpha)
+    if len(case.src_cell):
+        sim.set_sources(case.src_domain, case.src_cell, case.src_wave, case.waves)
+    if len(case.rec_cell):
+        sim.set_receivers(case.rec_domain, case.rec_cell, case.n_steps)
+    return sim
+
+
+def to_oracle(case, domain=0, **kw):
+    """Build the FP64 oracle for one domain of the case."""
+    from oracle.solver import OracleSim, beta_from_b_over_a
+    b = case.class_base[domain]
+    nloc = int(case.class_maps[domain].max()) + 1
+    sl = slice(b, b + nloc)
+    beta = beta_from_b_over_a(case.b_over_a[sl]) if case.nonlinear else np.zeros(nloc)
+    pp = case.pml_params or (1e-4, 1e6, 0.0)
+    cref = pp[2] if pp[2] > 0 else float(np.max(case.c))
+    return OracleSim(case.ndim, case.shapes[domain], case.dx, case.dt, case.nmech, case.class_maps[domain],
+                     case.c[sl], case.rho[sl], beta, case.kappa[sl], case.d[sl], case.alpha[sl],
+                     pml_cells=case.pml_cells, pml_R0=pp[0], pml_f_alpha=pp[1], pml_c_ref=cref,
+                     noise_amp=case.noise_amp, noise_seed=case.noise_seed, **kw)
+
+
+def oracle_traces(case, n_steps=None, energy=False):
+    """Run the oracle on every domain; returns traces [n_steps][n_rec] in the
+    order of case.rec_cell (FP64)."""
+    n = case.n_steps if n_steps is None else n_steps
+    out = np.zeros((n, len(case.rec_cell)))
+    for d in range(len(case.shapes)):
+        sim = to_oracle(case, d)
+        sm = case.src_domain == d
+        rm = np.nonzero(case.rec_domain == d)[0]
+        waves = case.waves.astype(np.float64)[case.src_wave[sm]]
+        rec, _ = sim.run(n, case.src_cell[sm], waves, case.rec_cell[rm])
+        out[:, rm] = rec
+    return out

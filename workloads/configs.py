@@ -1,0 +1,204 @@
+"""Seeded synthetic cases: plain arrays consumed by both the product and the
+oracle.  No arithmetic of the method lives here (see the package docstring).
+
+A Case holds the grid, the tissue classes (c, rho, alpha0, y, B/A), the class
+maps, sources and receivers.  The relaxation table (kappa, d, alpha per class)
+is filled in by the caller: from the calibration (bench) or drawn at random
+(parity tests, where any admissible table will do).
+"""
+import dataclasses
+import math
+from typing import List, Optional
+
+import numpy as np
+
+from . import (draw_tissue_classes, gaussian_derivative, layered_labels, linear_index,
+               smoothed_label_field, tone_burst)
+
+
+@dataclasses.dataclass
+class Case:
+    name: str
+    ndim: int
+    shapes: List[tuple]                 # (nx, ny, nz) per domain
+    dx: float
+    dt: float
+    nmech: int
+    pml_cells: int
+    class_maps: List[np.ndarray]        # uint8 (nz, ny, nx) per domain, local indices
+    class_base: List[int]
+    c: np.ndarray
+    rho: np.ndarray
+    alpha0: np.ndarray
+    y: np.ndarray
+    b_over_a: np.ndarray
+    nonlinear: bool
+    src_domain: np.ndarray
+    src_cell: np.ndarray
+    src_wave: np.ndarray
+    waves: np.ndarray                   # float32 [n_wave][n_t]
+    rec_domain: np.ndarray
+    rec_cell: np.ndarray
+    n_steps: int
+    noise_amp: float = 0.0
+    noise_seed: int = 0
+    pml_params: Optional[tuple] = None  # (R0, f_alpha, c_ref)
+    kappa: Optional[np.ndarray] = None  # [C][2]
+    d: Optional[np.ndarray] = None      # [C][2][N]
+    alpha: Optional[np.ndarray] = None  # [C][2][N]
+
+    @property
+    def n_classes(self):
+        return len(self.c)
+
+    def cells(self):
+        return sum(int(np.prod(s)) for s in self.shapes)
+
+
+def random_relaxation_table(seed, n_classes, nmech):
+    """Admissible relaxation parameters like those the calibration returns:
+    kappa in [0.98, 1], alpha log-uniform in [10^6.5, 10^10] and a relaxation
+    strength d / (d + kappa alpha) log-uniform in [1e-4, 3e-2] (the range
+    fitted tissue classes span), all inside the bounds of Table 2."""
+    rng = np.random.default_rng(seed)
+    kappa = rng.uniform(0.98, 1.0, size=(n_classes, 2))
+    alpha = 10.0 ** rng.uniform(6.5, 10.0, size=(n_classes, 2, nmech))
+    strength = 10.0 ** rng.uniform(-4.0, math.log10(3e-2), size=(n_classes, 2, nmech))
+    d = strength * kappa[:, :, None] * alpha / (1.0 - strength)
+    return kappa, d, alpha
+
+
+def with_table(case, kappa, d, alpha):
+    case.kappa = np.asarray(kappa, dtype=np.float64).reshape(case.n_classes, 2)
+    case.d = np.asarray(d, dtype=np.float64).reshape(case.n_classes, 2, case.nmech)
+    case.alpha = np.asarray(alpha, dtype=np.float64).reshape(case.n_classes, 2, case.nmech)
+    return case
+
+
+# ------------------------------------------------------------ named cases --
+def homogeneous_2d(n=256, steps=600):
+    """2D homogeneous: 256 x 256 cells, dx = 0.05 mm, c = 1540, rho = 1000,
+    alpha0 = 0.5, y = 1.1, N = 2, linear, 20-cell CPML, CFL 0.4, 600 steps;
+    point source (3 MHz, 3-cycle Gaussian-windowed) at the centre, receivers
+    1 mm and 4 mm from it (3 mm apart)."""
+    dx, c = 5e-5, 1540.0
+    dt = 0.4 * dx / c
+    shp = (n, n, 1)
+    ctr = n // 2
+    return Case(
+        name="2d_homogeneous_%d" % n, ndim=2, shapes=[shp], dx=dx, dt=dt, nmech=2, pml_cells=20,
+        class_maps=[np.zeros((1, n, n), np.uint8)], class_base=[0],
+        c=np.array([c]), rho=np.array([1000.0]), alpha0=np.array([0.5]), y=np.array([1.1]),
+        b_over_a=np.array([0.0]), nonlinear=False,
+        src_domain=np.zeros(1, np.int32), src_cell=np.array([linear_index(shp, ctr, ctr)]),
+        src_wave=np.zeros(1, np.int32), waves=tone_burst(steps, dt, 3e6, 3)[None, :],
+        rec_domain=np.zeros(2, np.int32),
+        rec_cell=np.array([linear_index(shp, ctr + 20, ctr), linear_index(shp, ctr + 80, ctr)]),
+        n_steps=steps)
+
+
+def two_layer_2d(n=2048, steps=4000, n_rec=128):
+    """2D two-layer: 2048 x 2048 cells, dx = 0.03 mm; interface at the middle
+    row; top c = 1580, rho = 1090, alpha0 = 0.9, y = 1.1, B/A = 6; bottom
+    c = 1450, rho = 950, alpha0 = 0.4, y = 1.4, B/A = 9; N = 4; 24-cell CPML;
+    CFL 0.4 on 1580 m/s; plane-wave line source (5 MHz, 4 cycles, 0.8 MPa)
+    along row 28; receivers on the centre column every 15 rows from row 64."""
+    dx = 3e-5
+    dt = 0.4 * dx / 1580.0
+    shp = (n, n, 1)
+    lab = layered_labels((1, n, n), [n // 2], axis=1)
+    P = 24
+    xs = np.arange(P, n - P)
+    rows = 64 + 15 * np.arange(n_rec)
+    rows = rows[rows < n - P]
+    return Case(
+        name="2d_two_layer_%d" % n, ndim=2, shapes=[shp], dx=dx, dt=dt, nmech=4, pml_cells=P,
+        class_maps=[lab], class_base=[0],
+        c=np.array([1580.0, 1450.0]), rho=np.array([1090.0, 950.0]), alpha0=np.array([0.9, 0.4]),
+        y=np.array([1.1, 1.4]), b_over_a=np.array([6.0, 9.0]), nonlinear=True,
+        src_domain=np.zeros(xs.size, np.int32), src_cell=linear_index(shp, xs, 28),
+        src_wave=np.zeros(xs.size, np.int32), waves=tone_burst(steps, dt, 5e6, 4, amplitude=0.8e6)[None, :],
+        rec_domain=np.zeros(rows.size, np.int32), rec_cell=linear_index(shp, n // 2, rows),
+        n_steps=steps)
+
+
+def heterogeneous_3d(shape=(960, 960, 720), steps=2000, seed=3, noise_seed=33, n_elem=64):
+    """3D heterogeneous: 960 x 960 x 720 cells (z slowest), dx = 0.1 mm,
+    24-cell CPML, 8 tissue classes (seed 3) from a smoothed random label field,
+    +-1 % per-voxel speed perturbation (SplitMix64 seed 33), N = 4, CFL 0.4 on
+    1650 * 1.01 m/s, 2000 steps.  Source: 64-element linear array along x at
+    z = 28 (pitch 3 cells, elements 2 x 100 cells) focused at 40 mm depth
+    (delays for 1540 m/s), 2.5 MHz, 3 cycles, 0.5 MPa.  Receivers: the 64
+    element centres and 64 points on the axis at z = 60 + 10 k (those inside
+    the grid)."""
+    nx, ny, nz = shape
+    dx = 1e-4
+    dt = 0.4 * dx / (1650.0 * 1.01)
+    P = 24
+    cls = draw_tissue_classes(8, seed)
+    lab = smoothed_label_field((nz, ny, nx), 8, seed, coarse=4, sigma=5.0)
+    zs = min(28, nz // 4)
+    cx, cy = nx // 2, ny // 2
+    pitch = 3
+    elem_y = min(100, max(2, ny - 2 * P - 2))
+    n_elem = max(1, min(n_elem, (nx - 2 * P - 2) // pitch))
+    x_e = cx - (n_elem * pitch) // 2 + pitch * np.arange(n_elem)
+    zf = zs + 400
+    dist = np.hypot((x_e + 0.5 - cx) * dx, (zf - zs) * dx)
+    delay = (dist.max() - dist) / 1540.0
+    waves = np.stack([tone_burst(steps, dt, 2.5e6, 3, amplitude=0.5e6, delay=t) for t in delay])
+    sx, sy, sw = [], [], []
+    for e in range(n_elem):
+        for ddx in range(2):
+            for yy in range(cy - elem_y // 2, cy - elem_y // 2 + elem_y):
+                sx.append(x_e[e] + ddx)
+                sy.append(yy)
+                sw.append(e)
+    src_cell = linear_index(shape, np.array(sx), np.array(sy), zs)
+    rz = 60 + 10 * np.arange(64)
+    rz = rz[rz < nz - P]
+    rec_cell = np.concatenate([linear_index(shape, x_e, cy, zs), linear_index(shape, cx, cy, rz)])
+    return Case(
+        name="3d_heterogeneous_%dx%dx%d" % shape, ndim=3, shapes=[tuple(shape)], dx=dx, dt=dt, nmech=4,
+        pml_cells=P, class_maps=[lab], class_base=[0],
+        c=cls["c"], rho=cls["rho"], alpha0=cls["alpha0"], y=cls["y"], b_over_a=cls["b_over_a"], nonlinear=True,
+        src_domain=np.zeros(len(sx), np.int32), src_cell=src_cell, src_wave=np.array(sw, np.int32), waves=waves,
+        rec_domain=np.zeros(rec_cell.size, np.int32), rec_cell=rec_cell, n_steps=steps,
+        noise_amp=0.01, noise_seed=noise_seed)
+
+
+def random_small(ndim, shapes, nmech, n_classes, seed, steps, pml=6, nonlinear=True, noise=0.01,
+                 amplitude=2e5, n_rec=12):
+    """Small heterogeneous case for parity tests: random label fields, random
+    tissue classes, one point source per domain and scattered receivers."""
+    rng = np.random.default_rng(seed)
+    cls = draw_tissue_classes(n_classes * len(shapes), seed)
+    dx = 1e-4
+    cmax = cls["c"].max() * (1 + noise)
+    dt = (0.4 if ndim < 3 else 0.35) * dx / cmax
+    maps, base = [], []
+    sd, sc, rd, rc = [], [], [], []
+    for d, shp in enumerate(shapes):
+        nx, ny, nz = shp
+        lab = rng.integers(0, n_classes, size=(nz, ny, nx)).astype(np.uint8)
+        if ndim >= 2:
+            lab = smoothed_label_field((nz, ny, nx), n_classes, seed + 17 * d, coarse=2, sigma=1.5)
+        maps.append(lab)
+        base.append(d * n_classes)
+        lo = [pml + 1 if s > 1 else 0 for s in shp]
+        hi = [s - pml - 1 if s > 1 else 1 for s in shp]
+        p = [int(rng.integers(lo[a], hi[a])) for a in range(3)]
+        sd.append(d)
+        sc.append(int(linear_index(shp, p[0], p[1], p[2])))
+        for _ in range(n_rec):
+            q = [int(rng.integers(0, shp[a])) for a in range(3)]
+            rd.append(d)
+            rc.append(int(linear_index(shp, q[0], q[1], q[2])))
+    waves = tone_burst(steps, dt, 2e6, 2, amplitude=amplitude)[None, :]
+    return Case(
+        name="random_%dd_%d" % (ndim, seed), ndim=ndim, shapes=[tuple(s) for s in shapes], dx=dx, dt=dt,
+        nmech=nmech, pml_cells=pml, class_maps=maps, class_base=base,
+        c=cls["c"], rho=cls["rho"], alpha0=cls["alpha0"], y=cls["y"], b_over_a=cls["b_over_a"],
+        nonlinear=nonlinear, src_domain=np.array(sd, np.int32), src_cell=np.array(sc, np.int64),
+        src_wave=np.zeros(len(sd), np.int32), waves=waves, rec_domain=np.array(rd, np.int32),
+        rec_cell=np.array(rc, np.int64), n_steps=steps, noise_amp=noise, noise_seed=seed * 7 + 1)
