@@ -89,6 +89,25 @@ def cpu_baseline(seconds_target=20.0):
                        "noise, nonlinear), %d steps in %.1f s" % (steps, el))
 
 
+def copy_probe(torch, gib, reps):
+    """Plain copy of a known size: reads gib GiB and writes gib GiB per launch.
+    Used to scale the FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    n = int(gib * (1 << 30) // 4)
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    print(json.dumps({"copy_probe_bytes_each_way": n * 4, "avg_ms": ms,
+                      "copy_GBps_read_plus_write": 2 * n * 4 / (ms / 1e3) / 1e9}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +117,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--march-chunk", type=int, default=0)
+    ap.add_argument("--rows-per-thread", type=int, default=0)
+    ap.add_argument("--copy-probe", type=float, default=0.0,
+                    help="only run a plain device-to-device copy of this many GiB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (got --gpus %d)" % args.gpus,
@@ -105,7 +127,10 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2606_11103_amd.native import FW_OPT_MARCH_CHUNK, FW_OPT_TILE_ROWS
+    if args.copy_probe > 0:
+        copy_probe(torch, args.copy_probe, max(args.steps, 1))
+        return
+    from paper_2606_11103_amd.native import FW_OPT_MARCH_CHUNK, FW_OPT_ROWS_PER_THREAD, FW_OPT_TILE_ROWS
     from workloads.adapters import to_simulation
 
     torch.cuda.set_device(0)
@@ -114,8 +139,12 @@ def main():
     fill_tables(case)
     print("# workload %s built in %.1f s" % (case.name, time.time() - t0), file=sys.stderr, flush=True)
     sim = to_simulation(case)
+    if args.rows_per_thread == 1:
+        sim.set_option(FW_OPT_ROWS_PER_THREAD, 1)
     if args.tile_rows:
         sim.set_option(FW_OPT_TILE_ROWS, args.tile_rows)
+    if args.rows_per_thread == 2:
+        sim.set_option(FW_OPT_ROWS_PER_THREAD, 2)
     if args.march_chunk:
         sim.set_option(FW_OPT_MARCH_CHUNK, args.march_chunk)
     print("# simulation ready (%.1f GB workspace)" % (sim.workspace.numel() / 1e9), file=sys.stderr, flush=True)

@@ -191,9 +191,12 @@ int fw_time_kernels(fw_sim *sim, int n_steps, void *hip_stream, double *avg_ms);
  * Tuning and behaviour options (host only):
  *   FW_OPT_GRAPH_STEPS   steps per captured HIP graph (0 = eager only); default 16.
  *   FW_OPT_MARCH_CHUNK   cells of the marching axis per tile (>= 8); default auto.
- *   FW_OPT_TILE_ROWS     3D tile rows along y per block: 8 or 16; default 16.
+ *   FW_OPT_TILE_ROWS     3D tile rows along y per block: 4, 8 or 16; default 16.
+ *   FW_OPT_ROWS_PER_THREAD  3D rows each thread owns: 1 or 2 (not with 4-row
+ *                        tiles); default 1.
+ * Options change the work decomposition only, never the results.
  */
-enum { FW_OPT_GRAPH_STEPS = 1, FW_OPT_MARCH_CHUNK = 2, FW_OPT_TILE_ROWS = 3 };
+enum { FW_OPT_GRAPH_STEPS = 1, FW_OPT_MARCH_CHUNK = 2, FW_OPT_TILE_ROWS = 3, FW_OPT_ROWS_PER_THREAD = 4 };
 int fw_set_option(fw_sim *sim, int key, int64_t value);
 
 #ifdef __cplusplus

@@ -12,6 +12,10 @@ HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # packed FP32 instructions are kept out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no implicit FMA contraction: the kernels spell out their fused
+    # multiply-adds, so the rounding sequence is the same in every template
+    # instantiation (results are bitwise independent of the tiling)
+    "-ffp-contract=off",
     "-Wall", "-Wno-unused-result",
 ]
 

@@ -54,6 +54,7 @@ struct StepArgs {
     int32_t n_tiles;
     int32_t tiles_per_xcd;     // ceil(n_tiles / 8): block b runs tile (b % 8) * tiles_per_xcd + b / 8
     int32_t pml;               // CPML width P
+    int32_t class_cap;         // entries per LDS class table (>= classes of any domain)
     float fd[4];               // staggered coefficients c_m / dx
     float dt;
     float noise_amp;
@@ -74,8 +75,8 @@ struct SrcRecArgs {
 };
 
 // Launchers (kernels.hip).  Return hipSuccess or the launch error.
-hipError_t launch_velocity(int ndim, int nmech, int tile_rows, const StepArgs &a, hipStream_t s);
-hipError_t launch_pressure(int ndim, int nmech, int tile_rows, const StepArgs &a, hipStream_t s);
+hipError_t launch_velocity(int ndim, int nmech, int tile_rows, int rows_per_thread, const StepArgs &a, hipStream_t s);
+hipError_t launch_pressure(int ndim, int nmech, int tile_rows, int rows_per_thread, const StepArgs &a, hipStream_t s);
 hipError_t launch_src_rec(const SrcRecArgs &a, hipStream_t s);
 // Tile footprint of a launch configuration: cells per tile along x and y.
 void tile_shape(int ndim, int tile_rows, int *tx, int *ty);

@@ -6,14 +6,18 @@
 // Work decomposition.  A tile is a 64-cell run along x (times a band of rows
 // along y in 3D) that marches along the slowest axis (z in 3D, y in 2D).
 // Each thread owns one column per row of the band and keeps the pressure
-// (velocity-kernel) or the marching-axis velocity (pressure-kernel) of eight
+// (velocity kernel) or the marching-axis velocity (pressure kernel) of eight
 // consecutive planes in registers, so the marching-axis stencil costs no
-// extra memory traffic.  The x and y stencils read the current plane from LDS.
-// Every output cell is written by exactly one thread with a fixed operation
-// order, so results do not depend on the tiling, the batching or the launch
-// path.  Blocks are mapped to tiles so that each of the eight XCDs receives a
-// contiguous range of the tile list (workgroups are dispatched round-robin
-// over the XCDs), keeping neighbouring tiles and their halos in one L2.
+// extra memory traffic.  The x and y stencils read the current plane from a
+// double-buffered LDS tile.  The plane after the current one is prefetched
+// into registers (own state, queue entry and halo) while the current plane is
+// computed, so each plane costs one barrier and HBM latency overlaps the
+// arithmetic.  Every output cell is written by exactly one thread with a
+// fixed operation order, so results do not depend on the tiling, the batching
+// or the launch path.  Blocks are mapped to tiles so that each of the eight
+// XCDs receives a contiguous range of the tile list (workgroups are
+// dispatched round-robin over the XCDs), keeping neighbouring tiles and their
+// halos in one L2.
 #include "fw_internal.h"
 
 namespace fw {
@@ -62,37 +66,74 @@ __device__ __forceinline__ int tile_index(const StepArgs &A)
     return (b & 7) * A.tiles_per_xcd + (b >> 3);
 }
 
-// One face of the velocity update along one axis: memory variables of the
-// gradient operator, the CPML variable inside the slab, then v.
-template <int N>
-__device__ __forceinline__ void velocity_face(const StepArgs &A, int axis, float D, int L, int L1,
-                                              const float *s_ik, const float *s_rho,
-                                              const float (*s_a)[kMaxLocalClasses],
-                                              const float (*s_b)[kMaxLocalClasses],
-                                              float *__restrict__ v, float *__restrict__ psi, int64_t g,
-                                              int64_t c, int64_t n, int32_t pml_off)
+__device__ __forceinline__ bool in_slab(int64_t c, int64_t n, int P) { return P > 0 && (c < P || c >= n - P); }
+
+// sum_m c_m d_m with an explicit fused-multiply-add chain.  The library is
+// compiled without implicit contraction, so every instantiation (tile shape,
+// batching) performs the same rounding sequence.
+__device__ __forceinline__ float stencil4(const float (&c)[4], float d1, float d2, float d3, float d4)
 {
-    const float m = 2.0f * A.dt / (s_rho[L] + s_rho[L1]);
-    float s = s_ik[L] * D;
-    float ps[N];
-    load_vec<N>(psi + g * N, ps);
-#pragma unroll
-    for (int nu = 0; nu < N; ++nu) {
-        ps[nu] = s_b[nu][L] * ps[nu] + s_a[nu][L] * D;
-        s += ps[nu];
-    }
-    store_vec<N>(psi + g * N, ps);
-    if (A.pml > 0 && (c < A.pml || c >= n - A.pml)) {
-        const float aF = A.pml_tab[pml_off + c];
-        const float bF = A.pml_tab[pml_off + n + c];
-        float *pp = A.f.pP1[axis];
-        const float q = bF * pp[g] + aF * D;
-        pp[g] = q;
-        s += q;
-    }
-    v[g] -= m * s;
+    return fmaf(c[3], d4, fmaf(c[2], d3, fmaf(c[1], d2, c[0] * d1)));
 }
 
+// Per-domain base pointers (uniform over the block, kept in scalar registers)
+// so that every per-thread index below is a 32-bit domain-local offset.
+struct DomPtrs {
+    float *p, *v[3], *psi1[3], *psi2, *pP1[3], *pP2[3];
+    const uint8_t *cls;
+};
+
+template <int N>
+__device__ __forceinline__ DomPtrs dom_ptrs(const StepArgs &A, const DomainDesc &D)
+{
+    const int64_t o = D.cell_off;
+    DomPtrs d;
+    d.p = A.f.p + o;
+    d.v[0] = A.f.vx + o;
+    d.v[1] = A.f.vy + o;
+    d.v[2] = A.f.vz + o;
+    d.psi1[0] = A.f.psi1x + o * N;
+    d.psi1[1] = A.f.psi1y + o * N;
+    d.psi1[2] = A.f.psi1z + o * N;
+    d.psi2 = A.f.psi2 + o * N;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        d.pP1[a] = A.f.pP1[a] + o;
+        d.pP2[a] = A.f.pP2[a] + o;
+    }
+    d.cls = A.f.cls + o;
+    return d;
+}
+
+// Geometry of a tile as seen by one thread (32-bit domain-local indices).
+template <int NDIM, int BX, int BY, int RY>
+struct TileGeom {
+    int nx, ny, nmarch, sm, x;
+    int yr[RY], col[RY];
+    bool ok[RY];
+    __device__ __forceinline__ void init(const Tile &T, const DomainDesc &D)
+    {
+        nx = (int)D.n[0];
+        ny = (int)D.n[1];
+        nmarch = NDIM == 3 ? (int)D.n[2] : (NDIM == 2 ? (int)D.n[1] : 1);
+        sm = NDIM == 3 ? nx * ny : nx;
+        x = T.x0 + (int)threadIdx.x;
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            yr[r] = NDIM == 3 ? T.y0 + (int)threadIdx.y * RY + r : 0;
+            ok[r] = x < nx && (NDIM < 3 || yr[r] < ny);
+            col[r] = (NDIM == 3 ? yr[r] * nx : 0) + x;
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Velocity update: for each axis a and face i+1/2,
+//   D = sum_m c_m (p[i+m] - p[i+1-m]) / dx,
+//   psi1_nu <- b1_nu psi1_nu + a1_nu D           (class of the owner cell i),
+//   psiP    <- bF psiP + aF D                    (inside the CPML slab of a),
+//   v_a     -= 2 dt / (rho_i + rho_{i+1}) (D / kappa_1 + sum_nu psi1_nu + psiP).
+// ---------------------------------------------------------------------------
 template <int NDIM, int N, int BX, int BY, int RY>
 __global__ __launch_bounds__(BX *BY) void k_velocity(const StepArgs A)
 {
@@ -102,166 +143,262 @@ __global__ __launch_bounds__(BX *BY) void k_velocity(const StepArgs A)
     constexpr int NT = BX * BY;
     constexpr int CX = BX + 1;
     constexpr int NHALO = NDIM == 3 ? 8 * LX + 8 * TY : 8;
-    constexpr int NCHALO = NDIM == 3 ? TY + BX : 1;
+    constexpr int HS = (NHALO + NT - 1) / NT;
+    constexpr int NCH = NDIM == 3 ? TY + BX : 1;
+    constexpr int CS = (NCH + NT - 1) / NT;
+    constexpr bool MARCH = NDIM >= 2;
     static_assert(NDIM == 3 || (BY == 1 && RY == 1), "bands of rows are 3D only");
-    __shared__ float sp[LY * LX];
-    __shared__ uint8_t scl[(TY + 1) * CX];
-    __shared__ float s_ik[kMaxLocalClasses], s_rho[kMaxLocalClasses];
-    __shared__ float s_a[N][kMaxLocalClasses], s_b[N][kMaxLocalClasses];
+    __shared__ float sp[2][LY * LX];
+    __shared__ uint8_t scl[2][(TY + 1) * CX];
+    // per-class coefficients of this domain, A.class_cap entries per table
+    extern __shared__ float s_dyn[];
+    const int C = A.class_cap;
+    float *s_ik = s_dyn, *s_rho = s_dyn + C, *s_a = s_dyn + 2 * C, *s_b = s_dyn + (2 + N) * C;
 
     const int ti = tile_index(A);
     if (ti >= A.n_tiles) return;
     const Tile T = A.tiles[ti];
     const DomainDesc D = A.doms[T.dom];
     const int tid = threadIdx.y * BX + threadIdx.x;
+    const int tx = threadIdx.x;
     for (int c = tid; c < D.n_classes; c += NT) {
         const ClassCoef &cc = A.classes[D.class_base + c];
         s_ik[c] = cc.ik1;
         s_rho[c] = cc.rho;
 #pragma unroll
         for (int nu = 0; nu < N; ++nu) {
-            s_a[nu][c] = cc.a1[nu];
-            s_b[nu][c] = cc.b1[nu];
+            s_a[nu * C + c] = cc.a1[nu];
+            s_b[nu * C + c] = cc.b1[nu];
         }
     }
+    TileGeom<NDIM, BX, BY, RY> G;
+    G.init(T, D);
+    const DomPtrs M = dom_ptrs<N>(A, D);
+    const int P = A.pml;
 
-    const int64_t nx = D.n[0], ny = D.n[1];
-    const int64_t nmarch = NDIM == 3 ? D.n[2] : (NDIM == 2 ? D.n[1] : 1);
-    const int64_t sm = NDIM == 3 ? nx * ny : nx;
-    const int64_t base = D.cell_off;
-    const float *__restrict__ p = A.f.p;
-    const uint8_t *__restrict__ cls = A.f.cls;
-    float *__restrict__ vmarch = NDIM == 3 ? A.f.vz : A.f.vy;
-    float *__restrict__ psimarch = NDIM == 3 ? A.f.psi1z : A.f.psi1y;
-    const int tx = threadIdx.x;
-    const int64_t x = T.x0 + tx;
-
-    int64_t yr[RY], col[RY];
-    bool ok[RY];
+    // halo slots of this thread: plane-relative offset (-1: outside the
+    // domain, value 0) and LDS index (-1: no slot)
+    int hoff[HS], hli[HS];
 #pragma unroll
-    for (int r = 0; r < RY; ++r) {
-        yr[r] = NDIM == 3 ? T.y0 + threadIdx.y * RY + r : 0;
-        ok[r] = x < nx && (NDIM < 3 || yr[r] < ny);
-        col[r] = base + (NDIM == 3 ? yr[r] * nx : 0) + x;
+    for (int s = 0; s < HS; ++s) {
+        const int h = tid + s * NT;
+        int hy = 0, hx = 0;
+        if constexpr (NDIM == 3) {
+            if (h < 8 * LX) {
+                const int rr = h / LX;
+                hy = rr < 4 ? rr : TY + rr;
+                hx = h - rr * LX;
+            } else {
+                const int hh = h - 8 * LX;
+                hy = 4 + (hh >> 3);
+                const int k = hh & 7;
+                hx = k < 4 ? k : BX + k;
+            }
+        } else {
+            hx = h < 4 ? h : BX + h;
+        }
+        const int gx = T.x0 - 4 + hx;
+        const int gy = NDIM == 3 ? T.y0 - 4 + hy : 0;
+        const bool inside = gx >= 0 && gx < G.nx && (NDIM < 3 || (gy >= 0 && gy < G.ny));
+        hli[s] = h < NHALO ? hy * LX + hx : -1;
+        hoff[s] = (h < NHALO && inside) ? (NDIM == 3 ? gy * G.nx : 0) + gx : -1;
+    }
+    int coff[CS], cli[CS];
+#pragma unroll
+    for (int s = 0; s < CS; ++s) {
+        const int h = tid + s * NT;
+        int gx, gy, li;
+        if (h < TY) {
+            gx = T.x0 + BX;
+            gy = NDIM == 3 ? T.y0 + h : 0;
+            li = h * CX + BX;
+        } else {
+            gx = T.x0 + (h - TY);
+            gy = T.y0 + TY;
+            li = TY * CX + (h - TY);
+        }
+        const bool inside = gx < G.nx && (NDIM < 3 || gy < G.ny);
+        cli[s] = h < NCH ? li : -1;
+        coff[s] = (h < NCH && inside) ? (NDIM == 3 ? gy * G.nx : 0) + gx : -1;
     }
 
+    // registers: pressure queue, class queue, current-plane private state
     float q[RY][8];
     int cq[RY][2];
-    const int z0 = T.z0;
+    float vc[RY][NDIM], pc[RY][NDIM][N], ppc[RY][NDIM];
+    const int z0 = T.z0, z1 = T.z1;
+
+    auto coord = [&](int r, int z, int a) { return a == 0 ? G.x : (a == 1 && NDIM == 3 ? G.yr[r] : z); };
+    auto extent = [&](int a) { return a == 0 ? G.nx : (a == 1 && NDIM == 3 ? G.ny : G.nmarch); };
+    auto load_private = [&](int z, float (&v)[RY][NDIM], float (&ps)[RY][NDIM][N], float (&pp)[RY][NDIM]) {
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            if (!G.ok[r]) continue;
+            const int g = G.col[r] + z * G.sm;
+#pragma unroll
+            for (int a = 0; a < NDIM; ++a) {
+                v[r][a] = M.v[a][g];
+                load_vec<N>(M.psi1[a] + (size_t)g * N, ps[r][a]);
+                pp[r][a] = in_slab(coord(r, z, a), extent(a), P) ? M.pP1[a][g] : 0.0f;
+            }
+        }
+    };
+
+    // ---- prologue: queue, plane z0 state, LDS buffer 0 ----
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
 #pragma unroll
         for (int j = 0; j < 8; ++j) q[r][j] = 0.0f;
-        cq[r][0] = 0;
-        cq[r][1] = 0;
-        if constexpr (NDIM >= 2) {
+        cq[r][0] = cq[r][1] = 0;
+        if (!G.ok[r]) continue;
+        if constexpr (MARCH) {
 #pragma unroll
-            for (int j = 0; j < 7; ++j) {
-                const int64_t zz = z0 - 3 + j;
-                q[r][j] = (ok[r] && zz >= 0 && zz < nmarch) ? p[col[r] + zz * sm] : 0.0f;
+            for (int j = 0; j < 8; ++j) {
+                const int zz = z0 - 3 + j;
+                q[r][j] = (zz >= 0 && zz < G.nmarch) ? M.p[G.col[r] + zz * G.sm] : 0.0f;
             }
-            cq[r][0] = ok[r] ? cls[col[r] + z0 * sm] : 0;
+            cq[r][0] = M.cls[G.col[r] + z0 * G.sm];
+            cq[r][1] = (z0 + 1 < G.nmarch) ? M.cls[G.col[r] + (z0 + 1) * G.sm] : cq[r][0];
+        } else {
+            q[r][3] = M.p[G.col[r]];
+            cq[r][0] = M.cls[G.col[r]];
         }
     }
-
-    for (int z = z0; z < T.z1; ++z) {
+    load_private(z0, vc, pc, ppc);
+    {
+        const int zoff = z0 * G.sm;
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
-            if constexpr (NDIM >= 2) {
-                const int64_t zz = z + 4;
-                q[r][7] = (ok[r] && zz < nmarch) ? p[col[r] + zz * sm] : 0.0f;
-                cq[r][1] = (ok[r] && z + 1 < nmarch) ? cls[col[r] + (z + 1) * sm] : cq[r][0];
-            } else {
-                q[r][3] = ok[r] ? p[col[r]] : 0.0f;
-                cq[r][0] = ok[r] ? cls[col[r]] : 0;
-            }
             const int row = NDIM == 3 ? threadIdx.y * RY + r : 0;
-            sp[(NDIM == 3 ? row + 4 : 0) * LX + 4 + tx] = q[r][3];
-            scl[row * CX + tx] = (uint8_t)cq[r][0];
+            sp[0][(NDIM == 3 ? row + 4 : 0) * LX + 4 + tx] = q[r][3];
+            scl[0][row * CX + tx] = (uint8_t)cq[r][0];
         }
-        const int64_t zoff = base + (int64_t)z * sm;
-        for (int h = tid; h < NHALO; h += NT) {
-            int hy, hx;
-            if constexpr (NDIM == 3) {
-                if (h < 8 * LX) {
-                    const int rr = h / LX;
-                    hy = rr < 4 ? rr : TY + rr;
-                    hx = h - rr * LX;
-                } else {
-                    const int hh = h - 8 * LX;
-                    hy = 4 + (hh >> 3);
-                    const int k = hh & 7;
-                    hx = k < 4 ? k : BX + k;
-                }
-            } else {
-                hy = 0;
-                hx = h < 4 ? h : BX + h;
-            }
-            const int64_t gx = T.x0 - 4 + hx;
-            const int64_t gy = NDIM == 3 ? T.y0 - 4 + hy : 0;
-            float val = 0.0f;
-            if (gx >= 0 && gx < nx && gy >= 0 && (NDIM < 3 || gy < ny))
-                val = p[zoff + (NDIM == 3 ? gy * nx : 0) + gx];
-            sp[hy * LX + hx] = val;
-        }
-        for (int h = tid; h < NCHALO; h += NT) {
-            int64_t gx, gy;
-            int li;
-            if (h < TY) {               // column right of the band
-                gx = T.x0 + BX;
-                gy = NDIM == 3 ? T.y0 + h : 0;
-                li = h * CX + BX;
-            } else {                    // row above the band (3D)
-                gx = T.x0 + (h - TY);
-                gy = T.y0 + TY;
-                li = TY * CX + (h - TY);
-            }
-            uint8_t val = 0;
-            if (gx < nx && (NDIM < 3 || gy < ny)) val = cls[zoff + (NDIM == 3 ? gy * nx : 0) + gx];
-            scl[li] = val;
-        }
-        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < HS; ++s)
+            if (hli[s] >= 0) sp[0][hli[s]] = hoff[s] >= 0 ? M.p[zoff + hoff[s]] : 0.0f;
+#pragma unroll
+        for (int s = 0; s < CS; ++s)
+            if (cli[s] >= 0) scl[0][cli[s]] = coff[s] >= 0 ? M.cls[zoff + coff[s]] : (uint8_t)0;
+    }
+    __syncthreads();
 
+    for (int z = z0; z < z1; ++z) {
+        const int b = (z - z0) & 1;
+        const bool more = z + 1 < z1;
+        // ---- prefetch plane z + 1 ----
+        float vn[RY][NDIM], pn[RY][NDIM][N], ppn[RY][NDIM];
+        float qn[RY];
+        int cqn[RY];
+        float hp[HS];
+        uint8_t hc[CS];
+        if (more) {
+            load_private(z + 1, vn, pn, ppn);
+            const int zoff = (z + 1) * G.sm;
+#pragma unroll
+            for (int r = 0; r < RY; ++r) {
+                qn[r] = 0.0f;
+                cqn[r] = cq[r][1];
+                if (!G.ok[r]) continue;
+                if (z + 5 < G.nmarch) qn[r] = M.p[G.col[r] + (z + 5) * G.sm];
+                if (z + 2 < G.nmarch) cqn[r] = M.cls[G.col[r] + (z + 2) * G.sm];
+            }
+#pragma unroll
+            for (int s = 0; s < HS; ++s) hp[s] = hoff[s] >= 0 ? M.p[zoff + hoff[s]] : 0.0f;
+#pragma unroll
+            for (int s = 0; s < CS; ++s) hc[s] = coff[s] >= 0 ? M.cls[zoff + coff[s]] : (uint8_t)0;
+        }
+
+        // ---- compute plane z ----
+        const float *spb = sp[b];
+        const uint8_t *sclb = scl[b];
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
-            if (!ok[r]) continue;
+            if (!G.ok[r]) continue;
             const int row = NDIM == 3 ? threadIdx.y * RY + r : 0;
-            const int ly = NDIM == 3 ? row + 4 : 0;
-            const float *sr = sp + ly * LX + 4 + tx;
-            const int64_t g = col[r] + (int64_t)z * sm;
+            const float *sr = spb + (NDIM == 3 ? row + 4 : 0) * LX + 4 + tx;
+            const int g = G.col[r] + z * G.sm;
             const int L = cq[r][0];
-            {
-                const float Dx = A.fd[0] * (sr[1] - sr[0]) + A.fd[1] * (sr[2] - sr[-1]) +
-                                 A.fd[2] * (sr[3] - sr[-2]) + A.fd[3] * (sr[4] - sr[-3]);
-                const int L1 = (x + 1 < nx) ? scl[row * CX + tx + 1] : L;
-                velocity_face<N>(A, 0, Dx, L, L1, s_ik, s_rho, s_a, s_b, A.f.vx, A.f.psi1x, g, x, nx,
-                                 D.pml_off[0]);
-            }
+            float Dv[3];
+            int Ln[3];
+            Dv[0] = stencil4(A.fd, sr[1] - sr[0], sr[2] - sr[-1], sr[3] - sr[-2], sr[4] - sr[-3]);
+            Ln[0] = (G.x + 1 < G.nx) ? sclb[row * CX + tx + 1] : L;
             if constexpr (NDIM == 3) {
-                const float Dy = A.fd[0] * (sr[LX] - sr[0]) + A.fd[1] * (sr[2 * LX] - sr[-LX]) +
-                                 A.fd[2] * (sr[3 * LX] - sr[-2 * LX]) + A.fd[3] * (sr[4 * LX] - sr[-3 * LX]);
-                const int L1 = (yr[r] + 1 < ny) ? scl[(row + 1) * CX + tx] : L;
-                velocity_face<N>(A, 1, Dy, L, L1, s_ik, s_rho, s_a, s_b, A.f.vy, A.f.psi1y, g, yr[r], ny,
-                                 D.pml_off[1]);
+                Dv[1] = stencil4(A.fd, sr[LX] - sr[0], sr[2 * LX] - sr[-LX], sr[3 * LX] - sr[-2 * LX],
+                                 sr[4 * LX] - sr[-3 * LX]);
+                Ln[1] = (G.yr[r] + 1 < G.ny) ? sclb[(row + 1) * CX + tx] : L;
             }
-            if constexpr (NDIM >= 2) {
-                const float Dz = A.fd[0] * (q[r][4] - q[r][3]) + A.fd[1] * (q[r][5] - q[r][2]) +
-                                 A.fd[2] * (q[r][6] - q[r][1]) + A.fd[3] * (q[r][7] - q[r][0]);
-                const int L1 = (z + 1 < nmarch) ? cq[r][1] : L;
-                velocity_face<N>(A, NDIM - 1, Dz, L, L1, s_ik, s_rho, s_a, s_b, vmarch, psimarch, g, z, nmarch,
-                                 D.pml_off[NDIM - 1]);
+            if constexpr (MARCH) {
+                Dv[NDIM - 1] = stencil4(A.fd, q[r][4] - q[r][3], q[r][5] - q[r][2], q[r][6] - q[r][1],
+                                        q[r][7] - q[r][0]);
+                Ln[NDIM - 1] = (z + 1 < G.nmarch) ? cq[r][1] : L;
+            }
+#pragma unroll
+            for (int a = 0; a < NDIM; ++a) {
+                const float Da = Dv[a];
+                const float m = 2.0f * A.dt / (s_rho[L] + s_rho[Ln[a]]);
+                float s = s_ik[L] * Da;
+#pragma unroll
+                for (int nu = 0; nu < N; ++nu) {
+                    pc[r][a][nu] = fmaf(s_a[nu * C + L], Da, s_b[nu * C + L] * pc[r][a][nu]);
+                    s += pc[r][a][nu];
+                }
+                store_vec<N>(M.psi1[a] + (size_t)g * N, pc[r][a]);
+                const int c = coord(r, z, a), n = extent(a);
+                if (in_slab(c, n, P)) {
+                    const int32_t off = D.pml_off[a];
+                    const float aF = A.pml_tab[off + c];
+                    const float bF = A.pml_tab[off + n + c];
+                    const float qv = fmaf(aF, Da, bF * ppc[r][a]);
+                    M.pP1[a][g] = qv;
+                    s += qv;
+                }
+                M.v[a][g] = fmaf(-m, s, vc[r][a]);
             }
         }
-        __syncthreads();
+
+        // ---- rotate and stage plane z + 1 ----
+        if (more) {
+            const int nb = b ^ 1;
 #pragma unroll
-        for (int r = 0; r < RY; ++r) {
+            for (int r = 0; r < RY; ++r) {
+                if constexpr (MARCH) {
 #pragma unroll
-            for (int j = 0; j < 7; ++j) q[r][j] = q[r][j + 1];
-            cq[r][0] = cq[r][1];
+                    for (int j = 0; j < 7; ++j) q[r][j] = q[r][j + 1];
+                    q[r][7] = qn[r];
+                    cq[r][0] = cq[r][1];
+                    cq[r][1] = cqn[r];
+                }
+#pragma unroll
+                for (int a = 0; a < NDIM; ++a) {
+                    vc[r][a] = vn[r][a];
+                    ppc[r][a] = ppn[r][a];
+#pragma unroll
+                    for (int nu = 0; nu < N; ++nu) pc[r][a][nu] = pn[r][a][nu];
+                }
+                const int row = NDIM == 3 ? threadIdx.y * RY + r : 0;
+                sp[nb][(NDIM == 3 ? row + 4 : 0) * LX + 4 + tx] = q[r][3];
+                scl[nb][row * CX + tx] = (uint8_t)cq[r][0];
+            }
+#pragma unroll
+            for (int s = 0; s < HS; ++s)
+                if (hli[s] >= 0) sp[nb][hli[s]] = hp[s];
+#pragma unroll
+            for (int s = 0; s < CS; ++s)
+                if (cli[s] >= 0) scl[nb][cli[s]] = hc[s];
+            __syncthreads();
         }
     }
 }
 
+// ---------------------------------------------------------------------------
+// Pressure update: for each cell,
+//   D_a = sum_m c_m (v_a[i+m-1] - v_a[i-m]) / dx,  S = sum_a D_a,
+//   psi2_nu <- b2_nu psi2_nu + a2_nu S     (summed over axes: the tissue
+//              coefficients are the same for every axis, so the sum of the
+//              per-axis recursions is itself one recursion),
+//   psiP_a  <- bC psiP_a + aC D_a          (inside the CPML slab of a),
+//   p       -= dt (K (1 + eps)^2 + 2 beta p) (S / kappa_2 + sum_nu psi2_nu + sum_a psiP_a).
+// ---------------------------------------------------------------------------
 template <int NDIM, int N, int BX, int BY, int RY>
 __global__ __launch_bounds__(BX *BY) void k_pressure(const StepArgs A)
 {
@@ -269,17 +406,22 @@ __global__ __launch_bounds__(BX *BY) void k_pressure(const StepArgs A)
     constexpr int LX = BX + 8;
     constexpr int LY = NDIM == 3 ? TY + 8 : 1;
     constexpr int NT = BX * BY;
+    constexpr int NHALO = 8 * TY + (NDIM == 3 ? 8 * BX : 0);
+    constexpr int HS = (NHALO + NT - 1) / NT;
+    constexpr bool MARCH = NDIM >= 2;
     static_assert(NDIM == 3 || (BY == 1 && RY == 1), "bands of rows are 3D only");
-    __shared__ float svx[TY * LX];
-    __shared__ float svy[NDIM == 3 ? LY * BX : 1];
-    __shared__ float s_ik[kMaxLocalClasses], s_K[kMaxLocalClasses], s_tb[kMaxLocalClasses];
-    __shared__ float s_a[N][kMaxLocalClasses], s_b[N][kMaxLocalClasses];
+    __shared__ float svx[2][TY * LX];
+    __shared__ float svy[2][NDIM == 3 ? LY * BX : 1];
+    extern __shared__ float s_dyn[];
+    const int C = A.class_cap;
+    float *s_ik = s_dyn, *s_K = s_dyn + C, *s_tb = s_dyn + 2 * C, *s_a = s_dyn + 3 * C, *s_b = s_dyn + (3 + N) * C;
 
     const int ti = tile_index(A);
     if (ti >= A.n_tiles) return;
     const Tile T = A.tiles[ti];
     const DomainDesc D = A.doms[T.dom];
     const int tid = threadIdx.y * BX + threadIdx.x;
+    const int tx = threadIdx.x;
     for (int c = tid; c < D.n_classes; c += NT) {
         const ClassCoef &cc = A.classes[D.class_base + c];
         s_ik[c] = cc.ik2;
@@ -287,142 +429,200 @@ __global__ __launch_bounds__(BX *BY) void k_pressure(const StepArgs A)
         s_tb[c] = cc.twobeta;
 #pragma unroll
         for (int nu = 0; nu < N; ++nu) {
-            s_a[nu][c] = cc.a2[nu];
-            s_b[nu][c] = cc.b2[nu];
+            s_a[nu * C + c] = cc.a2[nu];
+            s_b[nu * C + c] = cc.b2[nu];
         }
     }
+    TileGeom<NDIM, BX, BY, RY> G;
+    G.init(T, D);
+    const DomPtrs M = dom_ptrs<N>(A, D);
+    const float *__restrict__ vm = NDIM == 3 ? M.v[2] : M.v[1];
+    const int P = A.pml;
 
-    const int64_t nx = D.n[0], ny = D.n[1];
-    const int64_t nmarch = NDIM == 3 ? D.n[2] : (NDIM == 2 ? D.n[1] : 1);
-    const int64_t sm = NDIM == 3 ? nx * ny : nx;
-    const int64_t base = D.cell_off;
-    const float *__restrict__ vx = A.f.vx;
-    const float *__restrict__ vy = A.f.vy;
-    const float *__restrict__ vmarch = NDIM == 3 ? A.f.vz : A.f.vy;
-    float *__restrict__ p = A.f.p;
-    const int tx = threadIdx.x;
-    const int64_t x = T.x0 + tx;
-
-    int64_t yr[RY], col[RY];
-    bool ok[RY];
+    // halo slots: x-halo of vx (8 per row), then y-halo of vy (8 rows, 3D).
+    // hli >= 0 indexes svx, hli <= -2 indexes svy as -(hli + 2), -1: no slot.
+    int hoff[HS], hli[HS];
 #pragma unroll
-    for (int r = 0; r < RY; ++r) {
-        yr[r] = NDIM == 3 ? T.y0 + threadIdx.y * RY + r : 0;
-        ok[r] = x < nx && (NDIM < 3 || yr[r] < ny);
-        col[r] = base + (NDIM == 3 ? yr[r] * nx : 0) + x;
+    for (int s = 0; s < HS; ++s) {
+        const int h = tid + s * NT;
+        int gx, gy, li;
+        if (h < 8 * TY) {
+            const int row = h >> 3, k = h & 7;
+            const int hx = k < 4 ? k : BX + k;
+            gx = T.x0 - 4 + hx;
+            gy = NDIM == 3 ? T.y0 + row : 0;
+            li = row * LX + hx;
+        } else {
+            const int hh = h - 8 * TY;
+            const int rr = hh / BX;
+            const int hy = rr < 4 ? rr : TY + rr;
+            const int hx = hh - rr * BX;
+            gx = T.x0 + hx;
+            gy = T.y0 - 4 + hy;
+            li = -(hy * BX + hx) - 2;
+        }
+        const bool inside = gx >= 0 && gx < G.nx && (NDIM < 3 || (gy >= 0 && gy < G.ny));
+        hli[s] = h < NHALO ? li : -1;
+        hoff[s] = (h < NHALO && inside) ? (NDIM == 3 ? gy * G.nx : 0) + gx : -1;
     }
+    auto halo_load = [&](int s, int zoff) -> float {
+        if (hoff[s] < 0) return 0.0f;
+        return hli[s] >= 0 ? M.v[0][zoff + hoff[s]] : M.v[1][zoff + hoff[s]];
+    };
+    auto halo_store = [&](int buf, int s, float val) {
+        if (hli[s] >= 0) {
+            svx[buf][hli[s]] = val;
+        } else if (hli[s] <= -2) {
+            if constexpr (NDIM == 3) svy[buf][-(hli[s] + 2)] = val;
+        }
+    };
+
     float vq[RY][8];
-    const int z0 = T.z0;
+    float pc[RY], psc[RY][N], ppc[RY][NDIM], vxo[RY], vyo[RY];
+    int cc_[RY];
+    const int z0 = T.z0, z1 = T.z1;
+
+    auto coord = [&](int r, int z, int a) { return a == 0 ? G.x : (a == 1 && NDIM == 3 ? G.yr[r] : z); };
+    auto extent = [&](int a) { return a == 0 ? G.nx : (a == 1 && NDIM == 3 ? G.ny : G.nmarch); };
+    auto load_private = [&](int z, float (&pv)[RY], float (&ps)[RY][N], float (&pp)[RY][NDIM], int (&cl)[RY],
+                            float (&ox)[RY], float (&oy)[RY]) {
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            pv[r] = 0.0f;
+            cl[r] = 0;
+            ox[r] = 0.0f;
+            oy[r] = 0.0f;
+            if (!G.ok[r]) continue;
+            const int g = G.col[r] + z * G.sm;
+            pv[r] = M.p[g];
+            cl[r] = M.cls[g];
+            load_vec<N>(M.psi2 + (size_t)g * N, ps[r]);
+            ox[r] = M.v[0][g];
+            if constexpr (NDIM == 3) oy[r] = M.v[1][g];
+#pragma unroll
+            for (int a = 0; a < NDIM; ++a) pp[r][a] = in_slab(coord(r, z, a), extent(a), P) ? M.pP2[a][g] : 0.0f;
+        }
+    };
+    auto stage = [&](int buf, const float (&ox)[RY], const float (&oy)[RY]) {
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            const int row = NDIM == 3 ? threadIdx.y * RY + r : 0;
+            svx[buf][row * LX + 4 + tx] = ox[r];
+            if constexpr (NDIM == 3) svy[buf][(row + 4) * BX + tx] = oy[r];
+        }
+    };
+
+    // ---- prologue ----
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
 #pragma unroll
         for (int j = 0; j < 8; ++j) vq[r][j] = 0.0f;
-        if constexpr (NDIM >= 2) {
+        if constexpr (MARCH) {
+            if (!G.ok[r]) continue;
 #pragma unroll
-            for (int j = 0; j < 7; ++j) {
-                const int64_t zz = z0 - 4 + j;
-                vq[r][j] = (ok[r] && zz >= 0 && zz < nmarch) ? vmarch[col[r] + zz * sm] : 0.0f;
+            for (int j = 0; j < 8; ++j) {
+                const int zz = z0 - 4 + j;
+                vq[r][j] = (zz >= 0 && zz < G.nmarch) ? vm[G.col[r] + zz * G.sm] : 0.0f;
             }
         }
     }
+    load_private(z0, pc, psc, ppc, cc_, vxo, vyo);
+    stage(0, vxo, vyo);
+#pragma unroll
+    for (int s = 0; s < HS; ++s) halo_store(0, s, halo_load(s, z0 * G.sm));
+    __syncthreads();
 
-    for (int z = z0; z < T.z1; ++z) {
-        if constexpr (NDIM >= 2) {
+    for (int z = z0; z < z1; ++z) {
+        const int b = (z - z0) & 1;
+        const bool more = z + 1 < z1;
+        float pn[RY], psn[RY][N], ppn[RY][NDIM], vxn[RY], vyn[RY], vqn[RY];
+        int cn[RY];
+        float hval[HS];
+        if (more) {
+            load_private(z + 1, pn, psn, ppn, cn, vxn, vyn);
 #pragma unroll
             for (int r = 0; r < RY; ++r) {
-                const int64_t zz = z + 3;
-                vq[r][7] = (ok[r] && zz < nmarch) ? vmarch[col[r] + zz * sm] : 0.0f;
+                vqn[r] = 0.0f;
+                if (MARCH && G.ok[r] && z + 4 < G.nmarch) vqn[r] = vm[G.col[r] + (z + 4) * G.sm];
             }
+#pragma unroll
+            for (int s = 0; s < HS; ++s) hval[s] = halo_load(s, (z + 1) * G.sm);
         }
-        const int64_t zoff = base + (int64_t)z * sm;
-        for (int h = tid; h < TY * LX; h += NT) {
-            const int row = h / LX;
-            const int hx = h - row * LX;
-            const int64_t gx = T.x0 - 4 + hx;
-            const int64_t gy = NDIM == 3 ? T.y0 + row : 0;
-            float val = 0.0f;
-            if (gx >= 0 && gx < nx && (NDIM < 3 || gy < ny)) val = vx[zoff + (NDIM == 3 ? gy * nx : 0) + gx];
-            svx[h] = val;
-        }
-        if constexpr (NDIM == 3) {
-            for (int h = tid; h < LY * BX; h += NT) {
-                const int row = h / BX;
-                const int hx = h - row * BX;
-                const int64_t gx = T.x0 + hx;
-                const int64_t gy = T.y0 - 4 + row;
-                float val = 0.0f;
-                if (gx < nx && gy >= 0 && gy < ny) val = vy[zoff + gy * nx + gx];
-                svy[h] = val;
-            }
-        }
-        __syncthreads();
 
+        const float *svxb = svx[b];
+        const float *svyb = svy[b];
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
-            if (!ok[r]) continue;
+            if (!G.ok[r]) continue;
             const int row = NDIM == 3 ? threadIdx.y * RY + r : 0;
-            const int64_t g = col[r] + (int64_t)z * sm;
-            const float *sx = svx + row * LX + 4 + tx;
-            const float Dx = A.fd[0] * (sx[0] - sx[-1]) + A.fd[1] * (sx[1] - sx[-2]) +
-                             A.fd[2] * (sx[2] - sx[-3]) + A.fd[3] * (sx[3] - sx[-4]);
-            float Dy = 0.0f, Dz = 0.0f;
+            const int g = G.col[r] + z * G.sm;
+            const float *sx = svxb + row * LX + 4 + tx;
+            float Dd[3];
+            Dd[0] = stencil4(A.fd, sx[0] - sx[-1], sx[1] - sx[-2], sx[2] - sx[-3], sx[3] - sx[-4]);
             if constexpr (NDIM == 3) {
-                const float *sy = svy + (row + 4) * BX + tx;
-                Dy = A.fd[0] * (sy[0] - sy[-BX]) + A.fd[1] * (sy[BX] - sy[-2 * BX]) +
-                     A.fd[2] * (sy[2 * BX] - sy[-3 * BX]) + A.fd[3] * (sy[3 * BX] - sy[-4 * BX]);
+                const float *sy = svyb + (row + 4) * BX + tx;
+                Dd[1] = stencil4(A.fd, sy[0] - sy[-BX], sy[BX] - sy[-2 * BX], sy[2 * BX] - sy[-3 * BX],
+                                 sy[3 * BX] - sy[-4 * BX]);
             }
-            if constexpr (NDIM >= 2) {
-                Dz = A.fd[0] * (vq[r][4] - vq[r][3]) + A.fd[1] * (vq[r][5] - vq[r][2]) +
-                     A.fd[2] * (vq[r][6] - vq[r][1]) + A.fd[3] * (vq[r][7] - vq[r][0]);
+            if constexpr (MARCH) {
+                Dd[NDIM - 1] = stencil4(A.fd, vq[r][4] - vq[r][3], vq[r][5] - vq[r][2], vq[r][6] - vq[r][1],
+                                        vq[r][7] - vq[r][0]);
             }
-            const float S = Dx + Dy + Dz;
-            const int L = A.f.cls[g];
-            float ps[N];
-            load_vec<N>(A.f.psi2 + g * N, ps);
+            float S = Dd[0];
+#pragma unroll
+            for (int a = 1; a < NDIM; ++a) S += Dd[a];
+            const int L = cc_[r];
             float Tt = s_ik[L] * S;
 #pragma unroll
             for (int nu = 0; nu < N; ++nu) {
-                ps[nu] = s_b[nu][L] * ps[nu] + s_a[nu][L] * S;
-                Tt += ps[nu];
+                psc[r][nu] = fmaf(s_a[nu * C + L], S, s_b[nu * C + L] * psc[r][nu]);
+                Tt += psc[r][nu];
             }
-            store_vec<N>(A.f.psi2 + g * N, ps);
-            if (A.pml > 0) {
-                const int64_t cc[3] = {x, NDIM == 3 ? yr[r] : z, z};
-                const int64_t nn[3] = {nx, NDIM == 3 ? ny : nmarch, nmarch};
-                const float Dd[3] = {Dx, NDIM == 3 ? Dy : Dz, Dz};
+            store_vec<N>(M.psi2 + (size_t)g * N, psc[r]);
 #pragma unroll
-                for (int a = 0; a < NDIM; ++a) {
-                    const int64_t c = cc[a], n = nn[a];
-                    if (c < A.pml || c >= n - A.pml) {
-                        const int32_t off = D.pml_off[a];
-                        const float aC = A.pml_tab[off + 2 * n + c];
-                        const float bC = A.pml_tab[off + 3 * n + c];
-                        float *pp = A.f.pP2[a];
-                        const float qv = bC * pp[g] + aC * Dd[a];
-                        pp[g] = qv;
-                        Tt += qv;
-                    }
+            for (int a = 0; a < NDIM; ++a) {
+                const int c = coord(r, z, a), n = extent(a);
+                if (in_slab(c, n, P)) {
+                    const int32_t off = D.pml_off[a];
+                    const float aC = A.pml_tab[off + 2 * n + c];
+                    const float bC = A.pml_tab[off + 3 * n + c];
+                    const float qv = fmaf(aC, Dd[a], bC * ppc[r][a]);
+                    M.pP2[a][g] = qv;
+                    Tt += qv;
                 }
             }
             float K = s_K[L];
             if (A.noise_amp != 0.0f) {
-                const uint64_t li = (uint64_t)(g - base);
-                const uint64_t hsh = splitmix64(D.noise_seed ^ li);
+                const uint64_t hsh = splitmix64(D.noise_seed ^ (uint64_t)(uint32_t)g);
                 const float u = (float)(hsh >> 40) * 0x1.0p-24f;
-                const float e = A.noise_amp * (2.0f * u - 1.0f);
+                const float e = A.noise_amp * fmaf(2.0f, u, -1.0f);
                 const float f1 = 1.0f + e;
                 K = K * (f1 * f1);
             }
-            const float pn = p[g];
-            p[g] = pn - A.dt * (K + s_tb[L] * pn) * Tt;
+            const float pn0 = pc[r];
+            M.p[g] = fmaf(-(A.dt * fmaf(s_tb[L], pn0, K)), Tt, pn0);
         }
-        __syncthreads();
-        if constexpr (NDIM >= 2) {
+
+        if (more) {
+            const int nb = b ^ 1;
 #pragma unroll
             for (int r = 0; r < RY; ++r) {
+                if constexpr (MARCH) {
 #pragma unroll
-                for (int j = 0; j < 7; ++j) vq[r][j] = vq[r][j + 1];
+                    for (int j = 0; j < 7; ++j) vq[r][j] = vq[r][j + 1];
+                    vq[r][7] = vqn[r];
+                }
+                pc[r] = pn[r];
+                cc_[r] = cn[r];
+#pragma unroll
+                for (int nu = 0; nu < N; ++nu) psc[r][nu] = psn[r][nu];
+#pragma unroll
+                for (int a = 0; a < NDIM; ++a) ppc[r][a] = ppn[r][a];
             }
+            stage(nb, vxn, vyn);
+#pragma unroll
+            for (int s = 0; s < HS; ++s) halo_store(nb, s, hval[s]);
+            __syncthreads();
         }
     }
 }
@@ -451,19 +651,24 @@ hipError_t launch_pair(bool velocity, const StepArgs &a, hipStream_t s)
 {
     const dim3 block(BX, BY);
     const dim3 grid(8 * a.tiles_per_xcd);
+    const size_t lds = (size_t)a.class_cap * (velocity ? 2 + 2 * N : 3 + 2 * N) * sizeof(float);
     if (velocity)
-        k_velocity<NDIM, N, BX, BY, RY><<<grid, block, 0, s>>>(a);
+        k_velocity<NDIM, N, BX, BY, RY><<<grid, block, lds, s>>>(a);
     else
-        k_pressure<NDIM, N, BX, BY, RY><<<grid, block, 0, s>>>(a);
+        k_pressure<NDIM, N, BX, BY, RY><<<grid, block, lds, s>>>(a);
     return hipGetLastError();
 }
 
+// 3D launch shapes: (tile rows along y, rows per thread) -> block (64, rows / rpt)
 template <int NDIM, int N>
-hipError_t launch_nd(bool velocity, int tile_rows, const StepArgs &a, hipStream_t s)
+hipError_t launch_nd(bool velocity, int tile_rows, int rpt, const StepArgs &a, hipStream_t s)
 {
     if constexpr (NDIM == 3) {
-        if (tile_rows == 8) return launch_pair<3, N, 64, 4, 2>(velocity, a, s);
-        return launch_pair<3, N, 64, 4, 4>(velocity, a, s);
+        if (tile_rows == 4) return launch_pair<3, N, 64, 4, 1>(velocity, a, s);
+        if (tile_rows == 8 && rpt == 2) return launch_pair<3, N, 64, 4, 2>(velocity, a, s);
+        if (tile_rows == 8) return launch_pair<3, N, 64, 8, 1>(velocity, a, s);
+        if (rpt == 2) return launch_pair<3, N, 64, 8, 2>(velocity, a, s);
+        return launch_pair<3, N, 64, 16, 1>(velocity, a, s);
     } else if constexpr (NDIM == 2) {
         return launch_pair<2, N, 64, 1, 1>(velocity, a, s);
     } else {
@@ -472,24 +677,24 @@ hipError_t launch_nd(bool velocity, int tile_rows, const StepArgs &a, hipStream_
 }
 
 template <int NDIM>
-hipError_t launch_n(bool velocity, int nmech, int tile_rows, const StepArgs &a, hipStream_t s)
+hipError_t launch_n(bool velocity, int nmech, int tile_rows, int rpt, const StepArgs &a, hipStream_t s)
 {
     switch (nmech) {
-    case 1: return launch_nd<NDIM, 1>(velocity, tile_rows, a, s);
-    case 2: return launch_nd<NDIM, 2>(velocity, tile_rows, a, s);
-    case 3: return launch_nd<NDIM, 3>(velocity, tile_rows, a, s);
-    case 4: return launch_nd<NDIM, 4>(velocity, tile_rows, a, s);
+    case 1: return launch_nd<NDIM, 1>(velocity, tile_rows, rpt, a, s);
+    case 2: return launch_nd<NDIM, 2>(velocity, tile_rows, rpt, a, s);
+    case 3: return launch_nd<NDIM, 3>(velocity, tile_rows, rpt, a, s);
+    case 4: return launch_nd<NDIM, 4>(velocity, tile_rows, rpt, a, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_any(bool velocity, int ndim, int nmech, int tile_rows, const StepArgs &a, hipStream_t s)
+hipError_t launch_any(bool velocity, int ndim, int nmech, int tile_rows, int rpt, const StepArgs &a, hipStream_t s)
 {
     if (a.n_tiles <= 0) return hipSuccess;
     switch (ndim) {
-    case 1: return launch_n<1>(velocity, nmech, tile_rows, a, s);
-    case 2: return launch_n<2>(velocity, nmech, tile_rows, a, s);
-    case 3: return launch_n<3>(velocity, nmech, tile_rows, a, s);
+    case 1: return launch_n<1>(velocity, nmech, tile_rows, rpt, a, s);
+    case 2: return launch_n<2>(velocity, nmech, tile_rows, rpt, a, s);
+    case 3: return launch_n<3>(velocity, nmech, tile_rows, rpt, a, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -500,7 +705,7 @@ void tile_shape(int ndim, int tile_rows, int *tx, int *ty)
 {
     if (ndim == 3) {
         *tx = 64;
-        *ty = tile_rows == 8 ? 8 : 16;
+        *ty = tile_rows;
     } else if (ndim == 2) {
         *tx = 64;
         *ty = 1;
@@ -510,14 +715,14 @@ void tile_shape(int ndim, int tile_rows, int *tx, int *ty)
     }
 }
 
-hipError_t launch_velocity(int ndim, int nmech, int tile_rows, const StepArgs &a, hipStream_t s)
+hipError_t launch_velocity(int ndim, int nmech, int tile_rows, int rpt, const StepArgs &a, hipStream_t s)
 {
-    return launch_any(true, ndim, nmech, tile_rows, a, s);
+    return launch_any(true, ndim, nmech, tile_rows, rpt, a, s);
 }
 
-hipError_t launch_pressure(int ndim, int nmech, int tile_rows, const StepArgs &a, hipStream_t s)
+hipError_t launch_pressure(int ndim, int nmech, int tile_rows, int rpt, const StepArgs &a, hipStream_t s)
 {
-    return launch_any(false, ndim, nmech, tile_rows, a, s);
+    return launch_any(false, ndim, nmech, tile_rows, rpt, a, s);
 }
 
 hipError_t launch_src_rec(const SrcRecArgs &a, hipStream_t s)

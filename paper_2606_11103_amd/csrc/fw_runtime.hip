@@ -96,7 +96,7 @@ struct fw_sim {
     int64_t n_src = 0, n_rec = 0;
     int n_t = 0, n_t_max = 0;
     // options
-    int graph_steps = 16, march_chunk = 0, tile_rows = 16;
+    int graph_steps = 16, march_chunk = 0, tile_rows = 16, rows_per_thread = 1;
     // stepping
     int64_t host_step = 0;
     hipStream_t cap_stream = nullptr;
@@ -213,7 +213,7 @@ int build_tiles(fw_sim *s)
             // aim for a few thousand tiles over all domains, chunks of >= 32 planes
             const int64_t cols = nxtile * nytile;
             chunk = nmarch;
-            while (chunk > 64 && cols * ((nmarch + chunk - 1) / chunk) < 4096) chunk = (chunk + 1) / 2;
+            while (chunk > 16 && cols * ((nmarch + chunk - 1) / chunk) < 4096) chunk = (chunk + 1) / 2;
         }
         chunk = std::max<int64_t>(1, std::min<int64_t>(chunk, nmarch));
         for (int64_t z0 = 0; z0 < nmarch; z0 += chunk)
@@ -248,6 +248,9 @@ fw::StepArgs step_args(const fw_sim *s)
     a.n_tiles = s->n_tiles;
     a.tiles_per_xcd = s->tiles_per_xcd;
     a.pml = s->pml;
+    int cap = 1;
+    for (const auto &d : s->doms) cap = std::max(cap, (int)d.n_classes);
+    a.class_cap = (cap + 3) / 4 * 4;
     for (int m = 0; m < 4; ++m) a.fd[m] = (float)(kFD[m] / s->dx);
     a.dt = (float)s->dt;
     a.noise_amp = (float)s->noise_amp;
@@ -276,8 +279,8 @@ int enqueue_steps(fw_sim *s, int n, hipStream_t st)
     const fw::StepArgs a = step_args(s);
     const fw::SrcRecArgs r = srcrec_args(s);
     for (int i = 0; i < n; ++i) {
-        HIP_OR_FAIL(fw::launch_velocity(s->ndim, s->nmech, s->tile_rows, a, st));
-        HIP_OR_FAIL(fw::launch_pressure(s->ndim, s->nmech, s->tile_rows, a, st));
+        HIP_OR_FAIL(fw::launch_velocity(s->ndim, s->nmech, s->tile_rows, s->rows_per_thread, a, st));
+        HIP_OR_FAIL(fw::launch_pressure(s->ndim, s->nmech, s->tile_rows, s->rows_per_thread, a, st));
         HIP_OR_FAIL(fw::launch_src_rec(r, st));
     }
     return FW_OK;
@@ -721,9 +724,9 @@ int fw_time_kernels(fw_sim *sim, int n_steps, void *hip_stream, double *avg_ms)
     for (int i = 0; i < n_steps && rc == FW_OK; ++i) {
         hipEvent_t *e = &ev[(size_t)i * 4];
         hipError_t err = hipEventRecord(e[0], st);
-        if (err == hipSuccess) err = fw::launch_velocity(sim->ndim, sim->nmech, sim->tile_rows, a, st);
+        if (err == hipSuccess) err = fw::launch_velocity(sim->ndim, sim->nmech, sim->tile_rows, sim->rows_per_thread, a, st);
         if (err == hipSuccess) err = hipEventRecord(e[1], st);
-        if (err == hipSuccess) err = fw::launch_pressure(sim->ndim, sim->nmech, sim->tile_rows, a, st);
+        if (err == hipSuccess) err = fw::launch_pressure(sim->ndim, sim->nmech, sim->tile_rows, sim->rows_per_thread, a, st);
         if (err == hipSuccess) err = hipEventRecord(e[2], st);
         if (err == hipSuccess) err = fw::launch_src_rec(r, st);
         if (err == hipSuccess) err = hipEventRecord(e[3], st);
@@ -764,9 +767,16 @@ int fw_set_option(fw_sim *sim, int key, int64_t value)
         sim->tiles_dirty = true;
         return FW_OK;
     case FW_OPT_TILE_ROWS:
-        if (value != 8 && value != 16) return fail(FW_EINVAL, "tile rows must be 8 or 16");
+        if (value != 4 && value != 8 && value != 16) return fail(FW_EINVAL, "tile rows must be 4, 8 or 16");
+        if (value == 4 && sim->rows_per_thread == 2) return fail(FW_EINVAL, "4-row tiles use one row per thread");
         sim->tile_rows = (int)value;
         sim->tiles_dirty = true;
+        return FW_OK;
+    case FW_OPT_ROWS_PER_THREAD:
+        if (value != 1 && value != 2) return fail(FW_EINVAL, "rows per thread must be 1 or 2");
+        if (value == 2 && sim->tile_rows == 4) return fail(FW_EINVAL, "4-row tiles use one row per thread");
+        sim->rows_per_thread = (int)value;
+        sim->drop_graph();
         return FW_OK;
     default:
         return fail(FW_EINVAL, "unknown option %d", key);

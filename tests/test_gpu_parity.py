@@ -89,12 +89,15 @@ def test_graph_and_eager_paths_are_bitwise_identical():
 
 
 def test_tiling_does_not_change_results():
-    from paper_2606_11103_amd.native import FW_OPT_MARCH_CHUNK, FW_OPT_TILE_ROWS
+    from paper_2606_11103_amd.native import FW_OPT_MARCH_CHUNK, FW_OPT_ROWS_PER_THREAD, FW_OPT_TILE_ROWS
     case = _case("3d_random_N2_ragged")
-    _, a = _run(case, opts={FW_OPT_TILE_ROWS: 16})
-    _, b = _run(case, opts={FW_OPT_TILE_ROWS: 8, FW_OPT_MARCH_CHUNK: 8})
-    _, c = _run(case, opts={FW_OPT_TILE_ROWS: 16, FW_OPT_MARCH_CHUNK: 13})
-    assert np.array_equal(a, b) and np.array_equal(a, c)
+    _, ref = _run(case, opts={FW_OPT_TILE_ROWS: 16})
+    for rows, rpt, chunk in ((4, 1, 0), (8, 1, 8), (8, 2, 13), (16, 2, 0), (16, 1, 9)):
+        opts = {FW_OPT_TILE_ROWS: rows, FW_OPT_ROWS_PER_THREAD: rpt}
+        if chunk:
+            opts[FW_OPT_MARCH_CHUNK] = chunk
+        _, got = _run(case, opts=opts)
+        assert np.array_equal(ref, got), (rows, rpt, chunk)
 
 
 def test_batched_domains_equal_single_runs():
