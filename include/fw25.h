@@ -179,6 +179,35 @@ int fw_save_state(fw_sim *sim, void *d_dst, void *hip_stream);
 int fw_load_state(fw_sim *sim, const void *d_src, void *hip_stream);
 
 /*
+ * Discrete adjoint with checkpointed recomputation (linear media: beta = 0).
+ *
+ * Misfit J is any function of the receiver traces; the caller supplies
+ * d_adj_src[t][r] = dJ/d trace[t][r] (device float [n_steps][n_rec]).  The
+ * adjoint of every forward step (transposed velocity and pressure updates,
+ * memory-variable and CPML recursions included) is applied in reverse order,
+ * accumulating (+=) per cell, in the caller's unpadded cell layout (domains
+ * concatenated, each in its own linear order):
+ *   d_grad_K[x] = dJ/dK(x), K = rho c^2 (1 + eps)^2 the bulk modulus, and
+ *   d_grad_s[x] = dJ/ds(x), s(x) a scale of every relaxation coefficient d of
+ *                 the cell (d -> s d, kappa and alpha fixed).
+ * Then dJ/dc = 2 rho c (1 + eps)^2 dJ/dK and, when d is taken proportional to
+ * alpha0 within a class, dJ/dalpha0 = dJ/ds / alpha0.
+ *
+ * d_work is a caller-owned device buffer of fw_adjoint_workspace_bytes bytes
+ * holding ceil(n_steps / ckpt_every) state checkpoints, ckpt_every + 1
+ * recomputed states, the adjoint state and scratch.
+ * fw_forward_checkpointed resets the state, runs n_steps (recording the
+ * traces) and stores the checkpoints; fw_adjoint then sweeps the segments
+ * last to first, recomputing each segment's states from its checkpoint.
+ * Returns FW_EUNSUPPORTED if any class has beta != 0.
+ */
+int64_t fw_adjoint_workspace_bytes(const fw_sim *sim, int n_steps, int ckpt_every);
+int fw_forward_checkpointed(fw_sim *sim, int n_steps, int ckpt_every, void *d_work, int64_t bytes,
+                            void *hip_stream);
+int fw_adjoint(fw_sim *sim, int n_steps, int ckpt_every, void *d_work, int64_t bytes,
+               const float *d_adj_src, float *d_grad_K, float *d_grad_s, void *hip_stream);
+
+/*
  * Advance n_steps steps like fw_step, but launch every kernel eagerly with a
  * HIP event before and after it on hip_stream, wait for completion, and
  * return the average duration in milliseconds of each kernel kind:

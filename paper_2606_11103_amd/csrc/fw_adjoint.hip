@@ -1,0 +1,315 @@
+// gfx950 kernels of the discrete adjoint of one linear step (beta = 0).
+//
+// The forward step maps u^n = (p, v, psi1, psi2, psiP1, psiP2) to u^{n+1}.
+// Its transpose is applied in reverse order -- pressure sub-step, then
+// velocity sub-step -- using div_a = -grad_a^T of the staggered operators
+// (summation by parts with zero values beyond the grid).  Besides the adjoint
+// state, one reverse step accumulates per cell
+//   gK += lam_p^{n+1} * dp^{n+1}/dK   = lam_p^{n+1} * (-dt T^n),
+//   gs += sum over the recursions owned by the cell of mu (b_s psi^n + a_s D^n),
+// where s scales every d coefficient of the cell (d -> s d) and a_s, b_s are
+// the derivatives of Eqs. (relaxation_a)/(relaxation_b) with respect to s.
+// Three kernels per reverse step:
+//   adj_pressure : pointwise transpose of the pressure update (needs the
+//                  divergence of the forward v^{n+1/2}); writes lamD2_a.
+//   adj_velocity : lam_v -= grad_a(lamD2_a), transpose of the velocity update
+//                  (needs grad_a of the forward p^n); writes lamD1_a.
+//   adj_gradient : lam_p -= sum_a div_a(lamD1_a).
+// One thread per (x, y) column of a tile, marching the tile's z range with
+// direct global loads (neighbour reads are served by the caches).
+#include "fw_internal.h"
+
+namespace fw {
+
+namespace {
+
+__device__ __forceinline__ uint64_t splitmix64_a(uint64_t x)
+{
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ float st4(const float (&c)[4], float d1, float d2, float d3, float d4)
+{
+    return fmaf(c[3], d4, fmaf(c[2], d3, fmaf(c[1], d2, c[0] * d1)));
+}
+
+struct Geo {
+    int n[3];       // nx, ny, nz
+    int st[3];      // strides of x, y, z
+    int c[3];       // coordinates of the cell
+    int g;          // domain-local linear index
+};
+
+// staggered gradient (cell field -> face i+1/2 of axis a), zero beyond the grid
+__device__ __forceinline__ float grad_a(const float *__restrict__ f, const Geo &G, int a, const float (&fd)[4])
+{
+    const int i = G.c[a], n = G.n[a], s = G.st[a], g = G.g;
+    float d[4];
+#pragma unroll
+    for (int m = 1; m <= 4; ++m) {
+        const float fp = (i + m < n) ? f[g + m * s] : 0.0f;
+        const float fm = (i + 1 - m >= 0) ? f[g + (1 - m) * s] : 0.0f;
+        d[m - 1] = fp - fm;
+    }
+    return st4(fd, d[0], d[1], d[2], d[3]);
+}
+
+// staggered divergence term (face field -> cell i of axis a)
+__device__ __forceinline__ float div_a(const float *__restrict__ f, const Geo &G, int a, const float (&fd)[4])
+{
+    const int i = G.c[a], n = G.n[a], s = G.st[a], g = G.g;
+    float d[4];
+#pragma unroll
+    for (int m = 1; m <= 4; ++m) {
+        const float fp = (i + m - 1 < n) ? f[g + (m - 1) * s] : 0.0f;
+        const float fm = (i - m >= 0) ? f[g - m * s] : 0.0f;
+        d[m - 1] = fp - fm;
+    }
+    return st4(fd, d[0], d[1], d[2], d[3]);
+}
+
+template <int NDIM>
+__device__ __forceinline__ bool setup(const AdjArgs &A, Tile &T, DomainDesc &D)
+{
+    const int b = blockIdx.x;
+    const int ti = (b & 7) * A.s.tiles_per_xcd + (b >> 3);
+    if (ti >= A.s.n_tiles) return false;
+    T = A.s.tiles[ti];
+    D = A.s.doms[T.dom];
+    return true;
+}
+
+template <int NDIM>
+__device__ __forceinline__ bool column(const Tile &T, const DomainDesc &D, Geo &G)
+{
+    G.n[0] = (int)D.n[0];
+    G.n[1] = (int)D.n[1];
+    G.n[2] = (int)D.n[2];
+    G.st[0] = 1;
+    G.st[1] = G.n[0];
+    G.st[2] = G.n[0] * G.n[1];
+    G.c[0] = T.x0 + (int)threadIdx.x;
+    G.c[1] = NDIM == 3 ? T.y0 + (int)threadIdx.y : 0;
+    G.c[2] = 0;
+    return G.c[0] < G.n[0] && G.c[1] < G.n[1];
+}
+
+// march coordinate: z in 3D, y in 2D
+template <int NDIM>
+__device__ __forceinline__ void at_plane(Geo &G, int z)
+{
+    if (NDIM == 3) G.c[2] = z;
+    if (NDIM == 2) G.c[1] = z;
+    G.g = (G.c[2] * G.n[1] + G.c[1]) * G.n[0] + G.c[0];
+}
+
+__device__ __forceinline__ bool slab(int c, int n, int P) { return P > 0 && (c < P || c >= n - P); }
+
+template <int NDIM, int N>
+__global__ void k_adj_pressure(const AdjArgs A)
+{
+    Tile T;
+    DomainDesc D;
+    if (!setup<NDIM>(A, T, D)) return;
+    Geo G;
+    if (!column<NDIM>(T, D, G)) return;
+    const int64_t o = D.cell_off;
+    const float dt = A.s.dt;
+    const int P = A.s.pml;
+    for (int z = T.z0; z < T.z1; ++z) {
+        at_plane<NDIM>(G, z);
+        const int g = G.g;
+        const int64_t gg = o + g;
+        const int L = A.s.f.cls[gg];
+        const ClassCoef &cc = A.s.classes[D.class_base + L];
+        const ClassAdj &ca = A.cadj[D.class_base + L];
+        // forward divergence of v^{n+1/2} (state u^{n+1})
+        float Dd[3] = {0.0f, 0.0f, 0.0f};
+        const float *vn[3] = {A.fnext.vx + o, A.fnext.vy + o, A.fnext.vz + o};
+#pragma unroll
+        for (int a = 0; a < NDIM; ++a) Dd[a] = div_a(vn[a], G, a, A.s.fd);
+        float S = Dd[0];
+#pragma unroll
+        for (int a = 1; a < NDIM; ++a) S += Dd[a];
+        // T^n from the updated memory variables of u^{n+1}
+        float Tt = cc.ik2 * S;
+#pragma unroll
+        for (int nu = 0; nu < N; ++nu) Tt += A.fnext.psi2[gg * N + nu];
+#pragma unroll
+        for (int a = 0; a < NDIM; ++a)
+            if (slab(G.c[a], G.n[a], P)) Tt += A.fnext.pP2[a][gg];
+        float K = cc.K;
+        if (A.s.noise_amp != 0.0f) {
+            const uint64_t h = splitmix64_a(D.noise_seed ^ (uint64_t)(uint32_t)g);
+            const float u = (float)(h >> 40) * 0x1.0p-24f;
+            const float e = A.s.noise_amp * fmaf(2.0f, u, -1.0f);
+            const float f1 = 1.0f + e;
+            K = K * (f1 * f1);
+        }
+        const float lp = A.lam.p[gg];
+        const int64_t pk = D.packed_off + g;
+        A.gK[pk] += lp * (-dt * Tt);
+        const float q = -dt * K * lp;
+        float gdiv = cc.ik2 * q;
+        float gsum = 0.0f;
+#pragma unroll
+        for (int nu = 0; nu < N; ++nu) {
+            const float mu = A.lam.psi2[gg * N + nu] + q;
+            gdiv = fmaf(cc.a2[nu], mu, gdiv);
+            gsum = fmaf(mu, fmaf(ca.a2s[nu], S, ca.b2s[nu] * A.s.f.psi2[gg * N + nu]), gsum);
+            A.lam.psi2[gg * N + nu] = cc.b2[nu] * mu;
+        }
+#pragma unroll
+        for (int a = 0; a < NDIM; ++a) {
+            float ld = gdiv;
+            if (slab(G.c[a], G.n[a], P)) {
+                const int32_t off = D.pml_off[a];
+                const float aC = A.s.pml_tab[off + 2 * G.n[a] + G.c[a]];
+                const float bC = A.s.pml_tab[off + 3 * G.n[a] + G.c[a]];
+                const float mu = A.lam.pP2[a][gg] + q;
+                ld = fmaf(aC, mu, ld);
+                A.lam.pP2[a][gg] = bC * mu;
+            }
+            A.lamD2[a][gg] = ld;
+        }
+        A.gs[pk] += gsum;
+    }
+}
+
+template <int NDIM, int N>
+__global__ void k_adj_velocity(const AdjArgs A)
+{
+    Tile T;
+    DomainDesc D;
+    if (!setup<NDIM>(A, T, D)) return;
+    Geo G;
+    if (!column<NDIM>(T, D, G)) return;
+    const int64_t o = D.cell_off;
+    const float dt = A.s.dt;
+    const int P = A.s.pml;
+    float *lvx[3] = {A.lam.vx, A.lam.vy, A.lam.vz};
+    const float *psi1f[3] = {A.s.f.psi1x, A.s.f.psi1y, A.s.f.psi1z};
+    float *psi1l[3] = {A.lam.psi1x, A.lam.psi1y, A.lam.psi1z};
+    for (int z = T.z0; z < T.z1; ++z) {
+        at_plane<NDIM>(G, z);
+        const int g = G.g;
+        const int64_t gg = o + g;
+        const int L = A.s.f.cls[gg];
+        const ClassCoef &cc = A.s.classes[D.class_base + L];
+        const ClassAdj &ca = A.cadj[D.class_base + L];
+        float gsum = 0.0f;
+#pragma unroll
+        for (int a = 0; a < NDIM; ++a) {
+            const int i = G.c[a];
+            const int Ln = (i + 1 < G.n[a]) ? A.s.f.cls[gg + G.st[a]] : L;
+            const float m = 2.0f * dt / (cc.rho + A.s.classes[D.class_base + Ln].rho);
+            const float lv = lvx[a][gg] - grad_a(A.lamD2[a] + o, G, a, A.s.fd);
+            const float r = -m * lv;
+            const float D1 = grad_a(A.s.f.p + o, G, a, A.s.fd);
+            float ld = cc.ik1 * r;
+#pragma unroll
+            for (int nu = 0; nu < N; ++nu) {
+                const float mu = psi1l[a][gg * N + nu] + r;
+                ld = fmaf(cc.a1[nu], mu, ld);
+                gsum = fmaf(mu, fmaf(ca.a1s[nu], D1, ca.b1s[nu] * psi1f[a][gg * N + nu]), gsum);
+                psi1l[a][gg * N + nu] = cc.b1[nu] * mu;
+            }
+            if (slab(i, G.n[a], P)) {
+                const int32_t off = D.pml_off[a];
+                const float aF = A.s.pml_tab[off + i];
+                const float bF = A.s.pml_tab[off + G.n[a] + i];
+                const float mu = A.lam.pP1[a][gg] + r;
+                ld = fmaf(aF, mu, ld);
+                A.lam.pP1[a][gg] = bF * mu;
+            }
+            lvx[a][gg] = lv;
+            A.lamD1[a][gg] = ld;
+        }
+        A.gs[D.packed_off + g] += gsum;
+    }
+}
+
+template <int NDIM>
+__global__ void k_adj_gradient(const AdjArgs A)
+{
+    Tile T;
+    DomainDesc D;
+    if (!setup<NDIM>(A, T, D)) return;
+    Geo G;
+    if (!column<NDIM>(T, D, G)) return;
+    const int64_t o = D.cell_off;
+    for (int z = T.z0; z < T.z1; ++z) {
+        at_plane<NDIM>(G, z);
+        float acc = 0.0f;
+#pragma unroll
+        for (int a = 0; a < NDIM; ++a) acc += div_a(A.lamD1[a] + o, G, a, A.s.fd);
+        A.lam.p[o + G.g] -= acc;
+    }
+}
+
+// lam_p[cell] += sum of the residuals of the receivers at that cell; one
+// thread per distinct receiver cell, fixed summation order.
+__global__ __launch_bounds__(1024) void k_adj_inject(const AdjInjectArgs A)
+{
+    const int64_t t = A.step;
+    for (int64_t u = threadIdx.x; u < A.n_cells; u += blockDim.x) {
+        float s = 0.0f;
+        for (int32_t k = A.offsets[u]; k < A.offsets[u + 1]; ++k) s += A.res[t * A.n_rec + A.rec_index[k]];
+        A.lam_p[A.cells[u]] += s;
+    }
+}
+
+template <int NDIM, int N>
+hipError_t adj_launch(int which, const AdjArgs &a, hipStream_t s)
+{
+    int tx, ty;
+    tile_shape(NDIM, a.tile_rows, &tx, &ty);
+    const dim3 block(tx, NDIM == 3 ? ty : 1);
+    const dim3 grid(8 * a.s.tiles_per_xcd);
+    if (which == 0)
+        k_adj_pressure<NDIM, N><<<grid, block, 0, s>>>(a);
+    else if (which == 1)
+        k_adj_velocity<NDIM, N><<<grid, block, 0, s>>>(a);
+    else
+        k_adj_gradient<NDIM><<<grid, block, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+template <int NDIM>
+hipError_t adj_launch_n(int which, int nmech, const AdjArgs &a, hipStream_t s)
+{
+    switch (nmech) {
+    case 1: return adj_launch<NDIM, 1>(which, a, s);
+    case 2: return adj_launch<NDIM, 2>(which, a, s);
+    case 3: return adj_launch<NDIM, 3>(which, a, s);
+    case 4: return adj_launch<NDIM, 4>(which, a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_adjoint_step(int ndim, int nmech, const AdjArgs &a, hipStream_t s)
+{
+    if (a.s.n_tiles <= 0) return hipSuccess;
+    for (int which = 0; which < 3; ++which) {
+        hipError_t e = hipErrorInvalidValue;
+        if (ndim == 1) e = adj_launch_n<1>(which, nmech, a, s);
+        if (ndim == 2) e = adj_launch_n<2>(which, nmech, a, s);
+        if (ndim == 3) e = adj_launch_n<3>(which, nmech, a, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_adjoint_inject(const AdjInjectArgs &a, hipStream_t s)
+{
+    if (a.n_cells <= 0) return hipSuccess;
+    k_adj_inject<<<dim3(1), dim3(1024), 0, s>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace fw

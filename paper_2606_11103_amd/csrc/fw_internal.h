@@ -29,6 +29,7 @@ struct DomainDesc {
     int32_t pml_off[3];    // offset of the per-axis CPML tables [aF|bF|aC|bC] x n[a]
     int32_t pad;
     uint64_t noise_seed;
+    int64_t packed_off;    // first cell of the domain in the unpadded (caller) layout
 };
 
 // A tile: a block of cells along x (and y in 3D) marched over [z0, z1) of
@@ -73,6 +74,35 @@ struct SrcRecArgs {
     int32_t n_t_max;
     int64_t *step;             // device step counter
 };
+
+// d a / d s and d b / d s per mechanism when d -> s d (adjoint gradients)
+struct ClassAdj {
+    float a1s[kMaxMech], b1s[kMaxMech], a2s[kMaxMech], b2s[kMaxMech];
+};
+
+struct AdjArgs {
+    StepArgs s;                // tables, tiles and the forward state u^n (s.f)
+    Fields fnext;              // forward state u^{n+1}
+    Fields lam;                // adjoint state (same layout as the forward state)
+    float *lamD1[3], *lamD2[3];
+    float *gK, *gs;            // gradients, unpadded layout
+    const ClassAdj *cadj;
+    int32_t tile_rows;
+};
+
+struct AdjInjectArgs {
+    float *lam_p;
+    const int64_t *cells;      // distinct receiver cells (global index)
+    const int32_t *offsets;    // [n_cells + 1] into rec_index
+    const int32_t *rec_index;  // receivers grouped by cell
+    int64_t n_cells;
+    const float *res;          // [n_steps][n_rec] dJ/d trace
+    int64_t n_rec;
+    int64_t step;
+};
+
+hipError_t launch_adjoint_step(int ndim, int nmech, const AdjArgs &a, hipStream_t s);
+hipError_t launch_adjoint_inject(const AdjInjectArgs &a, hipStream_t s);
 
 // Launchers (kernels.hip).  Return hipSuccess or the launch error.
 hipError_t launch_velocity(int ndim, int nmech, int tile_rows, int rows_per_thread, const StepArgs &a, hipStream_t s);

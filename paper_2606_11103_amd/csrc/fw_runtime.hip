@@ -92,6 +92,9 @@ struct fw_sim {
     std::vector<double> kappa, dcoef, alpha;
     // device tables
     DevBuf d_doms, d_classes, d_pml, d_tiles, d_src_cell, d_src_wave, d_waves, d_rec_cell, d_traces, d_step;
+    DevBuf d_cadj, d_adj_cells, d_adj_off, d_adj_idx;
+    int64_t n_adj_cells = 0;
+    int64_t total_packed = 0;
     int n_tiles = 0, tiles_per_xcd = 0;
     int64_t n_src = 0, n_rec = 0;
     int n_t = 0, n_t_max = 0;
@@ -144,10 +147,9 @@ void layout(fw_sim *s)
     s->ws_bytes = off;
 }
 
-fw::Fields fields_of(const fw_sim *s)
+fw::Fields fields_at(const fw_sim *s, char *w)
 {
     fw::Fields f{};
-    char *w = s->ws;
     f.p = reinterpret_cast<float *>(w + s->off_p);
     f.vx = reinterpret_cast<float *>(w + s->off_v[0]);
     f.vy = reinterpret_cast<float *>(w + s->off_v[1]);
@@ -160,9 +162,11 @@ fw::Fields fields_of(const fw_sim *s)
         f.pP1[a] = reinterpret_cast<float *>(w + s->off_pP1[a]);
         f.pP2[a] = reinterpret_cast<float *>(w + s->off_pP2[a]);
     }
-    f.cls = reinterpret_cast<uint8_t *>(w + s->off_cls);
+    f.cls = reinterpret_cast<uint8_t *>(s->ws + s->off_cls);
     return f;
 }
+
+fw::Fields fields_of(const fw_sim *s) { return fields_at(s, s->ws); }
 
 // CPML recursion coefficients along one axis of n points (kappa = 1):
 // d = d0 delta^2, alpha = pi f_alpha (1 - delta), b = exp(-(d + alpha) dt),
@@ -367,7 +371,13 @@ int fw_create_grid(fw_sim **out, int ndim, int n_domains, const int64_t *shape, 
             D.n[a] = n;
         }
         D.cell_off = off;
+        D.packed_off = s->total_packed;
+        if (D.n[0] * D.n[1] * D.n[2] >= ((int64_t)1 << 31)) {
+            delete s;
+            return fail(FW_EINVAL, "domain %d has 2^31 cells or more", d);
+        }
         off = align_up(off + D.n[0] * D.n[1] * D.n[2], kAlignCells);
+        s->total_packed += D.n[0] * D.n[1] * D.n[2];
         s->doms.push_back(D);
     }
     s->total_cells = off;
@@ -495,9 +505,11 @@ int fw_set_relaxation_table(fw_sim *sim, int n_classes, const double *kappa, con
     const int N = sim->nmech;
     double min_kk = 1e300;
     std::vector<fw::ClassCoef> cc(n_classes);
+    std::vector<fw::ClassAdj> ca(n_classes);
     for (int k = 0; k < n_classes; ++k) {
         fw::ClassCoef &o = cc[k];
         std::memset(&o, 0, sizeof o);
+        std::memset(&ca[k], 0, sizeof ca[k]);
         const double k1 = kappa[2 * k], k2 = kappa[2 * k + 1];
         if (!(k1 > 0) || !(k2 > 0) || !std::isfinite(k1) || !std::isfinite(k2))
             return fail(FW_EINVAL, "class %d: kappa must be finite and > 0", k);
@@ -519,6 +531,12 @@ int fw_set_relaxation_table(fw_sim *sim, int n_classes, const double *kappa, con
                 const double aa = dd / (kap * (dd + kap * al)) * (bb - 1.0);
                 (i == 0 ? o.a1 : o.a2)[nu] = (float)aa;
                 (i == 0 ? o.b1 : o.b2)[nu] = (float)bb;
+                // derivatives with respect to a scale s of d (d -> s d) at s = 1
+                const double bs = -(dd / kap) * sim->dt * bb;
+                const double as = dd * al / ((dd + kap * al) * (dd + kap * al)) * (bb - 1.0) +
+                                  dd / (kap * (dd + kap * al)) * bs;
+                (i == 0 ? ca[k].a1s : ca[k].a2s)[nu] = (float)as;
+                (i == 0 ? ca[k].b1s : ca[k].b2s)[nu] = (float)bs;
             }
         }
     }
@@ -529,6 +547,8 @@ int fw_set_relaxation_table(fw_sim *sim, int n_classes, const double *kappa, con
     sim->alpha.assign(alpha, alpha + 2 * N * n_classes);
     HIP_OR_FAIL(sim->d_classes.ensure(cc.size() * sizeof(fw::ClassCoef)));
     HIP_OR_FAIL(hipMemcpy(sim->d_classes.ptr, cc.data(), cc.size() * sizeof(fw::ClassCoef), hipMemcpyHostToDevice));
+    HIP_OR_FAIL(sim->d_cadj.ensure(ca.size() * sizeof(fw::ClassAdj)));
+    HIP_OR_FAIL(hipMemcpy(sim->d_cadj.ptr, ca.data(), ca.size() * sizeof(fw::ClassAdj), hipMemcpyHostToDevice));
     sim->table_set = true;
     sim->drop_graph();
     return FW_OK;
@@ -605,6 +625,28 @@ int fw_set_receivers(fw_sim *sim, int64_t n_rec, const int32_t *domain, const in
         const size_t tb = (size_t)n_rec * std::max(n_t_max, 1) * sizeof(float);
         HIP_OR_FAIL(sim->d_traces.ensure(tb));
         HIP_OR_FAIL(hipMemset(sim->d_traces.ptr, 0, tb));
+        // receivers grouped by distinct cell, for the adjoint source injection
+        std::vector<int32_t> order(n_rec);
+        for (int64_t i = 0; i < n_rec; ++i) order[i] = (int32_t)i;
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return g[a] < g[b]; });
+        std::vector<int64_t> cells;
+        std::vector<int32_t> offs;
+        for (int64_t k = 0; k < n_rec; ++k) {
+            if (k == 0 || g[order[k]] != g[order[k - 1]]) {
+                cells.push_back(g[order[k]]);
+                offs.push_back((int32_t)k);
+            }
+        }
+        offs.push_back((int32_t)n_rec);
+        sim->n_adj_cells = (int64_t)cells.size();
+        HIP_OR_FAIL(sim->d_adj_cells.ensure(cells.size() * sizeof(int64_t)));
+        HIP_OR_FAIL(sim->d_adj_off.ensure(offs.size() * sizeof(int32_t)));
+        HIP_OR_FAIL(sim->d_adj_idx.ensure(order.size() * sizeof(int32_t)));
+        HIP_OR_FAIL(hipMemcpy(sim->d_adj_cells.ptr, cells.data(), cells.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+        HIP_OR_FAIL(hipMemcpy(sim->d_adj_off.ptr, offs.data(), offs.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        HIP_OR_FAIL(hipMemcpy(sim->d_adj_idx.ptr, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    } else {
+        sim->n_adj_cells = 0;
     }
     sim->drop_graph();
     return FW_OK;
@@ -748,6 +790,131 @@ int fw_time_kernels(fw_sim *sim, int n_steps, void *hip_stream, double *avg_ms)
     if (rc != FW_OK) return rc;
     for (int k = 0; k < 3; ++k) avg_ms[k] = tot[k] / n_steps;
     sim->host_step += n_steps;
+    return FW_OK;
+}
+
+
+// ------------------------------------------------------------------ adjoint --
+static int64_t adj_state_stride(const fw_sim *s) { return align_up(s->state_end + 8, kAlignBytes); }
+
+static int adj_layout(const fw_sim *s, int n_steps, int ckpt_every, int64_t *n_ck, int64_t *off_seg, int64_t *off_lam,
+                      int64_t *off_scr, int64_t *total)
+{
+    if (n_steps < 1 || ckpt_every < 1) return fail(FW_EINVAL, "n_steps and ckpt_every must be >= 1");
+    const int64_t SB = adj_state_stride(s);
+    *n_ck = (n_steps + ckpt_every - 1) / ckpt_every;
+    *off_seg = *n_ck * SB;
+    *off_lam = *off_seg + (int64_t)(std::min(ckpt_every, n_steps) + 1) * SB;
+    *off_scr = *off_lam + SB;
+    *total = *off_scr + align_up(2LL * 3 * s->total_cells * 4, kAlignBytes);
+    return FW_OK;
+}
+
+extern "C" int64_t fw_adjoint_workspace_bytes(const fw_sim *sim, int n_steps, int ckpt_every)
+{
+    if (!sim) return -1;
+    int64_t nck, os, ol, oc, tot;
+    if (adj_layout(sim, n_steps, ckpt_every, &nck, &os, &ol, &oc, &tot) != FW_OK) return -1;
+    return tot;
+}
+
+static int copy_state(fw_sim *s, char *dst, const char *src, hipStream_t st, bool with_step)
+{
+    HIP_OR_FAIL(hipMemcpyAsync(dst, src, (size_t)s->state_end, hipMemcpyDeviceToDevice, st));
+    (void)with_step;
+    return FW_OK;
+}
+
+extern "C" int fw_forward_checkpointed(fw_sim *sim, int n_steps, int ckpt_every, void *d_work, int64_t bytes,
+                                       void *hip_stream)
+{
+    g_err.clear();
+    if (!sim || !d_work) return fail(FW_EINVAL, "NULL argument");
+    int64_t nck, os, ol, oc, tot;
+    int rc = adj_layout(sim, n_steps, ckpt_every, &nck, &os, &ol, &oc, &tot);
+    if (rc != FW_OK) return rc;
+    if (bytes < tot) return fail(FW_ENOMEM, "adjoint workspace too small: %lld < %lld", (long long)bytes, (long long)tot);
+    if (!sim->ws || !sim->media_set || !sim->table_set) return fail(FW_ESTATE, "set up the simulation first");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    char *w = static_cast<char *>(d_work);
+    const int64_t SB = adj_state_stride(sim);
+    rc = fw_reset_state(sim, hip_stream);
+    if (rc != FW_OK) return rc;
+    for (int64_t k = 0; k < nck; ++k) {
+        rc = fw_save_state(sim, w + k * SB, hip_stream);
+        if (rc != FW_OK) return rc;
+        const int n = (int)std::min<int64_t>(ckpt_every, n_steps - k * ckpt_every);
+        rc = fw_step(sim, n, hip_stream);
+        if (rc != FW_OK) return rc;
+    }
+    (void)st;
+    return FW_OK;
+}
+
+extern "C" int fw_adjoint(fw_sim *sim, int n_steps, int ckpt_every, void *d_work, int64_t bytes, const float *d_adj_src,
+                          float *d_grad_K, float *d_grad_s, void *hip_stream)
+{
+    g_err.clear();
+    if (!sim || !d_work || !d_adj_src || !d_grad_K || !d_grad_s) return fail(FW_EINVAL, "NULL argument");
+    int64_t nck, os, ol, oc, tot;
+    int rc = adj_layout(sim, n_steps, ckpt_every, &nck, &os, &ol, &oc, &tot);
+    if (rc != FW_OK) return rc;
+    if (bytes < tot) return fail(FW_ENOMEM, "adjoint workspace too small: %lld < %lld", (long long)bytes, (long long)tot);
+    if (!sim->ws || !sim->media_set || !sim->table_set) return fail(FW_ESTATE, "set up the simulation first");
+    for (double b : sim->beta)
+        if (b != 0.0) return fail(FW_EUNSUPPORTED, "the adjoint supports linear media only (beta = 0 in every class)");
+    if (sim->tiles_dirty) {
+        rc = build_tiles(sim);
+        if (rc != FW_OK) return rc;
+    }
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    char *w = static_cast<char *>(d_work);
+    const int64_t SB = adj_state_stride(sim);
+    char *seg = w + os;
+    char *lam = w + ol;
+    float *scr = reinterpret_cast<float *>(w + oc);
+    HIP_OR_FAIL(hipMemsetAsync(lam, 0, (size_t)SB, st));
+    fw::AdjArgs A{};
+    A.s = step_args(sim);
+    A.lam = fields_at(sim, lam);
+    for (int a = 0; a < 3; ++a) {
+        A.lamD1[a] = scr + (int64_t)a * sim->total_cells;
+        A.lamD2[a] = scr + (int64_t)(3 + a) * sim->total_cells;
+    }
+    A.gK = d_grad_K;
+    A.gs = d_grad_s;
+    A.cadj = sim->d_cadj.as<fw::ClassAdj>();
+    A.tile_rows = sim->tile_rows;
+    fw::AdjInjectArgs J{};
+    J.lam_p = A.lam.p;
+    J.cells = sim->d_adj_cells.as<int64_t>();
+    J.offsets = sim->d_adj_off.as<int32_t>();
+    J.rec_index = sim->d_adj_idx.as<int32_t>();
+    J.n_cells = sim->n_adj_cells;
+    J.res = d_adj_src;
+    J.n_rec = sim->n_rec;
+    for (int64_t k = nck - 1; k >= 0; --k) {
+        const int64_t s0 = k * ckpt_every;
+        const int64_t s1 = std::min<int64_t>(s0 + ckpt_every, n_steps);
+        rc = fw_load_state(sim, w + k * SB, hip_stream);
+        if (rc != FW_OK) return rc;
+        rc = copy_state(sim, seg, sim->ws, st, false);
+        if (rc != FW_OK) return rc;
+        for (int64_t j = 1; j <= s1 - s0; ++j) {
+            rc = enqueue_steps(sim, 1, st);
+            if (rc != FW_OK) return rc;
+            rc = copy_state(sim, seg + j * SB, sim->ws, st, false);
+            if (rc != FW_OK) return rc;
+        }
+        for (int64_t n = s1 - 1; n >= s0; --n) {
+            J.step = n;
+            if (n < sim->n_t_max) HIP_OR_FAIL(fw::launch_adjoint_inject(J, st));
+            A.s.f = fields_at(sim, seg + (n - s0) * SB);
+            A.fnext = fields_at(sim, seg + (n - s0 + 1) * SB);
+            HIP_OR_FAIL(fw::launch_adjoint_step(sim->ndim, sim->nmech, A, st));
+        }
+    }
+    sim->host_step = n_steps;
     return FW_OK;
 }
 

@@ -127,6 +127,35 @@ class Simulation:
         check(lib.fw_time_kernels(self._h, int(n_steps), self._stream(stream), _ptr(out)))
         return out
 
+    # ------------------------------------------------------------ adjoint --
+    def adjoint_workspace(self, n_steps, ckpt_every):
+        nb = int(lib.fw_adjoint_workspace_bytes(self._h, int(n_steps), int(ckpt_every)))
+        if nb < 0:
+            raise native.FWError(native.FW_EINVAL, "bad adjoint workspace request")
+        return self.torch.empty(nb, dtype=self.torch.uint8, device=self.device)
+
+    def forward_checkpointed(self, n_steps, ckpt_every, work, stream=None):
+        """Reset, run n_steps and store checkpoints in work (see fw25.h)."""
+        check(lib.fw_forward_checkpointed(self._h, int(n_steps), int(ckpt_every), ctypes.c_void_p(work.data_ptr()),
+                                          int(work.numel()), self._stream(stream)))
+
+    def adjoint(self, n_steps, ckpt_every, work, adj_src, grad_K=None, grad_s=None, stream=None):
+        """Reverse sweep; adj_src is a device float tensor [n_steps][n_rec]
+        (dJ/d trace).  Returns (grad_K, grad_s) per cell, unpadded layout."""
+        torch = self.torch
+        ncell = sum(int(np.prod(s)) for s in self.shapes)
+        if grad_K is None:
+            grad_K = torch.zeros(ncell, dtype=torch.float32, device=self.device)
+        if grad_s is None:
+            grad_s = torch.zeros(ncell, dtype=torch.float32, device=self.device)
+        adj_src = adj_src.contiguous().to(device=self.device, dtype=torch.float32)
+        assert adj_src.numel() >= int(n_steps) * self.n_rec
+        check(lib.fw_adjoint(self._h, int(n_steps), int(ckpt_every), ctypes.c_void_p(work.data_ptr()),
+                             int(work.numel()), ctypes.c_void_p(adj_src.data_ptr()),
+                             ctypes.c_void_p(grad_K.data_ptr()), ctypes.c_void_p(grad_s.data_ptr()),
+                             self._stream(stream)))
+        return grad_K, grad_s
+
     def set_option(self, key, value):
         check(lib.fw_set_option(self._h, int(key), int(value)))
 

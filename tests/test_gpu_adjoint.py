@@ -1,0 +1,125 @@
+"""GPU discrete adjoint (checkpointed) vs the FP64 oracle adjoint, which is
+itself pinned by the dot-product and central-difference tests; plus
+checkpoint-interval invariance and a central-difference check on the GPU."""
+import numpy as np
+import pytest
+
+from workloads import configs
+from workloads.adapters import to_oracle, to_simulation
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _report(line):
+    import os
+    os.makedirs("gpurun_out", exist_ok=True)
+    with open(os.path.join("gpurun_out", "parity.txt"), "a") as fh:
+        fh.write(line + "\n")
+    print(line, flush=True)
+
+
+def _case(ndim, nmech, seed, steps, shapes=None):
+    if shapes is None:
+        shapes = [(64, 64, 1)] if ndim == 2 else [(36, 30, 28)]
+    c = configs.random_small(ndim, shapes, nmech, 3, seed=seed, steps=steps, pml=8 if ndim == 2 else 5,
+                             nonlinear=False, noise=0.01, n_rec=16)
+    return configs.with_table(c, *configs.random_relaxation_table(seed + 100, c.n_classes, c.nmech))
+
+
+def _gpu_gradient(case, ckpt, obs):
+    import torch
+    sim = to_simulation(case)
+    n = case.n_steps
+    work = sim.adjoint_workspace(n, ckpt)
+    sim.forward_checkpointed(n, ckpt, work)
+    tr = sim.read_receivers_device()
+    res = (case.dt * (tr.double() - torch.as_tensor(obs, device=tr.device))).float()
+    gK, gs = sim.adjoint(n, ckpt, work, res)
+    return sim.read_receivers(), gK.cpu().numpy(), gs.cpu().numpy()
+
+
+def _oracle_gradient(case, obs):
+    from oracle.solver import misfit_gradient
+    gK, gs, rec = [], [], []
+    for d in range(len(case.shapes)):
+        sim = to_oracle(case, d)
+        sm = case.src_domain == d
+        rm = np.nonzero(case.rec_domain == d)[0]
+        waves = case.waves.astype(np.float64)[case.src_wave[sm]]
+        J, k, s, r = misfit_gradient(sim, case.n_steps, case.src_cell[sm], waves, case.rec_cell[rm], obs[:, rm])
+        gK.append(k)
+        gs.append(s)
+        rec.append(r)
+    return np.concatenate(gK), np.concatenate(gs)
+
+
+@pytest.mark.parametrize("ndim,nmech,shapes", [(2, 2, None), (2, 4, [(64, 64, 1), (48, 72, 1)]), (3, 4, None)])
+def test_adjoint_gradients_match_fp64_adjoint(ndim, nmech, shapes):
+    case = _case(ndim, nmech, seed=21 + ndim + nmech, steps=160, shapes=shapes)
+    print("adjoint case", ndim, nmech, case.shapes, flush=True)
+    obs = np.zeros((case.n_steps, len(case.rec_cell)))
+    rec, gK, gs = _gpu_gradient(case, 23, obs)
+    oK, os_ = _oracle_gradient(case, obs)
+    rK, rs = _rel(gK, oK), _rel(gs, os_)
+    _report("adjoint %dD N=%d shapes=%s rel_L2 gK=%.3e gs=%.3e" % (ndim, nmech, case.shapes, rK, rs))
+    assert np.abs(oK).max() > 0 and np.abs(os_).max() > 0
+    assert rK <= 1e-4 and rs <= 1e-4
+
+
+def test_checkpoint_interval_does_not_change_gradients():
+    case = _case(2, 2, seed=3, steps=120)
+    obs = np.zeros((case.n_steps, len(case.rec_cell)))
+    _, k1, s1 = _gpu_gradient(case, 7, obs)
+    _, k2, s2 = _gpu_gradient(case, 55, obs)
+    _, k3, s3 = _gpu_gradient(case, 120, obs)
+    assert np.array_equal(k1, k2) and np.array_equal(k1, k3)
+    assert np.array_equal(s1, s2) and np.array_equal(s1, s3)
+
+
+def test_adjoint_central_difference_on_gpu():
+    """Class-level derivatives from the adjoint (per-cell gradients summed
+    over the cells of the class) vs central differences of J computed from
+    GPU traces (FP64 sums): dJ/dc_k (c of class k) and dJ/ds_k (every d of
+    class k scaled by s).  Whole classes are perturbed so that the change of
+    the traces stands well above FP32 rounding."""
+    import copy
+    case = _case(2, 2, seed=9, steps=150)
+    case.noise_amp = 0.0
+    case.pml_params = (1e-4, 1e6, float(case.c.max()) * 1.01)
+    rng = np.random.default_rng(0)
+    obs = np.zeros((case.n_steps, len(case.rec_cell)))
+    rec, gK, gs = _gpu_gradient(case, 50, obs)
+    lab = case.class_maps[0].reshape(-1)
+
+    def J_of(cs):
+        sim = to_simulation(cs)
+        sim.step(cs.n_steps)
+        r = sim.read_receivers().astype(np.float64)
+        return 0.5 * cs.dt * np.sum((r - obs) ** 2)
+
+    for k in range(case.n_classes):
+        m = lab == k
+        if not m.any():
+            continue
+        c0 = case.c[k]
+        adj_c = float(np.sum(2.0 * case.rho[k] * c0 * gK[m].astype(np.float64)))
+        h = 1e-3 * c0
+        cp, cm = copy.deepcopy(case), copy.deepcopy(case)
+        cp.c[k] += h
+        cm.c[k] -= h
+        fd_c = (J_of(cp) - J_of(cm)) / (2 * h)
+        adj_s = float(np.sum(gs[m].astype(np.float64)))
+        hs = 1e-2
+        sp_, sm_ = copy.deepcopy(case), copy.deepcopy(case)
+        sp_.d[k] *= 1 + hs
+        sm_.d[k] *= 1 - hs
+        fd_s = (J_of(sp_) - J_of(sm_)) / (2 * hs)
+        _report("adjoint FD class %d dJ/dc adj=%.6e fd=%.6e  dJ/ds adj=%.6e fd=%.6e" % (k, adj_c, fd_c, adj_s, fd_s))
+        assert abs(adj_c - fd_c) <= 1e-2 * abs(fd_c)
+        assert abs(adj_s - fd_s) <= 2e-2 * abs(fd_s) + 1e-3 * abs(adj_c * c0)

@@ -202,3 +202,39 @@ def random_small(ndim, shapes, nmech, n_classes, seed, steps, pml=6, nonlinear=T
         nonlinear=nonlinear, src_domain=np.array(sd, np.int32), src_cell=np.array(sc, np.int64),
         src_wave=np.zeros(len(sd), np.int32), waves=waves, rec_domain=np.array(rd, np.int32),
         rec_cell=np.array(rc, np.int64), n_steps=steps, noise_amp=noise, noise_seed=seed * 7 + 1)
+
+
+SWEEP_ALPHA0 = 0.0022 * (1.0 / 0.0022) ** (np.arange(32) / 31.0)
+SWEEP_Y = 0.4 + 0.1 * np.arange(17)
+SWEEP_FREQS = 1e6 + 2.714e6 * np.arange(8)
+
+
+def sweep_1d(n_cells=8192, nmech=2, steps=None, alpha0=None, y=None, c=1540.0, rho=1000.0, pml=24,
+             rec_every=8, src_cell=64):
+    """1D plane-wave sweep: one 8192-cell domain per (alpha0, y) pair, alpha0 in
+    32 log-spaced values 0.0022..1 and y in 17 values 0.4..2.0 (544 domains),
+    c = 1540, rho = 1000, linear, N = 2.  dx = c / (16 * 20 MHz) (16 points per
+    wavelength at the top of the band), CFL 0.2, 24-cell CPML at both ends.
+    Broadband source at cell 64: first derivative of a Gaussian with its
+    spectral peak at 6 MHz.  A receiver every 8 cells (from the source on)."""
+    a0 = SWEEP_ALPHA0 if alpha0 is None else np.asarray(alpha0, dtype=np.float64)
+    yy = SWEEP_Y if y is None else np.asarray(y, dtype=np.float64)
+    A0, Y = np.meshgrid(a0, yy, indexing="ij")
+    A0, Y = A0.ravel(), Y.ravel()
+    nd = A0.size
+    dx = c / (16 * 20e6)
+    dt = 0.2 * dx / c
+    if steps is None:
+        steps = int(round((n_cells - src_cell - pml) * dx / c / dt)) + 400
+    sigma = 1.0 / (np.sqrt(2.0) * np.pi * 6e6)
+    wave = gaussian_derivative(steps, dt, sigma, amplitude=1.0)
+    rc = np.arange(src_cell, n_cells - pml, rec_every)
+    shp = (n_cells, 1, 1)
+    return Case(
+        name="1d_sweep_%dx%d" % (nd, n_cells), ndim=1, shapes=[shp] * nd, dx=dx, dt=dt, nmech=nmech,
+        pml_cells=pml, class_maps=[np.zeros((1, 1, n_cells), np.uint8)] * nd, class_base=list(range(nd)),
+        c=np.full(nd, c), rho=np.full(nd, rho), alpha0=A0, y=Y, b_over_a=np.zeros(nd), nonlinear=False,
+        src_domain=np.arange(nd, dtype=np.int32), src_cell=np.full(nd, src_cell, np.int64),
+        src_wave=np.zeros(nd, np.int32), waves=wave[None, :],
+        rec_domain=np.repeat(np.arange(nd, dtype=np.int32), rc.size), rec_cell=np.tile(rc, nd).astype(np.int64),
+        n_steps=steps)
