@@ -217,6 +217,22 @@ int fw_adjoint(fw_sim *sim, int n_steps, int ckpt_every, void *d_work, int64_t b
 int fw_time_kernels(fw_sim *sim, int n_steps, void *hip_stream, double *avg_ms);
 
 /*
+ * One full step (like fw_step(sim, 1, ...)) that also evaluates, per domain,
+ * out[3 d + 0] = E^{n+1/2} = 1/2 sum_faces rho_f |v^{n+1/2}|^2
+ *                           + 1/2 sum_cells p^{n+1} p^n / K,
+ *   the staggered-time discrete energy, conserved exactly by the lossless
+ *   scheme because the divergence is minus the transposed gradient
+ *   (rho_f = mean density of the two cells of a face, K with the speed
+ *   perturbation, beta not included);
+ * out[3 d + 1] = max |p^{n+1}|;  out[3 d + 2] = number of non-finite p^{n+1}.
+ * FP64 sums in a fixed order.  out is host double [n_domains][3].
+ * Synchronises the stream.  Returns FW_ENONFINITE (out still filled) if any
+ * pressure is NaN or infinite.  On first use the library allocates one
+ * pressure-sized device buffer and one partial-sum buffer.
+ */
+int fw_energy_step(fw_sim *sim, double *out, void *hip_stream);
+
+/*
  * Tuning and behaviour options (host only):
  *   FW_OPT_GRAPH_STEPS   steps per captured HIP graph (0 = eager only); default 16.
  *   FW_OPT_MARCH_CHUNK   cells of the marching axis per tile (>= 8); default auto.

@@ -1,0 +1,107 @@
+// Diagnostics of one step: the staggered-time discrete energy
+//   E^{n+1/2} = 1/2 sum_faces rho_f |v^{n+1/2}|^2 + 1/2 sum_cells p^{n+1} p^n / K,
+// which the lossless scheme conserves exactly (div = -grad^T), the largest
+// |p^{n+1}| and the number of non-finite pressures.  FP64 accumulation per
+// thread and per block in a fixed order; one partial per tile, summed per
+// domain on the host.
+#include "fw_internal.h"
+
+namespace fw {
+
+namespace {
+
+__device__ __forceinline__ uint64_t splitmix64_d(uint64_t x)
+{
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+template <int NDIM>
+__global__ __launch_bounds__(1024) void k_energy(const StepArgs A, const float *__restrict__ p_old, double *partial)
+{
+    __shared__ double s_e[1024];
+    __shared__ float s_m[1024];
+    __shared__ int s_nf[1024];
+    const int b = blockIdx.x;
+    const int ti = (b & 7) * A.tiles_per_xcd + (b >> 3);
+    if (ti >= A.n_tiles) return;
+    const Tile T = A.tiles[ti];
+    const DomainDesc D = A.doms[T.dom];
+    const int nx = (int)D.n[0], ny = (int)D.n[1], nz = (int)D.n[2];
+    const int st[3] = {1, nx, nx * ny};
+    const int nn[3] = {nx, ny, nz};
+    const int64_t o = D.cell_off;
+    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+    const int x = T.x0 + (int)threadIdx.x;
+    int y = NDIM == 3 ? T.y0 + (int)threadIdx.y : 0;
+    double e = 0.0;
+    float mx = 0.0f;
+    int nf = 0;
+    const float *vv[3] = {A.f.vx + o, A.f.vy + o, A.f.vz + o};
+    if (x < nx && y < ny) {
+        for (int z = T.z0; z < T.z1; ++z) {
+            int c[3] = {x, y, 0};
+            if (NDIM == 3) c[2] = z;
+            if (NDIM == 2) c[1] = z;
+            const int g = (c[2] * ny + c[1]) * nx + c[0];
+            const int L = A.f.cls[o + g];
+            const ClassCoef &cc = A.classes[D.class_base + L];
+            float K = cc.K;
+            if (A.noise_amp != 0.0f) {
+                const uint64_t h = splitmix64_d(D.noise_seed ^ (uint64_t)(uint32_t)g);
+                const float u = (float)(h >> 40) * 0x1.0p-24f;
+                const float ep = A.noise_amp * fmaf(2.0f, u, -1.0f);
+                const float f1 = 1.0f + ep;
+                K = K * (f1 * f1);
+            }
+            const float pn = A.f.p[o + g];
+            if (!isfinite(pn)) ++nf;
+            mx = fmaxf(mx, fabsf(pn));
+            e += 0.5 * (double)pn * (double)p_old[o + g] / (double)K;
+#pragma unroll
+            for (int a = 0; a < NDIM; ++a) {
+                const int Ln = (c[a] + 1 < nn[a]) ? A.f.cls[o + g + st[a]] : L;
+                const double rf = 0.5 * ((double)cc.rho + (double)A.classes[D.class_base + Ln].rho);
+                const double va = vv[a][g];
+                e += 0.5 * rf * va * va;
+            }
+        }
+    }
+    s_e[tid] = e;
+    s_m[tid] = mx;
+    s_nf[tid] = nf;
+    __syncthreads();
+    const int nt = blockDim.x * blockDim.y;
+    for (int w = 512; w > 0; w >>= 1) {
+        if (tid < w && tid + w < nt) {
+            s_e[tid] += s_e[tid + w];
+            s_m[tid] = fmaxf(s_m[tid], s_m[tid + w]);
+            s_nf[tid] += s_nf[tid + w];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        partial[3 * (int64_t)ti] = s_e[0];
+        partial[3 * (int64_t)ti + 1] = (double)s_m[0];
+        partial[3 * (int64_t)ti + 2] = (double)s_nf[0];
+    }
+}
+
+}  // namespace
+
+hipError_t launch_energy(int ndim, const StepArgs &a, const float *p_old, double *partial, hipStream_t s)
+{
+    if (a.n_tiles <= 0) return hipSuccess;
+    int tx, ty;
+    tile_shape(ndim, 16, &tx, &ty);
+    (void)ty;
+    const dim3 grid(8 * a.tiles_per_xcd);
+    if (ndim == 1) k_energy<1><<<grid, dim3(tx, 1), 0, s>>>(a, p_old, partial);
+    if (ndim == 2) k_energy<2><<<grid, dim3(tx, 1), 0, s>>>(a, p_old, partial);
+    if (ndim == 3) k_energy<3><<<grid, dim3(tx, a.tile_rows), 0, s>>>(a, p_old, partial);
+    return hipGetLastError();
+}
+
+}  // namespace fw

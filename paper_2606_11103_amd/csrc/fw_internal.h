@@ -56,6 +56,7 @@ struct StepArgs {
     int32_t tiles_per_xcd;     // ceil(n_tiles / 8): block b runs tile (b % 8) * tiles_per_xcd + b / 8
     int32_t pml;               // CPML width P
     int32_t class_cap;         // entries per LDS class table (>= classes of any domain)
+    int32_t tile_rows;         // rows of a 3D tile along y
     float fd[4];               // staggered coefficients c_m / dx
     float dt;
     float noise_amp;
@@ -101,6 +102,7 @@ struct AdjInjectArgs {
     int64_t step;
 };
 
+hipError_t launch_energy(int ndim, const StepArgs &a, const float *p_old, double *partial, hipStream_t s);
 hipError_t launch_adjoint_step(int ndim, int nmech, const AdjArgs &a, hipStream_t s);
 hipError_t launch_adjoint_inject(const AdjInjectArgs &a, hipStream_t s);
 

@@ -93,6 +93,7 @@ struct fw_sim {
     // device tables
     DevBuf d_doms, d_classes, d_pml, d_tiles, d_src_cell, d_src_wave, d_waves, d_rec_cell, d_traces, d_step;
     DevBuf d_cadj, d_adj_cells, d_adj_off, d_adj_idx;
+    DevBuf d_pold, d_partial;
     int64_t n_adj_cells = 0;
     int64_t total_packed = 0;
     int n_tiles = 0, tiles_per_xcd = 0;
@@ -255,6 +256,7 @@ fw::StepArgs step_args(const fw_sim *s)
     int cap = 1;
     for (const auto &d : s->doms) cap = std::max(cap, (int)d.n_classes);
     a.class_cap = (cap + 3) / 4 * 4;
+    a.tile_rows = s->tile_rows;
     for (int m = 0; m < 4; ++m) a.fd[m] = (float)(kFD[m] / s->dx);
     a.dt = (float)s->dt;
     a.noise_amp = (float)s->noise_amp;
@@ -793,6 +795,44 @@ int fw_time_kernels(fw_sim *sim, int n_steps, void *hip_stream, double *avg_ms)
     return FW_OK;
 }
 
+
+extern "C" int fw_energy_step(fw_sim *sim, double *out, void *hip_stream)
+{
+    g_err.clear();
+    if (!sim || !out) return fail(FW_EINVAL, "NULL argument");
+    if (!sim->ws || !sim->media_set || !sim->table_set) return fail(FW_ESTATE, "set up the simulation first");
+    if (sim->tiles_dirty) {
+        int rc = build_tiles(sim);
+        if (rc != FW_OK) return rc;
+    }
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    HIP_OR_FAIL(sim->d_pold.ensure((size_t)sim->total_cells * sizeof(float)));
+    HIP_OR_FAIL(sim->d_partial.ensure((size_t)sim->n_tiles * 3 * sizeof(double)));
+    const fw::StepArgs a = step_args(sim);
+    const fw::SrcRecArgs r = srcrec_args(sim);
+    HIP_OR_FAIL(fw::launch_velocity(sim->ndim, sim->nmech, sim->tile_rows, sim->rows_per_thread, a, st));
+    HIP_OR_FAIL(hipMemcpyAsync(sim->d_pold.ptr, a.f.p, (size_t)sim->total_cells * sizeof(float),
+                               hipMemcpyDeviceToDevice, st));
+    HIP_OR_FAIL(fw::launch_pressure(sim->ndim, sim->nmech, sim->tile_rows, sim->rows_per_thread, a, st));
+    HIP_OR_FAIL(fw::launch_src_rec(r, st));
+    HIP_OR_FAIL(fw::launch_energy(sim->ndim, a, sim->d_pold.as<float>(), sim->d_partial.as<double>(), st));
+    std::vector<double> part((size_t)sim->n_tiles * 3);
+    HIP_OR_FAIL(hipMemcpyAsync(part.data(), sim->d_partial.ptr, part.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_OR_FAIL(hipStreamSynchronize(st));
+    std::vector<fw::Tile> tiles(sim->n_tiles);
+    HIP_OR_FAIL(hipMemcpy(tiles.data(), sim->d_tiles.ptr, tiles.size() * sizeof(fw::Tile), hipMemcpyDeviceToHost));
+    for (int d = 0; d < sim->n_domains; ++d) out[3 * d] = out[3 * d + 1] = out[3 * d + 2] = 0.0;
+    for (int t = 0; t < sim->n_tiles; ++t) {
+        double *o = out + 3 * tiles[t].dom;
+        o[0] += part[3 * (size_t)t];
+        o[1] = std::max(o[1], part[3 * (size_t)t + 1]);
+        o[2] += part[3 * (size_t)t + 2];
+    }
+    sim->host_step += 1;
+    for (int d = 0; d < sim->n_domains; ++d)
+        if (out[3 * d + 2] > 0) return fail(FW_ENONFINITE, "domain %d: %.0f non-finite pressure values", d, out[3 * d + 2]);
+    return FW_OK;
+}
 
 // ------------------------------------------------------------------ adjoint --
 static int64_t adj_state_stride(const fw_sim *s) { return align_up(s->state_end + 8, kAlignBytes); }

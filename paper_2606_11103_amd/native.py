@@ -43,6 +43,7 @@ SIGNATURES = {
     "fw_set_option": (_I, [_P, _I, _L]),
     "fw_time_kernels": (_I, [_P, _I, _P, _P]),
     "fw_adjoint_workspace_bytes": (_L, [_P, _I, _I]),
+    "fw_energy_step": (_I, [_P, _P, _P]),
     "fw_forward_checkpointed": (_I, [_P, _I, _I, _P, _L, _P]),
     "fw_adjoint": (_I, [_P, _I, _I, _P, _L, _P, _P, _P, _P]),
 }

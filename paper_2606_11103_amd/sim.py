@@ -127,6 +127,15 @@ class Simulation:
         check(lib.fw_time_kernels(self._h, int(n_steps), self._stream(stream), _ptr(out)))
         return out
 
+    def energy_step(self, stream=None, check_finite=True):
+        """One full step that also returns, per domain, (E^{n+1/2}, max|p|,
+        number of non-finite pressures) with FP64 sums."""
+        out = np.zeros((self.n_domains, 3), dtype=np.float64)
+        rc = lib.fw_energy_step(self._h, _ptr(out), self._stream(stream))
+        if rc != native.FW_ENONFINITE or check_finite:
+            check(rc)
+        return out
+
     # ------------------------------------------------------------ adjoint --
     def adjoint_workspace(self, n_steps, ckpt_every):
         nb = int(lib.fw_adjoint_workspace_bytes(self._h, int(n_steps), int(ckpt_every)))

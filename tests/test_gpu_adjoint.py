@@ -123,3 +123,47 @@ def test_adjoint_central_difference_on_gpu():
         _report("adjoint FD class %d dJ/dc adj=%.6e fd=%.6e  dJ/ds adj=%.6e fd=%.6e" % (k, adj_c, fd_c, adj_s, fd_s))
         assert abs(adj_c - fd_c) <= 1e-2 * abs(fd_c)
         assert abs(adj_s - fd_s) <= 2e-2 * abs(fd_s) + 1e-3 * abs(adj_c * c0)
+
+
+def test_autograd_function_gradients():
+    """FDTDFunction (torch.autograd) on per-voxel c and alpha0 maps: summed
+    gradients over each tissue class vs central differences of J taken
+    through the same function."""
+    import torch
+    from paper_2606_11103_amd.autograd import Problem, simulate
+    case = _case(2, 2, seed=13, steps=120)
+    lab = case.class_maps[0]
+    prob = Problem(ndim=2, shapes=case.shapes, dx=case.dx, dt=case.dt, nmech=case.nmech, pml_cells=case.pml_cells,
+                   labels=[lab], rho=case.rho, alpha0_ref=case.alpha0, kappa=case.kappa, d=case.d,
+                   alpha=case.alpha, src_domain=case.src_domain, src_cell=case.src_cell, src_wave=case.src_wave,
+                   waves=case.waves, rec_domain=case.rec_domain, rec_cell=case.rec_cell, n_steps=case.n_steps,
+                   ckpt_every=40, noise_amp=case.noise_amp, noise_seed=case.noise_seed,
+                   pml_params=(1e-4, 1e6, float(case.c.max()) * 1.05))
+    flat = lab.reshape(-1).astype(np.int64)
+    c0 = torch.tensor(case.c[flat], dtype=torch.float64)
+    a00 = torch.tensor(case.alpha0[flat], dtype=torch.float64)
+
+    def J_of(cm, am):
+        tr = simulate(cm, am, prob)
+        return 0.5 * case.dt * (tr.double() ** 2).sum()
+
+    cm = c0.clone().requires_grad_(True)
+    am = a00.clone().requires_grad_(True)
+    J = J_of(cm, am)
+    J.backward()
+    gc, ga = cm.grad.numpy(), am.grad.numpy()
+    with torch.no_grad():
+        for k in range(case.n_classes):
+            m = torch.as_tensor(flat == k)
+            if not bool(m.any()):
+                continue
+            h = 1e-3 * case.c[k]
+            fd_c = (J_of(c0 + h * m, a00) - J_of(c0 - h * m, a00)).item() / (2 * h)
+            ha = 1e-2 * case.alpha0[k]
+            fd_a = (J_of(c0, a00 + ha * m) - J_of(c0, a00 - ha * m)).item() / (2 * ha)
+            adj_c = float(gc[flat == k].sum())
+            adj_a = float(ga[flat == k].sum())
+            _report("autograd class %d dJ/dc adj=%.6e fd=%.6e  dJ/dalpha0 adj=%.6e fd=%.6e"
+                    % (k, adj_c, fd_c, adj_a, fd_a))
+            assert abs(adj_c - fd_c) <= 1e-2 * abs(fd_c)
+            assert abs(adj_a - fd_a) <= 2e-2 * abs(fd_a) + 1e-6 * abs(adj_c) * case.c[k] / case.alpha0[k]
