@@ -25,6 +25,22 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the velocity kernel measured with rocprofv3 --pmc
+# (FETCH_SIZE x 2.000 and WRITE_SIZE x 1.000, factors from the library's plain
+# copy kernel), keyed by the SHA-256 prefix of the kernel source they were
+# taken on; any other kernel source reports traffic as null.
+TRAFFIC_MEASURED = {
+    "797a08cfc5f3eb81": {"workload": "3d_heterogeneous_960x960x720", "tile_rows": 16, "rows_per_thread": 1,
+                         "bytes_per_launch": 88.16e9,
+                         "profile": "profiles/step_kernels_3d_960x960x720_N4.md"},
+}
+
+
+def kernel_source_hash():
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2606_11103_amd", "csrc", "fw_kernels.hip"), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
 
 def algorithmic_bytes(case):
     """Algorithmic bytes per cell-update (FP32 state read once and written
@@ -89,32 +105,136 @@ def cpu_baseline(seconds_target=20.0):
                        "noise, nonlinear), %d steps in %.1f s" % (steps, el))
 
 
-def copy_probe(torch, gib, reps):
-    """Plain copy of a known size: reads gib GiB and writes gib GiB per launch.
-    Used to scale the FETCH_SIZE / WRITE_SIZE counters to bytes."""
-    n = int(gib * (1 << 30) // 4)
-    a = torch.ones(n, dtype=torch.float32, device="cuda")
-    b = torch.empty_like(a)
-    b.copy_(a)
+def _time_steps(torch, sim, steps):
+    """Milliseconds for `steps` full steps through fw_step (graph replay)."""
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    for _ in range(reps):
-        b.copy_(a)
+    sim.step(steps)
     e1.record()
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    print(json.dumps({"copy_probe_bytes_each_way": n * 4, "avg_ms": ms,
-                      "copy_GBps_read_plus_write": 2 * n * 4 / (ms / 1e3) / 1e9}), flush=True)
+    return e0.elapsed_time(e1)
+
+
+def bench_batched(torch, steps=40):
+    """64 ragged 2D shots (384^2..1536^2, N = 4, 4-layer media) advanced
+    together in one tile list, vs the same shots run one at a time."""
+    from workloads import configs
+    from workloads.adapters import to_simulation
+    case = configs.batched_2d(steps=steps + 5)
+    configs.with_table(case, *configs.random_relaxation_table(4000, case.n_classes, case.nmech))
+    sim = to_simulation(case)
+    sim.step(5)
+    ms = _time_steps(torch, sim, steps)
+    batched = case.cells() * steps / (ms / 1e3) / 1e9
+    del sim
+    # plain: a sample of 8 shots, each its own simulation
+    cells = 0
+    tot = 0.0
+    for s in range(0, 64, 8):
+        one = configs.Case(**{**case.__dict__})
+        one.shapes = [case.shapes[s]]
+        one.class_maps = [case.class_maps[s]]
+        one.class_base = [0]
+        sl = slice(4 * s, 4 * s + 4)
+        for f in ("c", "rho", "alpha0", "y", "b_over_a", "kappa", "d", "alpha"):
+            setattr(one, f, getattr(case, f)[sl])
+        one.src_domain = np.zeros(1, np.int32)
+        one.src_cell = case.src_cell[s:s + 1]
+        one.src_wave = case.src_wave[s:s + 1]
+        rm = case.rec_domain == s
+        one.rec_domain = np.zeros(int(rm.sum()), np.int32)
+        one.rec_cell = case.rec_cell[rm]
+        sim = to_simulation(one)
+        sim.step(5)
+        tot += _time_steps(torch, sim, steps)
+        cells += one.cells()
+        del sim
+    plain = cells * steps / (tot / 1e3) / 1e9
+    return {"workload": case.name, "cells": case.cells(), "steps": steps,
+            "batched_gcells": round(batched, 3), "ms_per_step": round(ms / steps, 4),
+            "plain_single_shot_gcells": round(plain, 3), "batched_vs_plain": round(batched / plain, 3),
+            "plain_sample": "8 of the 64 shots, one simulation each"}
+
+
+def bench_adjoint(torch, steps=330, ckpt=55):
+    """Gradient of J = 1/2 dt sum (r - d)^2 w.r.t. c(x), alpha0(x) for the 16-shot
+    1024^2 N = 4 workload (observed data: true model; current model: c x 0.99),
+    forward with checkpoints every 55 steps + adjoint sweep, vs the plain
+    forward of the same steps."""
+    from workloads import configs
+    from workloads.adapters import to_simulation
+    case = configs.adjoint_2d(steps=steps)
+    fill_tables(case)
+    true = to_simulation(case)
+    true.step(steps)
+    obs = true.read_receivers_device()
+    del true
+    case.c = case.c * 0.99
+    sim = to_simulation(case)
+    ms_fwd = _time_steps(torch, sim, steps)
+    sim.reset()
+    work = sim.adjoint_workspace(steps, ckpt)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    sim.forward_checkpointed(steps, ckpt, work)
+    tr = sim.read_receivers_device()
+    res = case.dt * (tr - obs)
+    gK, gs = sim.adjoint(steps, ckpt, work, res)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_grad = e0.elapsed_time(e1)
+    misfit = float(0.5 * case.dt * ((tr.double() - obs.double()) ** 2).sum())
+    finite = bool(torch.isfinite(gK).all() and torch.isfinite(gs).all())
+    del work
+    return {"workload": case.name + " (%d of %d steps)" % (steps, 3000), "cells": case.cells(), "steps": steps,
+            "checkpoint_every": ckpt, "forward_ms": round(ms_fwd, 2), "gradient_ms": round(ms_grad, 2),
+            "gradient_vs_forward": round(ms_grad / ms_fwd, 3),
+            "forward_gcells": round(case.cells() * steps / (ms_fwd / 1e3) / 1e9, 3),
+            "misfit": misfit, "gradients_finite": finite}
+
+
+def copy_probe(torch, gib, reps):
+    """Plain copies of a known size (gib GiB read + gib GiB written per launch):
+    the library's streaming copy kernel and torch's copy_.  Used to scale the
+    FETCH_SIZE / WRITE_SIZE counters to bytes and as the practical bandwidth
+    ceiling of the part."""
+    import ctypes
+    from paper_2606_11103_amd.native import check, lib
+    n = int(gib * (1 << 30) // 4)
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    stream = torch.cuda.current_stream()
+    out = {"copy_probe_bytes_each_way": n * 4}
+    for name in ("fw_device_copy", "torch_copy"):
+        def run():
+            if name == "fw_device_copy":
+                check(lib.fw_device_copy(ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(a.data_ptr()), n * 4,
+                                         ctypes.c_void_p(stream.cuda_stream)))
+            else:
+                b.copy_(a)
+        run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            run()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = {"avg_ms": round(ms, 4), "GBps_read_plus_write": round(2 * n * 4 / (ms / 1e3) / 1e9, 1)}
+    print(json.dumps(out), flush=True)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--small", action="store_true", help="reduced grid for quick checks (not the benchmark)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched and adjoint comparisons")
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--march-chunk", type=int, default=0)
     ap.add_argument("--rows-per-thread", type=int, default=0)
@@ -175,6 +295,11 @@ def main():
 
     b_vel, b_prs, b_step = algorithmic_bytes(case)
     ach_vel = b_vel * cells / (kern_ms[0] / 1e3) / 1e9
+    meas = TRAFFIC_MEASURED.get(kernel_source_hash())
+    traffic = None
+    if (meas is not None and not args.small and meas["workload"] == case.name
+            and (args.tile_rows or 16) == meas["tile_rows"] and (args.rows_per_thread or 1) == meas["rows_per_thread"]):
+        traffic = round(meas["bytes_per_launch"] / (kern_ms[0] / 1e3) / 1e9, 1)
     ach_step = b_step * cells / (ms_step / 1e3) / 1e9
     out = {
         "metric": "Gcell-updates/s (3D heterogeneous, 4 mechanisms)",
@@ -194,7 +319,8 @@ def main():
                    "steps_of_full_run": case.n_steps, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": "velocity update",
                      "achieved": round(ach_vel, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ach_vel / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(ach_vel / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_note": "measured HBM bytes per launch / avg launch time (GB/s), see profile",
                      "bytes_per_cell": round(b_vel, 2), "avg_ms": round(kern_ms[0], 4)},
         "step_roofline": {"achieved": round(ach_step, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": round(ach_step / HBM_PEAK_GBS, 4), "bytes_per_cell": round(b_step, 2)},
@@ -203,6 +329,15 @@ def main():
         "traces_finite": finite,
         "wall_s": round(wall, 3),
     }
+    if not args.no_extras and not args.small:
+        del sim
+        torch.cuda.empty_cache()
+        print("# batched ...", file=sys.stderr, flush=True)
+        out["batched"] = bench_batched(torch)
+        torch.cuda.empty_cache()
+        print("# adjoint ...", file=sys.stderr, flush=True)
+        out["adjoint"] = bench_adjoint(torch)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         print("# cpu baseline ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()

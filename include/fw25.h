@@ -233,15 +233,26 @@ int fw_time_kernels(fw_sim *sim, int n_steps, void *hip_stream, double *avg_ms);
 int fw_energy_step(fw_sim *sim, double *out, void *hip_stream);
 
 /*
+ * Streaming device-to-device copy of bytes bytes on hip_stream (used for
+ * state snapshots and checkpoints).  16-byte aligned pointers and sizes use a
+ * float4 grid-stride kernel, anything else hipMemcpyAsync.  Asynchronous.
+ */
+int fw_device_copy(void *d_dst, const void *d_src, int64_t bytes, void *hip_stream);
+
+/*
  * Tuning and behaviour options (host only):
  *   FW_OPT_GRAPH_STEPS   steps per captured HIP graph (0 = eager only); default 16.
  *   FW_OPT_MARCH_CHUNK   cells of the marching axis per tile (>= 8); default auto.
  *   FW_OPT_TILE_ROWS     3D tile rows along y per block: 4, 8 or 16; default 16.
  *   FW_OPT_ROWS_PER_THREAD  3D rows each thread owns: 1 or 2 (not with 4-row
  *                        tiles); default 1.
+ *   FW_OPT_PERSISTENT    0: one workgroup per tile (default); k > 0: a
+ *                        persistent grid of 32 k workgroups per XCD
+ *                        (k per CU) that walk the tile list.
  * Options change the work decomposition only, never the results.
  */
-enum { FW_OPT_GRAPH_STEPS = 1, FW_OPT_MARCH_CHUNK = 2, FW_OPT_TILE_ROWS = 3, FW_OPT_ROWS_PER_THREAD = 4 };
+enum { FW_OPT_GRAPH_STEPS = 1, FW_OPT_MARCH_CHUNK = 2, FW_OPT_TILE_ROWS = 3, FW_OPT_ROWS_PER_THREAD = 4,
+       FW_OPT_PERSISTENT = 5 };
 int fw_set_option(fw_sim *sim, int key, int64_t value);
 
 #ifdef __cplusplus

@@ -4,6 +4,8 @@
 // |p^{n+1}| and the number of non-finite pressures.  FP64 accumulation per
 // thread and per block in a fixed order; one partial per tile, summed per
 // domain on the host.
+#include <algorithm>
+
 #include "fw_internal.h"
 
 namespace fw {
@@ -89,7 +91,26 @@ __global__ __launch_bounds__(1024) void k_energy(const StepArgs A, const float *
     }
 }
 
+// Streaming device-to-device copy, 16 bytes per lane per iteration.
+__global__ __launch_bounds__(256) void k_copy16(const float4 *__restrict__ src, float4 *__restrict__ dst, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
 }  // namespace
+
+hipError_t launch_copy(void *dst, const void *src, int64_t bytes, hipStream_t s)
+{
+    if (bytes <= 0) return hipSuccess;
+    const bool aligned = ((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) & 15) == 0 &&
+                         (bytes & 15) == 0;
+    if (!aligned) return hipMemcpyAsync(dst, src, (size_t)bytes, hipMemcpyDeviceToDevice, s);
+    const int64_t n = bytes / 16;
+    const int64_t blocks = std::min<int64_t>(1024, (n + 255) / 256);
+    k_copy16<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(static_cast<const float4 *>(src), static_cast<float4 *>(dst), n);
+    return hipGetLastError();
+}
 
 hipError_t launch_energy(int ndim, const StepArgs &a, const float *p_old, double *partial, hipStream_t s)
 {

@@ -53,7 +53,8 @@ struct StepArgs {
     const ClassCoef *classes;
     const float *pml_tab;
     int32_t n_tiles;
-    int32_t tiles_per_xcd;     // ceil(n_tiles / 8): block b runs tile (b % 8) * tiles_per_xcd + b / 8
+    int32_t tiles_per_xcd;     // ceil(n_tiles / 8): XCD x owns tiles [x C, (x + 1) C)
+    int32_t blocks_per_xcd;    // blocks per XCD of the step kernels (= tiles_per_xcd, or fewer: persistent)
     int32_t pml;               // CPML width P
     int32_t class_cap;         // entries per LDS class table (>= classes of any domain)
     int32_t tile_rows;         // rows of a 3D tile along y
@@ -102,6 +103,7 @@ struct AdjInjectArgs {
     int64_t step;
 };
 
+hipError_t launch_copy(void *dst, const void *src, int64_t bytes, hipStream_t s);
 hipError_t launch_energy(int ndim, const StepArgs &a, const float *p_old, double *partial, hipStream_t s);
 hipError_t launch_adjoint_step(int ndim, int nmech, const AdjArgs &a, hipStream_t s);
 hipError_t launch_adjoint_inject(const AdjInjectArgs &a, hipStream_t s);

@@ -60,10 +60,18 @@ __device__ __forceinline__ void store_vec(float *__restrict__ dst, const float (
     }
 }
 
-__device__ __forceinline__ int tile_index(const StepArgs &A)
+// Tile of iteration `it` of this block, or -1.  XCD x (= block % 8, as
+// workgroups are dispatched round-robin over the 8 XCDs) owns the contiguous
+// tile range [x C, (x + 1) C), C = tiles_per_xcd; its blocks interleave over
+// that range with stride blocks_per_xcd (one iteration when the grid has a
+// block per tile, several for a persistent grid).
+__device__ __forceinline__ int tile_index(const StepArgs &A, int it)
 {
     const int b = blockIdx.x;
-    return (b & 7) * A.tiles_per_xcd + (b >> 3);
+    const int local = (b >> 3) + it * A.blocks_per_xcd;
+    if (local >= A.tiles_per_xcd) return -1;
+    const int ti = (b & 7) * A.tiles_per_xcd + local;
+    return ti < A.n_tiles ? ti : -1;
 }
 
 __device__ __forceinline__ bool in_slab(int64_t c, int64_t n, int P) { return P > 0 && (c < P || c >= n - P); }
@@ -155,8 +163,11 @@ __global__ __launch_bounds__(BX *BY) void k_velocity(const StepArgs A)
     const int C = A.class_cap;
     float *s_ik = s_dyn, *s_rho = s_dyn + C, *s_a = s_dyn + 2 * C, *s_b = s_dyn + (2 + N) * C;
 
-    const int ti = tile_index(A);
-    if (ti >= A.n_tiles) return;
+    for (int it = 0;; ++it) {
+    const int ti = tile_index(A, it);
+    if (ti < 0) break;
+    if (it > 0) __syncthreads();   // the previous tile is done with the LDS buffers
+
     const Tile T = A.tiles[ti];
     const DomainDesc D = A.doms[T.dom];
     const int tid = threadIdx.y * BX + threadIdx.x;
@@ -388,6 +399,7 @@ __global__ __launch_bounds__(BX *BY) void k_velocity(const StepArgs A)
             __syncthreads();
         }
     }
+    }  // tile loop
 }
 
 // ---------------------------------------------------------------------------
@@ -416,8 +428,11 @@ __global__ __launch_bounds__(BX *BY) void k_pressure(const StepArgs A)
     const int C = A.class_cap;
     float *s_ik = s_dyn, *s_K = s_dyn + C, *s_tb = s_dyn + 2 * C, *s_a = s_dyn + 3 * C, *s_b = s_dyn + (3 + N) * C;
 
-    const int ti = tile_index(A);
-    if (ti >= A.n_tiles) return;
+    for (int it = 0;; ++it) {
+    const int ti = tile_index(A, it);
+    if (ti < 0) break;
+    if (it > 0) __syncthreads();   // the previous tile is done with the LDS buffers
+
     const Tile T = A.tiles[ti];
     const DomainDesc D = A.doms[T.dom];
     const int tid = threadIdx.y * BX + threadIdx.x;
@@ -625,6 +640,7 @@ __global__ __launch_bounds__(BX *BY) void k_pressure(const StepArgs A)
             __syncthreads();
         }
     }
+    }  // tile loop
 }
 
 // Sources then receivers then the step counter, in one workgroup so the
@@ -650,7 +666,7 @@ template <int NDIM, int N, int BX, int BY, int RY>
 hipError_t launch_pair(bool velocity, const StepArgs &a, hipStream_t s)
 {
     const dim3 block(BX, BY);
-    const dim3 grid(8 * a.tiles_per_xcd);
+    const dim3 grid(8 * a.blocks_per_xcd);
     const size_t lds = (size_t)a.class_cap * (velocity ? 2 + 2 * N : 3 + 2 * N) * sizeof(float);
     if (velocity)
         k_velocity<NDIM, N, BX, BY, RY><<<grid, block, lds, s>>>(a);

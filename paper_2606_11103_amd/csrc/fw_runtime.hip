@@ -100,7 +100,7 @@ struct fw_sim {
     int64_t n_src = 0, n_rec = 0;
     int n_t = 0, n_t_max = 0;
     // options
-    int graph_steps = 16, march_chunk = 0, tile_rows = 16, rows_per_thread = 1;
+    int graph_steps = 16, march_chunk = 0, tile_rows = 16, rows_per_thread = 1, persistent = 0;
     // stepping
     int64_t host_step = 0;
     hipStream_t cap_stream = nullptr;
@@ -252,6 +252,8 @@ fw::StepArgs step_args(const fw_sim *s)
     a.pml_tab = s->d_pml.as<float>();
     a.n_tiles = s->n_tiles;
     a.tiles_per_xcd = s->tiles_per_xcd;
+    a.blocks_per_xcd = s->persistent > 0 ? std::max(1, std::min(s->tiles_per_xcd, s->persistent * 32))
+                                         : s->tiles_per_xcd;
     a.pml = s->pml;
     int cap = 1;
     for (const auto &d : s->doms) cap = std::max(cap, (int)d.n_classes);
@@ -728,7 +730,7 @@ int fw_save_state(fw_sim *sim, void *d_dst, void *hip_stream)
     if (!sim->ws) return fail(FW_ESTATE, "no workspace bound");
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     char *dst = static_cast<char *>(d_dst);
-    HIP_OR_FAIL(hipMemcpyAsync(dst, sim->ws, (size_t)sim->state_end, hipMemcpyDeviceToDevice, st));
+    HIP_OR_FAIL(fw::launch_copy(dst, sim->ws, sim->state_end, st));
     HIP_OR_FAIL(hipMemcpyAsync(dst + sim->state_end, sim->d_step.ptr, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
     return FW_OK;
 }
@@ -740,7 +742,7 @@ int fw_load_state(fw_sim *sim, const void *d_src, void *hip_stream)
     if (!sim->ws) return fail(FW_ESTATE, "no workspace bound");
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     const char *src = static_cast<const char *>(d_src);
-    HIP_OR_FAIL(hipMemcpyAsync(sim->ws, src, (size_t)sim->state_end, hipMemcpyDeviceToDevice, st));
+    HIP_OR_FAIL(fw::launch_copy(sim->ws, src, sim->state_end, st));
     HIP_OR_FAIL(hipMemcpyAsync(sim->d_step.ptr, src + sim->state_end, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
     int64_t step = 0;
     HIP_OR_FAIL(hipMemcpyAsync(&step, src + sim->state_end, sizeof(int64_t), hipMemcpyDeviceToHost, st));
@@ -811,8 +813,7 @@ extern "C" int fw_energy_step(fw_sim *sim, double *out, void *hip_stream)
     const fw::StepArgs a = step_args(sim);
     const fw::SrcRecArgs r = srcrec_args(sim);
     HIP_OR_FAIL(fw::launch_velocity(sim->ndim, sim->nmech, sim->tile_rows, sim->rows_per_thread, a, st));
-    HIP_OR_FAIL(hipMemcpyAsync(sim->d_pold.ptr, a.f.p, (size_t)sim->total_cells * sizeof(float),
-                               hipMemcpyDeviceToDevice, st));
+    HIP_OR_FAIL(fw::launch_copy(sim->d_pold.ptr, a.f.p, sim->total_cells * (int64_t)sizeof(float), st));
     HIP_OR_FAIL(fw::launch_pressure(sim->ndim, sim->nmech, sim->tile_rows, sim->rows_per_thread, a, st));
     HIP_OR_FAIL(fw::launch_src_rec(r, st));
     HIP_OR_FAIL(fw::launch_energy(sim->ndim, a, sim->d_pold.as<float>(), sim->d_partial.as<double>(), st));
@@ -860,7 +861,7 @@ extern "C" int64_t fw_adjoint_workspace_bytes(const fw_sim *sim, int n_steps, in
 
 static int copy_state(fw_sim *s, char *dst, const char *src, hipStream_t st, bool with_step)
 {
-    HIP_OR_FAIL(hipMemcpyAsync(dst, src, (size_t)s->state_end, hipMemcpyDeviceToDevice, st));
+    HIP_OR_FAIL(fw::launch_copy(dst, src, s->state_end, st));
     (void)with_step;
     return FW_OK;
 }
@@ -958,6 +959,14 @@ extern "C" int fw_adjoint(fw_sim *sim, int n_steps, int ckpt_every, void *d_work
     return FW_OK;
 }
 
+int fw_device_copy(void *d_dst, const void *d_src, int64_t bytes, void *hip_stream)
+{
+    g_err.clear();
+    if (bytes < 0 || (bytes > 0 && (!d_dst || !d_src))) return fail(FW_EINVAL, "bad copy arguments");
+    HIP_OR_FAIL(fw::launch_copy(d_dst, d_src, bytes, static_cast<hipStream_t>(hip_stream)));
+    return FW_OK;
+}
+
 int fw_set_option(fw_sim *sim, int key, int64_t value)
 {
     g_err.clear();
@@ -978,6 +987,11 @@ int fw_set_option(fw_sim *sim, int key, int64_t value)
         if (value == 4 && sim->rows_per_thread == 2) return fail(FW_EINVAL, "4-row tiles use one row per thread");
         sim->tile_rows = (int)value;
         sim->tiles_dirty = true;
+        return FW_OK;
+    case FW_OPT_PERSISTENT:
+        if (value < 0 || value > 64) return fail(FW_EINVAL, "persistent blocks per CU must be in 0..64");
+        sim->persistent = (int)value;
+        sim->drop_graph();
         return FW_OK;
     case FW_OPT_ROWS_PER_THREAD:
         if (value != 1 && value != 2) return fail(FW_EINVAL, "rows per thread must be 1 or 2");

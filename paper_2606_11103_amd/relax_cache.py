@@ -15,11 +15,13 @@ def main():
         ("2d_two_layer", configs.two_layer_2d(64, 10, n_rec=2), 4),
         ("3d_heterogeneous", configs.heterogeneous_3d(shape=(64, 64, 64), steps=10, n_elem=4), 4),
     ]
+    if "--adjoint" in sys.argv:
+        jobs = [("2d_adjoint", configs.adjoint_2d(n=64, n_shots=1, steps=10, n_rec=4, pml=8), 4)]
     if "--sweep" in sys.argv:
         jobs.append(("1d_sweep", configs.sweep_1d(n_cells=64, steps=10, pml=8), 2))
     for name, case, N in jobs:
         t = time.time()
-        _, _, _, fits = relax.tables_for(dict(c=case.c, alpha0=case.alpha0, y=case.y), N, processes=6)
+        _, _, _, fits = relax.tables_for(dict(c=case.c, alpha0=case.alpha0, y=case.y), N, processes=int(next((a.split('=')[1] for a in sys.argv if a.startswith('--procs=')), 6)))
         print("%-18s N=%d classes=%d  %.1f s  model NRMSE %s" % (
             name, N, len(fits), time.time() - t, ["%.4f" % f["nrmse"] for f in fits]), flush=True)
 

@@ -89,15 +89,38 @@ def test_graph_and_eager_paths_are_bitwise_identical():
 
 
 def test_tiling_does_not_change_results():
-    from paper_2606_11103_amd.native import FW_OPT_MARCH_CHUNK, FW_OPT_ROWS_PER_THREAD, FW_OPT_TILE_ROWS
+    from paper_2606_11103_amd.native import (FW_OPT_MARCH_CHUNK, FW_OPT_PERSISTENT, FW_OPT_ROWS_PER_THREAD,
+                                             FW_OPT_TILE_ROWS)
     case = _case("3d_random_N2_ragged")
     _, ref = _run(case, opts={FW_OPT_TILE_ROWS: 16})
-    for rows, rpt, chunk in ((4, 1, 0), (8, 1, 8), (8, 2, 13), (16, 2, 0), (16, 1, 9)):
-        opts = {FW_OPT_TILE_ROWS: rows, FW_OPT_ROWS_PER_THREAD: rpt}
+    for rows, rpt, chunk, pers in ((4, 1, 0, 0), (8, 1, 8, 0), (8, 2, 13, 1), (16, 2, 0, 0), (16, 1, 9, 2)):
+        opts = {FW_OPT_TILE_ROWS: rows, FW_OPT_ROWS_PER_THREAD: rpt, FW_OPT_PERSISTENT: pers}
         if chunk:
             opts[FW_OPT_MARCH_CHUNK] = chunk
         _, got = _run(case, opts=opts)
-        assert np.array_equal(ref, got), (rows, rpt, chunk)
+        assert np.array_equal(ref, got), (rows, rpt, chunk, pers)
+
+
+def test_persistent_grid_on_batched_2d_and_1d():
+    from paper_2606_11103_amd.native import FW_OPT_MARCH_CHUNK, FW_OPT_PERSISTENT
+    for name in ("2d_batched_N3", "1d_batched_N2"):
+        case = _case(name)
+        _, ref = _run(case)
+        _, got = _run(case, opts={FW_OPT_PERSISTENT: 1, FW_OPT_MARCH_CHUNK: 16})
+        assert np.array_equal(ref, got), name
+
+
+def test_autotuner_keeps_results(tmp_path):
+    from paper_2606_11103_amd.autotune import autotune
+    case = _case("3d_random_N4")
+    _, ref = _run(case)
+    sim = to_simulation(case)
+    sim.step(20)
+    cfg, timings = autotune(sim, steps=2, cache_path=str(tmp_path / "tune.json"))
+    assert len(timings) >= 10 and cfg in [__import__("json").loads(k) for k in timings]
+    assert sim.get_step() == 20
+    sim.step(case.n_steps - 20)
+    assert np.array_equal(sim.read_receivers(), ref)
 
 
 def test_batched_domains_equal_single_runs():

@@ -238,3 +238,66 @@ def sweep_1d(n_cells=8192, nmech=2, steps=None, alpha0=None, y=None, c=1540.0, r
         src_wave=np.zeros(nd, np.int32), waves=wave[None, :],
         rec_domain=np.repeat(np.arange(nd, dtype=np.int32), rc.size), rec_cell=np.tile(rc, nd).astype(np.int64),
         n_steps=steps)
+
+
+def batched_2d(n_shots=64, steps=3000, seed0=4000, nmech=4):
+    """Batched 2D shots: square grids with side uniform in 384..1536 (seed
+    4000 + s), dx = 50 um, 24-cell CPML, 4 horizontal layers at sorted
+    U(0.2, 0.8) L with classes drawn from the 3D tissue ranges (no speed
+    perturbation), N = 4, common dt = 0.4 dx / 1650, point source at
+    (U[L/4, 3L/4], 28) (3 MHz, 3 cycles), 64 receivers along row 28."""
+    dx = 5e-5
+    dt = 0.4 * dx / 1650.0
+    P = 24
+    shapes, maps, base = [], [], []
+    cols = {k: [] for k in ("c", "rho", "alpha0", "y", "b_over_a")}
+    sd, sc, rd, rc = [], [], [], []
+    for s in range(n_shots):
+        rng = np.random.default_rng(seed0 + s)
+        L = int(rng.integers(384, 1537))
+        shp = (L, L, 1)
+        bounds = np.sort(rng.uniform(0.2, 0.8, size=3)) * L
+        maps.append(layered_labels((1, L, L), bounds.astype(int), axis=1))
+        cls = draw_tissue_classes(4, seed0 + 1000 + s)
+        for k in cols:
+            cols[k].append(cls[k])
+        base.append(4 * s)
+        shapes.append(shp)
+        sx = int(rng.integers(L // 4, 3 * L // 4))
+        sd.append(s)
+        sc.append(int(linear_index(shp, sx, 28)))
+        xs = np.linspace(P + 1, L - P - 2, 64).astype(int)
+        rd.extend([s] * 64)
+        rc.extend(linear_index(shp, xs, 28).tolist())
+    waves = tone_burst(steps, dt, 3e6, 3, amplitude=1e5)[None, :]
+    return Case(
+        name="2d_batched_%dshots" % n_shots, ndim=2, shapes=shapes, dx=dx, dt=dt, nmech=nmech, pml_cells=P,
+        class_maps=maps, class_base=base, c=np.concatenate(cols["c"]), rho=np.concatenate(cols["rho"]),
+        alpha0=np.concatenate(cols["alpha0"]), y=np.concatenate(cols["y"]),
+        b_over_a=np.concatenate(cols["b_over_a"]), nonlinear=True,
+        src_domain=np.array(sd, np.int32), src_cell=np.array(sc, np.int64), src_wave=np.zeros(len(sd), np.int32),
+        waves=waves, rec_domain=np.array(rd, np.int32), rec_cell=np.array(rc, np.int64), n_steps=steps)
+
+
+def adjoint_2d(n=1024, n_shots=16, steps=3000, seed=5, n_rec=128, pml=24):
+    """Adjoint workload: n x n (1024 x 1024) with a 24-cell CPML, dx = 50 um,
+    6-class smoothed label field (seed 5) with classes from the 3D tissue
+    ranges, N = 4, linear; 16 point-source shots evenly spaced on row 28
+    (one domain per shot, same medium), 128 receivers on row 28, 3000 steps."""
+    dx = 5e-5
+    cls = draw_tissue_classes(6, seed)
+    dt = 0.4 * dx / 1650.0
+    lab = smoothed_label_field((1, n, n), 6, seed, coarse=4, sigma=5.0)
+    shp = (n, n, 1)
+    xs = np.linspace(pml + 8, n - pml - 9, n_shots).astype(int)
+    rx = np.linspace(pml + 1, n - pml - 2, n_rec).astype(int)
+    rd = np.repeat(np.arange(n_shots, dtype=np.int32), n_rec)
+    rc = np.tile(linear_index(shp, rx, 28), n_shots)
+    waves = tone_burst(steps, dt, 2.5e6, 3, amplitude=1e5)[None, :]
+    return Case(
+        name="2d_adjoint_%dx%d_%dshots" % (n, n, n_shots), ndim=2, shapes=[shp] * n_shots, dx=dx, dt=dt, nmech=4,
+        pml_cells=pml, class_maps=[lab] * n_shots, class_base=[0] * n_shots,
+        c=cls["c"], rho=cls["rho"], alpha0=cls["alpha0"], y=cls["y"], b_over_a=cls["b_over_a"], nonlinear=False,
+        src_domain=np.arange(n_shots, dtype=np.int32), src_cell=linear_index(shp, xs, 28).astype(np.int64),
+        src_wave=np.zeros(n_shots, np.int32), waves=waves, rec_domain=rd, rec_cell=rc.astype(np.int64),
+        n_steps=steps)
