@@ -233,6 +233,15 @@ int fw_time_kernels(fw_sim *sim, int n_steps, void *hip_stream, double *avg_ms);
 int fw_energy_step(fw_sim *sim, double *out, void *hip_stream);
 
 /*
+ * Copy one field of one domain (cells in the domain's linear order) to dst
+ * (device memory if dst_is_device, else host): FW_FIELD_P the pressure,
+ * FW_FIELD_VX/VY/VZ the velocity at faces i+1/2 (stored at cell i).
+ * Synchronises the stream.
+ */
+enum { FW_FIELD_P = 0, FW_FIELD_VX = 1, FW_FIELD_VY = 2, FW_FIELD_VZ = 3 };
+int fw_read_field(fw_sim *sim, int field, int domain, float *dst, int dst_is_device, void *hip_stream);
+
+/*
  * Streaming device-to-device copy of bytes bytes on hip_stream (used for
  * state snapshots and checkpoints).  16-byte aligned pointers and sizes use a
  * float4 grid-stride kernel, anything else hipMemcpyAsync.  Asynchronous.

@@ -84,6 +84,13 @@ def speed_noise(ncell, amp, seed):
     return amp * (2.0 * u - 1.0)
 
 
+def crop_noise(index, amp, seed):
+    """speed_noise at arbitrary (full-domain) linear indices."""
+    idx = np.asarray(index, dtype=np.uint64)
+    u = (splitmix64(idx ^ np.uint64(seed)) >> np.uint64(40)).astype(np.float64) * 2.0 ** -24
+    return amp * (2.0 * u - 1.0)
+
+
 def pml_profile(n, P, dx, dt, R0, f_alpha, c_ref, staggered):
     """CPML recursion coefficients (a, b) along one axis of n points.
     staggered=True gives the faces (positions i + 1/2), else the cells."""
@@ -133,7 +140,7 @@ class OracleSim:
 
     def __init__(self, ndim, shape, dx, dt, nmech, class_map, c, rho, beta,
                  kappa, d, alpha, pml_cells=0, pml_R0=1e-4, pml_f_alpha=1e6, pml_c_ref=None,
-                 noise_amp=0.0, noise_seed=0, d_scale=None):
+                 noise_amp=0.0, noise_seed=0, d_scale=None, noise_index=None, axis_full=None):
         self.ndim = int(ndim)
         nx, ny, nz = (list(shape) + [1, 1, 1])[:3]
         self.shape = (int(nx), int(ny), int(nz))
@@ -147,7 +154,12 @@ class OracleSim:
         kappa = np.asarray(kappa, dtype=np.float64).reshape(-1, 2)
         d = np.asarray(d, dtype=np.float64).reshape(-1, 2, self.N)
         alpha = np.asarray(alpha, dtype=np.float64).reshape(-1, 2, self.N)
-        eps = speed_noise(self.nc, noise_amp, noise_seed) if noise_amp else np.zeros(self.nc)
+        # a crop of a larger domain: noise keyed by the full-domain linear
+        # index, CPML profiles of the full axes restricted to the crop
+        if noise_amp and noise_index is not None:
+            eps = crop_noise(np.asarray(noise_index).reshape(-1), noise_amp, noise_seed)
+        else:
+            eps = speed_noise(self.nc, noise_amp, noise_seed) if noise_amp else np.zeros(self.nc)
         cv = c[cls] * (1.0 + eps)
         self.rho = np.ascontiguousarray(rho[cls])
         self.c_voxel = cv
@@ -175,8 +187,11 @@ class OracleSim:
         pm = {k: np.zeros((3, self.nmax)) for k in ("aF", "bF", "aC", "bC")}
         for a in range(self.ndim):
             n_a = self.shape[a]
-            pm["aF"][a, :n_a], pm["bF"][a, :n_a] = pml_profile(n_a, pml_cells, dx, dt, pml_R0, pml_f_alpha, cref, True)
-            pm["aC"][a, :n_a], pm["bC"][a, :n_a] = pml_profile(n_a, pml_cells, dx, dt, pml_R0, pml_f_alpha, cref, False)
+            n_full, o = (n_a, 0) if axis_full is None else axis_full[a]
+            aF, bF = pml_profile(n_full, pml_cells, dx, dt, pml_R0, pml_f_alpha, cref, True)
+            aC, bC = pml_profile(n_full, pml_cells, dx, dt, pml_R0, pml_f_alpha, cref, False)
+            pm["aF"][a, :n_a], pm["bF"][a, :n_a] = aF[o:o + n_a], bF[o:o + n_a]
+            pm["aC"][a, :n_a], pm["bC"][a, :n_a] = aC[o:o + n_a], bC[o:o + n_a]
         self.pml = {k: np.ascontiguousarray(v) for k, v in pm.items()}
         self.reset()
 

@@ -959,6 +959,30 @@ extern "C" int fw_adjoint(fw_sim *sim, int n_steps, int ckpt_every, void *d_work
     return FW_OK;
 }
 
+int fw_read_field(fw_sim *sim, int field, int domain, float *dst, int dst_is_device, void *hip_stream)
+{
+    g_err.clear();
+    if (!sim || !dst) return fail(FW_EINVAL, "NULL argument");
+    if (!sim->ws) return fail(FW_ESTATE, "no workspace bound");
+    if (domain < 0 || domain >= sim->n_domains) return fail(FW_EINVAL, "domain %d out of range", domain);
+    const fw::Fields f = fields_of(sim);
+    const float *src = nullptr;
+    switch (field) {
+    case FW_FIELD_P: src = f.p; break;
+    case FW_FIELD_VX: src = f.vx; break;
+    case FW_FIELD_VY: src = sim->ndim >= 2 ? f.vy : nullptr; break;
+    case FW_FIELD_VZ: src = sim->ndim >= 3 ? f.vz : nullptr; break;
+    default: break;
+    }
+    if (!src) return fail(FW_EINVAL, "field %d does not exist in %dD", field, sim->ndim);
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const size_t n = (size_t)sim->cells(domain);
+    HIP_OR_FAIL(hipMemcpyAsync(dst, src + sim->doms[domain].cell_off, n * sizeof(float),
+                               dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+    HIP_OR_FAIL(hipStreamSynchronize(st));
+    return FW_OK;
+}
+
 int fw_device_copy(void *d_dst, const void *d_src, int64_t bytes, void *hip_stream)
 {
     g_err.clear();

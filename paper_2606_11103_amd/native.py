@@ -14,6 +14,8 @@ FW_OK, FW_EINVAL, FW_ESTATE, FW_EUNSTABLE, FW_EHIP, FW_ENOMEM, FW_ENONFINITE, FW
     0, -1, -2, -3, -4, -5, -6, -7
 FW_OPT_GRAPH_STEPS, FW_OPT_MARCH_CHUNK, FW_OPT_TILE_ROWS, FW_OPT_ROWS_PER_THREAD, FW_OPT_PERSISTENT = 1, 2, 3, 4, 5
 
+FW_FIELD_P, FW_FIELD_VX, FW_FIELD_VY, FW_FIELD_VZ = 0, 1, 2, 3
+
 _NAMES = {0: "FW_OK", -1: "FW_EINVAL", -2: "FW_ESTATE", -3: "FW_EUNSTABLE", -4: "FW_EHIP",
           -5: "FW_ENOMEM", -6: "FW_ENONFINITE", -7: "FW_EUNSUPPORTED"}
 
@@ -45,6 +47,7 @@ SIGNATURES = {
     "fw_adjoint_workspace_bytes": (_L, [_P, _I, _I]),
     "fw_energy_step": (_I, [_P, _P, _P]),
     "fw_device_copy": (_I, [_P, _P, _L, _P]),
+    "fw_read_field": (_I, [_P, _I, _I, _P, _I, _P]),
     "fw_forward_checkpointed": (_I, [_P, _I, _I, _P, _L, _P]),
     "fw_adjoint": (_I, [_P, _I, _I, _P, _L, _P, _P, _P, _P]),
 }

@@ -100,6 +100,19 @@ class Simulation:
                                         self._stream(stream)))
         return out
 
+    def read_field(self, field=0, domain=0, device=False, stream=None):
+        """One field of one domain (0 pressure, 1..3 velocity x/y/z), shaped
+        (nz, ny, nx); a torch device tensor if device else a numpy array."""
+        nx, ny, nz = self.shapes[domain]
+        if device:
+            out = self.torch.empty((nz, ny, nx), dtype=self.torch.float32, device=self.device)
+            check(lib.fw_read_field(self._h, int(field), int(domain), ctypes.c_void_p(out.data_ptr()), 1,
+                                    self._stream(stream)))
+            return out
+        out = np.empty((nz, ny, nx), dtype=np.float32)
+        check(lib.fw_read_field(self._h, int(field), int(domain), _ptr(out), 0, self._stream(stream)))
+        return out
+
     def reset(self, stream=None):
         check(lib.fw_reset_state(self._h, self._stream(stream)))
 

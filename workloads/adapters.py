@@ -51,3 +51,30 @@ def oracle_traces(case, n_steps=None, energy=False):
         rec, _ = sim.run(n, case.src_cell[sm], waves, case.rec_cell[rm])
         out[:, rm] = rec
     return out
+
+
+def to_oracle_crop(case, lo, hi, domain=0):
+    """Oracle for the box [lo, hi) (x, y, z cell bounds) of one domain: class
+    map, speed perturbation (keyed by the full-domain index) and CPML
+    profiles of the full axes restricted to the box.  Valid while the field
+    is zero outside the box (e.g. a few steps after the sources start)."""
+    from oracle.solver import OracleSim, beta_from_b_over_a
+    nx, ny, nz = case.shapes[domain]
+    lo = [int(v) for v in lo]
+    hi = [int(v) for v in hi]
+    cm = case.class_maps[domain][lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
+    zz, yy, xx = np.meshgrid(np.arange(lo[2], hi[2]), np.arange(lo[1], hi[1]), np.arange(lo[0], hi[0]),
+                             indexing="ij")
+    full_index = (zz.astype(np.int64) * ny + yy) * nx + xx
+    b = case.class_base[domain]
+    nloc = int(case.class_maps[domain].max()) + 1
+    sl = slice(b, b + nloc)
+    beta = beta_from_b_over_a(case.b_over_a[sl]) if case.nonlinear else np.zeros(nloc)
+    pp = case.pml_params or (1e-4, 1e6, 0.0)
+    cref = pp[2] if pp[2] > 0 else float(np.max(case.c))
+    shape = (hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2])
+    axis_full = [(nx, lo[0]), (ny, lo[1]), (nz, lo[2])]
+    return OracleSim(case.ndim, shape, case.dx, case.dt, case.nmech, cm, case.c[sl], case.rho[sl], beta,
+                     case.kappa[sl], case.d[sl], case.alpha[sl], pml_cells=case.pml_cells, pml_R0=pp[0],
+                     pml_f_alpha=pp[1], pml_c_ref=cref, noise_amp=case.noise_amp, noise_seed=case.noise_seed,
+                     noise_index=full_index, axis_full=axis_full)
