@@ -235,6 +235,8 @@ def main():
     ap.add_argument("--small", action="store_true", help="reduced grid for quick checks (not the benchmark)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched and adjoint comparisons")
+    ap.add_argument("--only", choices=("batched", "adjoint"), default=None,
+                    help="run only one comparison workload and print its JSON (profiling)")
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--march-chunk", type=int, default=0)
     ap.add_argument("--rows-per-thread", type=int, default=0)
@@ -249,6 +251,11 @@ def main():
     import torch
     if args.copy_probe > 0:
         copy_probe(torch, args.copy_probe, max(args.steps, 1))
+        return
+    if args.only:
+        torch.cuda.set_device(0)
+        fn = bench_batched if args.only == "batched" else bench_adjoint
+        print(json.dumps(fn(torch)), flush=True)
         return
     from paper_2606_11103_amd.native import FW_OPT_MARCH_CHUNK, FW_OPT_ROWS_PER_THREAD, FW_OPT_TILE_ROWS
     from workloads.adapters import to_simulation

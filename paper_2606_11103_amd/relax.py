@@ -156,19 +156,25 @@ def tables_for(classes, nmech, maxiter=50000, allow_fit=True, processes=None, pa
         if not allow_fit:
             raise KeyError("relaxation tables missing from cache: %d classes" % len(todo))
         jobs = [v for _, v in todo]
-        if len(jobs) > 1:
-            import multiprocessing as mp
-            with mp.get_context("fork").Pool(processes or min(8, os.cpu_count() or 1)) as pool:
-                out = pool.map(_fit_job, jobs)
-        else:
-            out = [_fit_job(jobs[0])]
-        cache = load_cache(path)
-        cache.update(dict(out))
-        os.makedirs(os.path.dirname(path), exist_ok=True)
-        tmp = path + ".tmp%d" % os.getpid()
-        with open(tmp, "w") as fh:
-            json.dump(cache, fh, indent=0, sort_keys=True)
-        os.replace(tmp, path)
+        nproc = processes or min(8, os.cpu_count() or 1)
+        # fit in chunks and write the cache after each, so that an interrupted
+        # run keeps what it has finished
+        chunk = max(1, 4 * nproc)
+        for start in range(0, len(jobs), chunk):
+            part = jobs[start:start + chunk]
+            if len(part) > 1:
+                import multiprocessing as mp
+                with mp.get_context("fork").Pool(min(nproc, len(part))) as pool:
+                    out = pool.map(_fit_job, part)
+            else:
+                out = [_fit_job(part[0])]
+            cache = load_cache(path)
+            cache.update(dict(out))
+            os.makedirs(os.path.dirname(path), exist_ok=True)
+            tmp = path + ".tmp%d" % os.getpid()
+            with open(tmp, "w") as fh:
+                json.dump(cache, fh, indent=0, sort_keys=True)
+            os.replace(tmp, path)
     fits = [cache[k] for k in keys]
     kappa = np.array([f["kappa"] for f in fits], dtype=np.float64)
     d = np.array([f["d"] for f in fits], dtype=np.float64)

@@ -1,0 +1,85 @@
+"""1D plane-wave sweep (544 domains, alpha0 x y grid, N = 2) in one batched
+launch: simulated attenuation and dispersion against the power law and the
+Kramers-Kronig phase velocity, measured as in Sec. 4.1-4.2 (two receivers
+at 0.05 D and 0.8 D, D = 10 wavelengths, 8 centre frequencies 1-20 MHz)."""
+import numpy as np
+import pytest
+
+from workloads import configs
+from workloads.adapters import to_simulation
+
+pytestmark = pytest.mark.gpu
+
+
+def _report(line):
+    import os
+    os.makedirs("gpurun_out", exist_ok=True)
+    with open(os.path.join("gpurun_out", "parity.txt"), "a") as fh:
+        fh.write(line + "\n")
+    print(line, flush=True)
+
+
+def measure(case, traces):
+    """Per domain: simulated alpha (Np/m) and phase speed (m/s) at the 8
+    measurement frequencies from the receiver pair nearest to 0.05 D and
+    0.8 D of each frequency."""
+    from oracle import analytic
+    nd = len(case.shapes)
+    rec_cells = case.rec_cell[case.rec_domain == 0]
+    src = int(case.src_cell[0])
+    nt = traces.shape[0]
+    pad = 4 * nt
+    f = np.fft.rfftfreq(pad, case.dt)
+    F = np.fft.rfft(traces.astype(np.float64), n=pad, axis=0)
+    alpha = np.zeros((nd, len(configs.SWEEP_FREQS)))
+    cph = np.zeros_like(alpha)
+    c0 = case.c[0]
+    for k, fk in enumerate(configs.SWEEP_FREQS):
+        D = 10.0 * c0 / fk
+        want = np.array([0.05 * D, 0.8 * D]) / case.dx + src
+        idx = [int(np.argmin(np.abs(rec_cells - w))) for w in want]
+        dist = (rec_cells[idx[1]] - rec_cells[idx[0]]) * case.dx
+        j = int(np.argmin(np.abs(f - fk)))
+        for dom in range(nd):
+            cols = np.nonzero(case.rec_domain == dom)[0]
+            P1, P2 = F[j, cols[idx[0]]], F[j, cols[idx[1]]]
+            alpha[dom, k] = analytic.two_receiver_attenuation(P1, P2, dist)
+            ph = -np.angle(P2 / P1)
+            kc = 2 * np.pi * f[j] / c0
+            ph = ph + 2 * np.pi * np.round((kc * dist - ph) / (2 * np.pi))
+            cph[dom, k] = 2 * np.pi * f[j] * dist / ph
+    return alpha, cph
+
+
+def test_sweep_attenuation_and_dispersion():
+    from oracle import analytic
+    from paper_2606_11103_amd import relax
+    case = configs.sweep_1d()
+    kappa, d, al, fits = relax.tables_for(dict(c=case.c, alpha0=case.alpha0, y=case.y), case.nmech,
+                                          allow_fit=False)
+    configs.with_table(case, kappa, d, al)
+    print("sweep", len(case.shapes), "domains x", case.shapes[0][0], "cells,", case.n_steps, "steps", flush=True)
+    sim = to_simulation(case)
+    sim.step(case.n_steps)
+    traces = sim.read_receivers()
+    assert np.all(np.isfinite(traces))
+    alpha, cph = measure(case, traces)
+    nrmse, disp = [], []
+    valid = np.array([not ft["failed"] for ft in fits])
+    for dom in range(len(case.shapes)):
+        target = analytic.power_law_alpha(configs.SWEEP_FREQS, case.alpha0[dom], case.y[dom])
+        nrmse.append(analytic.nrmse(alpha[dom], target))
+        c_kk = 1.0 / analytic.kk_inv_phase_velocity(configs.SWEEP_FREQS, case.c[dom], 1e6, case.alpha0[dom],
+                                                    case.y[dom])
+        disp.append(np.sqrt(np.mean((cph[dom] - c_kk) ** 2)))
+    nrmse, disp = np.array(nrmse), np.array(disp)
+    ok = valid & (nrmse <= 0.10) & (disp <= 5.0)
+    core = ok & (case.y >= 0.7 - 1e-9) & (case.y <= 1.4 + 1e-9)
+    np.save("gpurun_out/sweep_nrmse.npy", np.stack([case.alpha0, case.y, nrmse, disp, valid]))
+    _report("sweep 544x8192 N=2: valid %d/%d, NRMSE mean %.4f sd %.4f (core y 0.7-1.4: %.4f), "
+            "dispersion RMSE mean %.3f sd %.3f m/s" % (ok.sum(), len(ok), nrmse[ok].mean(), nrmse[ok].std(),
+                                                    nrmse[core].mean(), disp[ok].mean(), disp[ok].std()))
+    assert ok.sum() >= 0.7 * len(ok)
+    assert nrmse[ok].mean() < 0.03
+    assert nrmse[core].mean() < 0.03
+    assert disp[ok].mean() < 5.0
