@@ -65,6 +65,62 @@ __device__ __forceinline__ void store_vec(float *__restrict__ dst, const float (
 // tile range [x C, (x + 1) C), C = tiles_per_xcd; its blocks interleave over
 // that range with stride blocks_per_xcd (one iteration when the grid has a
 // block per tile, several for a persistent grid).
+// Streaming accesses for data each launch touches exactly once (memory
+// variables, own velocity/pressure values): the non-temporal hint lets the
+// caches keep the halo planes that neighbouring tiles read again.
+#ifndef FW_STREAMING
+#define FW_STREAMING 1
+#endif
+typedef float fw_v4f __attribute__((ext_vector_type(4)));
+typedef float fw_v2f __attribute__((ext_vector_type(2)));
+
+template <int N>
+__device__ __forceinline__ void load_stream(const float *__restrict__ src, float (&v)[N])
+{
+#if FW_STREAMING
+    if constexpr (N == 4) {
+        const fw_v4f t = __builtin_nontemporal_load(reinterpret_cast<const fw_v4f *>(src));
+        v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+    } else if constexpr (N == 2) {
+        const fw_v2f t = __builtin_nontemporal_load(reinterpret_cast<const fw_v2f *>(src));
+        v[0] = t.x; v[1] = t.y;
+    } else {
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] = __builtin_nontemporal_load(src + i);
+    }
+#else
+    load_vec<N>(src, v);
+#endif
+}
+
+template <int N>
+__device__ __forceinline__ void store_stream(float *__restrict__ dst, const float (&v)[N])
+{
+#if FW_STREAMING
+    if constexpr (N == 4) {
+        fw_v4f t = {v[0], v[1], v[2], v[3]};
+        __builtin_nontemporal_store(t, reinterpret_cast<fw_v4f *>(dst));
+    } else if constexpr (N == 2) {
+        fw_v2f t = {v[0], v[1]};
+        __builtin_nontemporal_store(t, reinterpret_cast<fw_v2f *>(dst));
+    } else {
+#pragma unroll
+        for (int i = 0; i < N; ++i) __builtin_nontemporal_store(v[i], dst + i);
+    }
+#else
+    store_vec<N>(dst, v);
+#endif
+}
+
+__device__ __forceinline__ void store1_stream(float *__restrict__ dst, float v)
+{
+#if FW_STREAMING
+    __builtin_nontemporal_store(v, dst);
+#else
+    *dst = v;
+#endif
+}
+
 __device__ __forceinline__ int tile_index(const StepArgs &A, int it)
 {
     const int b = blockIdx.x;
@@ -249,7 +305,7 @@ __global__ __launch_bounds__(BX *BY) void k_velocity(const StepArgs A)
 #pragma unroll
             for (int a = 0; a < NDIM; ++a) {
                 v[r][a] = M.v[a][g];
-                load_vec<N>(M.psi1[a] + (size_t)g * N, ps[r][a]);
+                load_stream<N>(M.psi1[a] + (size_t)g * N, ps[r][a]);
                 pp[r][a] = in_slab(coord(r, z, a), extent(a), P) ? M.pP1[a][g] : 0.0f;
             }
         }
@@ -353,7 +409,7 @@ __global__ __launch_bounds__(BX *BY) void k_velocity(const StepArgs A)
                     pc[r][a][nu] = fmaf(s_a[nu * C + L], Da, s_b[nu * C + L] * pc[r][a][nu]);
                     s += pc[r][a][nu];
                 }
-                store_vec<N>(M.psi1[a] + (size_t)g * N, pc[r][a]);
+                store_stream<N>(M.psi1[a] + (size_t)g * N, pc[r][a]);
                 const int c = coord(r, z, a), n = extent(a);
                 if (in_slab(c, n, P)) {
                     const int32_t off = D.pml_off[a];
@@ -363,7 +419,7 @@ __global__ __launch_bounds__(BX *BY) void k_velocity(const StepArgs A)
                     M.pP1[a][g] = qv;
                     s += qv;
                 }
-                M.v[a][g] = fmaf(-m, s, vc[r][a]);
+                store1_stream(M.v[a] + g, fmaf(-m, s, vc[r][a]));
             }
         }
 
@@ -511,7 +567,7 @@ __global__ __launch_bounds__(BX *BY) void k_pressure(const StepArgs A)
             const int g = G.col[r] + z * G.sm;
             pv[r] = M.p[g];
             cl[r] = M.cls[g];
-            load_vec<N>(M.psi2 + (size_t)g * N, ps[r]);
+            load_stream<N>(M.psi2 + (size_t)g * N, ps[r]);
             ox[r] = M.v[0][g];
             if constexpr (NDIM == 3) oy[r] = M.v[1][g];
 #pragma unroll
@@ -593,7 +649,7 @@ __global__ __launch_bounds__(BX *BY) void k_pressure(const StepArgs A)
                 psc[r][nu] = fmaf(s_a[nu * C + L], S, s_b[nu * C + L] * psc[r][nu]);
                 Tt += psc[r][nu];
             }
-            store_vec<N>(M.psi2 + (size_t)g * N, psc[r]);
+            store_stream<N>(M.psi2 + (size_t)g * N, psc[r]);
 #pragma unroll
             for (int a = 0; a < NDIM; ++a) {
                 const int c = coord(r, z, a), n = extent(a);
@@ -615,7 +671,7 @@ __global__ __launch_bounds__(BX *BY) void k_pressure(const StepArgs A)
                 K = K * (f1 * f1);
             }
             const float pn0 = pc[r];
-            M.p[g] = fmaf(-(A.dt * fmaf(s_tb[L], pn0, K)), Tt, pn0);
+            store1_stream(M.p + g, fmaf(-(A.dt * fmaf(s_tb[L], pn0, K)), Tt, pn0));
         }
 
         if (more) {

@@ -8,7 +8,7 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libfw25.so")
+LIB_PATH = os.environ.get("FW25_LIBRARY", os.path.join(_HERE, "libfw25.so"))
 
 FW_OK, FW_EINVAL, FW_ESTATE, FW_EUNSTABLE, FW_EHIP, FW_ENOMEM, FW_ENONFINITE, FW_EUNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6, -7
