@@ -47,7 +47,8 @@ struct Fields {
 };
 
 struct StepArgs {
-    Fields f;
+    Fields f;                  // state read by the step
+    Fields fo;                 // state written by the step (== f: in place)
     const DomainDesc *doms;
     const Tile *tiles;
     const ClassCoef *classes;

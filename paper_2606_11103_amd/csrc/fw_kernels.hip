@@ -148,24 +148,24 @@ struct DomPtrs {
 };
 
 template <int N>
-__device__ __forceinline__ DomPtrs dom_ptrs(const StepArgs &A, const DomainDesc &D)
+__device__ __forceinline__ DomPtrs dom_ptrs(const Fields &F, const DomainDesc &D)
 {
     const int64_t o = D.cell_off;
     DomPtrs d;
-    d.p = A.f.p + o;
-    d.v[0] = A.f.vx + o;
-    d.v[1] = A.f.vy + o;
-    d.v[2] = A.f.vz + o;
-    d.psi1[0] = A.f.psi1x + o * N;
-    d.psi1[1] = A.f.psi1y + o * N;
-    d.psi1[2] = A.f.psi1z + o * N;
-    d.psi2 = A.f.psi2 + o * N;
+    d.p = F.p + o;
+    d.v[0] = F.vx + o;
+    d.v[1] = F.vy + o;
+    d.v[2] = F.vz + o;
+    d.psi1[0] = F.psi1x + o * N;
+    d.psi1[1] = F.psi1y + o * N;
+    d.psi1[2] = F.psi1z + o * N;
+    d.psi2 = F.psi2 + o * N;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        d.pP1[a] = A.f.pP1[a] + o;
-        d.pP2[a] = A.f.pP2[a] + o;
+        d.pP1[a] = F.pP1[a] + o;
+        d.pP2[a] = F.pP2[a] + o;
     }
-    d.cls = A.f.cls + o;
+    d.cls = F.cls + o;
     return d;
 }
 
@@ -240,7 +240,9 @@ __global__ __launch_bounds__(BX *BY) void k_velocity(const StepArgs A)
     }
     TileGeom<NDIM, BX, BY, RY> G;
     G.init(T, D);
-    const DomPtrs M = dom_ptrs<N>(A, D);
+    // state read from A.f, written to A.fo (the same buffers when stepping in place)
+    const DomPtrs M = dom_ptrs<N>(A.f, D);
+    const DomPtrs Mo = dom_ptrs<N>(A.fo, D);
     const int P = A.pml;
 
     // halo slots of this thread: plane-relative offset (-1: outside the
@@ -409,17 +411,17 @@ __global__ __launch_bounds__(BX *BY) void k_velocity(const StepArgs A)
                     pc[r][a][nu] = fmaf(s_a[nu * C + L], Da, s_b[nu * C + L] * pc[r][a][nu]);
                     s += pc[r][a][nu];
                 }
-                store_stream<N>(M.psi1[a] + (size_t)g * N, pc[r][a]);
+                store_stream<N>(Mo.psi1[a] + (size_t)g * N, pc[r][a]);
                 const int c = coord(r, z, a), n = extent(a);
                 if (in_slab(c, n, P)) {
                     const int32_t off = D.pml_off[a];
                     const float aF = A.pml_tab[off + c];
                     const float bF = A.pml_tab[off + n + c];
                     const float qv = fmaf(aF, Da, bF * ppc[r][a]);
-                    M.pP1[a][g] = qv;
+                    Mo.pP1[a][g] = qv;
                     s += qv;
                 }
-                store1_stream(M.v[a] + g, fmaf(-m, s, vc[r][a]));
+                store1_stream(Mo.v[a] + g, fmaf(-m, s, vc[r][a]));
             }
         }
 
@@ -506,8 +508,11 @@ __global__ __launch_bounds__(BX *BY) void k_pressure(const StepArgs A)
     }
     TileGeom<NDIM, BX, BY, RY> G;
     G.init(T, D);
-    const DomPtrs M = dom_ptrs<N>(A, D);
-    const float *__restrict__ vm = NDIM == 3 ? M.v[2] : M.v[1];
+    // p and the memory variables read from A.f, the new velocity and every
+    // write in A.fo (the same buffers when stepping in place)
+    const DomPtrs M = dom_ptrs<N>(A.f, D);
+    const DomPtrs Mo = dom_ptrs<N>(A.fo, D);
+    const float *__restrict__ vm = NDIM == 3 ? Mo.v[2] : Mo.v[1];
     const int P = A.pml;
 
     // halo slots: x-halo of vx (8 per row), then y-halo of vy (8 rows, 3D).
@@ -538,7 +543,7 @@ __global__ __launch_bounds__(BX *BY) void k_pressure(const StepArgs A)
     }
     auto halo_load = [&](int s, int zoff) -> float {
         if (hoff[s] < 0) return 0.0f;
-        return hli[s] >= 0 ? M.v[0][zoff + hoff[s]] : M.v[1][zoff + hoff[s]];
+        return hli[s] >= 0 ? Mo.v[0][zoff + hoff[s]] : Mo.v[1][zoff + hoff[s]];
     };
     auto halo_store = [&](int buf, int s, float val) {
         if (hli[s] >= 0) {
@@ -568,8 +573,8 @@ __global__ __launch_bounds__(BX *BY) void k_pressure(const StepArgs A)
             pv[r] = M.p[g];
             cl[r] = M.cls[g];
             load_stream<N>(M.psi2 + (size_t)g * N, ps[r]);
-            ox[r] = M.v[0][g];
-            if constexpr (NDIM == 3) oy[r] = M.v[1][g];
+            ox[r] = Mo.v[0][g];
+            if constexpr (NDIM == 3) oy[r] = Mo.v[1][g];
 #pragma unroll
             for (int a = 0; a < NDIM; ++a) pp[r][a] = in_slab(coord(r, z, a), extent(a), P) ? M.pP2[a][g] : 0.0f;
         }
@@ -649,7 +654,7 @@ __global__ __launch_bounds__(BX *BY) void k_pressure(const StepArgs A)
                 psc[r][nu] = fmaf(s_a[nu * C + L], S, s_b[nu * C + L] * psc[r][nu]);
                 Tt += psc[r][nu];
             }
-            store_stream<N>(M.psi2 + (size_t)g * N, psc[r]);
+            store_stream<N>(Mo.psi2 + (size_t)g * N, psc[r]);
 #pragma unroll
             for (int a = 0; a < NDIM; ++a) {
                 const int c = coord(r, z, a), n = extent(a);
@@ -658,7 +663,7 @@ __global__ __launch_bounds__(BX *BY) void k_pressure(const StepArgs A)
                     const float aC = A.pml_tab[off + 2 * n + c];
                     const float bC = A.pml_tab[off + 3 * n + c];
                     const float qv = fmaf(aC, Dd[a], bC * ppc[r][a]);
-                    M.pP2[a][g] = qv;
+                    Mo.pP2[a][g] = qv;
                     Tt += qv;
                 }
             }
@@ -671,7 +676,7 @@ __global__ __launch_bounds__(BX *BY) void k_pressure(const StepArgs A)
                 K = K * (f1 * f1);
             }
             const float pn0 = pc[r];
-            store1_stream(M.p + g, fmaf(-(A.dt * fmaf(s_tb[L], pn0, K)), Tt, pn0));
+            store1_stream(Mo.p + g, fmaf(-(A.dt * fmaf(s_tb[L], pn0, K)), Tt, pn0));
         }
 
         if (more) {

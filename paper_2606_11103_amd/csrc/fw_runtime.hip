@@ -246,6 +246,7 @@ fw::StepArgs step_args(const fw_sim *s)
 {
     fw::StepArgs a{};
     a.f = fields_of(s);
+    a.fo = a.f;
     a.doms = s->d_doms.as<fw::DomainDesc>();
     a.tiles = s->d_tiles.as<fw::Tile>();
     a.classes = s->d_classes.as<fw::ClassCoef>();
@@ -937,15 +938,22 @@ extern "C" int fw_adjoint(fw_sim *sim, int n_steps, int ckpt_every, void *d_work
     for (int64_t k = nck - 1; k >= 0; --k) {
         const int64_t s0 = k * ckpt_every;
         const int64_t s1 = std::min<int64_t>(s0 + ckpt_every, n_steps);
-        rc = fw_load_state(sim, w + k * SB, hip_stream);
+        // segment states: the checkpoint goes to slot 0 (and the step counter
+        // to the device), then each recomputed step reads slot j and writes
+        // slot j + 1 directly (no copies)
+        rc = copy_state(sim, seg, w + k * SB, st, false);
         if (rc != FW_OK) return rc;
-        rc = copy_state(sim, seg, sim->ws, st, false);
-        if (rc != FW_OK) return rc;
+        HIP_OR_FAIL(hipMemcpyAsync(sim->d_step.ptr, w + k * SB + sim->state_end, sizeof(int64_t),
+                                   hipMemcpyDeviceToDevice, st));
         for (int64_t j = 1; j <= s1 - s0; ++j) {
-            rc = enqueue_steps(sim, 1, st);
-            if (rc != FW_OK) return rc;
-            rc = copy_state(sim, seg + j * SB, sim->ws, st, false);
-            if (rc != FW_OK) return rc;
+            fw::StepArgs a = step_args(sim);
+            a.f = fields_at(sim, seg + (j - 1) * SB);
+            a.fo = fields_at(sim, seg + j * SB);
+            fw::SrcRecArgs r = srcrec_args(sim);
+            r.p = a.fo.p;
+            HIP_OR_FAIL(fw::launch_velocity(sim->ndim, sim->nmech, sim->tile_rows, sim->rows_per_thread, a, st));
+            HIP_OR_FAIL(fw::launch_pressure(sim->ndim, sim->nmech, sim->tile_rows, sim->rows_per_thread, a, st));
+            HIP_OR_FAIL(fw::launch_src_rec(r, st));
         }
         for (int64_t n = s1 - 1; n >= s0; --n) {
             J.step = n;
