@@ -193,9 +193,12 @@ int fw_load_state(fw_sim *sim, const void *d_src, void *hip_stream);
  * Then dJ/dc = 2 rho c (1 + eps)^2 dJ/dK and, when d is taken proportional to
  * alpha0 within a class, dJ/dalpha0 = dJ/ds / alpha0.
  *
- * d_work is a caller-owned device buffer of fw_adjoint_workspace_bytes bytes
- * holding ceil(n_steps / ckpt_every) state checkpoints, ckpt_every + 1
- * recomputed states, the adjoint state and scratch.
+ * d_work is a caller-owned, 256-byte aligned device buffer of
+ * fw_adjoint_workspace_bytes bytes (FW_EINVAL if misaligned, FW_ENOMEM if
+ * smaller) holding ceil(n_steps / ckpt_every) state checkpoints,
+ * ckpt_every + 1 recomputed states, the adjoint state and scratch.
+ * d_grad_K and d_grad_s are accumulated into (the caller zeroes them); they
+ * and d_adj_src must be 4-byte aligned device buffers.
  * fw_forward_checkpointed resets the state, runs n_steps (recording the
  * traces) and stores the checkpoints; fw_adjoint then sweeps the segments
  * last to first, recomputing each segment's states from its checkpoint.

@@ -9,15 +9,22 @@
 //   gs += sum over the recursions owned by the cell of mu (b_s psi^n + a_s D^n),
 // where s scales every d coefficient of the cell (d -> s d) and a_s, b_s are
 // the derivatives of Eqs. (relaxation_a)/(relaxation_b) with respect to s.
-// Three kernels per reverse step:
-//   adj_pressure : pointwise transpose of the pressure update (needs the
-//                  divergence of the forward v^{n+1/2}); writes lamD2_a.
+// Two kernels per reverse step:
+//   adj_pressure : lam_p -= sum_a div_a(lamD1_a) of the reverse step before
+//                  (the last part of the velocity transpose, which needs the
+//                  neighbours' lamD1 and so cannot finish in the kernel that
+//                  writes it), then the pointwise transpose of the pressure
+//                  update (needs the divergence of the forward v^{n+1/2});
+//                  writes lamD2_a.
 //   adj_velocity : lam_v -= grad_a(lamD2_a), transpose of the velocity update
 //                  (needs grad_a of the forward p^n); writes lamD1_a.
-//   adj_gradient : lam_p -= sum_a div_a(lamD1_a).
+// adj_finish applies the last pending lamD1 after the final reverse step.
 // One thread per (x, y) column of a tile, marching the tile's z range with
-// direct global loads (neighbour reads are served by the caches).
+// direct global loads (neighbour reads are served by the caches); the memory
+// variables, gradients and own values, touched once per kernel, use vector
+// non-temporal accesses.
 #include "fw_internal.h"
+#include "fw_vec.h"
 
 namespace fw {
 
@@ -119,6 +126,8 @@ __global__ void k_adj_pressure(const AdjArgs A)
     const int64_t o = D.cell_off;
     const float dt = A.s.dt;
     const int P = A.s.pml;
+    const float *vn[3] = {A.fnext.vx + o, A.fnext.vy + o, A.fnext.vz + o};
+    const float *ld1[3] = {A.lamD1[0] + o, A.lamD1[1] + o, A.lamD1[2] + o};
     for (int z = T.z0; z < T.z1; ++z) {
         at_plane<NDIM>(G, z);
         const int g = G.g;
@@ -126,18 +135,30 @@ __global__ void k_adj_pressure(const AdjArgs A)
         const int L = A.s.f.cls[gg];
         const ClassCoef &cc = A.s.classes[D.class_base + L];
         const ClassAdj &ca = A.cadj[D.class_base + L];
+        // lam_p^{n+1}: the pending divergence of the velocity transpose
+        float lp = A.lam.p[gg];
+        if (A.fold_div) {
+            float acc = 0.0f;
+#pragma unroll
+            for (int a = 0; a < NDIM; ++a) acc += div_a(ld1[a], G, a, A.s.fd);
+            lp -= acc;
+            A.lam.p[gg] = lp;
+        }
         // forward divergence of v^{n+1/2} (state u^{n+1})
         float Dd[3] = {0.0f, 0.0f, 0.0f};
-        const float *vn[3] = {A.fnext.vx + o, A.fnext.vy + o, A.fnext.vz + o};
 #pragma unroll
         for (int a = 0; a < NDIM; ++a) Dd[a] = div_a(vn[a], G, a, A.s.fd);
         float S = Dd[0];
 #pragma unroll
         for (int a = 1; a < NDIM; ++a) S += Dd[a];
         // T^n from the updated memory variables of u^{n+1}
+        float psn[N], psf[N], lps[N];
+        load_stream<N>(A.fnext.psi2 + gg * N, psn);
+        load_stream<N>(A.s.f.psi2 + gg * N, psf);
+        load_stream<N>(A.lam.psi2 + gg * N, lps);
         float Tt = cc.ik2 * S;
 #pragma unroll
-        for (int nu = 0; nu < N; ++nu) Tt += A.fnext.psi2[gg * N + nu];
+        for (int nu = 0; nu < N; ++nu) Tt += psn[nu];
 #pragma unroll
         for (int a = 0; a < NDIM; ++a)
             if (slab(G.c[a], G.n[a], P)) Tt += A.fnext.pP2[a][gg];
@@ -149,19 +170,20 @@ __global__ void k_adj_pressure(const AdjArgs A)
             const float f1 = 1.0f + e;
             K = K * (f1 * f1);
         }
-        const float lp = A.lam.p[gg];
         const int64_t pk = D.packed_off + g;
-        A.gK[pk] += lp * (-dt * Tt);
+        const float gk0 = __builtin_nontemporal_load(A.gK + pk);
+        __builtin_nontemporal_store(gk0 + lp * (-dt * Tt), A.gK + pk);
         const float q = -dt * K * lp;
         float gdiv = cc.ik2 * q;
         float gsum = 0.0f;
 #pragma unroll
         for (int nu = 0; nu < N; ++nu) {
-            const float mu = A.lam.psi2[gg * N + nu] + q;
+            const float mu = lps[nu] + q;
             gdiv = fmaf(cc.a2[nu], mu, gdiv);
-            gsum = fmaf(mu, fmaf(ca.a2s[nu], S, ca.b2s[nu] * A.s.f.psi2[gg * N + nu]), gsum);
-            A.lam.psi2[gg * N + nu] = cc.b2[nu] * mu;
+            gsum = fmaf(mu, fmaf(ca.a2s[nu], S, ca.b2s[nu] * psf[nu]), gsum);
+            lps[nu] = cc.b2[nu] * mu;
         }
+        store_stream<N>(A.lam.psi2 + gg * N, lps);
 #pragma unroll
         for (int a = 0; a < NDIM; ++a) {
             float ld = gdiv;
@@ -175,7 +197,8 @@ __global__ void k_adj_pressure(const AdjArgs A)
             }
             A.lamD2[a][gg] = ld;
         }
-        A.gs[pk] += gsum;
+        const float gs0 = __builtin_nontemporal_load(A.gs + pk);
+        __builtin_nontemporal_store(gs0 + gsum, A.gs + pk);
     }
 }
 
@@ -206,17 +229,21 @@ __global__ void k_adj_velocity(const AdjArgs A)
             const int i = G.c[a];
             const int Ln = (i + 1 < G.n[a]) ? A.s.f.cls[gg + G.st[a]] : L;
             const float m = 2.0f * dt / (cc.rho + A.s.classes[D.class_base + Ln].rho);
-            const float lv = lvx[a][gg] - grad_a(A.lamD2[a] + o, G, a, A.s.fd);
+            const float lv = __builtin_nontemporal_load(lvx[a] + gg) - grad_a(A.lamD2[a] + o, G, a, A.s.fd);
             const float r = -m * lv;
             const float D1 = grad_a(A.s.f.p + o, G, a, A.s.fd);
+            float pf[N], pl[N];
+            load_stream<N>(psi1f[a] + gg * N, pf);
+            load_stream<N>(psi1l[a] + gg * N, pl);
             float ld = cc.ik1 * r;
 #pragma unroll
             for (int nu = 0; nu < N; ++nu) {
-                const float mu = psi1l[a][gg * N + nu] + r;
+                const float mu = pl[nu] + r;
                 ld = fmaf(cc.a1[nu], mu, ld);
-                gsum = fmaf(mu, fmaf(ca.a1s[nu], D1, ca.b1s[nu] * psi1f[a][gg * N + nu]), gsum);
-                psi1l[a][gg * N + nu] = cc.b1[nu] * mu;
+                gsum = fmaf(mu, fmaf(ca.a1s[nu], D1, ca.b1s[nu] * pf[nu]), gsum);
+                pl[nu] = cc.b1[nu] * mu;
             }
+            store_stream<N>(psi1l[a] + gg * N, pl);
             if (slab(i, G.n[a], P)) {
                 const int32_t off = D.pml_off[a];
                 const float aF = A.s.pml_tab[off + i];
@@ -225,15 +252,17 @@ __global__ void k_adj_velocity(const AdjArgs A)
                 ld = fmaf(aF, mu, ld);
                 A.lam.pP1[a][gg] = bF * mu;
             }
-            lvx[a][gg] = lv;
+            store1_stream(lvx[a] + gg, lv);
             A.lamD1[a][gg] = ld;
         }
-        A.gs[D.packed_off + g] += gsum;
+        const int64_t pk = D.packed_off + g;
+        const float gs0 = __builtin_nontemporal_load(A.gs + pk);
+        __builtin_nontemporal_store(gs0 + gsum, A.gs + pk);
     }
 }
 
 template <int NDIM>
-__global__ void k_adj_gradient(const AdjArgs A)
+__global__ void k_adj_finish(const AdjArgs A)
 {
     Tile T;
     DomainDesc D;
@@ -274,7 +303,7 @@ hipError_t adj_launch(int which, const AdjArgs &a, hipStream_t s)
     else if (which == 1)
         k_adj_velocity<NDIM, N><<<grid, block, 0, s>>>(a);
     else
-        k_adj_gradient<NDIM><<<grid, block, 0, s>>>(a);
+        k_adj_finish<NDIM><<<grid, block, 0, s>>>(a);
     return hipGetLastError();
 }
 
@@ -290,19 +319,28 @@ hipError_t adj_launch_n(int which, int nmech, const AdjArgs &a, hipStream_t s)
     }
 }
 
+hipError_t adj_launch_dim(int which, int ndim, int nmech, const AdjArgs &a, hipStream_t s)
+{
+    if (ndim == 1) return adj_launch_n<1>(which, nmech, a, s);
+    if (ndim == 2) return adj_launch_n<2>(which, nmech, a, s);
+    if (ndim == 3) return adj_launch_n<3>(which, nmech, a, s);
+    return hipErrorInvalidValue;
+}
+
 }  // namespace
 
 hipError_t launch_adjoint_step(int ndim, int nmech, const AdjArgs &a, hipStream_t s)
 {
     if (a.s.n_tiles <= 0) return hipSuccess;
-    for (int which = 0; which < 3; ++which) {
-        hipError_t e = hipErrorInvalidValue;
-        if (ndim == 1) e = adj_launch_n<1>(which, nmech, a, s);
-        if (ndim == 2) e = adj_launch_n<2>(which, nmech, a, s);
-        if (ndim == 3) e = adj_launch_n<3>(which, nmech, a, s);
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    hipError_t e = adj_launch_dim(0, ndim, nmech, a, s);
+    if (e != hipSuccess) return e;
+    return adj_launch_dim(1, ndim, nmech, a, s);
+}
+
+hipError_t launch_adjoint_finish(int ndim, const AdjArgs &a, hipStream_t s)
+{
+    if (a.s.n_tiles <= 0) return hipSuccess;
+    return adj_launch_dim(2, ndim, 1, a, s);
 }
 
 hipError_t launch_adjoint_inject(const AdjInjectArgs &a, hipStream_t s)

@@ -91,6 +91,8 @@ struct AdjArgs {
     float *gK, *gs;            // gradients, unpadded layout
     const ClassAdj *cadj;
     int32_t tile_rows;
+    int32_t fold_div;          // 1: lamD1 holds the previous reverse step's
+                               //    velocity output, still to be applied to lam_p
 };
 
 struct AdjInjectArgs {
@@ -106,7 +108,11 @@ struct AdjInjectArgs {
 
 hipError_t launch_copy(void *dst, const void *src, int64_t bytes, hipStream_t s);
 hipError_t launch_energy(int ndim, const StepArgs &a, const float *p_old, double *partial, hipStream_t s);
+// one reverse step: transpose of the pressure update (applying a pending
+// lamD1 first when a.fold_div is set), then of the velocity update
 hipError_t launch_adjoint_step(int ndim, int nmech, const AdjArgs &a, hipStream_t s);
+// lam_p -= sum_a div_a(lamD1_a): completes the last reverse step
+hipError_t launch_adjoint_finish(int ndim, const AdjArgs &a, hipStream_t s);
 hipError_t launch_adjoint_inject(const AdjInjectArgs &a, hipStream_t s);
 
 // Launchers (kernels.hip).  Return hipSuccess or the launch error.

@@ -876,6 +876,8 @@ extern "C" int fw_forward_checkpointed(fw_sim *sim, int n_steps, int ckpt_every,
     int rc = adj_layout(sim, n_steps, ckpt_every, &nck, &os, &ol, &oc, &tot);
     if (rc != FW_OK) return rc;
     if (bytes < tot) return fail(FW_ENOMEM, "adjoint workspace too small: %lld < %lld", (long long)bytes, (long long)tot);
+    if ((reinterpret_cast<uintptr_t>(d_work) % kAlignBytes) != 0)
+        return fail(FW_EINVAL, "adjoint workspace must be 256-byte aligned");
     if (!sim->ws || !sim->media_set || !sim->table_set) return fail(FW_ESTATE, "set up the simulation first");
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     char *w = static_cast<char *>(d_work);
@@ -902,6 +904,8 @@ extern "C" int fw_adjoint(fw_sim *sim, int n_steps, int ckpt_every, void *d_work
     int rc = adj_layout(sim, n_steps, ckpt_every, &nck, &os, &ol, &oc, &tot);
     if (rc != FW_OK) return rc;
     if (bytes < tot) return fail(FW_ENOMEM, "adjoint workspace too small: %lld < %lld", (long long)bytes, (long long)tot);
+    if ((reinterpret_cast<uintptr_t>(d_work) % kAlignBytes) != 0)
+        return fail(FW_EINVAL, "adjoint workspace must be 256-byte aligned");
     if (!sim->ws || !sim->media_set || !sim->table_set) return fail(FW_ESTATE, "set up the simulation first");
     for (double b : sim->beta)
         if (b != 0.0) return fail(FW_EUNSUPPORTED, "the adjoint supports linear media only (beta = 0 in every class)");
@@ -927,6 +931,7 @@ extern "C" int fw_adjoint(fw_sim *sim, int n_steps, int ckpt_every, void *d_work
     A.gs = d_grad_s;
     A.cadj = sim->d_cadj.as<fw::ClassAdj>();
     A.tile_rows = sim->tile_rows;
+    A.fold_div = 0;
     fw::AdjInjectArgs J{};
     J.lam_p = A.lam.p;
     J.cells = sim->d_adj_cells.as<int64_t>();
@@ -961,8 +966,10 @@ extern "C" int fw_adjoint(fw_sim *sim, int n_steps, int ckpt_every, void *d_work
             A.s.f = fields_at(sim, seg + (n - s0) * SB);
             A.fnext = fields_at(sim, seg + (n - s0 + 1) * SB);
             HIP_OR_FAIL(fw::launch_adjoint_step(sim->ndim, sim->nmech, A, st));
+            A.fold_div = 1;
         }
     }
+    if (A.fold_div) HIP_OR_FAIL(fw::launch_adjoint_finish(sim->ndim, A, st));
     sim->host_step = n_steps;
     return FW_OK;
 }
