@@ -100,7 +100,8 @@ def model_errors(c, alpha0_db, y, kappa, d, alpha, f_ref=1e6):
 def fit_class(c, alpha0_db, y, nmech=2, weights=WEIGHTS, n_freq=64, band=(1e6, 20e6),
               f_ref=1e6, maxiter=50000, tol=1e-25):
     """Fit one class; returns a dict with kappa [2], d [2][N], alpha [2][N],
-    the chosen weight and the model errors."""
+    the chosen weight and the model errors, plus every weight's candidate
+    under "cands" (for selection by simulated attenuation)."""
     from scipy.optimize import minimize
     N = int(nmech)
     f = np.logspace(math.log10(band[0]), math.log10(band[1]), n_freq)
@@ -108,6 +109,7 @@ def fit_class(c, alpha0_db, y, nmech=2, weights=WEIGHTS, n_freq=64, band=(1e6, 2
     x0 = np.array([1.0, 1.0] + [6.0] * (2 * N) + [9.0] * (2 * N))
     bounds = [(0.98, 1.0)] * 2 + [(2.0, 10.0)] * (2 * N) + [(5.0, 12.0)] * (2 * N)
     best = None
+    cands = []
     for w in weights:
         J = _objective_factory(f, kgt, w, c, N)
         res = minimize(J, x0, method="Nelder-Mead", bounds=bounds,
@@ -117,10 +119,12 @@ def fit_class(c, alpha0_db, y, nmech=2, weights=WEIGHTS, n_freq=64, band=(1e6, 2
         nr, disp = model_errors(c, alpha0_db, y, kappa, d, al, f_ref)
         cand = dict(kappa=kappa.tolist(), d=d.tolist(), alpha=al.tolist(), w=w, J=float(res.fun),
                     nrmse=nr, disp=disp)
+        cands.append(cand)
         if best is None or (nr, disp, w) < (best["nrmse"], best["disp"], best["w"]):
             best = cand
+    best = dict(best)
     best.update(c=float(c), alpha0=float(alpha0_db), y=float(y), nmech=N,
-                failed=bool(best["nrmse"] > 0.10 or best["disp"] > 5.0))
+                failed=bool(best["nrmse"] > 0.10 or best["disp"] > 5.0), cands=cands)
     return best
 
 
