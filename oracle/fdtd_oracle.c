@@ -14,6 +14,10 @@
  *   - the recursion of Eq. (relaxation_psi), psi <- b psi + a D, updated with
  *     the derivative of the same sub-step and then used ("update, then use"),
  *   - one more memory variable per axis for the CPML, same recursion form,
+ *     applied to the tissue-stretched derivative: the CPML stretches the
+ *     coordinate of the lossy medium, so the two stretch factors multiply
+ *     (d/dx~ = (1/s_pml)(1/s_tissue) d/dx), which keeps the layer
+ *     reflectionless and stable for any tissue,
  *   - a pressure-dependent bulk modulus K + 2 beta p for the nonlinearity,
  *   - the 2M-th order staggered stencil (M = 4) with leapfrog time stepping.
  * Every per-voxel coefficient arrives as its own FP64 array; nothing is
@@ -121,7 +125,7 @@ static void step_velocity(ora_sim *s)
                 sum += s->psi1[o];
             }
             const int64_t ia = coord_of(s, idx, a);
-            psiP[idx] = bF[ia] * psiP[idx] + aF[ia] * D;
+            psiP[idx] = bF[ia] * psiP[idx] + aF[ia] * sum;
             sum += psiP[idx];
             va[idx] -= s->dt / rho_face(s, idx, a) * sum;
         }
@@ -147,7 +151,7 @@ static void step_pressure(ora_sim *s)
             }
             const int64_t ia = coord_of(s, idx, a);
             double *psiP = s->psiP2 + (int64_t)a * nc;
-            psiP[idx] = s->pml_bC[a * s->nmax + ia] * psiP[idx] + s->pml_aC[a * s->nmax + ia] * D;
+            psiP[idx] = s->pml_bC[a * s->nmax + ia] * psiP[idx] + s->pml_aC[a * s->nmax + ia] * term;
             term += psiP[idx];
             T += term;
         }
@@ -261,7 +265,7 @@ int oracle_adjoint_step(ora_sim *s,
                 sum += s->b1[c] * s->psi1[o] + s->a1[c] * D;
             }
             const int64_t ia = coord_of(s, idx, a);
-            sum += s->pml_bF[a * s->nmax + ia] * s->psiP1[(int64_t)a * nc + idx] + s->pml_aF[a * s->nmax + ia] * D;
+            sum += s->pml_bF[a * s->nmax + ia] * s->psiP1[(int64_t)a * nc + idx] + s->pml_aF[a * s->nmax + ia] * sum;
             vnew[(int64_t)a * nc + idx] = s->v[(int64_t)a * nc + idx] - s->dt / rho_face(s, idx, a) * sum;
         }
     }
@@ -277,7 +281,7 @@ int oracle_adjoint_step(ora_sim *s,
                 term += s->b2[c] * s->psi2[o] + s->a2[c] * D;
             }
             const int64_t ia = coord_of(s, idx, a);
-            term += s->pml_bC[a * s->nmax + ia] * s->psiP2[(int64_t)a * nc + idx] + s->pml_aC[a * s->nmax + ia] * D;
+            term += s->pml_bC[a * s->nmax + ia] * s->psiP2[(int64_t)a * nc + idx] + s->pml_aC[a * s->nmax + ia] * term;
             Tx += term;
         }
         T[idx] = Tx;
@@ -292,17 +296,19 @@ int oracle_adjoint_step(ora_sim *s,
         q[idx] = qq;
         for (int a = 0; a < nd; ++a) {
             const int64_t ia = coord_of(s, idx, a);
-            double lD = s->ik2[idx] * qq;
+            /* term = Dt + psiP', psiP' = bC psiP + aC Dt: adjoint of Dt */
+            const double muP = lam_psiP2[(int64_t)a * nc + idx] + qq;
+            lam_psiP2[(int64_t)a * nc + idx] = s->pml_bC[a * s->nmax + ia] * muP;
+            const double lDt = qq + s->pml_aC[a * s->nmax + ia] * muP;
+            /* Dt = ik2 D + sum_nu psi2', psi2' = b2 psi2 + a2 D */
+            double lD = s->ik2[idx] * lDt;
             for (int nu = 0; nu < nm; ++nu) {
                 const int64_t o = ((int64_t)a * nm + nu) * nc + idx, c = (int64_t)nu * nc + idx;
-                const double mu = lam_psi2[o] + qq;
+                const double mu = lam_psi2[o] + lDt;
                 lD += s->a2[c] * mu;
                 gs[idx] += mu * (b2s[c] * s->psi2[o] + a2s[c] * D2[(int64_t)a * nc + idx]);
                 lam_psi2[o] = s->b2[c] * mu;
             }
-            const double muP = lam_psiP2[(int64_t)a * nc + idx] + qq;
-            lD += s->pml_aC[a * s->nmax + ia] * muP;
-            lam_psiP2[(int64_t)a * nc + idx] = s->pml_bC[a * s->nmax + ia] * muP;
             lamD2[(int64_t)a * nc + idx] = lD;
         }
     }
@@ -315,18 +321,20 @@ int oracle_adjoint_step(ora_sim *s,
             const double lv = lam_v[fa] - grad_face(s, lamD2 + (int64_t)a * nc, idx, a);
             const double r = -s->dt / rho_face(s, idx, a) * lv;
             const int64_t ia = coord_of(s, idx, a);
-            double lD = s->ik1[idx] * r;
+            /* sum = Dt + psiP', psiP' = bF psiP + aF Dt: adjoint of Dt */
+            const double muP = lam_psiP1[fa] + r;
+            lam_psiP1[fa] = s->pml_bF[a * s->nmax + ia] * muP;
+            const double lDt = r + s->pml_aF[a * s->nmax + ia] * muP;
+            /* Dt = ik1 D + sum_nu psi1', psi1' = b1 psi1 + a1 D */
+            double lD = s->ik1[idx] * lDt;
             double gsum = 0.0;
             for (int nu = 0; nu < nm; ++nu) {
                 const int64_t o = ((int64_t)a * nm + nu) * nc + idx, c = (int64_t)nu * nc + idx;
-                const double mu = lam_psi1[o] + r;
+                const double mu = lam_psi1[o] + lDt;
                 lD += s->a1[c] * mu;
                 gsum += mu * (b1s[c] * s->psi1[o] + a1s[c] * D1[fa]);
                 lam_psi1[o] = s->b1[c] * mu;
             }
-            const double muP = lam_psiP1[fa] + r;
-            lD += s->pml_aF[a * s->nmax + ia] * muP;
-            lam_psiP1[fa] = s->pml_bF[a * s->nmax + ia] * muP;
             lamD1[fa] = lD;
             lam_v[fa] = lv;
             gs[idx] += gsum;     /* face i+1/2 is owned by cell i */

@@ -17,7 +17,10 @@
 //                  update (needs the divergence of the forward v^{n+1/2});
 //                  writes lamD2_a.
 //   adj_velocity : lam_v -= grad_a(lamD2_a), transpose of the velocity update
-//                  (needs grad_a of the forward p^n); writes lamD1_a.
+//                  (needs grad_a of the forward p^n and the forward CPML
+//                  memory variable of u^{n+1}); writes lamD1_a.
+// The CPML stage comes first in the forward operators (D_a + psiP_a, then
+// the tissue stretch), so its transpose comes last here.
 // adj_finish applies the last pending lamD1 after the final reverse step.
 // One thread per (x, y) column of a tile, marching the tile's z range with
 // direct global loads (neighbour reads are served by the caches); the memory
@@ -144,10 +147,14 @@ __global__ void k_adj_pressure(const AdjArgs A)
             lp -= acc;
             A.lam.p[gg] = lp;
         }
-        // forward divergence of v^{n+1/2} (state u^{n+1})
+        // forward divergence of v^{n+1/2} (state u^{n+1}) after the CPML
+        // stage: D_a + psiP2_a^{n+1} in the slab of axis a
         float Dd[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int a = 0; a < NDIM; ++a) Dd[a] = div_a(vn[a], G, a, A.s.fd);
+        for (int a = 0; a < NDIM; ++a) {
+            Dd[a] = div_a(vn[a], G, a, A.s.fd);
+            if (slab(G.c[a], G.n[a], P)) Dd[a] += A.fnext.pP2[a][gg];
+        }
         float S = Dd[0];
 #pragma unroll
         for (int a = 1; a < NDIM; ++a) S += Dd[a];
@@ -159,9 +166,6 @@ __global__ void k_adj_pressure(const AdjArgs A)
         float Tt = cc.ik2 * S;
 #pragma unroll
         for (int nu = 0; nu < N; ++nu) Tt += psn[nu];
-#pragma unroll
-        for (int a = 0; a < NDIM; ++a)
-            if (slab(G.c[a], G.n[a], P)) Tt += A.fnext.pP2[a][gg];
         float K = cc.K;
         if (A.s.noise_amp != 0.0f) {
             const uint64_t h = splitmix64_a(D.noise_seed ^ (uint64_t)(uint32_t)g);
@@ -184,6 +188,8 @@ __global__ void k_adj_pressure(const AdjArgs A)
             lps[nu] = cc.b2[nu] * mu;
         }
         store_stream<N>(A.lam.psi2 + gg * N, lps);
+        // gdiv is the adjoint of the CPML-stretched divergence of each axis;
+        // transpose of D_a + psiP2_a, psiP2_a <- bC psiP2_a + aC D_a
 #pragma unroll
         for (int a = 0; a < NDIM; ++a) {
             float ld = gdiv;
@@ -191,8 +197,8 @@ __global__ void k_adj_pressure(const AdjArgs A)
                 const int32_t off = D.pml_off[a];
                 const float aC = A.s.pml_tab[off + 2 * G.n[a] + G.c[a]];
                 const float bC = A.s.pml_tab[off + 3 * G.n[a] + G.c[a]];
-                const float mu = A.lam.pP2[a][gg] + q;
-                ld = fmaf(aC, mu, ld);
+                const float mu = A.lam.pP2[a][gg] + gdiv;
+                ld = fmaf(aC, mu, gdiv);
                 A.lam.pP2[a][gg] = bC * mu;
             }
             A.lamD2[a][gg] = ld;
@@ -216,6 +222,7 @@ __global__ void k_adj_velocity(const AdjArgs A)
     float *lvx[3] = {A.lam.vx, A.lam.vy, A.lam.vz};
     const float *psi1f[3] = {A.s.f.psi1x, A.s.f.psi1y, A.s.f.psi1z};
     float *psi1l[3] = {A.lam.psi1x, A.lam.psi1y, A.lam.psi1z};
+    const float *pP1n[3] = {A.fnext.pP1[0], A.fnext.pP1[1], A.fnext.pP1[2]};
     for (int z = T.z0; z < T.z1; ++z) {
         at_plane<NDIM>(G, z);
         const int g = G.g;
@@ -231,7 +238,10 @@ __global__ void k_adj_velocity(const AdjArgs A)
             const float m = 2.0f * dt / (cc.rho + A.s.classes[D.class_base + Ln].rho);
             const float lv = __builtin_nontemporal_load(lvx[a] + gg) - grad_a(A.lamD2[a] + o, G, a, A.s.fd);
             const float r = -m * lv;
-            const float D1 = grad_a(A.s.f.p + o, G, a, A.s.fd);
+            // forward gradient of p^n after the CPML stage
+            float D1 = grad_a(A.s.f.p + o, G, a, A.s.fd);
+            const bool sl = slab(i, G.n[a], P);
+            if (sl) D1 += pP1n[a][gg];
             float pf[N], pl[N];
             load_stream<N>(psi1f[a] + gg * N, pf);
             load_stream<N>(psi1l[a] + gg * N, pl);
@@ -244,11 +254,13 @@ __global__ void k_adj_velocity(const AdjArgs A)
                 pl[nu] = cc.b1[nu] * mu;
             }
             store_stream<N>(psi1l[a] + gg * N, pl);
-            if (slab(i, G.n[a], P)) {
+            // ld is the adjoint of the CPML-stretched gradient; transpose of
+            // D + psiP1, psiP1 <- bF psiP1 + aF D
+            if (sl) {
                 const int32_t off = D.pml_off[a];
                 const float aF = A.s.pml_tab[off + i];
                 const float bF = A.s.pml_tab[off + G.n[a] + i];
-                const float mu = A.lam.pP1[a][gg] + r;
+                const float mu = A.lam.pP1[a][gg] + ld;
                 ld = fmaf(aF, mu, ld);
                 A.lam.pP1[a][gg] = bF * mu;
             }

@@ -111,9 +111,13 @@ struct TileGeom {
 // ---------------------------------------------------------------------------
 // Velocity update: for each axis a and face i+1/2,
 //   D = sum_m c_m (p[i+m] - p[i+1-m]) / dx,
+//   psiP    <- bF psiP + aF D,  D <- D + psiP   (inside the CPML slab of a),
 //   psi1_nu <- b1_nu psi1_nu + a1_nu D           (class of the owner cell i),
-//   psiP    <- bF psiP + aF D                    (inside the CPML slab of a),
-//   v_a     -= 2 dt / (rho_i + rho_{i+1}) (D / kappa_1 + sum_nu psi1_nu + psiP).
+//   v_a     -= 2 dt / (rho_i + rho_{i+1}) (D / kappa_1 + sum_nu psi1_nu).
+// The CPML stretch and the tissue stretch are applied one after the other
+// (their product is the stretch of the absorbing layer: the layer stretches
+// the coordinate of the lossy medium itself); as both are linear recursions
+// with fixed coefficients at a point, their order does not matter.
 // ---------------------------------------------------------------------------
 template <int NDIM, int N, int BX, int BY, int RY>
 __global__ __launch_bounds__(BX *BY) void k_velocity(const StepArgs A)
@@ -320,7 +324,18 @@ __global__ __launch_bounds__(BX *BY) void k_velocity(const StepArgs A)
             }
 #pragma unroll
             for (int a = 0; a < NDIM; ++a) {
-                const float Da = Dv[a];
+                // CPML stage first (slab cells only): D <- D + psiP, then the
+                // tissue stretch of the result; the two stretches compose
+                float Da = Dv[a];
+                const int c = coord(r, z, a), n = extent(a);
+                if (in_slab(c, n, P)) {
+                    const int32_t off = D.pml_off[a];
+                    const float aF = A.pml_tab[off + c];
+                    const float bF = A.pml_tab[off + n + c];
+                    const float qv = fmaf(aF, Da, bF * ppc[r][a]);
+                    Mo.pP1[a][g] = qv;
+                    Da += qv;
+                }
                 const float m = 2.0f * A.dt / (s_rho[L] + s_rho[Ln[a]]);
                 float s = s_ik[L] * Da;
 #pragma unroll
@@ -329,15 +344,6 @@ __global__ __launch_bounds__(BX *BY) void k_velocity(const StepArgs A)
                     s += pc[r][a][nu];
                 }
                 store_stream<N>(Mo.psi1[a] + (size_t)g * N, pc[r][a]);
-                const int c = coord(r, z, a), n = extent(a);
-                if (in_slab(c, n, P)) {
-                    const int32_t off = D.pml_off[a];
-                    const float aF = A.pml_tab[off + c];
-                    const float bF = A.pml_tab[off + n + c];
-                    const float qv = fmaf(aF, Da, bF * ppc[r][a]);
-                    Mo.pP1[a][g] = qv;
-                    s += qv;
-                }
                 store1_stream(Mo.v[a] + g, fmaf(-m, s, vc[r][a]));
             }
         }
@@ -379,12 +385,13 @@ __global__ __launch_bounds__(BX *BY) void k_velocity(const StepArgs A)
 
 // ---------------------------------------------------------------------------
 // Pressure update: for each cell,
-//   D_a = sum_m c_m (v_a[i+m-1] - v_a[i-m]) / dx,  S = sum_a D_a,
+//   D_a = sum_m c_m (v_a[i+m-1] - v_a[i-m]) / dx,
+//   psiP_a  <- bC psiP_a + aC D_a,  D_a <- D_a + psiP_a  (CPML slab of a),
+//   S = sum_a D_a,
 //   psi2_nu <- b2_nu psi2_nu + a2_nu S     (summed over axes: the tissue
 //              coefficients are the same for every axis, so the sum of the
 //              per-axis recursions is itself one recursion),
-//   psiP_a  <- bC psiP_a + aC D_a          (inside the CPML slab of a),
-//   p       -= dt (K (1 + eps)^2 + 2 beta p) (S / kappa_2 + sum_nu psi2_nu + sum_a psiP_a).
+//   p       -= dt (K (1 + eps)^2 + 2 beta p) (S / kappa_2 + sum_nu psi2_nu).
 // ---------------------------------------------------------------------------
 template <int NDIM, int N, int BX, int BY, int RY>
 __global__ __launch_bounds__(BX *BY) void k_pressure(const StepArgs A)
@@ -561,6 +568,21 @@ __global__ __launch_bounds__(BX *BY) void k_pressure(const StepArgs A)
                 Dd[NDIM - 1] = stencil4(A.fd, vq[r][4] - vq[r][3], vq[r][5] - vq[r][2], vq[r][6] - vq[r][1],
                                         vq[r][7] - vq[r][0]);
             }
+            // CPML stage per axis first (slab cells only), then the tissue
+            // stretch of the summed divergence (its coefficients do not
+            // depend on the axis)
+#pragma unroll
+            for (int a = 0; a < NDIM; ++a) {
+                const int c = coord(r, z, a), n = extent(a);
+                if (in_slab(c, n, P)) {
+                    const int32_t off = D.pml_off[a];
+                    const float aC = A.pml_tab[off + 2 * n + c];
+                    const float bC = A.pml_tab[off + 3 * n + c];
+                    const float qv = fmaf(aC, Dd[a], bC * ppc[r][a]);
+                    Mo.pP2[a][g] = qv;
+                    Dd[a] += qv;
+                }
+            }
             float S = Dd[0];
 #pragma unroll
             for (int a = 1; a < NDIM; ++a) S += Dd[a];
@@ -572,18 +594,6 @@ __global__ __launch_bounds__(BX *BY) void k_pressure(const StepArgs A)
                 Tt += psc[r][nu];
             }
             store_stream<N>(Mo.psi2 + (size_t)g * N, psc[r]);
-#pragma unroll
-            for (int a = 0; a < NDIM; ++a) {
-                const int c = coord(r, z, a), n = extent(a);
-                if (in_slab(c, n, P)) {
-                    const int32_t off = D.pml_off[a];
-                    const float aC = A.pml_tab[off + 2 * n + c];
-                    const float bC = A.pml_tab[off + 3 * n + c];
-                    const float qv = fmaf(aC, Dd[a], bC * ppc[r][a]);
-                    Mo.pP2[a][g] = qv;
-                    Tt += qv;
-                }
-            }
             float K = s_K[L];
             if (A.noise_amp != 0.0f) {
                 const uint64_t hsh = splitmix64(D.noise_seed ^ (uint64_t)(uint32_t)g);
