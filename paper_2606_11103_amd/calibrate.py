@@ -1,0 +1,158 @@
+"""Choice of the objective weight w by simulated attenuation (Sec. 3.2).
+
+The host fit (relax.fit_class) produces one parameter set per weight w of the
+objective.  The paper keeps, for each (alpha0, y) class, the weight whose
+*simulated* attenuation is closest to the power law.  Here every candidate
+of every class becomes one domain of a single batched 1D run on the GPU
+(the ragged-batch path of the step kernels), and the simulated attenuation
+and phase speed are measured as in Sec. 4.1-4.2:
+
+* plane wave from a broadband source (first derivative of a Gaussian with its
+  spectral peak at 6 MHz) in a 1D domain with CPML at both ends;
+* for each of the eight measurement frequencies f_k = 1 + 2.714 k MHz, two
+  receivers at 0.05 D and 0.8 D from the source, D = 10 wavelengths at f_k;
+* alpha(f_k) = ln|P_near / P_far| / distance and c(f_k) = 2 pi f_k distance /
+  unwrapped phase delay, with P the discrete Fourier transform of the trace
+  at exactly f_k;
+* attenuation NRMSE against alpha0 f^y (RMSE over the eight frequencies
+  divided by the target's range) and dispersion RMSE against the
+  Kramers-Kronig phase speed of Eq. (kk_relation).
+
+Selection: lowest simulated NRMSE, ties to the lower dispersion error, then
+to the smaller w.  A class is labelled failed above 10 % NRMSE or 5 m/s
+dispersion error.
+"""
+import math
+
+import numpy as np
+
+from . import relax
+
+MEASURE_FREQS = relax.MEASURE_FREQS
+
+
+def measurement_cells(dx, c, src_cell, freqs=MEASURE_FREQS):
+    """[n_freq][2] cells at 0.05 D and 0.8 D from the source, D = 10 c / f."""
+    out = np.zeros((len(freqs), 2), dtype=np.int64)
+    for k, f in enumerate(freqs):
+        D = 10.0 * c / f
+        out[k] = (src_cell + int(round(0.05 * D / dx)), src_cell + int(round(0.8 * D / dx)))
+    return out
+
+
+def broadband_pulse(n_t, dt, f_peak=6e6):
+    """First derivative of a Gaussian, spectral peak at f_peak, centred at
+    5 sigma, unit peak amplitude, sampled at t_s = (s + 1) dt (float32)."""
+    sigma = 1.0 / (2.0 * math.pi * f_peak)
+    t = (np.arange(n_t, dtype=np.float64) + 1.0) * dt
+    u = (t - 5.0 * sigma) / sigma
+    return (-u * np.exp(-0.5 * u * u) * math.exp(0.5)).astype(np.float32)
+
+
+def spectra(traces, dt, freqs):
+    """DFT of each column of traces [n_t][m] at the given frequencies, sample s
+    at time (s + 1) dt, kernel e^{-i 2 pi f t}: [len(freqs)][m] complex."""
+    t = (np.arange(traces.shape[0], dtype=np.float64) + 1.0) * dt
+    E = np.exp(-2j * np.pi * np.outer(freqs, t))
+    return E @ traces.astype(np.float64)
+
+
+def two_receiver_figures(P_near, P_far, dist, f, c_guess):
+    """(alpha in Np/m, phase speed in m/s) from the spectra at two receivers
+    dist apart; the phase delay is unwrapped around the delay at c_guess."""
+    alpha = np.log(np.abs(P_near) / np.abs(P_far)) / dist
+    ph = -np.angle(P_far / P_near)
+    kd = 2.0 * np.pi * f / c_guess * dist
+    ph = ph + 2.0 * np.pi * np.round((kd - ph) / (2.0 * np.pi))
+    return alpha, 2.0 * np.pi * f * dist / ph
+
+
+def errors(alpha_sim, c_sim, c0, alpha0_db, y, freqs=MEASURE_FREQS):
+    """(attenuation NRMSE, dispersion RMSE) of one domain's measurements."""
+    kt = relax.target_wavenumber(freqs, c0, alpha0_db, y)
+    at = kt.imag
+    ct = 2.0 * np.pi * np.asarray(freqs) / kt.real
+    nr = math.sqrt(np.mean((alpha_sim - at) ** 2)) / (at.max() - at.min())
+    return nr, math.sqrt(np.mean((c_sim - ct) ** 2))
+
+
+class SweepRun:
+    """One batched 1D run: domain j holds relaxation table j (kappa [2],
+    d [2][N], alpha [2][N]) at speed c and density rho."""
+
+    def __init__(self, kappa, d, alpha, c=1540.0, rho=1000.0, n_cells=8192, pml=24, src_cell=64, cfl=0.2,
+                 f_top=20e6, ppw=16):
+        self.kappa = np.asarray(kappa, dtype=np.float64)
+        self.d = np.asarray(d, dtype=np.float64)
+        self.alpha = np.asarray(alpha, dtype=np.float64)
+        self.n_dom = self.kappa.shape[0]
+        self.nmech = self.d.shape[2]
+        self.c, self.rho = float(c), float(rho)
+        self.dx = c / (ppw * f_top)
+        self.dt = cfl * self.dx / c
+        self.n_cells, self.pml, self.src_cell = int(n_cells), int(pml), int(src_cell)
+        self.pairs = measurement_cells(self.dx, c, src_cell)
+        if self.pairs.max() >= n_cells - pml:
+            raise ValueError("domain too short for the farthest receiver")
+        self.cells = np.unique(self.pairs.ravel())
+        self.n_steps = int(round((int(self.cells.max()) - src_cell) * self.dx / c / self.dt)) + 2000
+
+    def run(self):
+        """Simulate every domain; returns traces [n_steps][n_dom][n_cells_rec]."""
+        from .sim import Simulation
+        nd = self.n_dom
+        sim = Simulation(1, [(self.n_cells, 1, 1)] * nd, self.dx, self.dt, self.nmech, self.pml)
+        try:
+            sim.set_media([np.zeros(self.n_cells, np.uint8)] * nd, np.arange(nd), np.full(nd, self.c),
+                          np.full(nd, self.rho), np.zeros(nd))
+            sim.set_relaxation_table(self.kappa, self.d, self.alpha)
+            sim.set_sources(np.arange(nd), np.full(nd, self.src_cell), np.zeros(nd),
+                            broadband_pulse(self.n_steps, self.dt)[None, :])
+            m = self.cells.size
+            sim.set_receivers(np.repeat(np.arange(nd), m), np.tile(self.cells, nd), self.n_steps)
+            sim.step(self.n_steps)
+            tr = sim.read_receivers()
+        finally:
+            sim.close()
+        return tr.reshape(self.n_steps, nd, self.cells.size)
+
+    def measure(self, traces, chunk=256):
+        """(alpha [n_dom][n_freq], c [n_dom][n_freq]) from run()'s traces."""
+        nf = len(MEASURE_FREQS)
+        alpha = np.zeros((self.n_dom, nf))
+        cph = np.zeros((self.n_dom, nf))
+        col = {int(v): i for i, v in enumerate(self.cells)}
+        for k, f in enumerate(MEASURE_FREQS):
+            a, b = (col[int(v)] for v in self.pairs[k])
+            dist = (self.pairs[k, 1] - self.pairs[k, 0]) * self.dx
+            for s in range(0, self.n_dom, chunk):
+                e = min(self.n_dom, s + chunk)
+                P = spectra(np.concatenate([traces[:, s:e, a], traces[:, s:e, b]], axis=1), self.dt, [f])[0]
+                alpha[s:e, k], cph[s:e, k] = two_receiver_figures(P[:e - s], P[e - s:], dist, f, self.c)
+        return alpha, cph
+
+
+def select_weights(fits, c=1540.0, rho=1000.0, **kw):
+    """For fitted classes (relax.fit_class results carrying "cands"), simulate
+    every candidate and pick the weight with the lowest simulated attenuation
+    NRMSE.  Returns (chosen fits, nrmse [n_class][n_cand], disp [n_class][n_cand])."""
+    n_cls = len(fits)
+    n_cand = len(fits[0]["cands"])
+    flat = [cd for ft in fits for cd in ft["cands"]]
+    if any(len(ft["cands"]) != n_cand for ft in fits):
+        raise ValueError("every class needs the same number of candidates")
+    run = SweepRun([cd["kappa"] for cd in flat], [cd["d"] for cd in flat], [cd["alpha"] for cd in flat],
+                   c=c, rho=rho, **kw)
+    alpha, cph = run.measure(run.run())
+    nr = np.zeros((n_cls, n_cand))
+    dp = np.zeros((n_cls, n_cand))
+    chosen = []
+    for i, ft in enumerate(fits):
+        for j in range(n_cand):
+            nr[i, j], dp[i, j] = errors(alpha[i * n_cand + j], cph[i * n_cand + j], c, ft["alpha0"], ft["y"])
+        j = min(range(n_cand), key=lambda q: (nr[i, q], dp[i, q], ft["cands"][q]["w"]))
+        pick = dict(ft["cands"][j])
+        pick.update(c=ft["c"], alpha0=ft["alpha0"], y=ft["y"], nmech=ft["nmech"], sim_nrmse=float(nr[i, j]),
+                    sim_disp=float(dp[i, j]), failed=bool(nr[i, j] > 0.10 or dp[i, j] > 5.0))
+        chosen.append(pick)
+    return chosen, nr, dp

@@ -21,33 +21,30 @@ def _report(line):
 
 def measure(case, traces):
     """Per domain: simulated alpha (Np/m) and phase speed (m/s) at the 8
-    measurement frequencies from the receiver pair nearest to 0.05 D and
-    0.8 D of each frequency."""
+    measurement frequencies from the receivers at 0.05 D and 0.8 D of each
+    frequency (spectra: DFT evaluated at exactly that frequency)."""
     from oracle import analytic
     nd = len(case.shapes)
-    rec_cells = case.rec_cell[case.rec_domain == 0]
+    rec_cells = list(case.rec_cell[case.rec_domain == 0])
     src = int(case.src_cell[0])
-    nt = traces.shape[0]
-    pad = 4 * nt
-    f = np.fft.rfftfreq(pad, case.dt)
-    F = np.fft.rfft(traces.astype(np.float64), n=pad, axis=0)
+    pairs = configs.sweep_receiver_cells(case.dx, case.c[0], src)
+    t = (np.arange(traces.shape[0]) + 1.0) * case.dt
     alpha = np.zeros((nd, len(configs.SWEEP_FREQS)))
     cph = np.zeros_like(alpha)
     c0 = case.c[0]
     for k, fk in enumerate(configs.SWEEP_FREQS):
-        D = 10.0 * c0 / fk
-        want = np.array([0.05 * D, 0.8 * D]) / case.dx + src
-        idx = [int(np.argmin(np.abs(rec_cells - w))) for w in want]
-        dist = (rec_cells[idx[1]] - rec_cells[idx[0]]) * case.dx
-        j = int(np.argmin(np.abs(f - fk)))
+        ia, ib = rec_cells.index(pairs[k, 0]), rec_cells.index(pairs[k, 1])
+        dist = (pairs[k, 1] - pairs[k, 0]) * case.dx
+        kern = np.cos(2 * np.pi * fk * t) - 1j * np.sin(2 * np.pi * fk * t)
         for dom in range(nd):
             cols = np.nonzero(case.rec_domain == dom)[0]
-            P1, P2 = F[j, cols[idx[0]]], F[j, cols[idx[1]]]
+            P1 = kern @ traces[:, cols[ia]].astype(np.float64)
+            P2 = kern @ traces[:, cols[ib]].astype(np.float64)
             alpha[dom, k] = analytic.two_receiver_attenuation(P1, P2, dist)
             ph = -np.angle(P2 / P1)
-            kc = 2 * np.pi * f[j] / c0
+            kc = 2 * np.pi * fk / c0
             ph = ph + 2 * np.pi * np.round((kc * dist - ph) / (2 * np.pi))
-            cph[dom, k] = 2 * np.pi * f[j] * dist / ph
+            cph[dom, k] = 2 * np.pi * fk * dist / ph
     return alpha, cph
 
 

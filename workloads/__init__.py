@@ -33,8 +33,9 @@ def tone_burst(n_t, dt, f0, n_cycles, amplitude=1.0, delay=0.0):
 
 
 def gaussian_derivative(n_t, dt, sigma, amplitude=1.0, t0=None):
-    """Broadband first-derivative-of-Gaussian pulse, peak spectrum at
-    1/(sqrt(2) pi sigma), sampled at t_s = (s + 1) dt, float32."""
+    """Broadband first-derivative-of-Gaussian pulse -u exp(-u^2/2),
+    u = (t - t0)/sigma: amplitude spectrum f exp(-(2 pi f sigma)^2 / 2), peak
+    at 1/(2 pi sigma); sampled at t_s = (s + 1) dt, float32."""
     t = (np.arange(n_t, dtype=np.float64) + 1.0) * dt
     t0 = 5.0 * sigma if t0 is None else t0
     u = (t - t0) / sigma

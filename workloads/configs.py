@@ -209,14 +209,28 @@ SWEEP_Y = 0.4 + 0.1 * np.arange(17)
 SWEEP_FREQS = 1e6 + 2.714e6 * np.arange(8)
 
 
+def sweep_receiver_cells(dx, c=1540.0, src_cell=64, freqs=None):
+    """Receiver cells of the two-receiver measurement: for each measurement
+    frequency f, the cells nearest 0.05 D and 0.8 D from the source, with
+    D = 10 wavelengths at f (Sec. 4.1).  Returns [n_freq][2]."""
+    freqs = SWEEP_FREQS if freqs is None else np.asarray(freqs, dtype=np.float64)
+    out = []
+    for f in freqs:
+        D = 10.0 * c / f
+        out.append([src_cell + int(round(0.05 * D / dx)), src_cell + int(round(0.8 * D / dx))])
+    return np.array(out, dtype=np.int64)
+
+
 def sweep_1d(n_cells=8192, nmech=2, steps=None, alpha0=None, y=None, c=1540.0, rho=1000.0, pml=24,
-             rec_every=8, src_cell=64):
+             src_cell=64):
     """1D plane-wave sweep: one 8192-cell domain per (alpha0, y) pair, alpha0 in
     32 log-spaced values 0.0022..1 and y in 17 values 0.4..2.0 (544 domains),
     c = 1540, rho = 1000, linear, N = 2.  dx = c / (16 * 20 MHz) (16 points per
     wavelength at the top of the band), CFL 0.2, 24-cell CPML at both ends.
     Broadband source at cell 64: first derivative of a Gaussian with its
-    spectral peak at 6 MHz.  A receiver every 8 cells (from the source on)."""
+    spectral peak at 6 MHz.  Receivers at the measurement cells of
+    sweep_receiver_cells (16 per domain, those inside the grid); by default
+    the run lasts until the pulse has passed the farthest one."""
     a0 = SWEEP_ALPHA0 if alpha0 is None else np.asarray(alpha0, dtype=np.float64)
     yy = SWEEP_Y if y is None else np.asarray(y, dtype=np.float64)
     A0, Y = np.meshgrid(a0, yy, indexing="ij")
@@ -224,11 +238,12 @@ def sweep_1d(n_cells=8192, nmech=2, steps=None, alpha0=None, y=None, c=1540.0, r
     nd = A0.size
     dx = c / (16 * 20e6)
     dt = 0.2 * dx / c
+    rc = sweep_receiver_cells(dx, c, src_cell).ravel()
+    rc = rc[rc < n_cells - pml]
     if steps is None:
-        steps = int(round((n_cells - src_cell - pml) * dx / c / dt)) + 400
-    sigma = 1.0 / (np.sqrt(2.0) * np.pi * 6e6)
+        steps = int(round((int(rc.max()) - src_cell) * dx / c / dt)) + 2000
+    sigma = 1.0 / (2.0 * np.pi * 6e6)
     wave = gaussian_derivative(steps, dt, sigma, amplitude=1.0)
-    rc = np.arange(src_cell, n_cells - pml, rec_every)
     shp = (n_cells, 1, 1)
     return Case(
         name="1d_sweep_%dx%d" % (nd, n_cells), ndim=1, shapes=[shp] * nd, dx=dx, dt=dt, nmech=nmech,
