@@ -37,9 +37,14 @@ TRAFFIC_MEASURED = {
 
 
 def kernel_source_hash():
+    """SHA-256 prefix of the step kernels' sources (kernel file and the device
+    helper header it includes)."""
     import hashlib
-    with open(os.path.join(ROOT, "paper_2606_11103_amd", "csrc", "fw_kernels.hip"), "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in ("fw_kernels.hip", "fw_vec.h"):
+        with open(os.path.join(ROOT, "paper_2606_11103_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def algorithmic_bytes(case):
@@ -157,6 +162,45 @@ def bench_batched(torch, steps=40):
             "plain_sample": "8 of the 64 shots, one simulation each"}
 
 
+def _tables_or_random(case, seed):
+    """Cached calibrated tables of the case's classes, else (throughput only)
+    a seeded random table of realistic strength."""
+    from workloads import configs
+    try:
+        fill_tables(case, allow_fit=False)
+        return "calibrated"
+    except KeyError:
+        configs.with_table(case, *configs.random_relaxation_table(seed, case.n_classes, case.nmech))
+        return "random (calibration not cached)"
+
+
+def bench_two_layer(torch, steps=400):
+    """2D two-layer 2048 x 2048, N = 4, nonlinear, plane-wave line source."""
+    from workloads import configs
+    from workloads.adapters import to_simulation
+    case = configs.two_layer_2d(steps=steps + 10)
+    tab = _tables_or_random(case, 2)
+    sim = to_simulation(case)
+    sim.step(10)
+    ms = _time_steps(torch, sim, steps)
+    return {"workload": case.name, "cells": case.cells(), "steps": steps, "tables": tab,
+            "gcells": round(case.cells() * steps / (ms / 1e3) / 1e9, 3), "ms_per_step": round(ms / steps, 4)}
+
+
+def bench_sweep(torch, steps=2000):
+    """1D sweep: 544 domains x 8192 cells, N = 2, one batched launch."""
+    from workloads import configs
+    from workloads.adapters import to_simulation
+    case = configs.sweep_1d()
+    tab = _tables_or_random(case, 3)
+    sim = to_simulation(case)
+    sim.step(10)
+    ms = _time_steps(torch, sim, steps)
+    return {"workload": case.name, "cells": case.cells(), "steps": steps, "tables": tab,
+            "steps_of_full_run": case.n_steps,
+            "gcells": round(case.cells() * steps / (ms / 1e3) / 1e9, 3), "ms_per_step": round(ms / steps, 4)}
+
+
 def bench_adjoint(torch, steps=330, ckpt=55):
     """Gradient of J = 1/2 dt sum (r - d)^2 w.r.t. c(x), alpha0(x) for the 16-shot
     1024^2 N = 4 workload (observed data: true model; current model: c x 0.99),
@@ -234,8 +278,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--small", action="store_true", help="reduced grid for quick checks (not the benchmark)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the batched and adjoint comparisons")
-    ap.add_argument("--only", choices=("batched", "adjoint"), default=None,
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched, adjoint, two-layer 2D and 1D sweep workloads")
+    ap.add_argument("--only", choices=("batched", "adjoint", "two_layer", "sweep"), default=None,
                     help="run only one comparison workload and print its JSON (profiling)")
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--march-chunk", type=int, default=0)
@@ -254,7 +299,8 @@ def main():
         return
     if args.only:
         torch.cuda.set_device(0)
-        fn = bench_batched if args.only == "batched" else bench_adjoint
+        fn = dict(batched=bench_batched, adjoint=bench_adjoint, two_layer=bench_two_layer,
+                  sweep=bench_sweep)[args.only]
         print(json.dumps(fn(torch)), flush=True)
         return
     from paper_2606_11103_amd.native import FW_OPT_MARCH_CHUNK, FW_OPT_ROWS_PER_THREAD, FW_OPT_TILE_ROWS
@@ -344,6 +390,12 @@ def main():
         torch.cuda.empty_cache()
         print("# adjoint ...", file=sys.stderr, flush=True)
         out["adjoint"] = bench_adjoint(torch)
+        torch.cuda.empty_cache()
+        print("# two-layer 2D ...", file=sys.stderr, flush=True)
+        out["two_layer_2d"] = bench_two_layer(torch)
+        torch.cuda.empty_cache()
+        print("# 1D sweep ...", file=sys.stderr, flush=True)
+        out["sweep_1d"] = bench_sweep(torch)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         print("# cpu baseline ...", file=sys.stderr, flush=True)
