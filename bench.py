@@ -30,8 +30,8 @@ HBM_PEAK_GBS = 8000.0
 # copy kernel), keyed by the SHA-256 prefix of the kernel source they were
 # taken on; any other kernel source reports traffic as null.
 TRAFFIC_MEASURED = {
-    "797a08cfc5f3eb81": {"workload": "3d_heterogeneous_960x960x720", "tile_rows": 16, "rows_per_thread": 1,
-                         "bytes_per_launch": 88.16e9,
+    "42ee0b1c4cb5255b": {"workload": "3d_heterogeneous_960x960x720", "tile_rows": 16, "rows_per_thread": 1,
+                         "bytes_per_launch": 85.86e9,
                          "profile": "profiles/step_kernels_3d_960x960x720_N4.md"},
 }
 
@@ -126,10 +126,10 @@ def bench_batched(torch, steps=40):
     together in one tile list, vs the same shots run one at a time."""
     from workloads import configs
     from workloads.adapters import to_simulation
-    case = configs.batched_2d(steps=steps + 5)
+    case = configs.batched_2d(steps=steps + 32)
     configs.with_table(case, *configs.random_relaxation_table(4000, case.n_classes, case.nmech))
     sim = to_simulation(case)
-    sim.step(5)
+    sim.step(32)                    # untimed: captures the step graph
     ms = _time_steps(torch, sim, steps)
     batched = case.cells() * steps / (ms / 1e3) / 1e9
     del sim
@@ -151,7 +151,7 @@ def bench_batched(torch, steps=40):
         one.rec_domain = np.zeros(int(rm.sum()), np.int32)
         one.rec_cell = case.rec_cell[rm]
         sim = to_simulation(one)
-        sim.step(5)
+        sim.step(32)
         tot += _time_steps(torch, sim, steps)
         cells += one.cells()
         del sim
@@ -178,10 +178,10 @@ def bench_two_layer(torch, steps=400):
     """2D two-layer 2048 x 2048, N = 4, nonlinear, plane-wave line source."""
     from workloads import configs
     from workloads.adapters import to_simulation
-    case = configs.two_layer_2d(steps=steps + 10)
+    case = configs.two_layer_2d(steps=steps + 32)
     tab = _tables_or_random(case, 2)
     sim = to_simulation(case)
-    sim.step(10)
+    sim.step(32)                    # untimed: captures the step graph
     ms = _time_steps(torch, sim, steps)
     return {"workload": case.name, "cells": case.cells(), "steps": steps, "tables": tab,
             "gcells": round(case.cells() * steps / (ms / 1e3) / 1e9, 3), "ms_per_step": round(ms / steps, 4)}
@@ -194,7 +194,7 @@ def bench_sweep(torch, steps=2000):
     case = configs.sweep_1d()
     tab = _tables_or_random(case, 3)
     sim = to_simulation(case)
-    sim.step(10)
+    sim.step(32)                    # untimed: captures the step graph
     ms = _time_steps(torch, sim, steps)
     return {"workload": case.name, "cells": case.cells(), "steps": steps, "tables": tab,
             "steps_of_full_run": case.n_steps,
@@ -216,16 +216,24 @@ def bench_adjoint(torch, steps=330, ckpt=55):
     del true
     case.c = case.c * 0.99
     sim = to_simulation(case)
+    sim.step(32)                    # untimed: captures the step graph
+    sim.reset()
     ms_fwd = _time_steps(torch, sim, steps)
     sim.reset()
     work = sim.adjoint_workspace(steps, ckpt)
+
+    def gradient():
+        sim.forward_checkpointed(steps, ckpt, work)
+        tr = sim.read_receivers_device()
+        res = case.dt * (tr - obs)
+        gK, gs = sim.adjoint(steps, ckpt, work, res)
+        return tr, gK, gs
+
+    gradient()                      # untimed pass: first touch of the workspace
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    sim.forward_checkpointed(steps, ckpt, work)
-    tr = sim.read_receivers_device()
-    res = case.dt * (tr - obs)
-    gK, gs = sim.adjoint(steps, ckpt, work, res)
+    tr, gK, gs = gradient()
     e1.record()
     torch.cuda.synchronize()
     ms_grad = e0.elapsed_time(e1)
