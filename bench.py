@@ -110,6 +110,51 @@ def cpu_baseline(seconds_target=20.0):
                        "noise, nonlinear), %d steps in %.1f s" % (steps, el))
 
 
+def oracle_timings(seconds=8.0):
+    """The FP64 oracle (as it stands) on bounded samples of each workload, in
+    Gcell-updates/s of that sample; for reporting beside the GPU figures."""
+    from workloads import configs
+    from workloads.adapters import to_oracle
+
+    def timed(case, domains, label):
+        cells, steps_done, t_all = 0, 0, 0.0
+        for d in domains:
+            sim = to_oracle(case, d)
+            sm = case.src_domain == d
+            waves = case.waves.astype(np.float64)[case.src_wave[sm]]
+            rm = np.nonzero(case.rec_domain == d)[0]
+            n = 0
+            t0 = time.perf_counter()
+            while n < case.n_steps and time.perf_counter() - t0 < seconds / len(domains):
+                sim.run(10, case.src_cell[sm], waves, case.rec_cell[rm])
+                n += 10
+            t_all += time.perf_counter() - t0
+            c = int(np.prod(case.shapes[d]))
+            cells += c * n
+            steps_done = n
+        return {"workload": label, "gcells": round(cells / t_all / 1e9, 5), "seconds": round(t_all, 1),
+                "sample_steps": steps_done}
+
+    out = []
+    c1 = configs.homogeneous_2d()
+    fill_tables(c1)
+    out.append(timed(c1, [0], "2D homogeneous 256x256 N=2"))
+    c2 = configs.two_layer_2d()
+    fill_tables(c2)
+    out.append(timed(c2, [0], "2D two-layer 2048x2048 N=4 (first steps)"))
+    c3 = configs.heterogeneous_3d(shape=(128, 128, 96), steps=2000, n_elem=16)
+    fill_tables(c3)
+    out.append(timed(c3, [0], "3D heterogeneous recipe on 128x128x96"))
+    c4 = configs.batched_2d()
+    configs.with_table(c4, *configs.random_relaxation_table(4000, c4.n_classes, c4.nmech))
+    out.append(timed(c4, [0, 1, 2, 3], "batched 2D: 4 of the 64 shots"))
+    c5 = configs.sweep_1d()
+    _tables_or_random(c5, 3)
+    out.append(timed(c5, list(range(0, 544, 68)), "1D sweep: 8 of the 544 domains"))
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"oracle_timings": out, "cores": min(cores, os.cpu_count() or cores), "kind": "oracle FP64"}
+
+
 def _time_steps(torch, sim, steps):
     """Milliseconds for `steps` full steps through fw_step (graph replay)."""
     torch.cuda.synchronize()
@@ -295,7 +340,12 @@ def main():
     ap.add_argument("--rows-per-thread", type=int, default=0)
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="only run a plain device-to-device copy of this many GiB (HBM counter calibration)")
+    ap.add_argument("--oracle-timings", action="store_true",
+                    help="only time the FP64 oracle on bounded samples of each workload (host only)")
     args = ap.parse_args()
+    if args.oracle_timings:
+        print(json.dumps(oracle_timings()), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (got --gpus %d)" % args.gpus,
               file=sys.stderr)

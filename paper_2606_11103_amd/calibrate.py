@@ -156,3 +156,59 @@ def select_weights(fits, c=1540.0, rho=1000.0, **kw):
                     sim_disp=float(dp[i, j]), failed=bool(nr[i, j] > 0.10 or dp[i, j] > 5.0))
         chosen.append(pick)
     return chosen, nr, dp
+
+
+def tone_burst(n_t, dt, f0, n_cycles, amplitude=1.0):
+    """Gaussian-modulated sine: A sin(2 pi f0 (t - t0)) exp(-((t - t0)/sigma)^2),
+    sigma = n_cycles / (2 f0), t0 = 4 sigma, sampled at t_s = (s + 1) dt."""
+    sigma = n_cycles / (2.0 * f0)
+    t = (np.arange(n_t, dtype=np.float64) + 1.0) * dt - 4.0 * sigma
+    return (amplitude * np.sin(2.0 * np.pi * f0 * t) * np.exp(-(t / sigma) ** 2)).astype(np.float32)
+
+
+def pml_reflection(kappa, d, alpha, c=1540.0, rho=1000.0, f0=1e6, ppw=16, cfl=0.2, pml_wavelengths=3.0,
+                   depth_wavelengths=5.0, n_cycles=3):
+    """Reflection coefficient of the CPML for each relaxation table, in dB
+    (Sec. 4 protocol, 1D plane wave): source below the top layer, a receiver
+    at 0.8 D towards the bottom layer D = 5 wavelengths away, 1 MHz
+    Gaussian-modulated pulse, layer thickness 3 wavelengths.  Each table runs
+    in two domains of one batched launch: one that ends in the layer and one
+    long enough that nothing returns from its far end within the window; the
+    reflected wave is the difference of the two receiver traces,
+    R = 20 log10(max|difference| / max|incident|)."""
+    from .sim import Simulation
+    kappa = np.asarray(kappa, dtype=np.float64)
+    d = np.asarray(d, dtype=np.float64)
+    alpha = np.asarray(alpha, dtype=np.float64)
+    n_tab, nmech = kappa.shape[0], d.shape[2]
+    lam = c / f0
+    dx = lam / ppw
+    dt = cfl * dx / c
+    P = int(round(pml_wavelengths * ppw))
+    D = int(round(depth_wavelengths * ppw))
+    src = P + 4
+    rec = src + int(round(0.8 * D))
+    sigma = n_cycles / (2.0 * f0)
+    # the reflected pulse has passed the receiver (8 sigma long, centred at
+    # 4 sigma after the travel time) by the end of the window
+    travel = (2 * (src + D) - src - rec) * dx / c
+    n_steps = int(np.ceil((travel + 10.0 * sigma) / dt))
+    n_short = src + D + P
+    n_long = n_short + int(np.ceil(n_steps * cfl / 2.0)) + P + 8
+    shapes = [(n_short, 1, 1), (n_long, 1, 1)] * n_tab
+    nd = 2 * n_tab
+    sim = Simulation(1, shapes, dx, dt, nmech, P)
+    try:
+        sim.set_media([np.zeros(s[0], np.uint8) for s in shapes], np.repeat(np.arange(n_tab), 2),
+                      np.full(n_tab, c), np.full(n_tab, rho), np.zeros(n_tab))
+        sim.set_relaxation_table(kappa, d, alpha)
+        sim.set_sources(np.arange(nd), np.full(nd, src), np.zeros(nd), tone_burst(n_steps, dt, f0, n_cycles)[None, :])
+        sim.set_receivers(np.arange(nd), np.full(nd, rec), n_steps)
+        sim.step(n_steps)
+        tr = sim.read_receivers().astype(np.float64)
+    finally:
+        sim.close()
+    short, long_ = tr[:, 0::2], tr[:, 1::2]
+    refl = np.abs(short - long_).max(axis=0)
+    inc = np.abs(long_).max(axis=0)
+    return 20.0 * np.log10(np.maximum(refl, 1e-300) / inc)

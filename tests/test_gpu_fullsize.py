@@ -1,4 +1,10 @@
-"""Parity at the benchmark's full size and launch configuration.
+"""Parity at full size.
+
+The 2D two-layer workload (2048 x 2048, N = 4, nonlinear, 4000 steps) is
+compared over every receiver and step with the FP64 oracle's traces, stored
+under tests/golden by a script that runs only the oracle (the oracle needs
+minutes of host time for it); the inputs stored with them (tables, speeds,
+cells, waveform) are checked against the workload generator first.
 
 The 960 x 960 x 720 workload (N = 4, 24-cell CPML, 8 classes, speed
 perturbation, nonlinear, focused array) is run on the GPU exactly as
@@ -8,6 +14,8 @@ the FP64 oracle on the box that contains that support computes the same
 field; every pressure value of the box and every receiver inside it is
 compared, and the GPU field outside the box must be exactly zero.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -71,3 +79,32 @@ def test_full_size_3d_workload_matches_oracle_on_the_field_support():
     _report("full-size 3D 960x960x720 N=4 after %d steps: box %s rel_L2 field=%.3e receivers(%d)=%.3e"
             % (K, [h - l for l, h in zip(lo, hi)], rel_field, int(inside.sum()), rel_rec))
     assert rel_field <= 1e-5 and rel_rec <= 1e-5
+
+
+GOLDEN_2D = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "two_layer_2d_2048_oracle.npz")
+
+
+def test_full_size_two_layer_2d_matches_stored_oracle_traces():
+    g = np.load(GOLDEN_2D)
+    steps = int(g["steps"])
+    case = configs.two_layer_2d(steps=steps)
+    # the stored inputs are the workload's
+    np.testing.assert_array_equal(g["c"], case.c)
+    np.testing.assert_array_equal(g["rho"], case.rho)
+    np.testing.assert_array_equal(g["rec_cell"], case.rec_cell)
+    np.testing.assert_array_equal(g["src_cell"], case.src_cell)
+    np.testing.assert_array_equal(g["wave"], case.waves[0])
+    assert float(g["dx"]) == case.dx and float(g["dt"]) == case.dt
+    configs.with_table(case, g["kappa"], g["d"], g["alpha"])
+    print("full-size 2D two-layer", case.shapes, "steps", steps, flush=True)
+    sim = to_simulation(case)
+    sim.step(steps)
+    tr = sim.read_receivers()[:steps].astype(np.float64)
+    del sim
+    ref = g["traces"].astype(np.float64)
+    rel = float(np.linalg.norm(tr - ref) / np.linalg.norm(ref))
+    worst = float(np.max(np.linalg.norm(tr - ref, axis=0) / np.linalg.norm(ref, axis=0)))
+    _report("full-size 2D two-layer 2048x2048 N=4 nonlinear, %d steps x %d receivers: rel_L2 %.3e "
+            "(worst receiver %.3e), peak |p| %.3g Pa" % (steps, tr.shape[1], rel, worst, np.abs(ref).max()))
+    assert np.all(np.isfinite(tr))
+    assert rel <= 1e-4
