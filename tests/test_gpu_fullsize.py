@@ -108,3 +108,89 @@ def test_full_size_two_layer_2d_matches_stored_oracle_traces():
             "(worst receiver %.3e), peak |p| %.3g Pa" % (steps, tr.shape[1], rel, worst, np.abs(ref).max()))
     assert np.all(np.isfinite(tr))
     assert rel <= 1e-4
+
+
+def test_full_size_3d_run_is_finite_and_loses_energy_after_the_source():
+    """All 2000 steps of the benchmark workload: every pressure stays finite,
+    and once the source has ended (its pulses are over by step ~200) the FP64
+    staggered-time energy only decreases (attenuation, CPML absorption)."""
+    from paper_2606_11103_amd import relax
+    case = configs.heterogeneous_3d(shape=(960, 960, 720), steps=2000)
+    kappa, d, al, _ = relax.tables_for(dict(c=case.c, alpha0=case.alpha0, y=case.y), case.nmech, allow_fit=False)
+    configs.with_table(case, kappa, d, al)
+    print("full-size 3D, 2000 steps", flush=True)
+    sim = to_simulation(case)
+    marks = (400, 800, 1200, 1600, 2000)
+    energy = []
+    done = 0
+    for m in marks:
+        sim.step(m - 1 - done)
+        e = sim.energy_step()[0]
+        done = m
+        assert e[2] == 0
+        energy.append((m, e[0], e[1]))
+    tr = sim.read_receivers()
+    del sim
+    _report("full-size 3D 2000 steps: energy/max|p| at steps " +
+            ", ".join("%d: E %.3e, %.3g Pa" % v for v in energy))
+    assert np.all(np.isfinite(tr))
+    E = [v[1] for v in energy]
+    assert all(E[i + 1] < E[i] for i in range(len(E) - 1))
+
+
+def test_full_size_batched_2d_equals_single_shots():
+    """The 64 ragged shots of the batched benchmark (one tile list) give
+    bit-identical traces to the same shots run as simulations of their own."""
+    case = configs.batched_2d(steps=40)
+    configs.with_table(case, *configs.random_relaxation_table(4000, case.n_classes, case.nmech))
+    case.pml_params = (1e-4, 1e6, float(case.c.max()))
+    sim = to_simulation(case)
+    sim.step(40)
+    allr = sim.read_receivers()
+    del sim
+    for s in (0, 37, 63):
+        one = configs.Case(**{**case.__dict__})
+        one.shapes = [case.shapes[s]]
+        one.class_maps = [case.class_maps[s]]
+        one.class_base = [0]
+        b = case.class_base[s]
+        sl = slice(b, b + int(case.class_maps[s].max()) + 1)
+        for f in ("c", "rho", "alpha0", "y", "b_over_a", "kappa", "d", "alpha"):
+            setattr(one, f, getattr(case, f)[sl])
+        sm = case.src_domain == s
+        rm = case.rec_domain == s
+        one.src_domain = np.zeros(int(sm.sum()), np.int32)
+        one.src_cell = case.src_cell[sm]
+        one.src_wave = case.src_wave[sm]
+        one.rec_domain = np.zeros(int(rm.sum()), np.int32)
+        one.rec_cell = case.rec_cell[rm]
+        sim = to_simulation(one)
+        sim.step(40)
+        r = sim.read_receivers()
+        del sim
+        assert np.array_equal(r, allr[:, rm]), s
+
+
+def test_full_size_adjoint_is_independent_of_the_checkpoint_interval():
+    """The 1024 x 1024 x 16-shot adjoint workload over 110 steps: gradients
+    with checkpoints every 55 steps and every 22 steps are bit-identical and
+    finite."""
+    import torch
+    case = configs.adjoint_2d(steps=110)
+    from paper_2606_11103_amd import relax
+    kappa, d, al, _ = relax.tables_for(dict(c=case.c, alpha0=case.alpha0, y=case.y), case.nmech, allow_fit=False)
+    configs.with_table(case, kappa, d, al)
+    sim = to_simulation(case)
+    out = []
+    for ck in (55, 22):
+        work = sim.adjoint_workspace(110, ck)
+        sim.forward_checkpointed(110, ck, work)
+        tr = sim.read_receivers_device()
+        gK, gs = sim.adjoint(110, ck, work, case.dt * tr)
+        out.append((gK.cpu().numpy(), gs.cpu().numpy()))
+        del work
+        torch.cuda.empty_cache()
+    del sim
+    assert np.all(np.isfinite(out[0][0])) and np.all(np.isfinite(out[0][1]))
+    assert np.abs(out[0][0]).max() > 0
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
