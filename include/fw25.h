@@ -78,7 +78,12 @@ int fw_abi_version(void);
  *              alpha(delta) = pi f_alpha (1 - delta), kappa = 1, delta the
  *              depth into the slab measured from its inner edge at positions
  *              P - 1/2 and n - P - 1/2 (defaults 1e-4, 1e6, 0; c_ref = 0 takes
- *              the largest class speed given to fw_set_media).
+ *              the largest class speed given to fw_set_media).  Inside the
+ *              slab of an axis the CPML recursion acts on that axis'
+ *              derivative before the tissue recursions do, so the layer's
+ *              stretch is the product of the CPML and tissue stretches (the
+ *              layer stretches the coordinate of the lossy medium; the tissue
+ *              mechanisms continue inside it).
  * On success *out holds a new object owned by the caller (fw_destroy).
  */
 int fw_create_grid(fw_sim **out, int ndim, int n_domains, const int64_t *shape,
