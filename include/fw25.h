@@ -206,7 +206,10 @@ int fw_load_state(fw_sim *sim, const void *d_src, void *hip_stream);
  * and d_adj_src must be 4-byte aligned device buffers.
  * fw_forward_checkpointed resets the state, runs n_steps (recording the
  * traces) and stores the checkpoints; fw_adjoint then sweeps the segments
- * last to first, recomputing each segment's states from its checkpoint.
+ * last to first, recomputing each segment's states from its checkpoint into
+ * d_work.  fw_adjoint leaves the simulation's own state and step counter as
+ * they were (the recompute rewrites the traces of steps < n_steps with the
+ * same values), so stepping can continue after it.
  * Returns FW_EUNSUPPORTED if any class has beta != 0.
  */
 int64_t fw_adjoint_workspace_bytes(const fw_sim *sim, int n_steps, int ckpt_every);

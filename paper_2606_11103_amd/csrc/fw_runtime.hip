@@ -860,10 +860,9 @@ extern "C" int64_t fw_adjoint_workspace_bytes(const fw_sim *sim, int n_steps, in
     return tot;
 }
 
-static int copy_state(fw_sim *s, char *dst, const char *src, hipStream_t st, bool with_step)
+static int copy_state(fw_sim *s, char *dst, const char *src, hipStream_t st)
 {
     HIP_OR_FAIL(fw::launch_copy(dst, src, s->state_end, st));
-    (void)with_step;
     return FW_OK;
 }
 
@@ -879,7 +878,6 @@ extern "C" int fw_forward_checkpointed(fw_sim *sim, int n_steps, int ckpt_every,
     if ((reinterpret_cast<uintptr_t>(d_work) % kAlignBytes) != 0)
         return fail(FW_EINVAL, "adjoint workspace must be 256-byte aligned");
     if (!sim->ws || !sim->media_set || !sim->table_set) return fail(FW_ESTATE, "set up the simulation first");
-    hipStream_t st = static_cast<hipStream_t>(hip_stream);
     char *w = static_cast<char *>(d_work);
     const int64_t SB = adj_state_stride(sim);
     rc = fw_reset_state(sim, hip_stream);
@@ -891,7 +889,6 @@ extern "C" int fw_forward_checkpointed(fw_sim *sim, int n_steps, int ckpt_every,
         rc = fw_step(sim, n, hip_stream);
         if (rc != FW_OK) return rc;
     }
-    (void)st;
     return FW_OK;
 }
 
@@ -919,7 +916,10 @@ extern "C" int fw_adjoint(fw_sim *sim, int n_steps, int ckpt_every, void *d_work
     char *seg = w + os;
     char *lam = w + ol;
     float *scr = reinterpret_cast<float *>(w + oc);
-    HIP_OR_FAIL(hipMemsetAsync(lam, 0, (size_t)SB, st));
+    // the recompute below moves the device step counter; keep its value in
+    // the spare bytes after the adjoint state and restore it at the end
+    HIP_OR_FAIL(hipMemsetAsync(lam, 0, (size_t)sim->state_end, st));
+    HIP_OR_FAIL(hipMemcpyAsync(lam + sim->state_end, sim->d_step.ptr, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
     fw::AdjArgs A{};
     A.s = step_args(sim);
     A.lam = fields_at(sim, lam);
@@ -946,7 +946,7 @@ extern "C" int fw_adjoint(fw_sim *sim, int n_steps, int ckpt_every, void *d_work
         // segment states: the checkpoint goes to slot 0 (and the step counter
         // to the device), then each recomputed step reads slot j and writes
         // slot j + 1 directly (no copies)
-        rc = copy_state(sim, seg, w + k * SB, st, false);
+        rc = copy_state(sim, seg, w + k * SB, st);
         if (rc != FW_OK) return rc;
         HIP_OR_FAIL(hipMemcpyAsync(sim->d_step.ptr, w + k * SB + sim->state_end, sizeof(int64_t),
                                    hipMemcpyDeviceToDevice, st));
@@ -970,7 +970,7 @@ extern "C" int fw_adjoint(fw_sim *sim, int n_steps, int ckpt_every, void *d_work
         }
     }
     if (A.fold_div) HIP_OR_FAIL(fw::launch_adjoint_finish(sim->ndim, A, st));
-    sim->host_step = n_steps;
+    HIP_OR_FAIL(hipMemcpyAsync(sim->d_step.ptr, lam + sim->state_end, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
     return FW_OK;
 }
 

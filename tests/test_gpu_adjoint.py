@@ -82,6 +82,26 @@ def test_checkpoint_interval_does_not_change_gradients():
     assert np.array_equal(s1, s2) and np.array_equal(s1, s3)
 
 
+def test_stepping_continues_after_the_adjoint():
+    """fw_adjoint leaves the state and the step counter of the forward run:
+    steps taken after it continue the forward run bit for bit (the sources
+    keep their time index)."""
+    import torch
+    case = _case(2, 2, seed=4, steps=150)
+    n = 100
+    ref = to_simulation(case)
+    ref.step(case.n_steps)
+    full = ref.read_receivers()
+    sim = to_simulation(case)
+    work = sim.adjoint_workspace(n, 30)
+    sim.forward_checkpointed(n, 30, work)
+    res = torch.ones((case.n_steps, len(case.rec_cell)), dtype=torch.float32, device="cuda")
+    sim.adjoint(n, 30, work, res)
+    assert sim.get_step() == n
+    sim.step(case.n_steps - n)
+    assert np.array_equal(sim.read_receivers(), full)
+
+
 def test_adjoint_central_difference_on_gpu():
     """Class-level derivatives from the adjoint (per-cell gradients summed
     over the cells of the class) vs central differences of J computed from
