@@ -170,8 +170,13 @@ class Simulation:
             grad_K = torch.zeros(ncell, dtype=torch.float32, device=self.device)
         if grad_s is None:
             grad_s = torch.zeros(ncell, dtype=torch.float32, device=self.device)
-        adj_src = adj_src.contiguous().to(device=self.device, dtype=torch.float32)
-        assert adj_src.numel() >= int(n_steps) * self.n_rec
+        for g in (grad_K, grad_s):
+            if g.dtype != torch.float32 or not g.is_contiguous() or g.numel() != ncell or g.device != self.device:
+                raise ValueError("gradient buffers must be contiguous float32 tensors of %d cells on %s"
+                                 % (ncell, self.device))
+        adj_src = adj_src.to(device=self.device, dtype=torch.float32).contiguous()
+        if adj_src.numel() < min(int(n_steps), self.n_t_max) * self.n_rec:
+            raise ValueError("adj_src needs [n_steps][n_rec] values")
         check(lib.fw_adjoint(self._h, int(n_steps), int(ckpt_every), ctypes.c_void_p(work.data_ptr()),
                              int(work.numel()), ctypes.c_void_p(adj_src.data_ptr()),
                              ctypes.c_void_p(grad_K.data_ptr()), ctypes.c_void_p(grad_s.data_ptr()),
