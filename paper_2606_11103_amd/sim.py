@@ -124,13 +124,21 @@ class Simulation:
     def state_bytes(self):
         return int(lib.fw_state_bytes(self._h))
 
+    def _check_state_buffer(self, buf):
+        if (buf.device != self.device or not buf.is_contiguous()
+                or buf.numel() * buf.element_size() < self.state_bytes()):
+            raise ValueError("state buffer must be a contiguous device tensor of at least %d bytes on %s"
+                             % (self.state_bytes(), self.device))
+
     def save_state(self, buf=None, stream=None):
         if buf is None:
             buf = self.torch.empty(self.state_bytes(), dtype=self.torch.uint8, device=self.device)
+        self._check_state_buffer(buf)
         check(lib.fw_save_state(self._h, ctypes.c_void_p(buf.data_ptr()), self._stream(stream)))
         return buf
 
     def load_state(self, buf, stream=None):
+        self._check_state_buffer(buf)
         check(lib.fw_load_state(self._h, ctypes.c_void_p(buf.data_ptr()), self._stream(stream)))
 
     def time_kernels(self, n_steps, stream=None):
