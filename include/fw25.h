@@ -167,11 +167,22 @@ int fw_step(fw_sim *sim, int n_steps, void *hip_stream);
  */
 int fw_read_receivers(fw_sim *sim, float *dst, int64_t n_elems, int dst_is_device, void *hip_stream);
 
-/* Zero every state field, the traces and the step counter (asynchronous). */
+/* Zero every state field, the traces and the step counter, and clear the
+ * finite-check flag (asynchronous). */
 int fw_reset_state(fw_sim *sim, void *hip_stream);
 
 /* Host view of the number of steps enqueued since the last reset. */
 int fw_get_step(const fw_sim *sim, int64_t *step);
+
+/*
+ * Finite check of every step: the source/receiver kernel (part of every
+ * step, inside captured graphs too, no extra launch) flags the first trace
+ * row, i.e. the 0-based step index as in fw_read_receivers, that holds a
+ * NaN or infinite receiver value.  *row receives that row, or -1 if none
+ * since the last reset (only rows below n_t_max are recorded and checked).
+ * Synchronises the stream.  fw_energy_step checks the whole field instead.
+ */
+int fw_first_nonfinite_step(fw_sim *sim, int64_t *row, void *hip_stream);
 
 /* Bytes of a full state snapshot (fields, memory variables, CPML variables
  * and the step counter); -1 on a NULL sim. */

@@ -76,6 +76,7 @@ struct SrcRecArgs {
     int64_t n_rec;
     int32_t n_t_max;
     int64_t *step;             // device step counter
+    int64_t *bad_row;          // first trace row holding a non-finite value, -1 if none
 };
 
 // d a / d s and d b / d s per mechanism when d -> s d (adjoint gradients)

@@ -643,8 +643,15 @@ __global__ __launch_bounds__(1024) void k_src_rec(const SrcRecArgs A)
     __threadfence();
     __syncthreads();
     if (t < A.n_t_max) {
-        for (int64_t r = threadIdx.x; r < A.n_rec; r += blockDim.x)
-            A.traces[t * A.n_rec + r] = A.p[A.rec_cell[r]];
+        bool bad = false;
+        for (int64_t r = threadIdx.x; r < A.n_rec; r += blockDim.x) {
+            const float val = A.p[A.rec_cell[r]];
+            A.traces[t * A.n_rec + r] = val;
+            bad = bad || !isfinite(val);
+        }
+        // finite check: every thread that saw a non-finite value writes the
+        // same row, and only while no earlier row has been flagged
+        if (bad && *A.bad_row < 0) *A.bad_row = t;
     }
     __syncthreads();
     if (threadIdx.x == 0) *A.step = t + 1;

@@ -280,6 +280,7 @@ fw::SrcRecArgs srcrec_args(const fw_sim *s)
     a.n_rec = s->n_rec;
     a.n_t_max = s->n_t_max;
     a.step = s->d_step.as<int64_t>();
+    a.bad_row = s->d_step.as<int64_t>() + 1;
     return a;
 }
 
@@ -409,8 +410,10 @@ int fw_bind_workspace(fw_sim *sim, void *d_ptr, int64_t bytes)
         return fail(FW_ENOMEM, "workspace too small: %lld < %lld bytes", (long long)bytes, (long long)sim->ws_bytes);
     sim->ws = static_cast<char *>(d_ptr);
     HIP_OR_FAIL(hipMemset(sim->ws, 0, (size_t)sim->ws_bytes));
-    HIP_OR_FAIL(sim->d_step.ensure(sizeof(int64_t)));
+    // [0] step counter, [1] first trace row with a non-finite value (-1)
+    HIP_OR_FAIL(sim->d_step.ensure(2 * sizeof(int64_t)));
     HIP_OR_FAIL(hipMemset(sim->d_step.ptr, 0, sizeof(int64_t)));
+    HIP_OR_FAIL(hipMemset(static_cast<char *>(sim->d_step.ptr) + sizeof(int64_t), 0xff, sizeof(int64_t)));
     sim->host_step = 0;
     sim->media_set = sim->table_set = false;
     sim->drop_graph();
@@ -709,9 +712,22 @@ int fw_reset_state(fw_sim *sim, void *hip_stream)
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     HIP_OR_FAIL(hipMemsetAsync(sim->ws, 0, (size_t)sim->state_end, st));
     HIP_OR_FAIL(hipMemsetAsync(sim->d_step.ptr, 0, sizeof(int64_t), st));
+    HIP_OR_FAIL(hipMemsetAsync(static_cast<char *>(sim->d_step.ptr) + sizeof(int64_t), 0xff, sizeof(int64_t), st));
     if (sim->n_rec > 0)
         HIP_OR_FAIL(hipMemsetAsync(sim->d_traces.ptr, 0, (size_t)sim->n_rec * std::max(sim->n_t_max, 1) * sizeof(float), st));
     sim->host_step = 0;
+    return FW_OK;
+}
+
+int fw_first_nonfinite_step(fw_sim *sim, int64_t *row, void *hip_stream)
+{
+    g_err.clear();
+    if (!sim || !row) return fail(FW_EINVAL, "NULL argument");
+    if (!sim->ws) return fail(FW_ESTATE, "no workspace bound");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    HIP_OR_FAIL(hipMemcpyAsync(row, static_cast<char *>(sim->d_step.ptr) + sizeof(int64_t), sizeof(int64_t),
+                               hipMemcpyDeviceToHost, st));
+    HIP_OR_FAIL(hipStreamSynchronize(st));
     return FW_OK;
 }
 

@@ -121,6 +121,13 @@ class Simulation:
         check(lib.fw_get_step(self._h, ctypes.byref(v)))
         return v.value
 
+    def first_nonfinite_step(self, stream=None):
+        """First trace row (0-based step) with a non-finite receiver value
+        since the last reset, or -1 (checked by every step on the device)."""
+        v = ctypes.c_int64()
+        check(lib.fw_first_nonfinite_step(self._h, ctypes.byref(v), self._stream(stream)))
+        return v.value
+
     def state_bytes(self):
         return int(lib.fw_state_bytes(self._h))
 

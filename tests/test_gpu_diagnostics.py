@@ -54,7 +54,17 @@ def test_non_finite_pressure_is_reported():
     case.waves[0, 4] = np.float32(3e38)
     sim = to_simulation(case)
     sim.step(4)
+    assert sim.first_nonfinite_step() == -1
     with pytest.raises(FWError) as ei:
         for _ in range(3):
             sim.energy_step()
     assert ei.value.code == FW_ENONFINITE
+    # the per-step receiver check flags the first trace row with a
+    # non-finite value once the overflow has spread to a receiver
+    sim.step(case.n_steps - sim.get_step())
+    tr = sim.read_receivers()
+    bad_rows = np.nonzero(~np.all(np.isfinite(tr), axis=1))[0]
+    assert bad_rows.size > 0
+    assert sim.first_nonfinite_step() == bad_rows[0]
+    sim.reset()
+    assert sim.first_nonfinite_step() == -1
