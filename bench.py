@@ -80,7 +80,7 @@ def bench_case(full=True):
 def fill_tables(case, allow_fit=True):
     from paper_2606_11103_amd import relax
     classes = dict(c=case.c, alpha0=case.alpha0, y=case.y)
-    kappa, d, al, fits = relax.tables_for(classes, case.nmech, allow_fit=allow_fit)
+    kappa, d, al, fits = relax.tables_for(classes, case.nmech, allow_fit=allow_fit, dt=case.dt)
     case.kappa, case.d, case.alpha = kappa, d, al
     return fits
 

@@ -78,18 +78,23 @@ def errors(alpha_sim, c_sim, c0, alpha0_db, y, freqs=MEASURE_FREQS):
 
 class SweepRun:
     """One batched 1D run: domain j holds relaxation table j (kappa [2],
-    d [2][N], alpha [2][N]) at speed c and density rho."""
+    d [2][N], alpha [2][N], as fitted) at speed c and density rho.  With
+    step_match the tables are relax.step_matched to the run's time step
+    before they are simulated (self.kappa, self.d, self.alpha hold what runs)."""
 
     def __init__(self, kappa, d, alpha, c=1540.0, rho=1000.0, n_cells=8192, pml=24, src_cell=64, cfl=0.2,
-                 f_top=20e6, ppw=16):
-        self.kappa = np.asarray(kappa, dtype=np.float64)
-        self.d = np.asarray(d, dtype=np.float64)
-        self.alpha = np.asarray(alpha, dtype=np.float64)
-        self.n_dom = self.kappa.shape[0]
-        self.nmech = self.d.shape[2]
+                 f_top=20e6, ppw=16, step_match=True):
         self.c, self.rho = float(c), float(rho)
         self.dx = c / (ppw * f_top)
         self.dt = cfl * self.dx / c
+        kappa = np.asarray(kappa, dtype=np.float64)
+        d = np.asarray(d, dtype=np.float64)
+        alpha = np.asarray(alpha, dtype=np.float64)
+        if step_match:
+            kappa, d, alpha = relax.step_matched(kappa, d, alpha, self.dt)
+        self.kappa, self.d, self.alpha = kappa, d, alpha
+        self.n_dom = self.kappa.shape[0]
+        self.nmech = self.d.shape[2]
         self.n_cells, self.pml, self.src_cell = int(n_cells), int(pml), int(src_cell)
         self.pairs = measurement_cells(self.dx, c, src_cell)
         if self.pairs.max() >= n_cells - pml:
@@ -167,7 +172,7 @@ def tone_burst(n_t, dt, f0, n_cycles, amplitude=1.0):
 
 
 def pml_reflection(kappa, d, alpha, c=1540.0, rho=1000.0, f0=1e6, ppw=16, cfl=0.2, pml_wavelengths=3.0,
-                   depth_wavelengths=5.0, n_cycles=3):
+                   depth_wavelengths=5.0, n_cycles=3, step_match=True):
     """Reflection coefficient of the CPML for each relaxation table, in dB
     (Sec. 4 protocol, 1D plane wave): source below the top layer, a receiver
     at 0.8 D towards the bottom layer D = 5 wavelengths away, 1 MHz
@@ -175,7 +180,8 @@ def pml_reflection(kappa, d, alpha, c=1540.0, rho=1000.0, f0=1e6, ppw=16, cfl=0.
     in two domains of one batched launch: one that ends in the layer and one
     long enough that nothing returns from its far end within the window; the
     reflected wave is the difference of the two receiver traces,
-    R = 20 log10(max|difference| / max|incident|)."""
+    R = 20 log10(max|difference| / max|incident|).  With step_match the
+    tables are relax.step_matched to the run's time step first."""
     from .sim import Simulation
     kappa = np.asarray(kappa, dtype=np.float64)
     d = np.asarray(d, dtype=np.float64)
@@ -184,6 +190,8 @@ def pml_reflection(kappa, d, alpha, c=1540.0, rho=1000.0, f0=1e6, ppw=16, cfl=0.
     lam = c / f0
     dx = lam / ppw
     dt = cfl * dx / c
+    if step_match:
+        kappa, d, alpha = relax.step_matched(kappa, d, alpha, dt)
     P = int(round(pml_wavelengths * ppw))
     D = int(round(depth_wavelengths * ppw))
     src = P + 4

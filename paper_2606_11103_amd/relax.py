@@ -62,6 +62,32 @@ def model_wavenumber(f_hz, c, kappa, d, alpha):
     return w / c / np.sqrt(S[0] * S[1])
 
 
+def step_matched(kappa, d, alpha, dt):
+    """Mechanisms for a run at time step dt with the relaxation response of
+    the fitted (continuous) ones.
+
+    The recursion of Eq. (relaxation_psi) with b = exp(-R dt),
+    R = d/kappa + alpha, behaves at frequencies w dt << 1 like a relaxation
+    with the same DC gain a / (1 - b) = -d / (kappa (d + kappa alpha)) but the
+    rate (e^{R dt} - 1) / dt instead of R.  A fitted mechanism of rate
+    r = d/kappa + alpha and strength g = (d/kappa) / r therefore becomes
+    R = ln(1 + r dt) / dt, d' = kappa g R, alpha' = (1 - g) R: kappa, every
+    DC gain and every low-frequency pole are kept, and b = 1 / (1 + r dt)
+    (a backward-Euler step of the relaxation equation).  Rates far below
+    1/dt are left almost unchanged; rates at or above it -- which a fit of the
+    continuous model uses freely, and which the recursion would otherwise
+    turn into a frequency-independent term with no attenuation -- are
+    pulled below it.  kappa [..][2], d and alpha [..][2][N]."""
+    kappa = np.asarray(kappa, dtype=np.float64)
+    d = np.asarray(d, dtype=np.float64)
+    alpha = np.asarray(alpha, dtype=np.float64)
+    k = kappa[..., None]
+    r = d / k + alpha
+    g = (d / k) / r
+    R = np.log1p(r * dt) / dt
+    return kappa.copy(), k * g * R, (1.0 - g) * R
+
+
 def _unpack(x, N):
     kappa = np.array([x[0], x[1]])
     d = 10.0 ** np.asarray(x[2:2 + 2 * N]).reshape(2, N)
@@ -148,10 +174,12 @@ def load_cache(path=CACHE_PATH):
     return {}
 
 
-def tables_for(classes, nmech, maxiter=50000, allow_fit=True, processes=None, path=CACHE_PATH):
+def tables_for(classes, nmech, maxiter=50000, allow_fit=True, processes=None, path=CACHE_PATH, dt=None):
     """Return (kappa [C][2], d [C][2][N], alpha [C][2][N], fits) for classes =
     dict(c=[...], alpha0=[...], y=[...]).  Rows come from the cache when
-    present; otherwise they are fitted (in parallel) and the cache is updated."""
+    present; otherwise they are fitted (in parallel) and the cache is updated.
+    With dt the tables are step_matched to that time step (the fits
+    themselves, in `fits`, stay those of the continuous model)."""
     cache = load_cache(path)
     items = list(zip(classes["c"], classes["alpha0"], classes["y"]))
     keys = [_key(c, a0, y, nmech, maxiter) for c, a0, y in items]
@@ -183,4 +211,6 @@ def tables_for(classes, nmech, maxiter=50000, allow_fit=True, processes=None, pa
     kappa = np.array([f["kappa"] for f in fits], dtype=np.float64)
     d = np.array([f["d"] for f in fits], dtype=np.float64)
     al = np.array([f["alpha"] for f in fits], dtype=np.float64)
+    if dt is not None:
+        kappa, d, al = step_matched(kappa, d, al, dt)
     return kappa, d, al, fits

@@ -57,12 +57,12 @@ def _discrete_figures(run, kappa, d, al):
 
 
 def test_simulated_attenuation_of_soft_tissue_class():
-    """The cached N = 2 fit of (c 1540, alpha0 0.5, y 1.1) and a lossless
-    table in one batched 1D run with CPML at both ends: the library's
-    two-receiver measurement equals an independent one; both domains follow
-    the scheme's exact discrete wavenumber (so the CPML leaves the
-    measurement untouched); the lossy class meets the 10 % label against the
-    power law."""
+    """The cached N = 2 fit of (c 1540, alpha0 0.5, y 1.1), step-matched to
+    the run's time step, and a lossless table in one batched 1D run with CPML
+    at both ends: the library's two-receiver measurement equals an
+    independent one; both domains follow the scheme's exact discrete
+    wavenumber (so the CPML leaves the measurement untouched); the lossy
+    class follows the power law within the 3 % bar."""
     key = [k for k in relax.load_cache() if k.startswith("c=1540.000000|a0=0.5|y=1.100000|N=2")]
     assert key, "cached fit of the soft-tissue class is missing"
     ft = relax.load_cache()[key[0]]
@@ -77,8 +77,8 @@ def test_simulated_attenuation_of_soft_tissue_class():
     np.testing.assert_allclose(a, ai, rtol=1e-9, atol=1e-9)
     np.testing.assert_allclose(c, ci, rtol=1e-12)
     nr, disp = calibrate.errors(a[0], c[0], 1540.0, 0.5, 1.1)
-    ad, cd = _discrete_figures(run, kappa[0], d[0], al[0])
-    a0d, c0d = _discrete_figures(run, kappa[1], d[1], al[1])
+    ad, cd = _discrete_figures(run, run.kappa[0], run.d[0], run.alpha[0])
+    a0d, c0d = _discrete_figures(run, run.kappa[1], run.d[1], run.alpha[1])
     _report("calibration soft tissue N=2: simulated NRMSE %.4f dispersion %.3f m/s; vs discrete scheme: "
             "alpha max rel %.2e, c max %.3f m/s; lossless max |alpha| %.3g Np/m, max |c - c_discrete| %.3g m/s"
             % (nr, disp, np.max(np.abs(a[0] / ad - 1)), np.abs(c[0] - cd).max(), np.abs(a[1]).max(),
@@ -87,7 +87,7 @@ def test_simulated_attenuation_of_soft_tissue_class():
     assert np.abs(c[0] - cd).max() < 0.1
     assert np.abs(a[1]).max() < 0.1
     assert np.abs(c[1] - c0d).max() < 0.1
-    assert nr < 0.10 and disp < 5.0
+    assert nr < 0.03 and disp < 2.0
 
 
 def test_weight_selection_over_the_sweep():

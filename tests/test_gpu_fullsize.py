@@ -36,7 +36,8 @@ def _report(line):
 def test_full_size_3d_workload_matches_oracle_on_the_field_support():
     from paper_2606_11103_amd import relax
     case = configs.heterogeneous_3d(shape=(960, 960, 720), steps=2000)
-    kappa, d, al, _ = relax.tables_for(dict(c=case.c, alpha0=case.alpha0, y=case.y), case.nmech, allow_fit=False)
+    kappa, d, al, _ = relax.tables_for(dict(c=case.c, alpha0=case.alpha0, y=case.y), case.nmech,
+                                      allow_fit=False, dt=case.dt)
     configs.with_table(case, kappa, d, al)
     K = 10
     print("full-size 3D", case.shapes, "steps", K, flush=True)
@@ -116,7 +117,8 @@ def test_full_size_3d_run_is_finite_and_loses_energy_after_the_source():
     staggered-time energy only decreases (attenuation, CPML absorption)."""
     from paper_2606_11103_amd import relax
     case = configs.heterogeneous_3d(shape=(960, 960, 720), steps=2000)
-    kappa, d, al, _ = relax.tables_for(dict(c=case.c, alpha0=case.alpha0, y=case.y), case.nmech, allow_fit=False)
+    kappa, d, al, _ = relax.tables_for(dict(c=case.c, alpha0=case.alpha0, y=case.y), case.nmech,
+                                      allow_fit=False, dt=case.dt)
     configs.with_table(case, kappa, d, al)
     print("full-size 3D, 2000 steps", flush=True)
     sim = to_simulation(case)
@@ -178,7 +180,8 @@ def test_full_size_adjoint_is_independent_of_the_checkpoint_interval():
     import torch
     case = configs.adjoint_2d(steps=110)
     from paper_2606_11103_amd import relax
-    kappa, d, al, _ = relax.tables_for(dict(c=case.c, alpha0=case.alpha0, y=case.y), case.nmech, allow_fit=False)
+    kappa, d, al, _ = relax.tables_for(dict(c=case.c, alpha0=case.alpha0, y=case.y), case.nmech,
+                                      allow_fit=False, dt=case.dt)
     configs.with_table(case, kappa, d, al)
     sim = to_simulation(case)
     out = []

@@ -53,7 +53,7 @@ def test_sweep_attenuation_and_dispersion():
     from paper_2606_11103_amd import relax
     case = configs.sweep_1d()
     kappa, d, al, fits = relax.tables_for(dict(c=case.c, alpha0=case.alpha0, y=case.y), case.nmech,
-                                          allow_fit=False)
+                                          allow_fit=False, dt=case.dt)
     configs.with_table(case, kappa, d, al)
     print("sweep", len(case.shapes), "domains x", case.shapes[0][0], "cells,", case.n_steps, "steps", flush=True)
     sim = to_simulation(case)
