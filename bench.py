@@ -166,6 +166,17 @@ def _time_steps(torch, sim, steps):
     return e0.elapsed_time(e1)
 
 
+def _tune(sim):
+    """Launch shape from the autotuner (timed live, no cache); results are
+    bitwise independent of it.  The step graph is re-captured untimed."""
+    from paper_2606_11103_amd.autotune import autotune
+    cfg, _ = autotune(sim, steps=4, cache_path=None, use_cache=False)
+    snap = sim.save_state()
+    sim.step(32)
+    sim.load_state(snap)
+    return cfg
+
+
 def bench_batched(torch, steps=40):
     """64 ragged 2D shots (384^2..1536^2, N = 4, 4-layer media) advanced
     together in one tile list, vs the same shots run one at a time."""
@@ -175,6 +186,8 @@ def bench_batched(torch, steps=40):
     configs.with_table(case, *configs.random_relaxation_table(4000, case.n_classes, case.nmech))
     sim = to_simulation(case)
     sim.step(32)                    # untimed: captures the step graph
+    ms_default = _time_steps(torch, sim, steps)
+    cfg = _tune(sim)
     ms = _time_steps(torch, sim, steps)
     batched = case.cells() * steps / (ms / 1e3) / 1e9
     del sim
@@ -203,6 +216,7 @@ def bench_batched(torch, steps=40):
     plain = cells * steps / (tot / 1e3) / 1e9
     return {"workload": case.name, "cells": case.cells(), "steps": steps,
             "batched_gcells": round(batched, 3), "ms_per_step": round(ms / steps, 4),
+            "launch_shape": cfg, "default_shape_gcells": round(case.cells() * steps / (ms_default / 1e3) / 1e9, 3),
             "plain_single_shot_gcells": round(plain, 3), "batched_vs_plain": round(batched / plain, 3),
             "plain_sample": "8 of the 64 shots, one simulation each"}
 
@@ -240,10 +254,13 @@ def bench_sweep(torch, steps=2000):
     tab = _tables_or_random(case, 3)
     sim = to_simulation(case)
     sim.step(32)                    # untimed: captures the step graph
+    ms_default = _time_steps(torch, sim, steps)
+    cfg = _tune(sim)
     ms = _time_steps(torch, sim, steps)
     return {"workload": case.name, "cells": case.cells(), "steps": steps, "tables": tab,
             "steps_of_full_run": case.n_steps,
-            "gcells": round(case.cells() * steps / (ms / 1e3) / 1e9, 3), "ms_per_step": round(ms / steps, 4)}
+            "gcells": round(case.cells() * steps / (ms / 1e3) / 1e9, 3), "ms_per_step": round(ms / steps, 4),
+            "launch_shape": cfg, "default_shape_gcells": round(case.cells() * steps / (ms_default / 1e3) / 1e9, 3)}
 
 
 def bench_adjoint(torch, steps=330, ckpt=55):
