@@ -32,7 +32,11 @@ def _rel(a, b):
 
 def _case(name):
     if name == "2d_homogeneous_256":
+        # the full 2D homogeneous workload with its calibrated, step-matched table
+        from paper_2606_11103_amd import relax
         c = configs.homogeneous_2d(256, 600)
+        k, d, al, _ = relax.tables_for(dict(c=c.c, alpha0=c.alpha0, y=c.y), c.nmech, allow_fit=False, dt=c.dt)
+        return configs.with_table(c, k, d, al)
     elif name == "2d_random_N4":
         c = configs.random_small(2, [(150, 130, 1)], 4, 3, seed=1, steps=300)
     elif name == "2d_random_N1_linear":
