@@ -426,7 +426,7 @@ def main():
     meas = TRAFFIC_MEASURED.get(kernel_source_hash())
     traffic = None
     if (meas is not None and not args.small and meas["workload"] == case.name
-            and (args.tile_rows or 16) == meas["tile_rows"] and (args.rows_per_thread or 1) == meas["rows_per_thread"]):
+            and (args.tile_rows or 4) == meas["tile_rows"] and (args.rows_per_thread or 1) == meas["rows_per_thread"]):
         traffic = round(meas["bytes_per_launch"] / (kern_ms[0] / 1e3) / 1e9, 1)
     ach_step = b_step * cells / (ms_step / 1e3) / 1e9
     out = {

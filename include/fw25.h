@@ -273,8 +273,9 @@ int fw_device_copy(void *d_dst, const void *d_src, int64_t bytes, void *hip_stre
 /*
  * Tuning and behaviour options (host only):
  *   FW_OPT_GRAPH_STEPS   steps per captured HIP graph (0 = eager only); default 16.
- *   FW_OPT_MARCH_CHUNK   cells of the marching axis per tile (>= 8); default auto.
- *   FW_OPT_TILE_ROWS     3D tile rows along y per block: 4, 8 or 16; default 16.
+ *   FW_OPT_MARCH_CHUNK   cells of the marching axis per tile (>= 8); default auto
+ *                        (3D: about 48 planes; 2D: a few thousand tiles in all).
+ *   FW_OPT_TILE_ROWS     3D tile rows along y per block: 4, 8 or 16; default 4.
  *   FW_OPT_ROWS_PER_THREAD  3D rows each thread owns: 1 or 2 (not with 4-row
  *                        tiles); default 1.
  *   FW_OPT_PERSISTENT    0: one workgroup per tile (default); k > 0: a

@@ -16,21 +16,21 @@ from .native import FW_OPT_MARCH_CHUNK, FW_OPT_PERSISTENT, FW_OPT_ROWS_PER_THREA
 
 CACHE_PATH = os.path.join(os.path.expanduser("~"), ".cache", "fw25_autotune.json")
 
-DEFAULT = {"tile_rows": 16, "rows_per_thread": 1, "march_chunk": 0, "persistent": 0}
+DEFAULT = {"tile_rows": 4, "rows_per_thread": 1, "march_chunk": 0, "persistent": 0}
 
 
 def candidates(ndim):
     out = []
     if ndim == 3:
-        for rows, rpt in ((8, 1), (16, 1), (16, 2), (8, 2), (4, 1)):
+        for rows, rpt in ((4, 1), (8, 1), (16, 1), (16, 2), (8, 2)):
             for persistent in (0, 4):
-                for chunk in (0, 45, 180):
+                for chunk in (0, 24, 96):
                     out.append({"tile_rows": rows, "rows_per_thread": rpt, "march_chunk": chunk,
                                 "persistent": persistent})
     else:
         for persistent in (0, 2, 4, 8):
             for chunk in ((0, 16, 64) if ndim == 2 else (0,)):
-                out.append({"tile_rows": 16, "rows_per_thread": 1, "march_chunk": chunk, "persistent": persistent})
+                out.append({"tile_rows": 4, "rows_per_thread": 1, "march_chunk": chunk, "persistent": persistent})
     return out
 
 

@@ -100,7 +100,7 @@ struct fw_sim {
     int64_t n_src = 0, n_rec = 0;
     int n_t = 0, n_t_max = 0;
     // options
-    int graph_steps = 16, march_chunk = 0, tile_rows = 16, rows_per_thread = 1, persistent = 0;
+    int graph_steps = 16, march_chunk = 0, tile_rows = 4, rows_per_thread = 1, persistent = 0;
     // stepping
     int64_t host_step = 0;
     hipStream_t cap_stream = nullptr;
@@ -214,8 +214,13 @@ int build_tiles(fw_sim *s)
         const int64_t nytile = s->ndim == 3 ? (ny + ty - 1) / ty : 1;
         const int64_t nxtile = (nx + tx - 1) / tx;
         int64_t chunk = s->march_chunk;
-        if (chunk <= 0) {
-            // aim for a few thousand tiles over all domains, chunks of >= 32 planes
+        if (chunk <= 0 && s->ndim == 3) {
+            // about 48 planes per tile (measured best: many small 4-wave tiles
+            // keep several independent blocks on each CU)
+            const int64_t nch = (nmarch + 47) / 48;
+            chunk = (nmarch + nch - 1) / nch;
+        } else if (chunk <= 0) {
+            // aim for a few thousand tiles over all domains, chunks of >= 16 planes
             const int64_t cols = nxtile * nytile;
             chunk = nmarch;
             while (chunk > 16 && cols * ((nmarch + chunk - 1) / chunk) < 4096) chunk = (chunk + 1) / 2;
