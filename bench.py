@@ -30,8 +30,8 @@ HBM_PEAK_GBS = 8000.0
 # copy kernel), keyed by the SHA-256 prefix of the kernel source they were
 # taken on; any other kernel source reports traffic as null.
 TRAFFIC_MEASURED = {
-    "42ee0b1c4cb5255b": {"workload": "3d_heterogeneous_960x960x720", "tile_rows": 16, "rows_per_thread": 1,
-                         "bytes_per_launch": 85.86e9,
+    "baca8324244d30dc": {"workload": "3d_heterogeneous_960x960x720", "tile_rows": 4, "rows_per_thread": 1,
+                         "bytes_per_launch": 88.67e9,
                          "profile": "profiles/step_kernels_3d_960x960x720_N4.md"},
 }
 
