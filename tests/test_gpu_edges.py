@@ -1,0 +1,85 @@
+"""Edge cases of the HIP path against the FP64 oracle: no sources, a closed
+box without CPML, the smallest admissible domains in a ragged batch,
+sources and receivers on the grid's corners and faces, repeated receivers."""
+import zlib
+
+import numpy as np
+import pytest
+
+from workloads import configs, linear_index
+from workloads.adapters import oracle_traces, to_simulation
+
+pytestmark = pytest.mark.gpu
+
+
+def _report(line):
+    import os
+    os.makedirs("gpurun_out", exist_ok=True)
+    with open(os.path.join("gpurun_out", "parity.txt"), "a") as fh:
+        fh.write(line + "\n")
+    print(line, flush=True)
+
+
+def _tables(case, name):
+    return configs.with_table(case, *configs.random_relaxation_table(zlib.crc32(name.encode()) % 1000,
+                                                                     case.n_classes, case.nmech))
+
+
+def _parity(case, name):
+    print("edge case", name, case.shapes, flush=True)
+    sim = to_simulation(case)
+    sim.step(case.n_steps)
+    got = sim.read_receivers().astype(np.float64)
+    ref = oracle_traces(case)
+    rel = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    _report("edge %s rel_L2=%.3e steps=%d receivers=%d" % (name, rel, case.n_steps, len(case.rec_cell)))
+    assert np.abs(ref).max() > 0 and rel <= 1e-4
+    return got
+
+
+def test_without_sources_the_field_stays_zero():
+    case = _tables(configs.random_small(3, [(30, 28, 26)], 2, 2, seed=5, steps=40), "nosrc")
+    case.src_domain = case.src_domain[:0]
+    case.src_cell = case.src_cell[:0]
+    case.src_wave = case.src_wave[:0]
+    sim = to_simulation(case)
+    sim.step(39)
+    e = sim.energy_step()[0]
+    assert e[0] == 0.0 and e[1] == 0.0 and e[2] == 0
+    assert np.all(sim.read_receivers() == 0.0)
+
+
+def test_closed_box_without_cpml():
+    case = _tables(configs.random_small(2, [(90, 70, 1)], 3, 3, seed=12, steps=300, pml=0), "nopml")
+    _parity(case, "no_cpml_2d")
+
+
+def test_smallest_domains_in_a_ragged_batch():
+    """Every used dimension at its minimum, 2 P + 9 (P = 4), next to larger
+    domains of the same batch, in 3D and 1D."""
+    P = 4
+    m = 2 * P + 9
+    case = _tables(configs.random_small(3, [(m, m, m), (m + 13, m, m + 2), (m, m + 21, m)], 2, 2, seed=14,
+                                        steps=60, pml=P), "min3d")
+    _parity(case, "smallest_3d")
+    case = _tables(configs.random_small(1, [(m, 1, 1), (m + 1, 1, 1), (64, 1, 1)], 3, 2, seed=15, steps=80,
+                                        pml=P), "min1d")
+    _parity(case, "smallest_1d")
+
+
+def test_sources_and_receivers_on_corners_and_faces():
+    """Point sources in two opposite corners (inside the CPML) and receivers
+    on every face, corner and edge; one receiver cell listed three times."""
+    shp = (37, 31, 29)
+    case = _tables(configs.random_small(3, [shp], 2, 3, seed=16, steps=90, pml=5, amplitude=3e5), "corners")
+    nx, ny, nz = shp
+    src = [linear_index(shp, 0, 0, 0), linear_index(shp, nx - 1, ny - 1, nz - 1)]
+    case.src_domain = np.zeros(2, np.int32)
+    case.src_cell = np.array(src, np.int64)
+    case.src_wave = np.zeros(2, np.int32)
+    rec = [linear_index(shp, x, y, z) for x in (0, nx // 2, nx - 1) for y in (0, ny - 1) for z in (0, nz // 3, nz - 1)]
+    rec += [linear_index(shp, 1, 1, 1)] * 3
+    case.rec_domain = np.zeros(len(rec), np.int32)
+    case.rec_cell = np.array(rec, np.int64)
+    got = _parity(case, "corners_faces_3d")
+    assert np.array_equal(got[:, -1], got[:, -2]) and np.array_equal(got[:, -1], got[:, -3])
