@@ -131,6 +131,11 @@ int fw_set_media(fw_sim *sim, const uint8_t *h_class, const int32_t *class_base,
  * coefficients a, b of Eqs. (relaxation_a)/(relaxation_b) are computed in
  * FP64 on the host and rounded to FP32 for the device.  Re-checks the
  * stability bound with 1/sqrt(min kappa_1 kappa_2).
+ * The parameters are used as given.  The recursion keeps each mechanism's
+ * DC gain but realises the rate r = d/kappa + alpha as (e^{r dt} - 1)/dt, so
+ * a fit of the continuous model reaches its attenuation only where
+ * r dt << 1; mechanisms fitted without regard to dt should be mapped to the
+ * time step first (same kappa and DC gains, rate ln(1 + r dt)/dt).
  */
 int fw_set_relaxation_table(fw_sim *sim, int n_classes, const double *kappa,
                             const double *d, const double *alpha);
@@ -156,8 +161,9 @@ int fw_set_receivers(fw_sim *sim, int64_t n_rec, const int32_t *domain, const in
  * Advance every domain by n_steps time steps on hip_stream (asynchronous).
  * One step = velocity update (gradient, N memory variables per axis, CPML)
  * -> pressure update (divergence, N memory variables, CPML, nonlinearity)
- * -> sources -> receivers -> device step counter + 1.  Replays captured HIP
- * graphs of the configured length, with eager launches for the remainder.
+ * -> sources -> receivers (with the finite check of fw_first_nonfinite_step)
+ * -> device step counter + 1.  Replays captured HIP graphs of the configured
+ * length, with eager launches for the remainder.
  */
 int fw_step(fw_sim *sim, int n_steps, void *hip_stream);
 
