@@ -177,7 +177,7 @@ def _tune(sim):
     return cfg
 
 
-def bench_batched(torch, steps=40):
+def bench_batched(torch, steps=200):
     """64 ragged 2D shots (384^2..1536^2, N = 4, 4-layer media) advanced
     together in one tile list, vs the same shots run one at a time."""
     from workloads import configs
@@ -263,11 +263,12 @@ def bench_sweep(torch, steps=2000):
             "launch_shape": cfg, "default_shape_gcells": round(case.cells() * steps / (ms_default / 1e3) / 1e9, 3)}
 
 
-def bench_adjoint(torch, steps=330, ckpt=55):
+def bench_adjoint(torch, steps=3000, ckpt=55):
     """Gradient of J = 1/2 dt sum (r - d)^2 w.r.t. c(x), alpha0(x) for the 16-shot
-    1024^2 N = 4 workload (observed data: true model; current model: c x 0.99),
-    forward with checkpoints every 55 steps + adjoint sweep, vs the plain
-    forward of the same steps."""
+    1024^2 N = 4 workload over its 3000 steps (observed data: true model;
+    current model: c x 0.99), forward with checkpoints every 55 steps +
+    adjoint sweep (about 111 GB of checkpoints and segment states), vs the
+    plain forward of the same steps."""
     from workloads import configs
     from workloads.adapters import to_simulation
     case = configs.adjoint_2d(steps=steps)
@@ -283,6 +284,7 @@ def bench_adjoint(torch, steps=330, ckpt=55):
     ms_fwd = _time_steps(torch, sim, steps)
     sim.reset()
     work = sim.adjoint_workspace(steps, ckpt)
+    work_bytes = work.numel()
 
     def gradient():
         sim.forward_checkpointed(steps, ckpt, work)
@@ -302,7 +304,8 @@ def bench_adjoint(torch, steps=330, ckpt=55):
     misfit = float(0.5 * case.dt * ((tr.double() - obs.double()) ** 2).sum())
     finite = bool(torch.isfinite(gK).all() and torch.isfinite(gs).all())
     del work
-    return {"workload": case.name + " (%d of %d steps)" % (steps, 3000), "cells": case.cells(), "steps": steps,
+    return {"workload": case.name + (" (%d steps)" % steps if steps == 3000 else " (%d of 3000 steps)" % steps),
+            "cells": case.cells(), "steps": steps, "workspace_gb": round(work_bytes / 1e9, 1),
             "checkpoint_every": ckpt, "forward_ms": round(ms_fwd, 2), "gradient_ms": round(ms_grad, 2),
             "gradient_vs_forward": round(ms_grad / ms_fwd, 3),
             "forward_gcells": round(case.cells() * steps / (ms_fwd / 1e3) / 1e9, 3),
