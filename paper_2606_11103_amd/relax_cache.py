@@ -1,6 +1,7 @@
 """Fill the relaxation-table cache (data/relax_tables.json) for the named
 workloads by running the FP64 calibration (relax.fit_class) on every class
-that is not cached yet.  Usage: python -m paper_2606_11103_amd.relax_cache"""
+that is not cached yet.  Usage: python -m paper_2606_11103_amd.relax_cache
+[--adjoint] [--sweep] [--library] [--procs=N]"""
 import sys
 import time
 
@@ -19,6 +20,12 @@ def main():
         jobs = [("2d_adjoint", configs.adjoint_2d(n=64, n_shots=1, steps=10, n_rec=4, pml=8), 4)]
     if "--sweep" in sys.argv:
         jobs.append(("1d_sweep", configs.sweep_1d(n_cells=64, steps=10, pml=8), 2))
+    if "--library" in sys.argv:
+        lib = configs.library_classes()
+
+        class _Lib:
+            c, alpha0, y = lib["c"], lib["alpha0"], lib["y"]
+        jobs.append(("library", _Lib, 2))
     for name, case, N in jobs:
         t = time.time()
         _, _, _, fits = relax.tables_for(dict(c=case.c, alpha0=case.alpha0, y=case.y), N, processes=int(next((a.split('=')[1] for a in sys.argv if a.startswith('--procs=')), 6)))

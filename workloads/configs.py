@@ -207,6 +207,16 @@ def random_small(ndim, shapes, nmech, n_classes, seed, steps, pml=6, nonlinear=T
 SWEEP_ALPHA0 = 0.0022 * (1.0 / 0.0022) ** (np.arange(32) / 31.0)
 SWEEP_Y = 0.4 + 0.1 * np.arange(17)
 SWEEP_FREQS = 1e6 + 2.714e6 * np.arange(8)
+# relaxation library grid: 63 log-spaced alpha0 (every other one is a sweep
+# value) x the 17 sweep exponents = 1071 (alpha0, y) cells
+LIBRARY_ALPHA0 = 0.0022 * (1.0 / 0.0022) ** (np.arange(63) / 62.0)
+LIBRARY_Y = SWEEP_Y
+
+
+def library_classes(c=1540.0):
+    """dict(c, alpha0, y) of every cell of the relaxation library grid."""
+    A0, Y = np.meshgrid(LIBRARY_ALPHA0, LIBRARY_Y, indexing="ij")
+    return dict(c=np.full(A0.size, c), alpha0=A0.ravel(), y=Y.ravel())
 
 
 def sweep_receiver_cells(dx, c=1540.0, src_cell=64, freqs=None):
