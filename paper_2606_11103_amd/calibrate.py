@@ -220,3 +220,78 @@ def pml_reflection(kappa, d, alpha, c=1540.0, rho=1000.0, f0=1e6, ppw=16, cfl=0.
     refl = np.abs(short - long_).max(axis=0)
     inc = np.abs(long_).max(axis=0)
     return 20.0 * np.log10(np.maximum(refl, 1e-300) / inc)
+
+
+def two_layer_validation(layers, c=1540.0, rho=1000.0, f_pulse=5e6, n_cycles=3, ppw=16, f_top=20e6, cfl=0.2,
+                         step_match=True):
+    """Two-layer check of Sec. 4 (equal c and rho, different power laws).
+
+    layers: list of pairs ((kappa, d, alpha) of layer 1, (kappa, d, alpha) of
+    layer 2), fitted tables.  Per pair, three 1D domains run in one batched
+    launch: a two-layer domain with the broadband source, in which the
+    two-receiver attenuation is measured inside each layer (receivers at
+    0.05 D and 0.8 D from the source, and from the interface, per frequency);
+    and a two-layer and a homogeneous layer-1 domain with a Gaussian pulse at
+    f_pulse, whose difference at a receiver between source and interface is
+    the wave reflected by the interface.  Returns per pair a dict with the
+    measured alpha [2][8] and c [2][8] of the layers and R_db =
+    20 log10(max|reflected| / max|incident|)."""
+    from .sim import Simulation
+    dx = c / (ppw * f_top)
+    dt = cfl * dx / c
+    P, src = 24, 64
+    pairs = measurement_cells(dx, c, 0)                      # offsets from a start cell
+    x_if = src + int(pairs.max()) + 136                      # first cell of layer 2
+    x_refl = x_if - 300                                      # receiver of the reflection domains
+    n = x_if + int(pairs.max()) + 200 + P
+    n_steps = int(round((x_if + int(pairs.max()) - src) * dx / c / dt)) + 2000
+    tabs = []
+    for l1, l2 in layers:
+        for k, d_, a_ in (l1, l2):
+            k, d_, a_ = (np.asarray(v, dtype=np.float64)[None] for v in (k, d_, a_))
+            if step_match:
+                k, d_, a_ = relax.step_matched(k, d_, a_, dt)
+            tabs.append((k[0], d_[0], a_[0]))
+    n_pair = len(layers)
+    nd = 3 * n_pair
+    maps, base = [], []
+    two = np.zeros(n, np.uint8)
+    two[x_if:] = 1
+    for j in range(n_pair):
+        maps += [two, two, np.zeros(n, np.uint8)]
+        base += [2 * j] * 3
+    rec_att = np.unique(np.concatenate([src + pairs.ravel(), x_if + pairs.ravel()]))
+    rd, rc = [], []
+    for j in range(n_pair):
+        rd += [3 * j] * rec_att.size + [3 * j + 1, 3 * j + 2]
+        rc += list(rec_att) + [x_refl, x_refl]
+    waves = np.stack([broadband_pulse(n_steps, dt), tone_burst(n_steps, dt, f_pulse, n_cycles)])
+    sim = Simulation(1, [(n, 1, 1)] * nd, dx, dt, tabs[0][1].shape[1], P)
+    try:
+        sim.set_media(maps, base, np.full(2 * n_pair, c), np.full(2 * n_pair, rho), np.zeros(2 * n_pair))
+        sim.set_relaxation_table(np.array([t[0] for t in tabs]), np.array([t[1] for t in tabs]),
+                                 np.array([t[2] for t in tabs]))
+        sim.set_sources(np.arange(nd), np.full(nd, src), np.array([0, 1, 1] * n_pair), waves)
+        sim.set_receivers(np.array(rd), np.array(rc), n_steps)
+        sim.step(n_steps)
+        tr = sim.read_receivers().astype(np.float64)
+    finally:
+        sim.close()
+    out = []
+    stride = rec_att.size + 2
+    col = {int(v): i for i, v in enumerate(rec_att)}
+    for j in range(n_pair):
+        t = tr[:, j * stride:(j + 1) * stride]
+        alpha = np.zeros((2, len(MEASURE_FREQS)))
+        cph = np.zeros_like(alpha)
+        for layer, start in enumerate((src, x_if)):
+            for k, f in enumerate(MEASURE_FREQS):
+                a, b = col[start + int(pairs[k, 0])], col[start + int(pairs[k, 1])]
+                dist = (pairs[k, 1] - pairs[k, 0]) * dx
+                P2 = spectra(t[:, [a, b]], dt, [f])[0]
+                al, cc = two_receiver_figures(P2[:1], P2[1:], dist, f, c)
+                alpha[layer, k], cph[layer, k] = al[0], cc[0]
+        refl = np.abs(t[:, -2] - t[:, -1]).max()
+        out.append(dict(alpha=alpha, c=cph, R_db=float(20.0 * np.log10(max(refl, 1e-300) / np.abs(t[:, -1]).max())),
+                        interface_cell=x_if, reflection_receiver=x_refl, n_steps=n_steps, dx=dx, dt=dt))
+    return out

@@ -134,3 +134,51 @@ def test_weight_selection_over_the_library():
     np.save("gpurun_out/library_selection.npy", np.stack([lib["alpha0"], lib["y"], best, ok]))
     assert ok.sum() >= 0.7 * len(fits)
     assert best[ok].mean() < 0.03
+
+
+def test_two_layer_tissue_pairs():
+    """Sec. 4 two-layer check (c and rho equal across the interface): muscle
+    (alpha0 0.15, y 1.0), fat (0.40, 1.1) and liver (0.50, 1.1) in the pairs
+    the paper uses.  Per-layer attenuation NRMSE against each layer's power
+    law, and the interface reflection of a 5 MHz pulse; the reflection of one
+    pair is recomputed on the FP64 oracle."""
+    from oracle.solver import OracleSim
+    cache = relax.load_cache()
+    tissues = {"muscle": (0.15, 1.0), "fat": (0.40, 1.1), "liver": (0.50, 1.1)}
+    fits = {}
+    for name, (a0, y) in tissues.items():
+        f = cache.get(relax._key(1540.0, a0, y, 2, 50000))
+        if f is None:
+            pytest.skip("tissue fits not cached")
+        fits[name] = f
+    order = [("muscle", "fat"), ("muscle", "liver"), ("fat", "liver")]
+    paper = {("muscle", "fat"): (1.18, 0.847, -63.0), ("muscle", "liver"): (1.18, 1.41, -50.2),
+             ("fat", "liver"): (0.978, 2.32, -50.5)}
+    tab = lambda f: (f["kappa"], f["d"], f["alpha"])
+    res = calibrate.two_layer_validation([(tab(fits[a]), tab(fits[b])) for a, b in order])
+    for (a, b), r in zip(order, res):
+        nr = [calibrate.errors(r["alpha"][i], r["c"][i], 1540.0, *tissues[t])[0] for i, t in enumerate((a, b))]
+        _report("two-layer %s -> %s: NRMSE layer 1 %.2f %% layer 2 %.2f %%, interface reflection %.1f dB "
+                "(paper: %.2f %%, %.2f %%, %.1f dB)" % (a, b, 100 * nr[0], 100 * nr[1], r["R_db"], *paper[(a, b)]))
+        assert max(nr) < 0.03
+        assert r["R_db"] < -40.0
+    # FP64 oracle: the muscle -> liver reflection with the same tables and geometry
+    r = res[1]
+    k, d, al = relax.step_matched(np.array([fits["muscle"]["kappa"], fits["liver"]["kappa"]]),
+                                  np.array([fits["muscle"]["d"], fits["liver"]["d"]]),
+                                  np.array([fits["muscle"]["alpha"], fits["liver"]["alpha"]]), r["dt"])
+    n = r["interface_cell"] + 2560 + 200 + 24
+    t = (np.arange(r["n_steps"]) + 1.0) * r["dt"] - 4 * (3 / (2 * 5e6))
+    w = (np.sin(2 * np.pi * 5e6 * t) * np.exp(-(t / (3 / (2 * 5e6))) ** 2)).astype(np.float32).astype(np.float64)
+    out = []
+    for two in (True, False):
+        cm = np.zeros(n, np.uint8)
+        if two:
+            cm[r["interface_cell"]:] = 1
+        sim = OracleSim(1, (n, 1, 1), r["dx"], r["dt"], 2, cm, [1540.0, 1540.0], [1000.0, 1000.0], [0.0, 0.0],
+                        k, d, al, pml_cells=24, pml_c_ref=1540.0)
+        tr, _ = sim.run(r["n_steps"], [64], w[None, :], [r["reflection_receiver"]])
+        out.append(tr[:, 0])
+    R_or = 20 * np.log10(np.abs(out[0] - out[1]).max() / np.abs(out[1]).max())
+    _report("two-layer muscle -> liver reflection: library %.2f dB, FP64 oracle %.2f dB" % (r["R_db"], R_or))
+    assert abs(r["R_db"] - R_or) < 1.0
