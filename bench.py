@@ -246,6 +246,21 @@ def bench_two_layer(torch, steps=400):
             "gcells": round(case.cells() * steps / (ms / 1e3) / 1e9, 3), "ms_per_step": round(ms / steps, 4)}
 
 
+def bench_paper_shape(torch, steps=100):
+    """The 3D recipe at the grid of the paper's one timed run (499 x 499 x 1247
+    cells, N = 2), for a like-for-like look at its derived 2.05e9
+    cell-updates/s per H100 (context, not a target)."""
+    from workloads import configs
+    from workloads.adapters import to_simulation
+    case = configs.heterogeneous_3d(shape=(499, 499, 1247), steps=steps + 32, n_elem=64, nmech=2)
+    tab = _tables_or_random(case, 5)
+    sim = to_simulation(case)
+    sim.step(32)                    # untimed: captures the step graph
+    ms = _time_steps(torch, sim, steps)
+    return {"workload": case.name, "cells": case.cells(), "steps": steps, "tables": tab,
+            "gcells": round(case.cells() * steps / (ms / 1e3) / 1e9, 3), "ms_per_step": round(ms / steps, 4)}
+
+
 def bench_sweep(torch, steps=2000):
     """1D sweep: 544 domains x 8192 cells, N = 2, one batched launch."""
     from workloads import configs
@@ -353,7 +368,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched, adjoint, two-layer 2D and 1D sweep workloads")
-    ap.add_argument("--only", choices=("batched", "adjoint", "two_layer", "sweep"), default=None,
+    ap.add_argument("--only", choices=("batched", "adjoint", "two_layer", "sweep", "paper_shape"), default=None,
                     help="run only one comparison workload and print its JSON (profiling)")
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--march-chunk", type=int, default=0)
@@ -378,7 +393,7 @@ def main():
     if args.only:
         torch.cuda.set_device(0)
         fn = dict(batched=bench_batched, adjoint=bench_adjoint, two_layer=bench_two_layer,
-                  sweep=bench_sweep)[args.only]
+                  sweep=bench_sweep, paper_shape=bench_paper_shape)[args.only]
         print(json.dumps(fn(torch)), flush=True)
         return
     from paper_2606_11103_amd.native import FW_OPT_MARCH_CHUNK, FW_OPT_ROWS_PER_THREAD, FW_OPT_TILE_ROWS
@@ -474,6 +489,9 @@ def main():
         torch.cuda.empty_cache()
         print("# 1D sweep ...", file=sys.stderr, flush=True)
         out["sweep_1d"] = bench_sweep(torch)
+        torch.cuda.empty_cache()
+        print("# paper's 3D shape, N = 2 ...", file=sys.stderr, flush=True)
+        out["paper_shape_3d"] = bench_paper_shape(torch)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         print("# cpu baseline ...", file=sys.stderr, flush=True)

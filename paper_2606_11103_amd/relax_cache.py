@@ -15,6 +15,7 @@ def main():
         ("2d_homogeneous", configs.homogeneous_2d(64, 10), 2),
         ("2d_two_layer", configs.two_layer_2d(64, 10, n_rec=2), 4),
         ("3d_heterogeneous", configs.heterogeneous_3d(shape=(64, 64, 64), steps=10, n_elem=4), 4),
+        ("3d_heterogeneous_N2", configs.heterogeneous_3d(shape=(64, 64, 64), steps=10, n_elem=4, nmech=2), 2),
     ]
     if "--adjoint" in sys.argv:
         jobs = [("2d_adjoint", configs.adjoint_2d(n=64, n_shots=1, steps=10, n_rec=4, pml=8), 4)]

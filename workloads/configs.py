@@ -122,7 +122,7 @@ def two_layer_2d(n=2048, steps=4000, n_rec=128):
         n_steps=steps)
 
 
-def heterogeneous_3d(shape=(960, 960, 720), steps=2000, seed=3, noise_seed=33, n_elem=64):
+def heterogeneous_3d(shape=(960, 960, 720), steps=2000, seed=3, noise_seed=33, n_elem=64, nmech=4):
     """3D heterogeneous: 960 x 960 x 720 cells (z slowest), dx = 0.1 mm,
     24-cell CPML, 8 tissue classes (seed 3) from a smoothed random label field,
     +-1 % per-voxel speed perturbation (SplitMix64 seed 33), N = 4, CFL 0.4 on
@@ -159,7 +159,8 @@ def heterogeneous_3d(shape=(960, 960, 720), steps=2000, seed=3, noise_seed=33, n
     rz = rz[rz < nz - P]
     rec_cell = np.concatenate([linear_index(shape, x_e, cy, zs), linear_index(shape, cx, cy, rz)])
     return Case(
-        name="3d_heterogeneous_%dx%dx%d" % shape, ndim=3, shapes=[tuple(shape)], dx=dx, dt=dt, nmech=4,
+        name="3d_heterogeneous_%dx%dx%d" % tuple(shape) + ("" if nmech == 4 else "_N%d" % nmech), ndim=3,
+        shapes=[tuple(shape)], dx=dx, dt=dt, nmech=nmech,
         pml_cells=P, class_maps=[lab], class_base=[0],
         c=cls["c"], rho=cls["rho"], alpha0=cls["alpha0"], y=cls["y"], b_over_a=cls["b_over_a"], nonlinear=True,
         src_domain=np.zeros(len(sx), np.int32), src_cell=src_cell, src_wave=np.array(sw, np.int32), waves=waves,
