@@ -18,9 +18,10 @@ and phase speed are measured as in Sec. 4.1-4.2:
   divided by the target's range) and dispersion RMSE against the
   Kramers-Kronig phase speed of Eq. (kk_relation).
 
-Selection: lowest simulated NRMSE, ties to the lower dispersion error, then
-to the smaller w.  A class is labelled failed above 10 % NRMSE or 5 m/s
-dispersion error.
+Selection (relax.choose with the simulated figures): the lowest simulated
+NRMSE among the candidates within both bars of the failure label (10 % NRMSE,
+5 m/s dispersion error), else among all; ties to the lower dispersion error,
+then to the smaller w.
 """
 import math
 
@@ -139,8 +140,8 @@ class SweepRun:
 
 def select_weights(fits, c=1540.0, rho=1000.0, **kw):
     """For fitted classes (relax.fit_class results carrying "cands"), simulate
-    every candidate and pick the weight with the lowest simulated attenuation
-    NRMSE.  Returns (chosen fits, nrmse [n_class][n_cand], disp [n_class][n_cand])."""
+    every candidate and pick the weight by relax.choose on the simulated
+    figures.  Returns (chosen fits, nrmse [n_class][n_cand], disp [n_class][n_cand])."""
     n_cls = len(fits)
     n_cand = len(fits[0]["cands"])
     flat = [cd for ft in fits for cd in ft["cands"]]
@@ -155,10 +156,10 @@ def select_weights(fits, c=1540.0, rho=1000.0, **kw):
     for i, ft in enumerate(fits):
         for j in range(n_cand):
             nr[i, j], dp[i, j] = errors(alpha[i * n_cand + j], cph[i * n_cand + j], c, ft["alpha0"], ft["y"])
-        j = min(range(n_cand), key=lambda q: (nr[i, q], dp[i, q], ft["cands"][q]["w"]))
+        j = relax.choose(ft["cands"], nr[i], dp[i])
         pick = dict(ft["cands"][j])
         pick.update(c=ft["c"], alpha0=ft["alpha0"], y=ft["y"], nmech=ft["nmech"], sim_nrmse=float(nr[i, j]),
-                    sim_disp=float(dp[i, j]), failed=bool(nr[i, j] > 0.10 or dp[i, j] > 5.0))
+                    sim_disp=float(dp[i, j]), failed=not relax.passes(nr[i, j], dp[i, j]))
         chosen.append(pick)
     return chosen, nr, dp
 

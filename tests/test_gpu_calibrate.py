@@ -90,50 +90,58 @@ def test_simulated_attenuation_of_soft_tissue_class():
     assert nr < 0.03 and disp < 2.0
 
 
+def _selection_stats(fits, nr, dp):
+    """Per class: the candidate chosen on the simulated figures and the one
+    chosen on the closed-form figures, with their simulated NRMSE."""
+    j_sim = np.array([relax.choose(f["cands"], nr[i], dp[i]) for i, f in enumerate(fits)])
+    j_mod = np.array([relax.choose(f["cands"]) for f in fits])
+    rows = np.arange(len(fits))
+    ok = np.array([relax.passes(nr[i, j], dp[i, j]) for i, j in enumerate(j_sim)])
+    return j_sim, j_mod, nr[rows, j_sim], nr[rows, j_mod], dp[rows, j_sim], ok
+
+
 def test_weight_selection_over_the_sweep():
     case = configs.sweep_1d(n_cells=64, steps=10, pml=8)
     cache = relax.load_cache()
     keys = [relax._key(c, a0, y, 2, 50000) for c, a0, y in zip(case.c, case.alpha0, case.y)]
-    fits = [cache.get(k) for k in keys]
-    if any(f is None or "cands" not in f for f in fits):
+    if any(k not in cache or "cands" not in cache[k] for k in keys):
         pytest.skip("sweep fits with per-weight candidates are not cached")
+    fits = [relax.effective(cache[k]) for k in keys]
     chosen, nr, dp = calibrate.select_weights(fits)
-    n_cand = nr.shape[1]
-    model_pick = np.array([[cd["w"] for cd in f["cands"]].index(f["w"]) for f in fits])
-    sim_model = nr[np.arange(len(fits)), model_pick]
-    sim_best = nr.min(axis=1)
-    assert np.all(sim_best <= sim_model)
-    ok = np.array([not c["failed"] for c in chosen])
-    _report("weight selection %d classes x %d weights: valid %d, simulated NRMSE mean %.4f sd %.4f "
-            "(model-selected weights: %.4f), dispersion mean %.3f m/s"
-            % (len(fits), n_cand, ok.sum(), sim_best[ok].mean(), sim_best[ok].std(), sim_model[ok].mean(),
-               dp[np.arange(len(fits)), nr.argmin(axis=1)][ok].mean()))
-    np.save("gpurun_out/weight_selection.npy", np.stack([case.alpha0, case.y, sim_best, sim_model, ok]))
+    j_sim, j_mod, nr_sim, nr_mod, dp_sim, ok = _selection_stats(fits, nr, dp)
+    assert np.array_equal(j_sim, [[cd["w"] for cd in f["cands"]].index(c["w"]) for f, c in zip(fits, chosen)])
+    ok_mod = np.array([relax.passes(nr[i, j], dp[i, j]) for i, j in enumerate(j_mod)])
+    _report("weight selection %d classes x %d weights: within both bars %d (closed-form choice: %d), "
+            "simulated NRMSE mean %.4f sd %.4f (closed-form choice %.4f), dispersion mean %.3f m/s"
+            % (len(fits), nr.shape[1], ok.sum(), ok_mod.sum(), nr_sim[ok].mean(), nr_sim[ok].std(),
+               nr_mod[ok_mod].mean(), dp_sim[ok].mean()))
+    np.save("gpurun_out/weight_selection.npy", np.stack([case.alpha0, case.y, nr_sim, nr_mod, ok]))
+    assert ok.sum() >= ok_mod.sum()
     assert ok.sum() >= 0.7 * len(fits)
-    assert sim_best[ok].mean() < 0.03
+    assert nr_sim[ok].mean() < 0.03
 
 
 def test_weight_selection_over_the_library():
     """The 1071-cell (alpha0, y) relaxation library, every weight's candidate
-    simulated in one batched launch (5355 domains); per cell the weight with
-    the lowest simulated NRMSE.  Reported beside the paper's heat-map
-    statistics (Sec. 4, 1328 cells: 2.61 % +- 1.83 %)."""
+    simulated in one batched launch (5355 domains), each cell keeping the
+    weight chosen on its simulated figures.  Reported beside the paper's
+    heat-map statistics (Sec. 4, 1328 cells: 2.61 % +- 1.83 %)."""
     lib = configs.library_classes()
     cache = relax.load_cache()
     keys = [relax._key(c, a0, y, 2, 50000) for c, a0, y in zip(lib["c"], lib["alpha0"], lib["y"])]
-    fits = [cache.get(k) for k in keys]
-    if any(f is None or "cands" not in f for f in fits):
+    if any(k not in cache or "cands" not in cache[k] for k in keys):
         pytest.skip("library fits with per-weight candidates are not cached")
+    fits = [relax.effective(cache[k]) for k in keys]
     chosen, nr, dp = calibrate.select_weights(fits)
-    best = nr.min(axis=1)
-    ok = np.array([not c["failed"] for c in chosen])
-    _report("relaxation library %d cells x %d weights: valid %d, simulated NRMSE mean %.4f sd %.4f, "
-            "dispersion mean %.3f m/s (paper: 1328 cells, 2.61 %% +- 1.83 %%)"
-            % (len(fits), nr.shape[1], ok.sum(), best[ok].mean(), best[ok].std(),
-               dp[np.arange(len(fits)), nr.argmin(axis=1)][ok].mean()))
-    np.save("gpurun_out/library_selection.npy", np.stack([lib["alpha0"], lib["y"], best, ok]))
+    j_sim, j_mod, nr_sim, nr_mod, dp_sim, ok = _selection_stats(fits, nr, dp)
+    core = ok & (lib["y"] >= 0.7 - 1e-9) & (lib["y"] <= 1.4 + 1e-9)
+    _report("relaxation library %d cells x %d weights: within both bars %d, simulated NRMSE mean %.4f sd %.4f "
+            "(core y 0.7-1.4: %.4f), dispersion mean %.3f sd %.3f m/s (paper: 1328 cells, 2.61 %% +- 1.83 %%, "
+            "1.14 +- 0.76 m/s)" % (len(fits), nr.shape[1], ok.sum(), nr_sim[ok].mean(), nr_sim[ok].std(),
+                                   nr_sim[core].mean(), dp_sim[ok].mean(), dp_sim[ok].std()))
+    np.save("gpurun_out/library_selection.npy", np.stack([lib["alpha0"], lib["y"], nr_sim, dp_sim, ok]))
     assert ok.sum() >= 0.7 * len(fits)
-    assert best[ok].mean() < 0.03
+    assert nr_sim[ok].mean() < 0.03
 
 
 def test_two_layer_tissue_pairs():
