@@ -375,6 +375,8 @@ def main():
     ap.add_argument("--rows-per-thread", type=int, default=0)
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="only run a plain device-to-device copy of this many GiB (HBM counter calibration)")
+    ap.add_argument("--adjoint-steps", type=int, default=3000,
+                    help="steps of the adjoint workload (3000: the full workload; fewer for profiling)")
     ap.add_argument("--oracle-timings", action="store_true",
                     help="only time the FP64 oracle on bounded samples of each workload (host only)")
     args = ap.parse_args()
@@ -392,8 +394,8 @@ def main():
         return
     if args.only:
         torch.cuda.set_device(0)
-        fn = dict(batched=bench_batched, adjoint=bench_adjoint, two_layer=bench_two_layer,
-                  sweep=bench_sweep, paper_shape=bench_paper_shape)[args.only]
+        fn = dict(batched=bench_batched, adjoint=lambda t: bench_adjoint(t, steps=args.adjoint_steps),
+                  two_layer=bench_two_layer, sweep=bench_sweep, paper_shape=bench_paper_shape)[args.only]
         print(json.dumps(fn(torch)), flush=True)
         return
     from paper_2606_11103_amd.native import FW_OPT_MARCH_CHUNK, FW_OPT_ROWS_PER_THREAD, FW_OPT_TILE_ROWS
@@ -482,7 +484,7 @@ def main():
         out["batched"] = bench_batched(torch)
         torch.cuda.empty_cache()
         print("# adjoint ...", file=sys.stderr, flush=True)
-        out["adjoint"] = bench_adjoint(torch)
+        out["adjoint"] = bench_adjoint(torch, steps=args.adjoint_steps)
         torch.cuda.empty_cache()
         print("# two-layer 2D ...", file=sys.stderr, flush=True)
         out["two_layer_2d"] = bench_two_layer(torch)
