@@ -24,8 +24,8 @@
 // adj_finish applies the last pending lamD1 after the final reverse step.
 // One thread per (x, y) column of a tile, marching the tile's z range with
 // direct global loads (neighbour reads are served by the caches); the memory
-// variables, gradients and own values, touched once per kernel, use vector
-// non-temporal accesses.
+// variables use vector accesses.  (Non-temporal hints, which help the step
+// kernels, measured about 1 % slower here.)
 #include "fw_internal.h"
 #include "fw_vec.h"
 
@@ -160,9 +160,9 @@ __global__ void k_adj_pressure(const AdjArgs A)
         for (int a = 1; a < NDIM; ++a) S += Dd[a];
         // T^n from the updated memory variables of u^{n+1}
         float psn[N], psf[N], lps[N];
-        load_stream<N>(A.fnext.psi2 + gg * N, psn);
-        load_stream<N>(A.s.f.psi2 + gg * N, psf);
-        load_stream<N>(A.lam.psi2 + gg * N, lps);
+        load_vec<N>(A.fnext.psi2 + gg * N, psn);
+        load_vec<N>(A.s.f.psi2 + gg * N, psf);
+        load_vec<N>(A.lam.psi2 + gg * N, lps);
         float Tt = cc.ik2 * S;
 #pragma unroll
         for (int nu = 0; nu < N; ++nu) Tt += psn[nu];
@@ -175,8 +175,8 @@ __global__ void k_adj_pressure(const AdjArgs A)
             K = K * (f1 * f1);
         }
         const int64_t pk = D.packed_off + g;
-        const float gk0 = __builtin_nontemporal_load(A.gK + pk);
-        __builtin_nontemporal_store(gk0 + lp * (-dt * Tt), A.gK + pk);
+        const float gk0 = A.gK[pk];
+        A.gK[pk] = gk0 + lp * (-dt * Tt);
         const float q = -dt * K * lp;
         float gdiv = cc.ik2 * q;
         float gsum = 0.0f;
@@ -187,7 +187,7 @@ __global__ void k_adj_pressure(const AdjArgs A)
             gsum = fmaf(mu, fmaf(ca.a2s[nu], S, ca.b2s[nu] * psf[nu]), gsum);
             lps[nu] = cc.b2[nu] * mu;
         }
-        store_stream<N>(A.lam.psi2 + gg * N, lps);
+        store_vec<N>(A.lam.psi2 + gg * N, lps);
         // gdiv is the adjoint of the CPML-stretched divergence of each axis;
         // transpose of D_a + psiP2_a, psiP2_a <- bC psiP2_a + aC D_a
 #pragma unroll
@@ -203,8 +203,8 @@ __global__ void k_adj_pressure(const AdjArgs A)
             }
             A.lamD2[a][gg] = ld;
         }
-        const float gs0 = __builtin_nontemporal_load(A.gs + pk);
-        __builtin_nontemporal_store(gs0 + gsum, A.gs + pk);
+        const float gs0 = A.gs[pk];
+        A.gs[pk] = gs0 + gsum;
     }
 }
 
@@ -236,15 +236,15 @@ __global__ void k_adj_velocity(const AdjArgs A)
             const int i = G.c[a];
             const int Ln = (i + 1 < G.n[a]) ? A.s.f.cls[gg + G.st[a]] : L;
             const float m = 2.0f * dt / (cc.rho + A.s.classes[D.class_base + Ln].rho);
-            const float lv = __builtin_nontemporal_load(lvx[a] + gg) - grad_a(A.lamD2[a] + o, G, a, A.s.fd);
+            const float lv = lvx[a][gg] - grad_a(A.lamD2[a] + o, G, a, A.s.fd);
             const float r = -m * lv;
             // forward gradient of p^n after the CPML stage
             float D1 = grad_a(A.s.f.p + o, G, a, A.s.fd);
             const bool sl = slab(i, G.n[a], P);
             if (sl) D1 += pP1n[a][gg];
             float pf[N], pl[N];
-            load_stream<N>(psi1f[a] + gg * N, pf);
-            load_stream<N>(psi1l[a] + gg * N, pl);
+            load_vec<N>(psi1f[a] + gg * N, pf);
+            load_vec<N>(psi1l[a] + gg * N, pl);
             float ld = cc.ik1 * r;
 #pragma unroll
             for (int nu = 0; nu < N; ++nu) {
@@ -253,7 +253,7 @@ __global__ void k_adj_velocity(const AdjArgs A)
                 gsum = fmaf(mu, fmaf(ca.a1s[nu], D1, ca.b1s[nu] * pf[nu]), gsum);
                 pl[nu] = cc.b1[nu] * mu;
             }
-            store_stream<N>(psi1l[a] + gg * N, pl);
+            store_vec<N>(psi1l[a] + gg * N, pl);
             // ld is the adjoint of the CPML-stretched gradient; transpose of
             // D + psiP1, psiP1 <- bF psiP1 + aF D
             if (sl) {
@@ -264,12 +264,12 @@ __global__ void k_adj_velocity(const AdjArgs A)
                 ld = fmaf(aF, mu, ld);
                 A.lam.pP1[a][gg] = bF * mu;
             }
-            store1_stream(lvx[a] + gg, lv);
+            lvx[a][gg] = lv;
             A.lamD1[a][gg] = ld;
         }
         const int64_t pk = D.packed_off + g;
-        const float gs0 = __builtin_nontemporal_load(A.gs + pk);
-        __builtin_nontemporal_store(gs0 + gsum, A.gs + pk);
+        const float gs0 = A.gs[pk];
+        A.gs[pk] = gs0 + gsum;
     }
 }
 
