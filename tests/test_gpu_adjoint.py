@@ -59,9 +59,11 @@ def _oracle_gradient(case, obs):
     return np.concatenate(gK), np.concatenate(gs)
 
 
-@pytest.mark.parametrize("ndim,nmech,shapes", [(2, 2, None), (2, 4, [(64, 64, 1), (48, 72, 1)]), (3, 4, None)])
-def test_adjoint_gradients_match_fp64_adjoint(ndim, nmech, shapes):
-    case = _case(ndim, nmech, seed=21 + ndim + nmech, steps=160, shapes=shapes)
+@pytest.mark.parametrize("ndim,nmech,shapes,steps", [
+    (2, 4, [(64, 64, 1), (64, 64, 1)], 200),      # the workload's small check: 2 shots of 64^2, 200 steps
+    (2, 2, None, 160), (2, 4, [(64, 64, 1), (48, 72, 1)], 160), (3, 4, None, 160)])
+def test_adjoint_gradients_match_fp64_adjoint(ndim, nmech, shapes, steps):
+    case = _case(ndim, nmech, seed=21 + ndim + nmech + len(shapes or []), steps=steps, shapes=shapes)
     print("adjoint case", ndim, nmech, case.shapes, flush=True)
     obs = np.zeros((case.n_steps, len(case.rec_cell)))
     rec, gK, gs = _gpu_gradient(case, 23, obs)
