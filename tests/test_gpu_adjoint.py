@@ -189,3 +189,35 @@ def test_autograd_function_gradients():
                     % (k, adj_c, fd_c, adj_a, fd_a))
             assert abs(adj_c - fd_c) <= 1e-2 * abs(fd_c)
             assert abs(adj_a - fd_a) <= 2e-2 * abs(fd_a) + 1e-6 * abs(adj_c) * case.c[k] / case.alpha0[k]
+
+
+def test_adjoint_error_returns():
+    """Documented failures of the adjoint calls: nonlinear media
+    (FW_EUNSUPPORTED), a workspace smaller than fw_adjoint_workspace_bytes
+    (FW_ENOMEM) or not 256-byte aligned (FW_EINVAL)."""
+    import torch
+    from paper_2606_11103_amd.native import FW_EINVAL, FW_ENOMEM, FW_EUNSUPPORTED, FWError
+    case = _case(2, 2, seed=3, steps=40)
+    sim = to_simulation(case)
+    work = sim.adjoint_workspace(40, 20)
+    res = torch.zeros((40, len(case.rec_cell)), dtype=torch.float32, device="cuda")
+    sim.forward_checkpointed(40, 20, work)
+    with pytest.raises(FWError) as ei:
+        sim.adjoint(40, 20, work[:-256], res)
+    assert ei.value.code == FW_ENOMEM
+    with pytest.raises(FWError) as ei:
+        sim.adjoint(40, 20, work[4:], res)
+    assert ei.value.code in (FW_EINVAL, FW_ENOMEM)
+    big = sim.adjoint_workspace(40, 20)
+    pad = torch.empty(big.numel() + 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(FWError) as ei:
+        sim.adjoint(40, 20, pad[4:4 + big.numel()], res)
+    assert ei.value.code == FW_EINVAL
+    nl = configs.random_small(2, [(64, 64, 1)], 2, 3, seed=3, steps=40, pml=8, nonlinear=True)
+    configs.with_table(nl, *configs.random_relaxation_table(103, nl.n_classes, nl.nmech))
+    sim2 = to_simulation(nl)
+    w2 = sim2.adjoint_workspace(40, 20)
+    sim2.forward_checkpointed(40, 20, w2)
+    with pytest.raises(FWError) as ei:
+        sim2.adjoint(40, 20, w2, res)
+    assert ei.value.code == FW_EUNSUPPORTED
