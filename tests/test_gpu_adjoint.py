@@ -6,6 +6,7 @@ import pytest
 
 from workloads import configs
 from workloads.adapters import to_oracle, to_simulation
+from reporting import report
 
 pytestmark = pytest.mark.gpu
 
@@ -14,14 +15,6 @@ def _rel(a, b):
     a = np.asarray(a, np.float64)
     b = np.asarray(b, np.float64)
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
-
-
-def _report(line):
-    import os
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open(os.path.join("gpurun_out", "parity.txt"), "a") as fh:
-        fh.write(line + "\n")
-    print(line, flush=True)
 
 
 def _case(ndim, nmech, seed, steps, shapes=None):
@@ -69,7 +62,7 @@ def test_adjoint_gradients_match_fp64_adjoint(ndim, nmech, shapes, steps):
     rec, gK, gs = _gpu_gradient(case, 23, obs)
     oK, os_ = _oracle_gradient(case, obs)
     rK, rs = _rel(gK, oK), _rel(gs, os_)
-    _report("adjoint %dD N=%d shapes=%s rel_L2 gK=%.3e gs=%.3e" % (ndim, nmech, case.shapes, rK, rs))
+    report("adjoint %dD N=%d shapes=%s rel_L2 gK=%.3e gs=%.3e" % (ndim, nmech, case.shapes, rK, rs))
     assert np.abs(oK).max() > 0 and np.abs(os_).max() > 0
     assert rK <= 1e-4 and rs <= 1e-4
 
@@ -142,7 +135,7 @@ def test_adjoint_central_difference_on_gpu():
         sp_.d[k] *= 1 + hs
         sm_.d[k] *= 1 - hs
         fd_s = (J_of(sp_) - J_of(sm_)) / (2 * hs)
-        _report("adjoint FD class %d dJ/dc adj=%.6e fd=%.6e  dJ/ds adj=%.6e fd=%.6e" % (k, adj_c, fd_c, adj_s, fd_s))
+        report("adjoint FD class %d dJ/dc adj=%.6e fd=%.6e  dJ/ds adj=%.6e fd=%.6e" % (k, adj_c, fd_c, adj_s, fd_s))
         assert abs(adj_c - fd_c) <= 1e-2 * abs(fd_c)
         assert abs(adj_s - fd_s) <= 2e-2 * abs(fd_s) + 1e-3 * abs(adj_c * c0)
 
@@ -185,7 +178,7 @@ def test_autograd_function_gradients():
             fd_a = (J_of(c0, a00 + ha * m) - J_of(c0, a00 - ha * m)).item() / (2 * ha)
             adj_c = float(gc[flat == k].sum())
             adj_a = float(ga[flat == k].sum())
-            _report("autograd class %d dJ/dc adj=%.6e fd=%.6e  dJ/dalpha0 adj=%.6e fd=%.6e"
+            report("autograd class %d dJ/dc adj=%.6e fd=%.6e  dJ/dalpha0 adj=%.6e fd=%.6e"
                     % (k, adj_c, fd_c, adj_a, fd_a))
             assert abs(adj_c - fd_c) <= 1e-2 * abs(fd_c)
             assert abs(adj_a - fd_a) <= 2e-2 * abs(fd_a) + 1e-6 * abs(adj_c) * case.c[k] / case.alpha0[k]

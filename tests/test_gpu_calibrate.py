@@ -8,16 +8,9 @@ import pytest
 from oracle import analytic
 from paper_2606_11103_amd import calibrate, relax
 from workloads import configs
+from reporting import report, save
 
 pytestmark = pytest.mark.gpu
-
-
-def _report(line):
-    import os
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open(os.path.join("gpurun_out", "parity.txt"), "a") as fh:
-        fh.write(line + "\n")
-    print(line, flush=True)
 
 
 def _independent_measure(run, traces):
@@ -79,7 +72,7 @@ def test_simulated_attenuation_of_soft_tissue_class():
     nr, disp = calibrate.errors(a[0], c[0], 1540.0, 0.5, 1.1)
     ad, cd = _discrete_figures(run, run.kappa[0], run.d[0], run.alpha[0])
     a0d, c0d = _discrete_figures(run, run.kappa[1], run.d[1], run.alpha[1])
-    _report("calibration soft tissue N=2: simulated NRMSE %.4f dispersion %.3f m/s; vs discrete scheme: "
+    report("calibration soft tissue N=2: simulated NRMSE %.4f dispersion %.3f m/s; vs discrete scheme: "
             "alpha max rel %.2e, c max %.3f m/s; lossless max |alpha| %.3g Np/m, max |c - c_discrete| %.3g m/s"
             % (nr, disp, np.max(np.abs(a[0] / ad - 1)), np.abs(c[0] - cd).max(), np.abs(a[1]).max(),
                np.abs(c[1] - c0d).max()))
@@ -111,11 +104,11 @@ def test_weight_selection_over_the_sweep():
     j_sim, j_mod, nr_sim, nr_mod, dp_sim, ok = _selection_stats(fits, nr, dp)
     assert np.array_equal(j_sim, [[cd["w"] for cd in f["cands"]].index(c["w"]) for f, c in zip(fits, chosen)])
     ok_mod = np.array([relax.passes(nr[i, j], dp[i, j]) for i, j in enumerate(j_mod)])
-    _report("weight selection %d classes x %d weights: within both bars %d (closed-form choice: %d), "
+    report("weight selection %d classes x %d weights: within both bars %d (closed-form choice: %d), "
             "simulated NRMSE mean %.4f sd %.4f (closed-form choice %.4f), dispersion mean %.3f m/s"
             % (len(fits), nr.shape[1], ok.sum(), ok_mod.sum(), nr_sim[ok].mean(), nr_sim[ok].std(),
                nr_mod[ok_mod].mean(), dp_sim[ok].mean()))
-    np.save("gpurun_out/weight_selection.npy", np.stack([case.alpha0, case.y, nr_sim, nr_mod, ok]))
+    save("weight_selection.npy", np.stack([case.alpha0, case.y, nr_sim, nr_mod, ok]))
     assert ok.sum() >= ok_mod.sum()
     assert ok.sum() >= 0.7 * len(fits)
     assert nr_sim[ok].mean() < 0.03
@@ -135,11 +128,11 @@ def test_weight_selection_over_the_library():
     chosen, nr, dp = calibrate.select_weights(fits)
     j_sim, j_mod, nr_sim, nr_mod, dp_sim, ok = _selection_stats(fits, nr, dp)
     core = ok & (lib["y"] >= 0.7 - 1e-9) & (lib["y"] <= 1.4 + 1e-9)
-    _report("relaxation library %d cells x %d weights: within both bars %d, simulated NRMSE mean %.4f sd %.4f "
+    report("relaxation library %d cells x %d weights: within both bars %d, simulated NRMSE mean %.4f sd %.4f "
             "(core y 0.7-1.4: %.4f), dispersion mean %.3f sd %.3f m/s (paper: 1328 cells, 2.61 %% +- 1.83 %%, "
             "1.14 +- 0.76 m/s)" % (len(fits), nr.shape[1], ok.sum(), nr_sim[ok].mean(), nr_sim[ok].std(),
                                    nr_sim[core].mean(), dp_sim[ok].mean(), dp_sim[ok].std()))
-    np.save("gpurun_out/library_selection.npy", np.stack([lib["alpha0"], lib["y"], nr_sim, dp_sim, ok]))
+    save("library_selection.npy", np.stack([lib["alpha0"], lib["y"], nr_sim, dp_sim, ok]))
     assert ok.sum() >= 0.7 * len(fits)
     assert nr_sim[ok].mean() < 0.03
 
@@ -166,7 +159,7 @@ def test_two_layer_tissue_pairs():
     res = calibrate.two_layer_validation([(tab(fits[a]), tab(fits[b])) for a, b in order])
     for (a, b), r in zip(order, res):
         nr = [calibrate.errors(r["alpha"][i], r["c"][i], 1540.0, *tissues[t])[0] for i, t in enumerate((a, b))]
-        _report("two-layer %s -> %s: NRMSE layer 1 %.2f %% layer 2 %.2f %%, interface reflection %.1f dB "
+        report("two-layer %s -> %s: NRMSE layer 1 %.2f %% layer 2 %.2f %%, interface reflection %.1f dB "
                 "(paper: %.2f %%, %.2f %%, %.1f dB)" % (a, b, 100 * nr[0], 100 * nr[1], r["R_db"], *paper[(a, b)]))
         assert max(nr) < 0.03
         assert r["R_db"] < -40.0
@@ -188,5 +181,5 @@ def test_two_layer_tissue_pairs():
         tr, _ = sim.run(r["n_steps"], [64], w[None, :], [r["reflection_receiver"]])
         out.append(tr[:, 0])
     R_or = 20 * np.log10(np.abs(out[0] - out[1]).max() / np.abs(out[1]).max())
-    _report("two-layer muscle -> liver reflection: library %.2f dB, FP64 oracle %.2f dB" % (r["R_db"], R_or))
+    report("two-layer muscle -> liver reflection: library %.2f dB, FP64 oracle %.2f dB" % (r["R_db"], R_or))
     assert abs(r["R_db"] - R_or) < 1.0

@@ -8,16 +8,9 @@ import pytest
 
 from workloads import configs, linear_index
 from workloads.adapters import oracle_traces, to_simulation
+from reporting import report
 
 pytestmark = pytest.mark.gpu
-
-
-def _report(line):
-    import os
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open(os.path.join("gpurun_out", "parity.txt"), "a") as fh:
-        fh.write(line + "\n")
-    print(line, flush=True)
 
 
 def _tables(case, name):
@@ -32,7 +25,7 @@ def _parity(case, name):
     got = sim.read_receivers().astype(np.float64)
     ref = oracle_traces(case)
     rel = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
-    _report("edge %s rel_L2=%.3e steps=%d receivers=%d" % (name, rel, case.n_steps, len(case.rec_cell)))
+    report("edge %s rel_L2=%.3e steps=%d receivers=%d" % (name, rel, case.n_steps, len(case.rec_cell)))
     assert np.abs(ref).max() > 0 and rel <= 1e-4
     return got
 

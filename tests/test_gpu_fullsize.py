@@ -21,16 +21,9 @@ import pytest
 
 from workloads import configs
 from workloads.adapters import to_oracle_crop, to_simulation
+from reporting import report
 
 pytestmark = pytest.mark.gpu
-
-
-def _report(line):
-    import os
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open(os.path.join("gpurun_out", "parity.txt"), "a") as fh:
-        fh.write(line + "\n")
-    print(line, flush=True)
 
 
 def test_full_size_3d_workload_matches_oracle_on_the_field_support():
@@ -77,7 +70,7 @@ def test_full_size_3d_workload_matches_oracle_on_the_field_support():
     ref = orc.p.reshape(box.shape)
     rel_field = float(np.linalg.norm(box - ref) / np.linalg.norm(ref))
     rel_rec = float(np.linalg.norm(traces[:, inside] - rec) / np.linalg.norm(rec))
-    _report("full-size 3D 960x960x720 N=4 after %d steps: box %s rel_L2 field=%.3e receivers(%d)=%.3e"
+    report("full-size 3D 960x960x720 N=4 after %d steps: box %s rel_L2 field=%.3e receivers(%d)=%.3e"
             % (K, [h - l for l, h in zip(lo, hi)], rel_field, int(inside.sum()), rel_rec))
     assert rel_field <= 1e-5 and rel_rec <= 1e-5
 
@@ -107,7 +100,7 @@ def test_full_size_two_layer_2d_matches_stored_oracle_traces():
     reached = np.linalg.norm(ref, axis=0) > 0
     worst = float(np.max(np.linalg.norm((tr - ref)[:, reached], axis=0) / np.linalg.norm(ref[:, reached], axis=0)))
     assert np.all(tr[:, ~reached] == 0.0)
-    _report("full-size 2D two-layer 2048x2048 N=4 nonlinear, %d steps x %d receivers (%d reached): rel_L2 %.3e "
+    report("full-size 2D two-layer 2048x2048 N=4 nonlinear, %d steps x %d receivers (%d reached): rel_L2 %.3e "
             "(worst receiver %.3e), peak |p| %.3g Pa" % (steps, tr.shape[1], int(reached.sum()), rel, worst,
                                                          np.abs(ref).max()))
     assert np.all(np.isfinite(tr))
@@ -136,7 +129,7 @@ def test_full_size_3d_run_is_finite_and_loses_energy_after_the_source():
         energy.append((m, e[0], e[1]))
     tr = sim.read_receivers()
     del sim
-    _report("full-size 3D 2000 steps: energy/max|p| at steps " +
+    report("full-size 3D 2000 steps: energy/max|p| at steps " +
             ", ".join("%d: E %.3e, %.3g Pa" % v for v in energy))
     assert np.all(np.isfinite(tr))
     E = [v[1] for v in energy]

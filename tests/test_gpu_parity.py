@@ -9,19 +9,11 @@ import pytest
 
 from workloads import configs
 from workloads.adapters import oracle_traces, to_simulation
+from reporting import report
 
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-4
-
-
-def _report(line):
-    """Append a result line to gpurun_out/parity.txt (kept with the run)."""
-    import os
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open(os.path.join("gpurun_out", "parity.txt"), "a") as fh:
-        fh.write(line + "\n")
-    print(line, flush=True)
 
 
 def _rel(a, b):
@@ -71,7 +63,7 @@ def test_traces_match_oracle(name):
     assert np.all(np.isfinite(got))
     assert np.abs(ref).max() > 0
     rel = _rel(got, ref)
-    _report("%s rel_L2=%.3e steps=%d receivers=%d" % (name, rel, case.n_steps, len(case.rec_cell)))
+    report("%s rel_L2=%.3e steps=%d receivers=%d" % (name, rel, case.n_steps, len(case.rec_cell)))
     assert rel <= TOL
 
 

@@ -8,16 +8,9 @@ import pytest
 
 from oracle.solver import OracleSim
 from paper_2606_11103_amd import calibrate, relax
+from reporting import report
 
 pytestmark = pytest.mark.gpu
-
-
-def _report(line):
-    import os
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open(os.path.join("gpurun_out", "parity.txt"), "a") as fh:
-        fh.write(line + "\n")
-    print(line, flush=True)
 
 
 def _oracle_reflection(kappa, d, al, c=1540.0, f0=1e6, ppw=16, cfl=0.2, pmlw=3.0, Dw=5.0, nc=3):
@@ -63,6 +56,6 @@ def test_pml_reflection_over_tissue_tables():
         allR.append(R[:-1])
         assert R[-1] < -50.0
     allR = np.concatenate(allR)
-    _report("CPML reflection (3 wavelengths, 1 MHz) over %d tissue tables: median %.1f dB, max %.1f dB, "
+    report("CPML reflection (3 wavelengths, 1 MHz) over %d tissue tables: median %.1f dB, max %.1f dB, "
             "below -50 dB: %d/%d" % (allR.size, np.median(allR), allR.max(), int((allR < -50).sum()), allR.size))
     assert np.all(allR < -50.0)

@@ -7,16 +7,9 @@ import pytest
 
 from workloads import configs
 from workloads.adapters import to_simulation
+from reporting import report, save
 
 pytestmark = pytest.mark.gpu
-
-
-def _report(line):
-    import os
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open(os.path.join("gpurun_out", "parity.txt"), "a") as fh:
-        fh.write(line + "\n")
-    print(line, flush=True)
 
 
 def measure(case, traces):
@@ -72,8 +65,8 @@ def test_sweep_attenuation_and_dispersion():
     nrmse, disp = np.array(nrmse), np.array(disp)
     ok = valid & (nrmse <= 0.10) & (disp <= 5.0)
     core = ok & (case.y >= 0.7 - 1e-9) & (case.y <= 1.4 + 1e-9)
-    np.save("gpurun_out/sweep_nrmse.npy", np.stack([case.alpha0, case.y, nrmse, disp, valid]))
-    _report("sweep 544x8192 N=2: valid %d/%d, NRMSE mean %.4f sd %.4f (core y 0.7-1.4: %.4f), "
+    save("sweep_nrmse.npy", np.stack([case.alpha0, case.y, nrmse, disp, valid]))
+    report("sweep 544x8192 N=2: valid %d/%d, NRMSE mean %.4f sd %.4f (core y 0.7-1.4: %.4f), "
             "dispersion RMSE mean %.3f sd %.3f m/s" % (ok.sum(), len(ok), nrmse[ok].mean(), nrmse[ok].std(),
                                                     nrmse[core].mean(), disp[ok].mean(), disp[ok].std()))
     assert ok.sum() >= 0.7 * len(ok)
