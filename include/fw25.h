@@ -280,17 +280,19 @@ int fw_device_copy(void *d_dst, const void *d_src, int64_t bytes, void *hip_stre
  * Tuning and behaviour options (host only):
  *   FW_OPT_GRAPH_STEPS   steps per captured HIP graph (0 = eager only); default 16.
  *   FW_OPT_MARCH_CHUNK   cells of the marching axis per tile (>= 8); default auto
- *                        (3D: about 48 planes; 2D: a few thousand tiles in all).
+ *                        (3D: about 48 planes; 2D: 8 rows).
  *   FW_OPT_TILE_ROWS     3D tile rows along y per block: 4, 8 or 16; default 4.
  *   FW_OPT_ROWS_PER_THREAD  3D rows each thread owns: 1 or 2 (not with 4-row
  *                        tiles); default 1.
  *   FW_OPT_PERSISTENT    0: one workgroup per tile (default); k > 0: a
  *                        persistent grid of 32 k workgroups per XCD
  *                        (k per CU) that walk the tile list.
+ *   FW_OPT_TILE_ORDER    order of the tiles of one marching chunk: 0 = x
+ *                        fastest (default), 1 = y fastest.
  * Options change the work decomposition only, never the results.
  */
 enum { FW_OPT_GRAPH_STEPS = 1, FW_OPT_MARCH_CHUNK = 2, FW_OPT_TILE_ROWS = 3, FW_OPT_ROWS_PER_THREAD = 4,
-       FW_OPT_PERSISTENT = 5 };
+       FW_OPT_PERSISTENT = 5, FW_OPT_TILE_ORDER = 6 };
 int fw_set_option(fw_sim *sim, int key, int64_t value);
 
 #ifdef __cplusplus

@@ -29,7 +29,7 @@ def candidates(ndim):
                                 "persistent": persistent})
     else:
         for persistent in (0, 2, 4, 8):
-            for chunk in ((0, 16, 64) if ndim == 2 else (0,)):
+            for chunk in ((0, 16, 32) if ndim == 2 else (0,)):
                 out.append({"tile_rows": 4, "rows_per_thread": 1, "march_chunk": chunk, "persistent": persistent})
     return out
 

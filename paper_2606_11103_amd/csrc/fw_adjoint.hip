@@ -22,8 +22,10 @@
 // The CPML stage comes first in the forward operators (D_a + psiP_a, then
 // the tissue stretch), so its transpose comes last here.
 // adj_finish applies the last pending lamD1 after the final reverse step.
-// One thread per (x, y) column of a tile, marching the tile's z range with
-// direct global loads (neighbour reads are served by the caches); the memory
+// One thread per (x, y) column of a tile, marching the tile's z range (y in
+// 2D).  Stencil operands along the marching axis are kept in a register queue
+// of eight planes, so each plane of them is read from memory once per tile;
+// the in-plane neighbours are direct loads served by the caches.  The memory
 // variables use vector accesses.  (Non-temporal hints, which help the step
 // kernels, measured about 1 % slower here.)
 #include "fw_internal.h"
@@ -118,12 +120,73 @@ __device__ __forceinline__ void at_plane(Geo &G, int z)
 
 __device__ __forceinline__ bool slab(int c, int n, int P) { return P > 0 && (c < P || c >= n - P); }
 
+// Marching axis (none in 1D, where a tile is one row) and its register queue:
+// q[j] holds the operand at marching coordinate first + j, zero beyond the
+// grid.  With first = z - 3 the queue serves the gradient of plane z
+// (operand at z-3 .. z+4), with first = z - 4 the divergence (z-4 .. z+3);
+// both take sum_m c_m (q[3+m] - q[4-m]), the same operations as grad_a and
+// div_a.
+template <int NDIM>
+struct March {
+    static constexpr bool on = NDIM >= 2;
+    static constexpr int axis = NDIM - 1;
+    int col, stride, n;
+    __device__ __forceinline__ void init(const Geo &G)
+    {
+        col = G.c[0] + (NDIM == 3 ? G.c[1] * G.n[0] : 0);
+        stride = G.st[axis];
+        n = G.n[axis];
+    }
+    __device__ __forceinline__ float at(const float *__restrict__ f, int zz) const
+    {
+        return (zz >= 0 && zz < n) ? f[col + zz * stride] : 0.0f;
+    }
+    __device__ __forceinline__ void fill(float (&q)[8], const float *__restrict__ f, int first) const
+    {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) q[j] = at(f, first + j);
+    }
+    __device__ __forceinline__ void push(float (&q)[8], const float *__restrict__ f, int zz) const
+    {
+#pragma unroll
+        for (int j = 0; j < 7; ++j) q[j] = q[j + 1];
+        q[7] = zz < n ? f[col + zz * stride] : 0.0f;
+    }
+};
+
+__device__ __forceinline__ float qdiff(const float (&c)[4], const float (&q)[8])
+{
+    return st4(c, q[4] - q[3], q[5] - q[2], q[6] - q[1], q[7] - q[0]);
+}
+
 template <int NDIM, int N>
 __global__ void k_adj_pressure(const AdjArgs A)
 {
     Tile T;
     DomainDesc D;
     if (!setup<NDIM>(A, T, D)) return;
+    // class tables of the domain in LDS: 1/kappa_2, K, a2, b2, da2/ds, db2/ds
+    extern __shared__ float s_tab[];
+    const int C = A.s.class_cap;
+    float *s_ik = s_tab, *s_K = s_tab + C, *s_a = s_tab + 2 * C, *s_b = s_a + N * C, *s_as = s_b + N * C,
+          *s_bs = s_as + N * C;
+    {
+        const int tid = threadIdx.y * blockDim.x + threadIdx.x, nt = blockDim.x * blockDim.y;
+        for (int c = tid; c < D.n_classes; c += nt) {
+            const ClassCoef &cc = A.s.classes[D.class_base + c];
+            const ClassAdj &ca = A.cadj[D.class_base + c];
+            s_ik[c] = cc.ik2;
+            s_K[c] = cc.K;
+#pragma unroll
+            for (int nu = 0; nu < N; ++nu) {
+                s_a[nu * C + c] = cc.a2[nu];
+                s_b[nu * C + c] = cc.b2[nu];
+                s_as[nu * C + c] = ca.a2s[nu];
+                s_bs[nu * C + c] = ca.b2s[nu];
+            }
+        }
+    }
+    __syncthreads();
     Geo G;
     if (!column<NDIM>(T, D, G)) return;
     const int64_t o = D.cell_off;
@@ -131,30 +194,47 @@ __global__ void k_adj_pressure(const AdjArgs A)
     const int P = A.s.pml;
     const float *vn[3] = {A.fnext.vx + o, A.fnext.vy + o, A.fnext.vz + o};
     const float *ld1[3] = {A.lamD1[0] + o, A.lamD1[1] + o, A.lamD1[2] + o};
+    using MQ = March<NDIM>;
+    MQ Q;
+    Q.init(G);
+    constexpr int ma = MQ::axis;
+    float qv[8], ql[8];   // v_ma and lamD1_ma, planes z-4 .. z+3
+    if constexpr (MQ::on) {
+        Q.fill(qv, vn[ma], T.z0 - 4);
+        if (A.fold_div) Q.fill(ql, ld1[ma], T.z0 - 4);
+    }
     for (int z = T.z0; z < T.z1; ++z) {
         at_plane<NDIM>(G, z);
         const int g = G.g;
         const int64_t gg = o + g;
         const int L = A.s.f.cls[gg];
-        const ClassCoef &cc = A.s.classes[D.class_base + L];
-        const ClassAdj &ca = A.cadj[D.class_base + L];
         // lam_p^{n+1}: the pending divergence of the velocity transpose
         float lp = A.lam.p[gg];
         if (A.fold_div) {
             float acc = 0.0f;
 #pragma unroll
-            for (int a = 0; a < NDIM; ++a) acc += div_a(ld1[a], G, a, A.s.fd);
+            for (int a = 0; a < NDIM; ++a) {
+                if (MQ::on && a == ma)
+                    acc += qdiff(A.s.fd, ql);
+                else
+                    acc += div_a(ld1[a], G, a, A.s.fd);
+            }
             lp -= acc;
             A.lam.p[gg] = lp;
+            if constexpr (MQ::on) Q.push(ql, ld1[ma], z + 4);
         }
         // forward divergence of v^{n+1/2} (state u^{n+1}) after the CPML
         // stage: D_a + psiP2_a^{n+1} in the slab of axis a
         float Dd[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int a = 0; a < NDIM; ++a) {
-            Dd[a] = div_a(vn[a], G, a, A.s.fd);
+            if (MQ::on && a == ma)
+                Dd[a] = qdiff(A.s.fd, qv);
+            else
+                Dd[a] = div_a(vn[a], G, a, A.s.fd);
             if (slab(G.c[a], G.n[a], P)) Dd[a] += A.fnext.pP2[a][gg];
         }
+        if constexpr (MQ::on) Q.push(qv, vn[ma], z + 4);
         float S = Dd[0];
 #pragma unroll
         for (int a = 1; a < NDIM; ++a) S += Dd[a];
@@ -163,10 +243,10 @@ __global__ void k_adj_pressure(const AdjArgs A)
         load_vec<N>(A.fnext.psi2 + gg * N, psn);
         load_vec<N>(A.s.f.psi2 + gg * N, psf);
         load_vec<N>(A.lam.psi2 + gg * N, lps);
-        float Tt = cc.ik2 * S;
+        float Tt = s_ik[L] * S;
 #pragma unroll
         for (int nu = 0; nu < N; ++nu) Tt += psn[nu];
-        float K = cc.K;
+        float K = s_K[L];
         if (A.s.noise_amp != 0.0f) {
             const uint64_t h = splitmix64_a(D.noise_seed ^ (uint64_t)(uint32_t)g);
             const float u = (float)(h >> 40) * 0x1.0p-24f;
@@ -178,14 +258,14 @@ __global__ void k_adj_pressure(const AdjArgs A)
         const float gk0 = A.gK[pk];
         A.gK[pk] = gk0 + lp * (-dt * Tt);
         const float q = -dt * K * lp;
-        float gdiv = cc.ik2 * q;
+        float gdiv = s_ik[L] * q;
         float gsum = 0.0f;
 #pragma unroll
         for (int nu = 0; nu < N; ++nu) {
             const float mu = lps[nu] + q;
-            gdiv = fmaf(cc.a2[nu], mu, gdiv);
-            gsum = fmaf(mu, fmaf(ca.a2s[nu], S, ca.b2s[nu] * psf[nu]), gsum);
-            lps[nu] = cc.b2[nu] * mu;
+            gdiv = fmaf(s_a[nu * C + L], mu, gdiv);
+            gsum = fmaf(mu, fmaf(s_as[nu * C + L], S, s_bs[nu * C + L] * psf[nu]), gsum);
+            lps[nu] = s_b[nu * C + L] * mu;
         }
         store_vec<N>(A.lam.psi2 + gg * N, lps);
         // gdiv is the adjoint of the CPML-stretched divergence of each axis;
@@ -214,6 +294,28 @@ __global__ void k_adj_velocity(const AdjArgs A)
     Tile T;
     DomainDesc D;
     if (!setup<NDIM>(A, T, D)) return;
+    // class tables of the domain in LDS: 1/kappa_1, rho, a1, b1, da1/ds, db1/ds
+    extern __shared__ float s_tab[];
+    const int C = A.s.class_cap;
+    float *s_ik = s_tab, *s_rho = s_tab + C, *s_a = s_tab + 2 * C, *s_b = s_a + N * C, *s_as = s_b + N * C,
+          *s_bs = s_as + N * C;
+    {
+        const int tid = threadIdx.y * blockDim.x + threadIdx.x, nt = blockDim.x * blockDim.y;
+        for (int c = tid; c < D.n_classes; c += nt) {
+            const ClassCoef &cc = A.s.classes[D.class_base + c];
+            const ClassAdj &ca = A.cadj[D.class_base + c];
+            s_ik[c] = cc.ik1;
+            s_rho[c] = cc.rho;
+#pragma unroll
+            for (int nu = 0; nu < N; ++nu) {
+                s_a[nu * C + c] = cc.a1[nu];
+                s_b[nu * C + c] = cc.b1[nu];
+                s_as[nu * C + c] = ca.a1s[nu];
+                s_bs[nu * C + c] = ca.b1s[nu];
+            }
+        }
+    }
+    __syncthreads();
     Geo G;
     if (!column<NDIM>(T, D, G)) return;
     const int64_t o = D.cell_off;
@@ -223,35 +325,45 @@ __global__ void k_adj_velocity(const AdjArgs A)
     const float *psi1f[3] = {A.s.f.psi1x, A.s.f.psi1y, A.s.f.psi1z};
     float *psi1l[3] = {A.lam.psi1x, A.lam.psi1y, A.lam.psi1z};
     const float *pP1n[3] = {A.fnext.pP1[0], A.fnext.pP1[1], A.fnext.pP1[2]};
+    using MQ = March<NDIM>;
+    MQ Q;
+    Q.init(G);
+    constexpr int ma = MQ::axis;
+    const float *pf0 = A.s.f.p + o;
+    const float *ld2m = A.lamD2[ma] + o;
+    float qp[8], ql[8];   // p and lamD2_ma, planes z-3 .. z+4
+    if constexpr (MQ::on) {
+        Q.fill(qp, pf0, T.z0 - 3);
+        Q.fill(ql, ld2m, T.z0 - 3);
+    }
     for (int z = T.z0; z < T.z1; ++z) {
         at_plane<NDIM>(G, z);
         const int g = G.g;
         const int64_t gg = o + g;
         const int L = A.s.f.cls[gg];
-        const ClassCoef &cc = A.s.classes[D.class_base + L];
-        const ClassAdj &ca = A.cadj[D.class_base + L];
         float gsum = 0.0f;
 #pragma unroll
         for (int a = 0; a < NDIM; ++a) {
             const int i = G.c[a];
             const int Ln = (i + 1 < G.n[a]) ? A.s.f.cls[gg + G.st[a]] : L;
-            const float m = 2.0f * dt / (cc.rho + A.s.classes[D.class_base + Ln].rho);
-            const float lv = lvx[a][gg] - grad_a(A.lamD2[a] + o, G, a, A.s.fd);
+            const float m = 2.0f * dt / (s_rho[L] + s_rho[Ln]);
+            const bool mq = MQ::on && a == ma;
+            const float lv = lvx[a][gg] - (mq ? qdiff(A.s.fd, ql) : grad_a(A.lamD2[a] + o, G, a, A.s.fd));
             const float r = -m * lv;
             // forward gradient of p^n after the CPML stage
-            float D1 = grad_a(A.s.f.p + o, G, a, A.s.fd);
+            float D1 = mq ? qdiff(A.s.fd, qp) : grad_a(pf0, G, a, A.s.fd);
             const bool sl = slab(i, G.n[a], P);
             if (sl) D1 += pP1n[a][gg];
             float pf[N], pl[N];
             load_vec<N>(psi1f[a] + gg * N, pf);
             load_vec<N>(psi1l[a] + gg * N, pl);
-            float ld = cc.ik1 * r;
+            float ld = s_ik[L] * r;
 #pragma unroll
             for (int nu = 0; nu < N; ++nu) {
                 const float mu = pl[nu] + r;
-                ld = fmaf(cc.a1[nu], mu, ld);
-                gsum = fmaf(mu, fmaf(ca.a1s[nu], D1, ca.b1s[nu] * pf[nu]), gsum);
-                pl[nu] = cc.b1[nu] * mu;
+                ld = fmaf(s_a[nu * C + L], mu, ld);
+                gsum = fmaf(mu, fmaf(s_as[nu * C + L], D1, s_bs[nu * C + L] * pf[nu]), gsum);
+                pl[nu] = s_b[nu * C + L] * mu;
             }
             store_vec<N>(psi1l[a] + gg * N, pl);
             // ld is the adjoint of the CPML-stretched gradient; transpose of
@@ -266,6 +378,10 @@ __global__ void k_adj_velocity(const AdjArgs A)
             }
             lvx[a][gg] = lv;
             A.lamD1[a][gg] = ld;
+        }
+        if constexpr (MQ::on) {
+            Q.push(qp, pf0, z + 5);
+            Q.push(ql, ld2m, z + 5);
         }
         const int64_t pk = D.packed_off + g;
         const float gs0 = A.gs[pk];
@@ -310,10 +426,11 @@ hipError_t adj_launch(int which, const AdjArgs &a, hipStream_t s)
     tile_shape(NDIM, a.tile_rows, &tx, &ty);
     const dim3 block(tx, NDIM == 3 ? ty : 1);
     const dim3 grid(8 * a.s.tiles_per_xcd);
+    const size_t lds = (size_t)a.s.class_cap * (2 + 4 * N) * sizeof(float);
     if (which == 0)
-        k_adj_pressure<NDIM, N><<<grid, block, 0, s>>>(a);
+        k_adj_pressure<NDIM, N><<<grid, block, lds, s>>>(a);
     else if (which == 1)
-        k_adj_velocity<NDIM, N><<<grid, block, 0, s>>>(a);
+        k_adj_velocity<NDIM, N><<<grid, block, lds, s>>>(a);
     else
         k_adj_finish<NDIM><<<grid, block, 0, s>>>(a);
     return hipGetLastError();

@@ -100,7 +100,7 @@ struct fw_sim {
     int64_t n_src = 0, n_rec = 0;
     int n_t = 0, n_t_max = 0;
     // options
-    int graph_steps = 16, march_chunk = 0, tile_rows = 4, rows_per_thread = 1, persistent = 0;
+    int graph_steps = 16, march_chunk = 0, tile_rows = 4, rows_per_thread = 1, persistent = 0, tile_order = 0;
     // stepping
     int64_t host_step = 0;
     hipStream_t cap_stream = nullptr;
@@ -220,23 +220,28 @@ int build_tiles(fw_sim *s)
             const int64_t nch = (nmarch + 47) / 48;
             chunk = (nmarch + nch - 1) / nch;
         } else if (chunk <= 0) {
-            // aim for a few thousand tiles over all domains, chunks of >= 16 planes
-            const int64_t cols = nxtile * nytile;
-            chunk = nmarch;
-            while (chunk > 16 && cols * ((nmarch + chunk - 1) / chunk) < 4096) chunk = (chunk + 1) / 2;
+            // 2D: 8 rows per one-wave tile (measured best on single and
+            // batched grids: the many short tiles keep more waves in flight
+            // than the queue warm-up of each tile costs); 1D: one row
+            chunk = 8;
         }
         chunk = std::max<int64_t>(1, std::min<int64_t>(chunk, nmarch));
+        // tile order inside a chunk: x fastest (order 0) or y fastest
+        // (order 1: the y neighbours of a tile run right after it, so the
+        // halo rows they share are still in L2 when the second one reads them)
+        const int64_t n_in = nxtile * nytile;
         for (int64_t z0 = 0; z0 < nmarch; z0 += chunk)
-            for (int64_t yt = 0; yt < nytile; ++yt)
-                for (int64_t xt = 0; xt < nxtile; ++xt) {
-                    fw::Tile t{};
-                    t.dom = d;
-                    t.x0 = (int32_t)(xt * tx);
-                    t.y0 = (int32_t)(yt * ty);
-                    t.z0 = (int32_t)z0;
-                    t.z1 = (int32_t)std::min(nmarch, z0 + chunk);
-                    tiles.push_back(t);
-                }
+            for (int64_t k = 0; k < n_in; ++k) {
+                const int64_t xt = s->tile_order == 1 ? k / nytile : k % nxtile;
+                const int64_t yt = s->tile_order == 1 ? k % nytile : k / nxtile;
+                fw::Tile t{};
+                t.dom = d;
+                t.x0 = (int32_t)(xt * tx);
+                t.y0 = (int32_t)(yt * ty);
+                t.z0 = (int32_t)z0;
+                t.z1 = (int32_t)std::min(nmarch, z0 + chunk);
+                tiles.push_back(t);
+            }
     }
     s->n_tiles = (int)tiles.size();
     s->tiles_per_xcd = (s->n_tiles + 7) / 8;
@@ -1052,6 +1057,11 @@ int fw_set_option(fw_sim *sim, int key, int64_t value)
         if (value < 0 || value > 64) return fail(FW_EINVAL, "persistent blocks per CU must be in 0..64");
         sim->persistent = (int)value;
         sim->drop_graph();
+        return FW_OK;
+    case FW_OPT_TILE_ORDER:
+        if (value != 0 && value != 1) return fail(FW_EINVAL, "tile order must be 0 (x fastest) or 1 (y fastest)");
+        sim->tile_order = (int)value;
+        sim->tiles_dirty = true;
         return FW_OK;
     case FW_OPT_ROWS_PER_THREAD:
         if (value != 1 && value != 2) return fail(FW_EINVAL, "rows per thread must be 1 or 2");
