@@ -25,9 +25,11 @@ def _case(ndim, nmech, seed, steps, shapes=None):
     return configs.with_table(c, *configs.random_relaxation_table(seed + 100, c.n_classes, c.nmech))
 
 
-def _gpu_gradient(case, ckpt, obs):
+def _gpu_gradient(case, ckpt, obs, opts=None):
     import torch
     sim = to_simulation(case)
+    for k, v in (opts or {}).items():
+        sim.set_option(k, v)
     n = case.n_steps
     work = sim.adjoint_workspace(n, ckpt)
     sim.forward_checkpointed(n, ckpt, work)
@@ -54,7 +56,9 @@ def _oracle_gradient(case, obs):
 
 @pytest.mark.parametrize("ndim,nmech,shapes,steps", [
     (2, 4, [(64, 64, 1), (64, 64, 1)], 200),      # the workload's small check: 2 shots of 64^2, 200 steps
-    (2, 2, None, 160), (2, 4, [(64, 64, 1), (48, 72, 1)], 160), (3, 4, None, 160)])
+    (2, 2, None, 160), (2, 4, [(64, 64, 1), (48, 72, 1)], 160), (3, 4, None, 160),
+    (3, 2, [(36, 30, 28), (21, 26, 33)], 120),     # ragged 3D batch
+    (1, 3, [(300, 1, 1), (181, 1, 1)], 200)])
 def test_adjoint_gradients_match_fp64_adjoint(ndim, nmech, shapes, steps):
     case = _case(ndim, nmech, seed=21 + ndim + nmech + len(shapes or []), steps=steps, shapes=shapes)
     print("adjoint case", ndim, nmech, case.shapes, flush=True)
@@ -75,6 +79,21 @@ def test_checkpoint_interval_does_not_change_gradients():
     _, k3, s3 = _gpu_gradient(case, 120, obs)
     assert np.array_equal(k1, k2) and np.array_equal(k1, k3)
     assert np.array_equal(s1, s2) and np.array_equal(s1, s3)
+
+
+def test_adjoint_tiling_does_not_change_gradients():
+    """The adjoint kernels march the same tiles as the forward ones, with a
+    register queue along the marching axis: chunks of 8 planes (several
+    chunk boundaries on a 28-plane grid), 8-row tiles and y-fastest tile
+    order give bit-identical gradients."""
+    from paper_2606_11103_amd.native import FW_OPT_MARCH_CHUNK, FW_OPT_TILE_ORDER, FW_OPT_TILE_ROWS
+    case = _case(3, 2, seed=9, steps=100, shapes=[(36, 30, 28), (21, 26, 19)])
+    obs = np.zeros((case.n_steps, len(case.rec_cell)))
+    _, k0, s0 = _gpu_gradient(case, 25, obs)
+    for opts in ({FW_OPT_MARCH_CHUNK: 8}, {FW_OPT_TILE_ROWS: 8, FW_OPT_MARCH_CHUNK: 11},
+                 {FW_OPT_TILE_ORDER: 1, FW_OPT_MARCH_CHUNK: 9}):
+        _, k1, s1 = _gpu_gradient(case, 25, obs, opts)
+        assert np.array_equal(k0, k1) and np.array_equal(s0, s1), opts
 
 
 def test_stepping_continues_after_the_adjoint():
