@@ -279,7 +279,7 @@ int fw_device_copy(void *d_dst, const void *d_src, int64_t bytes, void *hip_stre
 /*
  * Tuning and behaviour options (host only):
  *   FW_OPT_GRAPH_STEPS   steps per captured HIP graph (0 = eager only); default 16.
- *   FW_OPT_MARCH_CHUNK   cells of the marching axis per tile (>= 8); default auto
+ *   FW_OPT_MARCH_CHUNK   cells of the marching axis per tile (>= 1); default auto
  *                        (3D: about 48 planes; 2D: 8 rows).
  *   FW_OPT_TILE_ROWS     3D tile rows along y per block: 4, 8 or 16; default 4.
  *   FW_OPT_ROWS_PER_THREAD  3D rows each thread owns: 1 or 2 (not with 4-row
@@ -287,12 +287,19 @@ int fw_device_copy(void *d_dst, const void *d_src, int64_t bytes, void *hip_stre
  *   FW_OPT_PERSISTENT    0: one workgroup per tile (default); k > 0: a
  *                        persistent grid of 32 k workgroups per XCD
  *                        (k per CU) that walk the tile list.
- *   FW_OPT_TILE_ORDER    order of the tiles of one marching chunk: 0 = x
- *                        fastest (default), 1 = y fastest.
+ *   FW_OPT_TILE_ORDER    order of the marching tiles: 0 = x fastest within a
+ *                        chunk (default), 1 = y fastest, 2 = plane-major with
+ *                        XCD k owning y-band k of every chunk (3D).
+ *   FW_OPT_PLANE_VELOCITY  3D: 1 (default) = the velocity update runs on
+ *                        64 x 4 tiles of one plane each, plane-major with XCD k
+ *                        owning y-band k of every plane (z stencil read from
+ *                        memory: the eight-plane window stays in the last-level
+ *                        cache); 0 = it marches the same tiles as the pressure
+ *                        update.  Not used with a persistent grid.
  * Options change the work decomposition only, never the results.
  */
 enum { FW_OPT_GRAPH_STEPS = 1, FW_OPT_MARCH_CHUNK = 2, FW_OPT_TILE_ROWS = 3, FW_OPT_ROWS_PER_THREAD = 4,
-       FW_OPT_PERSISTENT = 5, FW_OPT_TILE_ORDER = 6 };
+       FW_OPT_PERSISTENT = 5, FW_OPT_TILE_ORDER = 6, FW_OPT_PLANE_VELOCITY = 7 };
 int fw_set_option(fw_sim *sim, int key, int64_t value);
 
 #ifdef __cplusplus

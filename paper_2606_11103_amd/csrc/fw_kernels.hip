@@ -146,6 +146,7 @@ __global__ __launch_bounds__(BX *BY) void k_velocity(const StepArgs A)
     if (it > 0) __syncthreads();   // the previous tile is done with the LDS buffers
 
     const Tile T = A.tiles[ti];
+    if (T.z1 <= T.z0) continue;    // padding of a banded tile list
     const DomainDesc D = A.doms[T.dom];
     const int tid = threadIdx.y * BX + threadIdx.x;
     const int tx = threadIdx.x;
@@ -416,6 +417,7 @@ __global__ __launch_bounds__(BX *BY) void k_pressure(const StepArgs A)
     if (it > 0) __syncthreads();   // the previous tile is done with the LDS buffers
 
     const Tile T = A.tiles[ti];
+    if (T.z1 <= T.z0) continue;    // padding of a banded tile list
     const DomainDesc D = A.doms[T.dom];
     const int tid = threadIdx.y * BX + threadIdx.x;
     const int tx = threadIdx.x;
@@ -631,6 +633,154 @@ __global__ __launch_bounds__(BX *BY) void k_pressure(const StepArgs A)
     }  // tile loop
 }
 
+// ---------------------------------------------------------------------------
+// Single-plane velocity update (3D, 64 x 4 tiles of one plane, one tile per
+// block).  Its tile list is plane-major and XCD k owns y-band k of every
+// plane, so all XCDs work on the same few planes: the eight-plane window of
+// the z stencil stays in the last-level cache and is read straight from
+// memory instead of being carried in a register queue, and the concurrent
+// tiles cover one contiguous stretch of each field.  The x/y stencils read
+// an LDS tile.  There is no prefetch state, so more waves fit on a SIMD to
+// hide the latency.  Each output is computed with the same operations, in
+// the same order, as in k_velocity, so the two give identical bits.  (The
+// pressure update moves less than half the bytes per cell, so the window
+// reads weigh more there; it keeps the marching kernel.)
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(256) void k_velocity_plane(const StepArgs A)
+{
+    constexpr int BX = 64, TY = 4, LX = BX + 8, LY = TY + 8, NT = BX * TY, CX = BX + 1;
+    constexpr int NHALO = 8 * LX + 8 * TY;
+    constexpr int HS = (NHALO + NT - 1) / NT;
+    constexpr int NCH = TY + BX;
+    __shared__ float sp[LY * LX];
+    __shared__ uint8_t scl[(TY + 1) * CX];
+    extern __shared__ float s_dyn[];
+    const int C = A.class_cap;
+    float *s_ik = s_dyn, *s_rho = s_dyn + C, *s_a = s_dyn + 2 * C, *s_b = s_dyn + (2 + N) * C;
+
+    const int b = blockIdx.x;
+    const int ti = (b & 7) * A.vtiles_per_xcd + (b >> 3);
+    if (ti >= A.n_vtiles) return;
+    const Tile T = A.vtiles[ti];
+    if (T.z1 <= T.z0) return;      // padding of the banded list
+    const DomainDesc D = A.doms[T.dom];
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * BX + tx;
+    for (int c = tid; c < D.n_classes; c += NT) {
+        const ClassCoef &cc = A.classes[D.class_base + c];
+        s_ik[c] = cc.ik1;
+        s_rho[c] = cc.rho;
+#pragma unroll
+        for (int nu = 0; nu < N; ++nu) {
+            s_a[nu * C + c] = cc.a1[nu];
+            s_b[nu * C + c] = cc.b1[nu];
+        }
+    }
+    const int nx = (int)D.n[0], ny = (int)D.n[1], nz = (int)D.n[2], sm = nx * ny;
+    const int x = T.x0 + tx, y = T.y0 + ty, z = T.z0;
+    const bool ok = x < nx && y < ny;
+    const int zoff = z * sm;
+    const int g = zoff + y * nx + x;
+    const DomPtrs M = dom_ptrs<N>(A.f, D);
+    const DomPtrs Mo = dom_ptrs<N>(A.fo, D);
+    const int P = A.pml;
+
+    // x/y halo of p (4 rows above and below over the tile's width plus the
+    // corners, 4 columns left and right of its rows), zero outside the domain
+#pragma unroll
+    for (int s = 0; s < HS; ++s) {
+        const int h = tid + s * NT;
+        if (h < NHALO) {
+            int hy, hx;
+            if (h < 8 * LX) {
+                const int rr = h / LX;
+                hy = rr < 4 ? rr : TY + rr;
+                hx = h - rr * LX;
+            } else {
+                const int hh = h - 8 * LX;
+                hy = 4 + (hh >> 3);
+                const int k = hh & 7;
+                hx = k < 4 ? k : BX + k;
+            }
+            const int gx = T.x0 - 4 + hx, gy = T.y0 - 4 + hy;
+            const bool inside = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+            sp[hy * LX + hx] = inside ? M.p[zoff + gy * nx + gx] : 0.0f;
+        }
+    }
+    // classes of the next column and of the next row of the tile
+    if (tid < NCH) {
+        int gx, gy, li;
+        if (tid < TY) {
+            gx = T.x0 + BX;
+            gy = T.y0 + tid;
+            li = tid * CX + BX;
+        } else {
+            gx = T.x0 + (tid - TY);
+            gy = T.y0 + TY;
+            li = TY * CX + (tid - TY);
+        }
+        scl[li] = (gx < nx && gy < ny) ? M.cls[zoff + gy * nx + gx] : (uint8_t)0;
+    }
+    // own column: p at z-3 .. z+4, classes at z and z+1, private state
+    float q[8];
+    float vc[3], pc[3][N], ppc[3];
+    int L = 0, Lz = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) q[j] = 0.0f;
+    if (ok) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int zz = z - 3 + j;
+            if (zz >= 0 && zz < nz) q[j] = M.p[g + (j - 3) * sm];
+        }
+        L = M.cls[g];
+        Lz = (z + 1 < nz) ? M.cls[g + sm] : L;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int c = a == 0 ? x : (a == 1 ? y : z), n = a == 0 ? nx : (a == 1 ? ny : nz);
+            vc[a] = M.v[a][g];
+            load_stream<N>(M.psi1[a] + (size_t)g * N, pc[a]);
+            ppc[a] = in_slab(c, n, P) ? M.pP1[a][g] : 0.0f;
+        }
+    }
+    sp[(ty + 4) * LX + 4 + tx] = q[3];
+    scl[ty * CX + tx] = (uint8_t)L;
+    __syncthreads();
+    if (!ok) return;
+
+    const float *sr = sp + (ty + 4) * LX + 4 + tx;
+    float Dv[3];
+    int Ln[3];
+    Dv[0] = stencil4(A.fd, sr[1] - sr[0], sr[2] - sr[-1], sr[3] - sr[-2], sr[4] - sr[-3]);
+    Ln[0] = (x + 1 < nx) ? scl[ty * CX + tx + 1] : L;
+    Dv[1] = stencil4(A.fd, sr[LX] - sr[0], sr[2 * LX] - sr[-LX], sr[3 * LX] - sr[-2 * LX], sr[4 * LX] - sr[-3 * LX]);
+    Ln[1] = (y + 1 < ny) ? scl[(ty + 1) * CX + tx] : L;
+    Dv[2] = stencil4(A.fd, q[4] - q[3], q[5] - q[2], q[6] - q[1], q[7] - q[0]);
+    Ln[2] = Lz;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float Da = Dv[a];
+        const int c = a == 0 ? x : (a == 1 ? y : z), n = a == 0 ? nx : (a == 1 ? ny : nz);
+        if (in_slab(c, n, P)) {
+            const int32_t off = D.pml_off[a];
+            const float aF = A.pml_tab[off + c];
+            const float bF = A.pml_tab[off + n + c];
+            const float qv = fmaf(aF, Da, bF * ppc[a]);
+            Mo.pP1[a][g] = qv;
+            Da += qv;
+        }
+        const float m = 2.0f * A.dt / (s_rho[L] + s_rho[Ln[a]]);
+        float sacc = s_ik[L] * Da;
+#pragma unroll
+        for (int nu = 0; nu < N; ++nu) {
+            pc[a][nu] = fmaf(s_a[nu * C + L], Da, s_b[nu * C + L] * pc[a][nu]);
+            sacc += pc[a][nu];
+        }
+        store_stream<N>(Mo.psi1[a] + (size_t)g * N, pc[a]);
+        store1_stream(Mo.v[a] + g, fmaf(-m, sacc, vc[a]));
+    }
+}
+
 // Sources then receivers then the step counter, in one workgroup so the
 // receivers see the injected values.
 __global__ __launch_bounds__(1024) void k_src_rec(const SrcRecArgs A)
@@ -675,6 +825,12 @@ template <int NDIM, int N>
 hipError_t launch_nd(bool velocity, int tile_rows, int rpt, const StepArgs &a, hipStream_t s)
 {
     if constexpr (NDIM == 3) {
+        if (velocity && a.plane) {
+            if (a.n_vtiles <= 0) return hipSuccess;
+            const size_t lds = (size_t)a.class_cap * (2 + 2 * N) * sizeof(float);
+            k_velocity_plane<N><<<dim3(8 * a.vtiles_per_xcd), dim3(64, 4), lds, s>>>(a);
+            return hipGetLastError();
+        }
         if (tile_rows == 4) return launch_pair<3, N, 64, 4, 1>(velocity, a, s);
         if (tile_rows == 8 && rpt == 2) return launch_pair<3, N, 64, 4, 2>(velocity, a, s);
         if (tile_rows == 8) return launch_pair<3, N, 64, 8, 1>(velocity, a, s);

@@ -10,6 +10,7 @@
 #include <map>
 #include <new>
 #include <string>
+#include <limits>
 #include <vector>
 
 #include "../../include/fw25.h"
@@ -91,16 +92,17 @@ struct fw_sim {
     uint64_t noise_seed = 0;
     std::vector<double> kappa, dcoef, alpha;
     // device tables
-    DevBuf d_doms, d_classes, d_pml, d_tiles, d_src_cell, d_src_wave, d_waves, d_rec_cell, d_traces, d_step;
+    DevBuf d_doms, d_classes, d_pml, d_tiles, d_vtiles, d_src_cell, d_src_wave, d_waves, d_rec_cell, d_traces, d_step;
     DevBuf d_cadj, d_adj_cells, d_adj_off, d_adj_idx;
     DevBuf d_pold, d_partial;
     int64_t n_adj_cells = 0;
     int64_t total_packed = 0;
-    int n_tiles = 0, tiles_per_xcd = 0;
+    int n_tiles = 0, tiles_per_xcd = 0, n_vtiles = 0, vtiles_per_xcd = 0;
     int64_t n_src = 0, n_rec = 0;
     int n_t = 0, n_t_max = 0;
     // options
-    int graph_steps = 16, march_chunk = 0, tile_rows = 4, rows_per_thread = 1, persistent = 0, tile_order = 0;
+    int graph_steps = 16, march_chunk = 0, tile_rows = 4, rows_per_thread = 1, persistent = 0, tile_order = 0,
+        plane_velocity = 1;
     // stepping
     int64_t host_step = 0;
     hipStream_t cap_stream = nullptr;
@@ -203,50 +205,108 @@ int stability_check(const fw_sim *s, double min_kappa_prod)
     return FW_OK;
 }
 
+// Plane-major tile list in 8 segments, one per XCD: segment k holds y-band k
+// (of the y-tiles) of every chunk of planes, domain by domain; segments are
+// padded with empty tiles (z1 == z0, skipped by every kernel) to one length.
+static std::vector<fw::Tile> banded_tiles(const fw_sim *s, int tx, int ty, int64_t chunk_or_auto)
+{
+    std::vector<fw::Tile> seg[8];
+    for (int d = 0; d < s->n_domains; ++d) {
+        const int64_t nx = s->doms[d].n[0], ny = s->doms[d].n[1], nz = s->doms[d].n[2];
+        const int64_t nytile = (ny + ty - 1) / ty, nxtile = (nx + tx - 1) / tx;
+        int64_t chunk = chunk_or_auto;
+        if (chunk <= 0) {
+            const int64_t nch = (nz + 47) / 48;
+            chunk = (nz + nch - 1) / nch;
+        }
+        chunk = std::max<int64_t>(1, std::min<int64_t>(chunk, nz));
+        for (int64_t z0 = 0; z0 < nz; z0 += chunk)
+            for (int k = 0; k < 8; ++k)
+                for (int64_t yt = k * nytile / 8; yt < (k + 1) * nytile / 8; ++yt)
+                    for (int64_t xt = 0; xt < nxtile; ++xt) {
+                        fw::Tile t{};
+                        t.dom = d;
+                        t.x0 = (int32_t)(xt * tx);
+                        t.y0 = (int32_t)(yt * ty);
+                        t.z0 = (int32_t)z0;
+                        t.z1 = (int32_t)std::min(nz, z0 + chunk);
+                        seg[k].push_back(t);
+                    }
+    }
+    size_t len = 0;
+    for (int k = 0; k < 8; ++k) len = std::max(len, seg[k].size());
+    std::vector<fw::Tile> tiles;
+    tiles.reserve(8 * len);
+    for (int k = 0; k < 8; ++k) {
+        tiles.insert(tiles.end(), seg[k].begin(), seg[k].end());
+        tiles.insert(tiles.end(), len - seg[k].size(), fw::Tile{});
+    }
+    return tiles;
+}
+
+static int upload_tiles(const std::vector<fw::Tile> &tiles, DevBuf &buf, int *n, int *per_xcd)
+{
+    if (tiles.size() > (size_t)std::numeric_limits<int32_t>::max() - 8)
+        return fail(FW_EINVAL, "too many tiles (%zu): use longer march chunks", tiles.size());
+    *n = (int)tiles.size();
+    *per_xcd = (*n + 7) / 8;
+    if (tiles.empty()) return FW_OK;
+    HIP_OR_FAIL(buf.ensure(tiles.size() * sizeof(fw::Tile)));
+    HIP_OR_FAIL(hipMemcpy(buf.ptr, tiles.data(), tiles.size() * sizeof(fw::Tile), hipMemcpyHostToDevice));
+    return FW_OK;
+}
+
 int build_tiles(fw_sim *s)
 {
     int tx, ty;
     fw::tile_shape(s->ndim, s->tile_rows, &tx, &ty);
     std::vector<fw::Tile> tiles;
-    for (int d = 0; d < s->n_domains; ++d) {
-        const int64_t nx = s->doms[d].n[0], ny = s->doms[d].n[1], nz = s->doms[d].n[2];
-        const int64_t nmarch = s->ndim == 3 ? nz : (s->ndim == 2 ? ny : 1);
-        const int64_t nytile = s->ndim == 3 ? (ny + ty - 1) / ty : 1;
-        const int64_t nxtile = (nx + tx - 1) / tx;
-        int64_t chunk = s->march_chunk;
-        if (chunk <= 0 && s->ndim == 3) {
-            // about 48 planes per tile (measured best: many small 4-wave tiles
-            // keep several independent blocks on each CU)
-            const int64_t nch = (nmarch + 47) / 48;
-            chunk = (nmarch + nch - 1) / nch;
-        } else if (chunk <= 0) {
-            // 2D: 8 rows per one-wave tile (measured best on single and
-            // batched grids: the many short tiles keep more waves in flight
-            // than the queue warm-up of each tile costs); 1D: one row
-            chunk = 8;
-        }
-        chunk = std::max<int64_t>(1, std::min<int64_t>(chunk, nmarch));
-        // tile order inside a chunk: x fastest (order 0) or y fastest
-        // (order 1: the y neighbours of a tile run right after it, so the
-        // halo rows they share are still in L2 when the second one reads them)
-        const int64_t n_in = nxtile * nytile;
-        for (int64_t z0 = 0; z0 < nmarch; z0 += chunk)
-            for (int64_t k = 0; k < n_in; ++k) {
-                const int64_t xt = s->tile_order == 1 ? k / nytile : k % nxtile;
-                const int64_t yt = s->tile_order == 1 ? k % nytile : k / nxtile;
-                fw::Tile t{};
-                t.dom = d;
-                t.x0 = (int32_t)(xt * tx);
-                t.y0 = (int32_t)(yt * ty);
-                t.z0 = (int32_t)z0;
-                t.z1 = (int32_t)std::min(nmarch, z0 + chunk);
-                tiles.push_back(t);
+    if (s->tile_order == 2 && s->ndim == 3) {
+        tiles = banded_tiles(s, tx, ty, s->march_chunk);
+    } else {
+        for (int d = 0; d < s->n_domains; ++d) {
+            const int64_t nx = s->doms[d].n[0], ny = s->doms[d].n[1], nz = s->doms[d].n[2];
+            const int64_t nmarch = s->ndim == 3 ? nz : (s->ndim == 2 ? ny : 1);
+            const int64_t nytile = s->ndim == 3 ? (ny + ty - 1) / ty : 1;
+            const int64_t nxtile = (nx + tx - 1) / tx;
+            int64_t chunk = s->march_chunk;
+            if (chunk <= 0 && s->ndim == 3) {
+                // about 48 planes per tile (measured best: many small 4-wave tiles
+                // keep several independent blocks on each CU)
+                const int64_t nch = (nmarch + 47) / 48;
+                chunk = (nmarch + nch - 1) / nch;
+            } else if (chunk <= 0) {
+                // 2D: 8 rows per one-wave tile (measured best on single and
+                // batched grids: the many short tiles keep more waves in flight
+                // than the queue warm-up of each tile costs); 1D: one row
+                chunk = 8;
             }
+            chunk = std::max<int64_t>(1, std::min<int64_t>(chunk, nmarch));
+            // tile order inside a chunk: x fastest (order 0) or y fastest
+            // (order 1: the y neighbours of a tile run right after it, so the
+            // halo rows they share are still in L2 when the second one reads them)
+            const int64_t n_in = nxtile * nytile;
+            for (int64_t z0 = 0; z0 < nmarch; z0 += chunk)
+                for (int64_t k = 0; k < n_in; ++k) {
+                    const int64_t xt = s->tile_order == 1 ? k / nytile : k % nxtile;
+                    const int64_t yt = s->tile_order == 1 ? k % nytile : k / nxtile;
+                    fw::Tile t{};
+                    t.dom = d;
+                    t.x0 = (int32_t)(xt * tx);
+                    t.y0 = (int32_t)(yt * ty);
+                    t.z0 = (int32_t)z0;
+                    t.z1 = (int32_t)std::min(nmarch, z0 + chunk);
+                    tiles.push_back(t);
+                }
+        }
     }
-    s->n_tiles = (int)tiles.size();
-    s->tiles_per_xcd = (s->n_tiles + 7) / 8;
-    HIP_OR_FAIL(s->d_tiles.ensure(tiles.size() * sizeof(fw::Tile)));
-    HIP_OR_FAIL(hipMemcpy(s->d_tiles.ptr, tiles.data(), tiles.size() * sizeof(fw::Tile), hipMemcpyHostToDevice));
+    int rc = upload_tiles(tiles, s->d_tiles, &s->n_tiles, &s->tiles_per_xcd);
+    if (rc != FW_OK) return rc;
+    // single-plane velocity tiles (3D): 64 x 4, one plane each
+    std::vector<fw::Tile> vt;
+    if (s->ndim == 3 && s->plane_velocity) vt = banded_tiles(s, 64, 4, 1);
+    rc = upload_tiles(vt, s->d_vtiles, &s->n_vtiles, &s->vtiles_per_xcd);
+    if (rc != FW_OK) return rc;
     s->tiles_dirty = false;
     s->drop_graph();
     return FW_OK;
@@ -270,6 +330,12 @@ fw::StepArgs step_args(const fw_sim *s)
     for (const auto &d : s->doms) cap = std::max(cap, (int)d.n_classes);
     a.class_cap = (cap + 3) / 4 * 4;
     a.tile_rows = s->tile_rows;
+    // the single-plane velocity kernel takes one tile per block: not with a
+    // persistent grid
+    a.plane = (s->ndim == 3 && s->plane_velocity && s->persistent == 0 && s->n_vtiles > 0) ? 1 : 0;
+    a.vtiles = s->d_vtiles.as<fw::Tile>();
+    a.n_vtiles = s->n_vtiles;
+    a.vtiles_per_xcd = s->vtiles_per_xcd;
     for (int m = 0; m < 4; ++m) a.fd[m] = (float)(kFD[m] / s->dx);
     a.dt = (float)s->dt;
     a.noise_amp = (float)s->noise_amp;
@@ -1043,7 +1109,7 @@ int fw_set_option(fw_sim *sim, int key, int64_t value)
         sim->drop_graph();
         return FW_OK;
     case FW_OPT_MARCH_CHUNK:
-        if (value != 0 && value < 8) return fail(FW_EINVAL, "march chunk must be 0 (auto) or >= 8");
+        if (value < 0) return fail(FW_EINVAL, "march chunk must be 0 (auto) or >= 1");
         sim->march_chunk = (int)value;
         sim->tiles_dirty = true;
         return FW_OK;
@@ -1059,8 +1125,14 @@ int fw_set_option(fw_sim *sim, int key, int64_t value)
         sim->drop_graph();
         return FW_OK;
     case FW_OPT_TILE_ORDER:
-        if (value != 0 && value != 1) return fail(FW_EINVAL, "tile order must be 0 (x fastest) or 1 (y fastest)");
+        if (value < 0 || value > 2)
+            return fail(FW_EINVAL, "tile order must be 0 (x fastest), 1 (y fastest) or 2 (plane-major XCD bands)");
         sim->tile_order = (int)value;
+        sim->tiles_dirty = true;
+        return FW_OK;
+    case FW_OPT_PLANE_VELOCITY:
+        if (value != 0 && value != 1) return fail(FW_EINVAL, "plane velocity must be 0 or 1");
+        sim->plane_velocity = (int)value;
         sim->tiles_dirty = true;
         return FW_OK;
     case FW_OPT_ROWS_PER_THREAD:
