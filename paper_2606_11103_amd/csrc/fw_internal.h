@@ -46,6 +46,9 @@ struct Fields {
     uint8_t *cls;
 };
 
+// planes per tile of the 3D pressure plane kernel
+constexpr int kPressurePlanes = 4;
+
 struct StepArgs {
     Fields f;                  // state read by the step
     Fields fo;                 // state written by the step (== f: in place)
@@ -59,10 +62,13 @@ struct StepArgs {
     int32_t pml;               // CPML width P
     int32_t class_cap;         // entries per LDS class table (>= classes of any domain)
     int32_t tile_rows;         // rows of a 3D tile along y
-    int32_t plane;             // 1: the 3D velocity update runs the single-plane kernel on vtiles
-    const Tile *vtiles;        // 64 x 4 tiles of one plane, plane-major, XCD k owning y-band k
+    int32_t plane;             // 1: 3D updates run the plane kernels on vtiles / ptiles
+    const Tile *vtiles;        // velocity: 64 x 4 tiles of one plane, plane-major, XCD k owning y-band k
     int32_t n_vtiles;
     int32_t vtiles_per_xcd;
+    const Tile *ptiles;        // pressure: 64 x 4 tiles of kPressurePlanes planes, same banding
+    int32_t n_ptiles;
+    int32_t ptiles_per_xcd;
     float fd[4];               // staggered coefficients c_m / dx
     float dt;
     float noise_amp;

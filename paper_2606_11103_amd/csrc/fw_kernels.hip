@@ -642,15 +642,15 @@ __global__ __launch_bounds__(BX *BY) void k_pressure(const StepArgs A)
 // tiles cover one contiguous stretch of each field.  The x/y stencils read
 // an LDS tile.  There is no prefetch state, so more waves fit on a SIMD to
 // hide the latency.  Each output is computed with the same operations, in
-// the same order, as in k_velocity, so the two give identical bits.  (The
-// pressure update moves less than half the bytes per cell, so the window
-// reads weigh more there; it keeps the marching kernel.)
+// the same order, as in k_velocity, so the two give identical bits.
 // ---------------------------------------------------------------------------
 template <int N>
 __global__ __launch_bounds__(256) void k_velocity_plane(const StepArgs A)
 {
     constexpr int BX = 64, TY = 4, LX = BX + 8, LY = TY + 8, NT = BX * TY, CX = BX + 1;
-    constexpr int NHALO = 8 * LX + 8 * TY;
+    // halo cells the stencils read: 3 rows above and 4 below the tile over
+    // its own columns, 3 columns left and 4 right over its own rows
+    constexpr int NHALO = 7 * BX + 7 * TY;
     constexpr int HS = (NHALO + NT - 1) / NT;
     constexpr int NCH = TY + BX;
     __shared__ float sp[LY * LX];
@@ -685,22 +685,22 @@ __global__ __launch_bounds__(256) void k_velocity_plane(const StepArgs A)
     const DomPtrs Mo = dom_ptrs<N>(A.fo, D);
     const int P = A.pml;
 
-    // x/y halo of p (4 rows above and below over the tile's width plus the
-    // corners, 4 columns left and right of its rows), zero outside the domain
+    // x/y halo of p, zero outside the domain (LDS row hy holds y0 - 4 + hy,
+    // column hx holds x0 - 4 + hx; the corners are never read)
 #pragma unroll
     for (int s = 0; s < HS; ++s) {
         const int h = tid + s * NT;
         if (h < NHALO) {
             int hy, hx;
-            if (h < 8 * LX) {
-                const int rr = h / LX;
-                hy = rr < 4 ? rr : TY + rr;
-                hx = h - rr * LX;
+            if (h < 7 * BX) {
+                const int rr = h / BX;
+                hy = rr < 3 ? rr + 1 : TY + 1 + rr;
+                hx = 4 + h - rr * BX;
             } else {
-                const int hh = h - 8 * LX;
-                hy = 4 + (hh >> 3);
-                const int k = hh & 7;
-                hx = k < 4 ? k : BX + k;
+                const int hh = h - 7 * BX;
+                hy = 4 + hh / 7;
+                const int k = hh - (hh / 7) * 7;
+                hx = k < 3 ? k + 1 : BX + 1 + k;
             }
             const int gx = T.x0 - 4 + hx, gy = T.y0 - 4 + hy;
             const bool inside = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
@@ -738,7 +738,7 @@ __global__ __launch_bounds__(256) void k_velocity_plane(const StepArgs A)
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const int c = a == 0 ? x : (a == 1 ? y : z), n = a == 0 ? nx : (a == 1 ? ny : nz);
-            vc[a] = M.v[a][g];
+            vc[a] = load1_stream(M.v[a] + g);   // no other tile of this launch reads it
             load_stream<N>(M.psi1[a] + (size_t)g * N, pc[a]);
             ppc[a] = in_slab(c, n, P) ? M.pP1[a][g] : 0.0f;
         }
@@ -778,6 +778,166 @@ __global__ __launch_bounds__(256) void k_velocity_plane(const StepArgs A)
         }
         store_stream<N>(Mo.psi1[a] + (size_t)g * N, pc[a]);
         store1_stream(Mo.v[a] + g, fmaf(-m, sacc, vc[a]));
+    }
+}
+
+// Pressure update on tiles of kPressurePlanes consecutive planes (3D, 64 x 4,
+// one tile per block), from a list in which XCD k owns y-band k of every
+// group of planes.  The v_z window of the group (its planes - 4 .. + 3 past
+// the last) is loaded once into registers; each plane stages the x-halo of
+// v_x and the y-halo of v_y in a double-buffered LDS tile (one barrier per
+// plane).  Same operations in the same order as k_pressure.
+template <int N>
+__global__ __launch_bounds__(256) void k_pressure_planes(const StepArgs A)
+{
+    constexpr int NP = kPressurePlanes;
+    constexpr int BX = 64, TY = 4, LX = BX + 8, LY = TY + 8, NT = BX * TY;
+    // halo cells the stencils read: x-4 .. x-1 and x+64 .. x+66 of v_x over
+    // the tile's rows, y-4 .. y-1 and y+4 .. y+6 of v_y over its columns
+    constexpr int NHALO = 7 * TY + 7 * BX;
+    constexpr int HS = (NHALO + NT - 1) / NT;
+    __shared__ float svx[2][TY * LX];
+    __shared__ float svy[2][LY * BX];
+    extern __shared__ float s_dyn[];
+    const int C = A.class_cap;
+    float *s_ik = s_dyn, *s_K = s_dyn + C, *s_tb = s_dyn + 2 * C, *s_a = s_dyn + 3 * C, *s_b = s_dyn + (3 + N) * C;
+
+    const int b = blockIdx.x;
+    const int ti = (b & 7) * A.ptiles_per_xcd + (b >> 3);
+    if (ti >= A.n_ptiles) return;
+    const Tile T = A.ptiles[ti];
+    if (T.z1 <= T.z0) return;      // padding of the banded list
+    const DomainDesc D = A.doms[T.dom];
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * BX + tx;
+    for (int c = tid; c < D.n_classes; c += NT) {
+        const ClassCoef &cc = A.classes[D.class_base + c];
+        s_ik[c] = cc.ik2;
+        s_K[c] = cc.K;
+        s_tb[c] = cc.twobeta;
+#pragma unroll
+        for (int nu = 0; nu < N; ++nu) {
+            s_a[nu * C + c] = cc.a2[nu];
+            s_b[nu * C + c] = cc.b2[nu];
+        }
+    }
+    const int nx = (int)D.n[0], ny = (int)D.n[1], nz = (int)D.n[2], sm = nx * ny;
+    const int x = T.x0 + tx, y = T.y0 + ty;
+    const bool ok = x < nx && y < ny;
+    // p and the memory variables read from A.f, the new velocity and every
+    // write in A.fo (the same buffers when stepping in place)
+    const DomPtrs M = dom_ptrs<N>(A.f, D);
+    const DomPtrs Mo = dom_ptrs<N>(A.fo, D);
+    const int P = A.pml;
+    const int col = y * nx + x;
+
+    // v_z of the group's window: planes z0 - 4 .. z0 + NP + 2, zero outside
+    float vq[NP + 7];
+#pragma unroll
+    for (int j = 0; j < NP + 7; ++j) {
+        const int zz = T.z0 - 4 + j;
+        vq[j] = (ok && zz >= 0 && zz < nz) ? Mo.v[2][col + zz * sm] : 0.0f;
+    }
+    // halo slots: plane-relative offset (-1: outside the domain, value 0) and
+    // target (>= 0: svx index, <= -2: svy index -(li + 2), -1: no slot)
+    int hoff[HS], hli[HS];
+#pragma unroll
+    for (int s = 0; s < HS; ++s) {
+        const int h = tid + s * NT;
+        int gx, gy, li;
+        if (h < 7 * TY) {
+            const int row = h / 7, k = h - (h / 7) * 7;
+            const int hx = k < 4 ? k : BX + k;
+            gx = T.x0 - 4 + hx;
+            gy = T.y0 + row;
+            li = row * LX + hx;
+        } else {
+            const int hh = h - 7 * TY;
+            const int rr = hh / BX;
+            const int hy = rr < 4 ? rr : TY + rr;
+            const int hx = hh - rr * BX;
+            gx = T.x0 + hx;
+            gy = T.y0 - 4 + hy;
+            li = -(hy * BX + hx) - 2;
+        }
+        const bool inside = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+        hli[s] = h < NHALO ? li : -1;
+        hoff[s] = (h < NHALO && inside) ? gy * nx + gx : -1;
+    }
+
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        const int z = T.z0 + j;
+        if (z >= T.z1) break;
+        const int zoff = z * sm;
+        const int g = zoff + col;
+        float *bx = svx[j & 1], *by = svy[j & 1];
+#pragma unroll
+        for (int s = 0; s < HS; ++s) {
+            if (hli[s] == -1) continue;
+            const float val = hoff[s] < 0 ? 0.0f : (hli[s] >= 0 ? Mo.v[0][zoff + hoff[s]] : Mo.v[1][zoff + hoff[s]]);
+            if (hli[s] >= 0)
+                bx[hli[s]] = val;
+            else
+                by[-(hli[s] + 2)] = val;
+        }
+        float ox = 0.0f, oy = 0.0f, pc = 0.0f, psc[N], ppc[3];
+        int L = 0;
+        if (ok) {
+            pc = load1_stream(M.p + g);   // no other tile of this launch reads it
+            L = M.cls[g];
+            load_stream<N>(M.psi2 + (size_t)g * N, psc);
+            ox = Mo.v[0][g];
+            oy = Mo.v[1][g];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int c = a == 0 ? x : (a == 1 ? y : z), n = a == 0 ? nx : (a == 1 ? ny : nz);
+                ppc[a] = in_slab(c, n, P) ? M.pP2[a][g] : 0.0f;
+            }
+        }
+        bx[ty * LX + 4 + tx] = ox;
+        by[(ty + 4) * BX + tx] = oy;
+        // the buffer written here was last read in plane j - 2, before the
+        // barrier of plane j - 1 that every thread has passed
+        __syncthreads();
+        if (!ok) continue;
+        const float *sx = bx + ty * LX + 4 + tx;
+        const float *sy = by + (ty + 4) * BX + tx;
+        float Dd[3];
+        Dd[0] = stencil4(A.fd, sx[0] - sx[-1], sx[1] - sx[-2], sx[2] - sx[-3], sx[3] - sx[-4]);
+        Dd[1] = stencil4(A.fd, sy[0] - sy[-BX], sy[BX] - sy[-2 * BX], sy[2 * BX] - sy[-3 * BX], sy[3 * BX] - sy[-4 * BX]);
+        Dd[2] = stencil4(A.fd, vq[j + 4] - vq[j + 3], vq[j + 5] - vq[j + 2], vq[j + 6] - vq[j + 1], vq[j + 7] - vq[j]);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int c = a == 0 ? x : (a == 1 ? y : z), n = a == 0 ? nx : (a == 1 ? ny : nz);
+            if (in_slab(c, n, P)) {
+                const int32_t off = D.pml_off[a];
+                const float aC = A.pml_tab[off + 2 * n + c];
+                const float bC = A.pml_tab[off + 3 * n + c];
+                const float qv = fmaf(aC, Dd[a], bC * ppc[a]);
+                Mo.pP2[a][g] = qv;
+                Dd[a] += qv;
+            }
+        }
+        float S = Dd[0];
+#pragma unroll
+        for (int a = 1; a < 3; ++a) S += Dd[a];
+        float Tt = s_ik[L] * S;
+#pragma unroll
+        for (int nu = 0; nu < N; ++nu) {
+            psc[nu] = fmaf(s_a[nu * C + L], S, s_b[nu * C + L] * psc[nu]);
+            Tt += psc[nu];
+        }
+        store_stream<N>(Mo.psi2 + (size_t)g * N, psc);
+        float K = s_K[L];
+        if (A.noise_amp != 0.0f) {
+            const uint64_t hsh = splitmix64(D.noise_seed ^ (uint64_t)(uint32_t)g);
+            const float u = (float)(hsh >> 40) * 0x1.0p-24f;
+            const float e = A.noise_amp * fmaf(2.0f, u, -1.0f);
+            const float f1 = 1.0f + e;
+            K = K * (f1 * f1);
+        }
+        const float pn0 = pc;
+        store1_stream(Mo.p + g, fmaf(-(A.dt * fmaf(s_tb[L], pn0, K)), Tt, pn0));
     }
 }
 
@@ -825,10 +985,12 @@ template <int NDIM, int N>
 hipError_t launch_nd(bool velocity, int tile_rows, int rpt, const StepArgs &a, hipStream_t s)
 {
     if constexpr (NDIM == 3) {
-        if (velocity && a.plane) {
-            if (a.n_vtiles <= 0) return hipSuccess;
-            const size_t lds = (size_t)a.class_cap * (2 + 2 * N) * sizeof(float);
-            k_velocity_plane<N><<<dim3(8 * a.vtiles_per_xcd), dim3(64, 4), lds, s>>>(a);
+        if (a.plane) {
+            const size_t lds = (size_t)a.class_cap * (velocity ? 2 + 2 * N : 3 + 2 * N) * sizeof(float);
+            if (velocity && a.n_vtiles > 0)
+                k_velocity_plane<N><<<dim3(8 * a.vtiles_per_xcd), dim3(64, 4), lds, s>>>(a);
+            else if (!velocity && a.n_ptiles > 0)
+                k_pressure_planes<N><<<dim3(8 * a.ptiles_per_xcd), dim3(64, 4), lds, s>>>(a);
             return hipGetLastError();
         }
         if (tile_rows == 4) return launch_pair<3, N, 64, 4, 1>(velocity, a, s);

@@ -92,17 +92,17 @@ struct fw_sim {
     uint64_t noise_seed = 0;
     std::vector<double> kappa, dcoef, alpha;
     // device tables
-    DevBuf d_doms, d_classes, d_pml, d_tiles, d_vtiles, d_src_cell, d_src_wave, d_waves, d_rec_cell, d_traces, d_step;
+    DevBuf d_doms, d_classes, d_pml, d_tiles, d_vtiles, d_ptiles, d_src_cell, d_src_wave, d_waves, d_rec_cell, d_traces, d_step;
     DevBuf d_cadj, d_adj_cells, d_adj_off, d_adj_idx;
     DevBuf d_pold, d_partial;
     int64_t n_adj_cells = 0;
     int64_t total_packed = 0;
-    int n_tiles = 0, tiles_per_xcd = 0, n_vtiles = 0, vtiles_per_xcd = 0;
+    int n_tiles = 0, tiles_per_xcd = 0, n_vtiles = 0, vtiles_per_xcd = 0, n_ptiles = 0, ptiles_per_xcd = 0;
     int64_t n_src = 0, n_rec = 0;
     int n_t = 0, n_t_max = 0;
     // options
     int graph_steps = 16, march_chunk = 0, tile_rows = 4, rows_per_thread = 1, persistent = 0, tile_order = 0,
-        plane_velocity = 1;
+        plane_kernels = 1;
     // stepping
     int64_t host_step = 0;
     hipStream_t cap_stream = nullptr;
@@ -302,10 +302,16 @@ int build_tiles(fw_sim *s)
     }
     int rc = upload_tiles(tiles, s->d_tiles, &s->n_tiles, &s->tiles_per_xcd);
     if (rc != FW_OK) return rc;
-    // single-plane velocity tiles (3D): 64 x 4, one plane each
-    std::vector<fw::Tile> vt;
-    if (s->ndim == 3 && s->plane_velocity) vt = banded_tiles(s, 64, 4, 1);
+    // plane-kernel tiles (3D): 64 x 4, one plane each for the velocity
+    // update, kPressurePlanes planes for the pressure update
+    std::vector<fw::Tile> vt, pt;
+    if (s->ndim == 3 && s->plane_kernels) {
+        vt = banded_tiles(s, 64, 4, 1);
+        pt = banded_tiles(s, 64, 4, fw::kPressurePlanes);
+    }
     rc = upload_tiles(vt, s->d_vtiles, &s->n_vtiles, &s->vtiles_per_xcd);
+    if (rc != FW_OK) return rc;
+    rc = upload_tiles(pt, s->d_ptiles, &s->n_ptiles, &s->ptiles_per_xcd);
     if (rc != FW_OK) return rc;
     s->tiles_dirty = false;
     s->drop_graph();
@@ -330,12 +336,14 @@ fw::StepArgs step_args(const fw_sim *s)
     for (const auto &d : s->doms) cap = std::max(cap, (int)d.n_classes);
     a.class_cap = (cap + 3) / 4 * 4;
     a.tile_rows = s->tile_rows;
-    // the single-plane velocity kernel takes one tile per block: not with a
-    // persistent grid
-    a.plane = (s->ndim == 3 && s->plane_velocity && s->persistent == 0 && s->n_vtiles > 0) ? 1 : 0;
+    // the plane kernels take one tile per block: not with a persistent grid
+    a.plane = (s->ndim == 3 && s->plane_kernels && s->persistent == 0 && s->n_vtiles > 0) ? 1 : 0;
     a.vtiles = s->d_vtiles.as<fw::Tile>();
     a.n_vtiles = s->n_vtiles;
     a.vtiles_per_xcd = s->vtiles_per_xcd;
+    a.ptiles = s->d_ptiles.as<fw::Tile>();
+    a.n_ptiles = s->n_ptiles;
+    a.ptiles_per_xcd = s->ptiles_per_xcd;
     for (int m = 0; m < 4; ++m) a.fd[m] = (float)(kFD[m] / s->dx);
     a.dt = (float)s->dt;
     a.noise_amp = (float)s->noise_amp;
@@ -1130,9 +1138,9 @@ int fw_set_option(fw_sim *sim, int key, int64_t value)
         sim->tile_order = (int)value;
         sim->tiles_dirty = true;
         return FW_OK;
-    case FW_OPT_PLANE_VELOCITY:
-        if (value != 0 && value != 1) return fail(FW_EINVAL, "plane velocity must be 0 or 1");
-        sim->plane_velocity = (int)value;
+    case FW_OPT_PLANE_KERNELS:
+        if (value != 0 && value != 1) return fail(FW_EINVAL, "plane kernels must be 0 or 1");
+        sim->plane_kernels = (int)value;
         sim->tiles_dirty = true;
         return FW_OK;
     case FW_OPT_ROWS_PER_THREAD:

@@ -82,6 +82,15 @@ __device__ __forceinline__ void store_stream(float *__restrict__ dst, const floa
 #endif
 }
 
+__device__ __forceinline__ float load1_stream(const float *__restrict__ src)
+{
+#if FW_STREAMING
+    return __builtin_nontemporal_load(src);
+#else
+    return *src;
+#endif
+}
+
 __device__ __forceinline__ void store1_stream(float *__restrict__ dst, float v)
 {
 #if FW_STREAMING

@@ -85,19 +85,19 @@ def test_graph_and_eager_paths_are_bitwise_identical():
 
 
 def test_tiling_does_not_change_results():
-    from paper_2606_11103_amd.native import (FW_OPT_MARCH_CHUNK, FW_OPT_PERSISTENT, FW_OPT_PLANE_VELOCITY,
+    from paper_2606_11103_amd.native import (FW_OPT_MARCH_CHUNK, FW_OPT_PERSISTENT, FW_OPT_PLANE_KERNELS,
                                              FW_OPT_ROWS_PER_THREAD, FW_OPT_TILE_ORDER, FW_OPT_TILE_ROWS)
     case = _case("3d_random_N2_ragged")
     # reference: both updates marching 16-row tiles
-    _, ref = _run(case, opts={FW_OPT_TILE_ROWS: 16, FW_OPT_PLANE_VELOCITY: 0})
-    # (tile rows, rows per thread, chunk, persistent, tile order, single-plane velocity); a
-    # persistent grid keeps the marching velocity kernel
+    _, ref = _run(case, opts={FW_OPT_TILE_ROWS: 16, FW_OPT_PLANE_KERNELS: 0})
+    # (tile rows, rows per thread, chunk, persistent, tile order, plane kernels); a persistent
+    # grid keeps the marching kernels.  The 29-plane grid leaves a 1-plane pressure tile.
     for rows, rpt, chunk, pers, order, plane in (
             (4, 1, 0, 0, 0, 1), (8, 1, 8, 0, 0, 0), (8, 2, 13, 1, 0, 1), (16, 2, 0, 0, 0, 0), (16, 1, 9, 2, 0, 1),
             (4, 1, 0, 0, 1, 0), (8, 2, 11, 1, 1, 1), (4, 1, 1, 0, 2, 1), (4, 1, 1, 0, 0, 0), (8, 1, 1, 0, 2, 0),
             (4, 1, 3, 0, 2, 1), (4, 1, 1, 1, 2, 0), (16, 1, 0, 0, 2, 1)):
         opts = {FW_OPT_TILE_ROWS: rows, FW_OPT_ROWS_PER_THREAD: rpt, FW_OPT_PERSISTENT: pers, FW_OPT_TILE_ORDER: order,
-                FW_OPT_PLANE_VELOCITY: plane}
+                FW_OPT_PLANE_KERNELS: plane}
         if chunk:
             opts[FW_OPT_MARCH_CHUNK] = chunk
         _, got = _run(case, opts=opts)
