@@ -30,8 +30,11 @@ HBM_PEAK_GBS = 8000.0
 # copy kernel), keyed by the SHA-256 prefix of the kernel source they were
 # taken on; any other kernel source reports traffic as null.
 TRAFFIC_MEASURED = {
-    "baca8324244d30dc": {"workload": "3d_heterogeneous_960x960x720", "tile_rows": 4, "rows_per_thread": 1,
-                         "bytes_per_launch": 88.67e9,
+    # velocity update (single-plane kernel): FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 per launch.
+    # FETCH_SIZE counts L2 misses sent to the data fabric, so it includes the z-window reads
+    # that the last-level cache serves: an upper bound on the HBM bytes.
+    "720884815f9be17f": {"workload": "3d_heterogeneous_960x960x720", "tile_rows": 4, "rows_per_thread": 1,
+                         "bytes_per_launch": 98.48e9,
                          "profile": "profiles/step_kernels_3d_960x960x720_N4.md"},
 }
 
@@ -468,7 +471,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "velocity update",
                      "achieved": round(ach_vel, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach_vel / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "traffic_note": "measured HBM bytes per launch / avg launch time (GB/s), see profile",
+                     "traffic_note": "FETCH_SIZE + WRITE_SIZE bytes per launch (L2 misses to the fabric: includes last-level-cache hits) / avg launch time (GB/s), see profile",
                      "bytes_per_cell": round(b_vel, 2), "avg_ms": round(kern_ms[0], 4)},
         "step_roofline": {"achieved": round(ach_step, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": round(ach_step / HBM_PEAK_GBS, 4), "bytes_per_cell": round(b_step, 2)},

@@ -290,13 +290,14 @@ int fw_device_copy(void *d_dst, const void *d_src, int64_t bytes, void *hip_stre
  *   FW_OPT_TILE_ORDER    order of the marching tiles: 0 = x fastest within a
  *                        chunk (default), 1 = y fastest, 2 = plane-major with
  *                        XCD k owning y-band k of every chunk (3D).
- *   FW_OPT_PLANE_KERNELS 3D: 1 (default) = the velocity update runs on 64 x 4
+ *   FW_OPT_PLANE_KERNELS 3D: 1 = the velocity update runs on 64 x 4
  *                        tiles of one plane and the pressure update on 64 x 4
  *                        tiles of 4 planes, plane-major with XCD k owning
  *                        y-band k of every plane (the z stencil reads its
  *                        eight-plane window from memory: it stays in the
  *                        last-level cache); 0 = both march the tiles set by the
- *                        options above.  Not used with a persistent grid.
+ *                        options above; -1 (default) = 1 with N >= 3
+ *                        mechanisms, else 0.  Not used with a persistent grid.
  * Options change the work decomposition only, never the results.
  */
 enum { FW_OPT_GRAPH_STEPS = 1, FW_OPT_MARCH_CHUNK = 2, FW_OPT_TILE_ROWS = 3, FW_OPT_ROWS_PER_THREAD = 4,
