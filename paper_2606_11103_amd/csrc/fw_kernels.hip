@@ -634,31 +634,33 @@ __global__ __launch_bounds__(BX *BY) void k_pressure(const StepArgs A)
 }
 
 // ---------------------------------------------------------------------------
-// Single-plane velocity update (3D, 64 x 4 tiles of one plane, one tile per
-// block).  Its tile list is plane-major and XCD k owns y-band k of every
-// plane, so all XCDs work on the same few planes: the eight-plane window of
-// the z stencil stays in the last-level cache and is read straight from
-// memory instead of being carried in a register queue, and the concurrent
-// tiles cover one contiguous stretch of each field.  The x/y stencils read
-// an LDS tile.  There is no prefetch state, so more waves fit on a SIMD to
-// hide the latency.  Each output is computed with the same operations, in
-// the same order, as in k_velocity, so the two give identical bits.
+// Plane velocity update (3D, 64 x 4 tiles of kVelocityPlanes planes, one
+// tile per block).  Its tile list is plane-major and XCD k owns y-band k of
+// every plane, so all XCDs work on the same few planes: the window of the z
+// stencil stays in the last-level cache and is read straight from memory
+// instead of being carried in a register queue, and the concurrent tiles
+// cover one contiguous stretch of each field.  The x/y stencils read an LDS
+// tile.  There is no prefetch state, so more waves fit on a SIMD to hide the
+// latency.  Each output is computed with the same operations, in the same
+// order, as in k_velocity, so the two give identical bits.
 // ---------------------------------------------------------------------------
 template <int N>
 __global__ __launch_bounds__(256) void k_velocity_plane(const StepArgs A)
 {
+    constexpr int NP = kVelocityPlanes;
+    constexpr int NB = NP > 1 ? 2 : 1;      // LDS buffers
     constexpr int BX = 64, TY = 4, LX = BX + 8, LY = TY + 8, NT = BX * TY, CX = BX + 1;
     // halo cells the stencils read: 3 rows above and 4 below the tile over
-    // its own columns, 3 columns left and 4 right over its own rows
+    // its own columns, 3 columns left and 4 right over its own rows (LDS row
+    // hy holds y0 - 4 + hy, column hx holds x0 - 4 + hx; corners never read)
     constexpr int NHALO = 7 * BX + 7 * TY;
     constexpr int HS = (NHALO + NT - 1) / NT;
     constexpr int NCH = TY + BX;
-    __shared__ float sp[LY * LX];
-    __shared__ uint8_t scl[(TY + 1) * CX];
+    __shared__ float sp[NB][LY * LX];
+    __shared__ uint8_t scl[NB][(TY + 1) * CX];
     extern __shared__ float s_dyn[];
     const int C = A.class_cap;
     float *s_ik = s_dyn, *s_rho = s_dyn + C, *s_a = s_dyn + 2 * C, *s_b = s_dyn + (2 + N) * C;
-
     const int b = blockIdx.x;
     const int ti = (b & 7) * A.vtiles_per_xcd + (b >> 3);
     if (ti >= A.n_vtiles) return;
@@ -677,107 +679,120 @@ __global__ __launch_bounds__(256) void k_velocity_plane(const StepArgs A)
         }
     }
     const int nx = (int)D.n[0], ny = (int)D.n[1], nz = (int)D.n[2], sm = nx * ny;
-    const int x = T.x0 + tx, y = T.y0 + ty, z = T.z0;
+    const int x = T.x0 + tx, y = T.y0 + ty;
     const bool ok = x < nx && y < ny;
-    const int zoff = z * sm;
-    const int g = zoff + y * nx + x;
+    const int col = y * nx + x;
     const DomPtrs M = dom_ptrs<N>(A.f, D);
     const DomPtrs Mo = dom_ptrs<N>(A.fo, D);
     const int P = A.pml;
-
-    // x/y halo of p, zero outside the domain (LDS row hy holds y0 - 4 + hy,
-    // column hx holds x0 - 4 + hx; the corners are never read)
+    // the z window first (its reads come from the last-level cache and take
+    // longest): p at planes z0 - 3 .. z0 + NP + 3, classes at z0 .. z0 + NP
+    float q[NP + 7];
+    int cz[NP + 1];
+#pragma unroll
+    for (int j = 0; j < NP + 7; ++j) {
+        const int zz = T.z0 - 3 + j;
+        q[j] = (ok && zz >= 0 && zz < nz) ? M.p[col + zz * sm] : 0.0f;
+    }
+#pragma unroll
+    for (int j = 0; j <= NP; ++j) {
+        const int zz = T.z0 + j;
+        cz[j] = (ok && zz < nz) ? M.cls[col + zz * sm] : 0;
+    }
+    int hoff[HS], hli[HS];
 #pragma unroll
     for (int s = 0; s < HS; ++s) {
         const int h = tid + s * NT;
-        if (h < NHALO) {
-            int hy, hx;
-            if (h < 7 * BX) {
-                const int rr = h / BX;
-                hy = rr < 3 ? rr + 1 : TY + 1 + rr;
-                hx = 4 + h - rr * BX;
-            } else {
-                const int hh = h - 7 * BX;
-                hy = 4 + hh / 7;
-                const int k = hh - (hh / 7) * 7;
-                hx = k < 3 ? k + 1 : BX + 1 + k;
-            }
-            const int gx = T.x0 - 4 + hx, gy = T.y0 - 4 + hy;
-            const bool inside = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-            sp[hy * LX + hx] = inside ? M.p[zoff + gy * nx + gx] : 0.0f;
+        int hy = 0, hx = 0;
+        if (h < 7 * BX) {
+            const int rr = h / BX;
+            hy = rr < 3 ? rr + 1 : TY + 1 + rr;
+            hx = 4 + h - rr * BX;
+        } else {
+            const int hh = h - 7 * BX;
+            hy = 4 + hh / 7;
+            const int k = hh - (hh / 7) * 7;
+            hx = k < 3 ? k + 1 : BX + 1 + k;
         }
+        const int gx = T.x0 - 4 + hx, gy = T.y0 - 4 + hy;
+        const bool inside = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+        hli[s] = h < NHALO ? hy * LX + hx : -1;
+        hoff[s] = (h < NHALO && inside) ? gy * nx + gx : -1;
     }
-    // classes of the next column and of the next row of the tile
+    int coff = -1, cli = -1;
     if (tid < NCH) {
-        int gx, gy, li;
+        int gx, gy;
         if (tid < TY) {
             gx = T.x0 + BX;
             gy = T.y0 + tid;
-            li = tid * CX + BX;
+            cli = tid * CX + BX;
         } else {
             gx = T.x0 + (tid - TY);
             gy = T.y0 + TY;
-            li = TY * CX + (tid - TY);
+            cli = TY * CX + (tid - TY);
         }
-        scl[li] = (gx < nx && gy < ny) ? M.cls[zoff + gy * nx + gx] : (uint8_t)0;
+        coff = (gx < nx && gy < ny) ? gy * nx + gx : -1;
     }
-    // own column: p at z-3 .. z+4, classes at z and z+1, private state
-    float q[8];
-    float vc[3], pc[3][N], ppc[3];
-    int L = 0, Lz = 0;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) q[j] = 0.0f;
-    if (ok) {
+    for (int j = 0; j < NP; ++j) {
+        const int z = T.z0 + j;
+        if (z >= T.z1) break;
+        const int zoff = z * sm;
+        const int g = zoff + col;
+        float *bp = sp[j % NB];
+        uint8_t *bc = scl[j % NB];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int zz = z - 3 + j;
-            if (zz >= 0 && zz < nz) q[j] = M.p[g + (j - 3) * sm];
+        for (int s = 0; s < HS; ++s)
+            if (hli[s] >= 0) bp[hli[s]] = hoff[s] >= 0 ? M.p[zoff + hoff[s]] : 0.0f;
+        if (cli >= 0) bc[cli] = coff >= 0 ? M.cls[zoff + coff] : (uint8_t)0;
+        float vc[3], pc[3][N], ppc[3];
+        if (ok) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int c = a == 0 ? x : (a == 1 ? y : z), n = a == 0 ? nx : (a == 1 ? ny : nz);
+                vc[a] = load1_stream(M.v[a] + g);
+                load_stream<N>(M.psi1[a] + (size_t)g * N, pc[a]);
+                ppc[a] = in_slab(c, n, P) ? M.pP1[a][g] : 0.0f;
+            }
         }
-        L = M.cls[g];
-        Lz = (z + 1 < nz) ? M.cls[g + sm] : L;
+        bp[(ty + 4) * LX + 4 + tx] = q[j + 3];
+        bc[ty * CX + tx] = (uint8_t)cz[j];
+        // with two buffers, the one written here was last read in plane
+        // j - 2, before the barrier of plane j - 1 that every thread passed
+        __syncthreads();
+        if (!ok) continue;
+        const int L = cz[j];
+        const float *sr = bp + (ty + 4) * LX + 4 + tx;
+        float Dv[3];
+        int Ln[3];
+        Dv[0] = stencil4(A.fd, sr[1] - sr[0], sr[2] - sr[-1], sr[3] - sr[-2], sr[4] - sr[-3]);
+        Ln[0] = (x + 1 < nx) ? bc[ty * CX + tx + 1] : L;
+        Dv[1] = stencil4(A.fd, sr[LX] - sr[0], sr[2 * LX] - sr[-LX], sr[3 * LX] - sr[-2 * LX], sr[4 * LX] - sr[-3 * LX]);
+        Ln[1] = (y + 1 < ny) ? bc[(ty + 1) * CX + tx] : L;
+        Dv[2] = stencil4(A.fd, q[j + 4] - q[j + 3], q[j + 5] - q[j + 2], q[j + 6] - q[j + 1], q[j + 7] - q[j]);
+        Ln[2] = (z + 1 < nz) ? cz[j + 1] : L;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
+            float Da = Dv[a];
             const int c = a == 0 ? x : (a == 1 ? y : z), n = a == 0 ? nx : (a == 1 ? ny : nz);
-            vc[a] = load1_stream(M.v[a] + g);   // no other tile of this launch reads it
-            load_stream<N>(M.psi1[a] + (size_t)g * N, pc[a]);
-            ppc[a] = in_slab(c, n, P) ? M.pP1[a][g] : 0.0f;
-        }
-    }
-    sp[(ty + 4) * LX + 4 + tx] = q[3];
-    scl[ty * CX + tx] = (uint8_t)L;
-    __syncthreads();
-    if (!ok) return;
-
-    const float *sr = sp + (ty + 4) * LX + 4 + tx;
-    float Dv[3];
-    int Ln[3];
-    Dv[0] = stencil4(A.fd, sr[1] - sr[0], sr[2] - sr[-1], sr[3] - sr[-2], sr[4] - sr[-3]);
-    Ln[0] = (x + 1 < nx) ? scl[ty * CX + tx + 1] : L;
-    Dv[1] = stencil4(A.fd, sr[LX] - sr[0], sr[2 * LX] - sr[-LX], sr[3 * LX] - sr[-2 * LX], sr[4 * LX] - sr[-3 * LX]);
-    Ln[1] = (y + 1 < ny) ? scl[(ty + 1) * CX + tx] : L;
-    Dv[2] = stencil4(A.fd, q[4] - q[3], q[5] - q[2], q[6] - q[1], q[7] - q[0]);
-    Ln[2] = Lz;
+            if (in_slab(c, n, P)) {
+                const int32_t off = D.pml_off[a];
+                const float aF = A.pml_tab[off + c];
+                const float bF = A.pml_tab[off + n + c];
+                const float qv = fmaf(aF, Da, bF * ppc[a]);
+                Mo.pP1[a][g] = qv;
+                Da += qv;
+            }
+            const float m = 2.0f * A.dt / (s_rho[L] + s_rho[Ln[a]]);
+            float sacc = s_ik[L] * Da;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        float Da = Dv[a];
-        const int c = a == 0 ? x : (a == 1 ? y : z), n = a == 0 ? nx : (a == 1 ? ny : nz);
-        if (in_slab(c, n, P)) {
-            const int32_t off = D.pml_off[a];
-            const float aF = A.pml_tab[off + c];
-            const float bF = A.pml_tab[off + n + c];
-            const float qv = fmaf(aF, Da, bF * ppc[a]);
-            Mo.pP1[a][g] = qv;
-            Da += qv;
+            for (int nu = 0; nu < N; ++nu) {
+                pc[a][nu] = fmaf(s_a[nu * C + L], Da, s_b[nu * C + L] * pc[a][nu]);
+                sacc += pc[a][nu];
+            }
+            store_stream<N>(Mo.psi1[a] + (size_t)g * N, pc[a]);
+            store1_stream(Mo.v[a] + g, fmaf(-m, sacc, vc[a]));
         }
-        const float m = 2.0f * A.dt / (s_rho[L] + s_rho[Ln[a]]);
-        float sacc = s_ik[L] * Da;
-#pragma unroll
-        for (int nu = 0; nu < N; ++nu) {
-            pc[a][nu] = fmaf(s_a[nu * C + L], Da, s_b[nu * C + L] * pc[a][nu]);
-            sacc += pc[a][nu];
-        }
-        store_stream<N>(Mo.psi1[a] + (size_t)g * N, pc[a]);
-        store1_stream(Mo.v[a] + g, fmaf(-m, sacc, vc[a]));
     }
 }
 

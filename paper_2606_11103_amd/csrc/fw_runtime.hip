@@ -310,11 +310,11 @@ int build_tiles(fw_sim *s)
     }
     int rc = upload_tiles(tiles, s->d_tiles, &s->n_tiles, &s->tiles_per_xcd);
     if (rc != FW_OK) return rc;
-    // plane-kernel tiles (3D): 64 x 4, one plane each for the velocity
-    // update, kPressurePlanes planes for the pressure update
+    // plane-kernel tiles (3D): 64 x 4, kVelocityPlanes planes each for the
+    // velocity update, kPressurePlanes for the pressure update
     std::vector<fw::Tile> vt, pt;
     if (plane_on(s)) {
-        vt = banded_tiles(s, 64, 4, 1);
+        vt = banded_tiles(s, 64, 4, fw::kVelocityPlanes);
         pt = banded_tiles(s, 64, 4, fw::kPressurePlanes);
     }
     rc = upload_tiles(vt, s->d_vtiles, &s->n_vtiles, &s->vtiles_per_xcd);
