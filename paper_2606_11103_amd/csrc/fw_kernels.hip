@@ -18,6 +18,12 @@
 // XCDs receives a contiguous range of the tile list (workgroups are
 // dispatched round-robin over the XCDs), keeping neighbouring tiles and their
 // halos in one L2.
+//
+// 3D grids with N >= 3 use the plane kernels at the end of this file instead:
+// short tiles (one plane for the velocity update, four for the pressure
+// update) on plane-major lists in which XCD k owns y-band k of every plane,
+// with the z stencil read from memory; they compute the same operations in
+// the same order.
 #include "fw_internal.h"
 #include "fw_vec.h"
 
