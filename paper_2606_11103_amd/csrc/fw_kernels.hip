@@ -805,9 +805,10 @@ __global__ __launch_bounds__(256) void k_velocity_plane(const StepArgs A)
 // Pressure update on tiles of kPressurePlanes consecutive planes (3D, 64 x 4,
 // one tile per block), from a list in which XCD k owns y-band k of every
 // group of planes.  The v_z window of the group (its planes - 4 .. + 3 past
-// the last) is loaded once into registers; each plane stages the x-halo of
-// v_x and the y-halo of v_y in a double-buffered LDS tile (one barrier per
-// plane).  Same operations in the same order as k_pressure.
+// the last) is loaded once into registers; each plane loads its own state
+// and the x-halo of v_x and y-halo of v_y into registers, then stages the
+// halos in a double-buffered LDS tile (one barrier per plane).  Same
+// operations in the same order as k_pressure.
 template <int N>
 __global__ __launch_bounds__(256) void k_pressure_planes(const StepArgs A)
 {
@@ -885,26 +886,24 @@ __global__ __launch_bounds__(256) void k_pressure_planes(const StepArgs A)
         hoff[s] = (h < NHALO && inside) ? gy * nx + gx : -1;
     }
 
-#pragma unroll
-    for (int j = 0; j < NP; ++j) {
-        const int z = T.z0 + j;
-        if (z >= T.z1) break;
+    auto load_plane = [&](int z, float (&hv)[HS], float &ox, float &oy, float &pc, int &L, float (&psc)[N],
+                          float (&ppc)[3]) {
         const int zoff = z * sm;
         const int g = zoff + col;
-        float *bx = svx[j & 1], *by = svy[j & 1];
 #pragma unroll
-        for (int s = 0; s < HS; ++s) {
-            if (hli[s] == -1) continue;
-            const float val = hoff[s] < 0 ? 0.0f : (hli[s] >= 0 ? Mo.v[0][zoff + hoff[s]] : Mo.v[1][zoff + hoff[s]]);
-            if (hli[s] >= 0)
-                bx[hli[s]] = val;
-            else
-                by[-(hli[s] + 2)] = val;
-        }
-        float ox = 0.0f, oy = 0.0f, pc = 0.0f, psc[N], ppc[3];
-        int L = 0;
+        for (int s = 0; s < HS; ++s)
+            hv[s] = (hli[s] == -1 || hoff[s] < 0) ? 0.0f
+                    : (hli[s] >= 0 ? Mo.v[0][zoff + hoff[s]] : Mo.v[1][zoff + hoff[s]]);
+        ox = 0.0f;
+        oy = 0.0f;
+        pc = 0.0f;
+        L = 0;
+#pragma unroll
+        for (int nu = 0; nu < N; ++nu) psc[nu] = 0.0f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) ppc[a] = 0.0f;
         if (ok) {
-            pc = load1_stream(M.p + g);   // no other tile of this launch reads it
+            pc = load1_stream(M.p + g);
             L = M.cls[g];
             load_stream<N>(M.psi2 + (size_t)g * N, psc);
             ox = Mo.v[0][g];
@@ -915,50 +914,73 @@ __global__ __launch_bounds__(256) void k_pressure_planes(const StepArgs A)
                 ppc[a] = in_slab(c, n, P) ? M.pP2[a][g] : 0.0f;
             }
         }
+    };
+    float hv[HS], ox, oy, pc, psc[N], ppc[3];
+    int L;
+    load_plane(T.z0, hv, ox, oy, pc, L, psc, ppc);
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        const int z = T.z0 + j;
+        if (z >= T.z1) break;
+        const int g = z * sm + col;
+        float *bx = svx[j & 1], *by = svy[j & 1];
+#pragma unroll
+        for (int s = 0; s < HS; ++s) {
+            if (hli[s] >= 0)
+                bx[hli[s]] = hv[s];
+            else if (hli[s] <= -2)
+                by[-(hli[s] + 2)] = hv[s];
+        }
         bx[ty * LX + 4 + tx] = ox;
         by[(ty + 4) * BX + tx] = oy;
         // the buffer written here was last read in plane j - 2, before the
         // barrier of plane j - 1 that every thread has passed
         __syncthreads();
-        if (!ok) continue;
-        const float *sx = bx + ty * LX + 4 + tx;
-        const float *sy = by + (ty + 4) * BX + tx;
-        float Dd[3];
-        Dd[0] = stencil4(A.fd, sx[0] - sx[-1], sx[1] - sx[-2], sx[2] - sx[-3], sx[3] - sx[-4]);
-        Dd[1] = stencil4(A.fd, sy[0] - sy[-BX], sy[BX] - sy[-2 * BX], sy[2 * BX] - sy[-3 * BX], sy[3 * BX] - sy[-4 * BX]);
-        Dd[2] = stencil4(A.fd, vq[j + 4] - vq[j + 3], vq[j + 5] - vq[j + 2], vq[j + 6] - vq[j + 1], vq[j + 7] - vq[j]);
+        if (ok) {   // threads outside the domain still own halo slots
+            const float *sx = bx + ty * LX + 4 + tx;
+            const float *sy = by + (ty + 4) * BX + tx;
+            float Dd[3];
+            Dd[0] = stencil4(A.fd, sx[0] - sx[-1], sx[1] - sx[-2], sx[2] - sx[-3], sx[3] - sx[-4]);
+            Dd[1] = stencil4(A.fd, sy[0] - sy[-BX], sy[BX] - sy[-2 * BX], sy[2 * BX] - sy[-3 * BX],
+                             sy[3 * BX] - sy[-4 * BX]);
+            Dd[2] = stencil4(A.fd, vq[j + 4] - vq[j + 3], vq[j + 5] - vq[j + 2], vq[j + 6] - vq[j + 1],
+                             vq[j + 7] - vq[j]);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const int c = a == 0 ? x : (a == 1 ? y : z), n = a == 0 ? nx : (a == 1 ? ny : nz);
-            if (in_slab(c, n, P)) {
-                const int32_t off = D.pml_off[a];
-                const float aC = A.pml_tab[off + 2 * n + c];
-                const float bC = A.pml_tab[off + 3 * n + c];
-                const float qv = fmaf(aC, Dd[a], bC * ppc[a]);
-                Mo.pP2[a][g] = qv;
-                Dd[a] += qv;
+            for (int a = 0; a < 3; ++a) {
+                const int c = a == 0 ? x : (a == 1 ? y : z), n = a == 0 ? nx : (a == 1 ? ny : nz);
+                if (in_slab(c, n, P)) {
+                    const int32_t off = D.pml_off[a];
+                    const float aC = A.pml_tab[off + 2 * n + c];
+                    const float bC = A.pml_tab[off + 3 * n + c];
+                    const float qv = fmaf(aC, Dd[a], bC * ppc[a]);
+                    Mo.pP2[a][g] = qv;
+                    Dd[a] += qv;
+                }
             }
-        }
-        float S = Dd[0];
+            float S = Dd[0];
 #pragma unroll
-        for (int a = 1; a < 3; ++a) S += Dd[a];
-        float Tt = s_ik[L] * S;
+            for (int a = 1; a < 3; ++a) S += Dd[a];
+            float Tt = s_ik[L] * S;
 #pragma unroll
-        for (int nu = 0; nu < N; ++nu) {
-            psc[nu] = fmaf(s_a[nu * C + L], S, s_b[nu * C + L] * psc[nu]);
-            Tt += psc[nu];
+            for (int nu = 0; nu < N; ++nu) {
+                psc[nu] = fmaf(s_a[nu * C + L], S, s_b[nu * C + L] * psc[nu]);
+                Tt += psc[nu];
+            }
+            store_stream<N>(Mo.psi2 + (size_t)g * N, psc);
+            float K = s_K[L];
+            if (A.noise_amp != 0.0f) {
+                const uint64_t hsh = splitmix64(D.noise_seed ^ (uint64_t)(uint32_t)g);
+                const float u = (float)(hsh >> 40) * 0x1.0p-24f;
+                const float e = A.noise_amp * fmaf(2.0f, u, -1.0f);
+                const float f1 = 1.0f + e;
+                K = K * (f1 * f1);
+            }
+            const float pn0 = pc;
+            store1_stream(Mo.p + g, fmaf(-(A.dt * fmaf(s_tb[L], pn0, K)), Tt, pn0));
         }
-        store_stream<N>(Mo.psi2 + (size_t)g * N, psc);
-        float K = s_K[L];
-        if (A.noise_amp != 0.0f) {
-            const uint64_t hsh = splitmix64(D.noise_seed ^ (uint64_t)(uint32_t)g);
-            const float u = (float)(hsh >> 40) * 0x1.0p-24f;
-            const float e = A.noise_amp * fmaf(2.0f, u, -1.0f);
-            const float f1 = 1.0f + e;
-            K = K * (f1 * f1);
-        }
-        const float pn0 = pc;
-        store1_stream(Mo.p + g, fmaf(-(A.dt * fmaf(s_tb[L], pn0, K)), Tt, pn0));
+        // all of the next plane's loads are issued together, before its LDS
+        // stores (more loads in flight than staging each halo value in turn)
+        if (j + 1 < NP && z + 1 < T.z1) load_plane(z + 1, hv, ox, oy, pc, L, psc, ppc);
     }
 }
 

@@ -113,6 +113,23 @@ def test_persistent_grid_on_batched_2d_and_1d():
         assert np.array_equal(ref, got), name
 
 
+def test_plane_kernels_on_a_ragged_3d_batch():
+    """Three 3D domains of different shapes (ragged in x, y and z; y-tile
+    counts 5, 10 and 25, so the XCD bands of the plane lists are uneven and
+    padded) in one launch, N = 4: plane kernels bitwise equal to the marching
+    kernels, and to the FP64 oracle within the bar."""
+    from paper_2606_11103_amd.native import FW_OPT_PLANE_KERNELS
+    case = configs.random_small(3, [(70, 17, 21), (33, 38, 17), (130, 97, 18)], 4, 3, seed=41, steps=90, pml=4)
+    case = configs.with_table(case, *configs.random_relaxation_table(141, case.n_classes, case.nmech))
+    _, march = _run(case, opts={FW_OPT_PLANE_KERNELS: 0})
+    _, plane = _run(case, opts={FW_OPT_PLANE_KERNELS: 1})
+    assert np.array_equal(march, plane)
+    ref = oracle_traces(case)
+    rel = float(np.linalg.norm(plane.astype(np.float64) - ref) / np.linalg.norm(ref))
+    report("plane kernels, ragged 3D batch of 3, N=4: rel L2 vs FP64 oracle = %.3e" % rel)
+    assert rel <= 1e-4
+
+
 def test_autotuner_keeps_results(tmp_path):
     from paper_2606_11103_amd.autotune import autotune
     case = _case("3d_random_N4")
