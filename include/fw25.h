@@ -296,8 +296,9 @@ int fw_device_copy(void *d_dst, const void *d_src, int64_t bytes, void *hip_stre
  *                        y-band k of every plane (the z stencil reads its
  *                        eight-plane window from memory: it stays in the
  *                        last-level cache); 0 = both march the tiles set by the
- *                        options above; -1 (default) = 1 with N >= 3
- *                        mechanisms, else 0.  Not used with a persistent grid.
+ *                        options above; -1 (default) = the pressure update
+ *                        always, the velocity update with N >= 2 mechanisms.
+ *                        Not used with a persistent grid.
  * Options change the work decomposition only, never the results.
  */
 enum { FW_OPT_GRAPH_STEPS = 1, FW_OPT_MARCH_CHUNK = 2, FW_OPT_TILE_ROWS = 3, FW_OPT_ROWS_PER_THREAD = 4,

@@ -65,7 +65,8 @@ struct StepArgs {
     int32_t pml;               // CPML width P
     int32_t class_cap;         // entries per LDS class table (>= classes of any domain)
     int32_t tile_rows;         // rows of a 3D tile along y
-    int32_t plane;             // 1: 3D updates run the plane kernels on vtiles / ptiles
+    int32_t plane;             // 1: the 3D velocity update runs its plane kernel on vtiles
+    int32_t plane_p;           // 1: the 3D pressure update runs its plane kernel on ptiles
     const Tile *vtiles;        // velocity: 64 x 4 tiles of kVelocityPlanes planes, plane-major, XCD k owning y-band k
     int32_t n_vtiles;
     int32_t vtiles_per_xcd;

@@ -19,7 +19,8 @@
 // dispatched round-robin over the XCDs), keeping neighbouring tiles and their
 // halos in one L2.
 //
-// 3D grids with N >= 3 use the plane kernels at the end of this file instead:
+// 3D grids use the plane kernels at the end of this file instead (by default
+// the pressure one always, the velocity one from N = 2 memory variables on):
 // short tiles (one plane for the velocity update, four for the pressure
 // update) on plane-major lists in which XCD k owns y-band k of every plane,
 // with the z stencil read from memory; they compute the same operations in
@@ -1028,12 +1029,14 @@ template <int NDIM, int N>
 hipError_t launch_nd(bool velocity, int tile_rows, int rpt, const StepArgs &a, hipStream_t s)
 {
     if constexpr (NDIM == 3) {
-        if (a.plane) {
-            const size_t lds = (size_t)a.class_cap * (velocity ? 2 + 2 * N : 3 + 2 * N) * sizeof(float);
-            if (velocity && a.n_vtiles > 0)
-                k_velocity_plane<N><<<dim3(8 * a.vtiles_per_xcd), dim3(64, 4), lds, s>>>(a);
-            else if (!velocity && a.n_ptiles > 0)
-                k_pressure_planes<N><<<dim3(8 * a.ptiles_per_xcd), dim3(64, 4), lds, s>>>(a);
+        if (velocity && a.plane) {
+            const size_t lds = (size_t)a.class_cap * (2 + 2 * N) * sizeof(float);
+            k_velocity_plane<N><<<dim3(8 * a.vtiles_per_xcd), dim3(64, 4), lds, s>>>(a);
+            return hipGetLastError();
+        }
+        if (!velocity && a.plane_p) {
+            const size_t lds = (size_t)a.class_cap * (3 + 2 * N) * sizeof(float);
+            k_pressure_planes<N><<<dim3(8 * a.ptiles_per_xcd), dim3(64, 4), lds, s>>>(a);
             return hipGetLastError();
         }
         if (tile_rows == 4) return launch_pair<3, N, 64, 4, 1>(velocity, a, s);

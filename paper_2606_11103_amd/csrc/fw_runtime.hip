@@ -256,12 +256,20 @@ static int upload_tiles(const std::vector<fw::Tile> &tiles, DevBuf &buf, int *n,
     return FW_OK;
 }
 
-// plane kernels in use for the 3D updates: option 1, or -1 (auto) with
-// N >= 3 memory variables (measured: 5-19 % faster at N = 3, 4; at N = 2
-// within 2 % either way, at N = 1 11 % slower than the marching kernels)
-static bool plane_on(const fw_sim *s)
+// plane kernels in use for the 3D updates: option 1 for both, 0 for neither;
+// -1 (auto) picks per update from measurements on 960 x 960 x 720: the
+// pressure plane kernel wins at every N (N = 1: 4.28 against 4.97 ms), the
+// velocity plane kernel from N = 2 on (N = 2: 10.55 / 10.63 ms, N = 4: 14.96 /
+// 16.70 ms) but not at N = 1 (9.05 / 7.89 ms: with one memory variable per
+// axis the z-window reads weigh too much)
+static bool plane_velocity_on(const fw_sim *s)
 {
-    return s->ndim == 3 && (s->plane_kernels == 1 || (s->plane_kernels < 0 && s->nmech >= 3));
+    return s->ndim == 3 && (s->plane_kernels == 1 || (s->plane_kernels < 0 && s->nmech >= 2));
+}
+
+static bool plane_pressure_on(const fw_sim *s)
+{
+    return s->ndim == 3 && s->plane_kernels != 0;
 }
 
 int build_tiles(fw_sim *s)
@@ -313,10 +321,8 @@ int build_tiles(fw_sim *s)
     // plane-kernel tiles (3D): 64 x 4, kVelocityPlanes planes each for the
     // velocity update, kPressurePlanes for the pressure update
     std::vector<fw::Tile> vt, pt;
-    if (plane_on(s)) {
-        vt = banded_tiles(s, 64, 4, fw::kVelocityPlanes);
-        pt = banded_tiles(s, 64, 4, fw::kPressurePlanes);
-    }
+    if (plane_velocity_on(s)) vt = banded_tiles(s, 64, 4, fw::kVelocityPlanes);
+    if (plane_pressure_on(s)) pt = banded_tiles(s, 64, 4, fw::kPressurePlanes);
     rc = upload_tiles(vt, s->d_vtiles, &s->n_vtiles, &s->vtiles_per_xcd);
     if (rc != FW_OK) return rc;
     rc = upload_tiles(pt, s->d_ptiles, &s->n_ptiles, &s->ptiles_per_xcd);
@@ -345,7 +351,8 @@ fw::StepArgs step_args(const fw_sim *s)
     a.class_cap = (cap + 3) / 4 * 4;
     a.tile_rows = s->tile_rows;
     // the plane kernels take one tile per block: not with a persistent grid
-    a.plane = (plane_on(s) && s->persistent == 0 && s->n_vtiles > 0) ? 1 : 0;
+    a.plane = (plane_velocity_on(s) && s->persistent == 0 && s->n_vtiles > 0) ? 1 : 0;
+    a.plane_p = (plane_pressure_on(s) && s->persistent == 0 && s->n_ptiles > 0) ? 1 : 0;
     a.vtiles = s->d_vtiles.as<fw::Tile>();
     a.n_vtiles = s->n_vtiles;
     a.vtiles_per_xcd = s->vtiles_per_xcd;

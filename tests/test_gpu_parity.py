@@ -130,6 +130,23 @@ def test_plane_kernels_on_a_ragged_3d_batch():
     assert rel <= 1e-4
 
 
+def test_default_kernel_choice_with_one_mechanism():
+    """N = 1 in 3D: by default the marching velocity kernel and the plane
+    pressure kernel; bitwise equal to marching both, and to the oracle within
+    the bar."""
+    from paper_2606_11103_amd.native import FW_OPT_PLANE_KERNELS
+    case = configs.random_small(3, [(70, 17, 21), (130, 97, 18)], 1, 3, seed=43, steps=90, pml=4)
+    case = configs.with_table(case, *configs.random_relaxation_table(143, case.n_classes, case.nmech))
+    _, march = _run(case, opts={FW_OPT_PLANE_KERNELS: 0})
+    _, auto = _run(case)
+    _, plane = _run(case, opts={FW_OPT_PLANE_KERNELS: 1})
+    assert np.array_equal(march, auto) and np.array_equal(march, plane)
+    ref = oracle_traces(case)
+    rel = float(np.linalg.norm(auto.astype(np.float64) - ref) / np.linalg.norm(ref))
+    report("default kernels, ragged 3D batch of 2, N=1: rel L2 vs FP64 oracle = %.3e" % rel)
+    assert rel <= 1e-4
+
+
 def test_autotuner_keeps_results(tmp_path):
     from paper_2606_11103_amd.autotune import autotune
     case = _case("3d_random_N4")
