@@ -23,8 +23,11 @@ DEFAULT = {"plane_kernels": -1, "tile_rows": 4, "rows_per_thread": 1, "march_chu
 def candidates(ndim):
     out = []
     if ndim == 3:
-        # the plane kernels ignore the marching shape
-        out.append({"plane_kernels": 1, "tile_rows": 4, "rows_per_thread": 1, "march_chunk": 0, "persistent": 0})
+        # the plane kernels ignore the marching shape; -1 picks them per update
+        # (with N = 1 the velocity update then marches the default shape)
+        for plane in (-1, 1):
+            out.append({"plane_kernels": plane, "tile_rows": 4, "rows_per_thread": 1, "march_chunk": 0,
+                        "persistent": 0})
         for rows, rpt in ((4, 1), (8, 1), (16, 1), (16, 2), (8, 2)):
             for persistent in (0, 4):
                 for chunk in (0, 24, 96):
