@@ -78,19 +78,27 @@ struct StepArgs {
     float noise_amp;
 };
 
+// One distinct source or receiver cell: the waveform row of its source (-1:
+// none; a cell holds at most one source) and its receivers, entries
+// [r0, r1) of the grouped list.
+struct SrcRecCell {
+    int64_t cell;              // global cell index
+    int32_t wave, r0, r1, pad;
+};
+
 struct SrcRecArgs {
     float *p;
-    const int64_t *src_cell;   // global cell index
-    const int32_t *src_wave;
+    const SrcRecCell *cells;   // distinct source/receiver cells, sorted by cell
+    int64_t n_cells;
+    const int32_t *rec_of;     // receiver indices grouped by cell
     const float *waves;        // [n_wave][n_t]
-    int64_t n_src;
     int32_t n_t;
-    const int64_t *rec_cell;
     float *traces;             // [n_t_max][n_rec]
     int64_t n_rec;
     int32_t n_t_max;
     int64_t *step;             // device step counter
     int64_t *bad_row;          // first trace row holding a non-finite value, -1 if none
+    uint32_t *done;            // workgroups finished in this launch (0 between launches)
 };
 
 // d a / d s and d b / d s per mechanism when d -> s d (adjoint gradients)

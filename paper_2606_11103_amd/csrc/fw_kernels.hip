@@ -25,6 +25,8 @@
 // update) on plane-major lists in which XCD k owns y-band k of every plane,
 // with the z stencil read from memory; they compute the same operations in
 // the same order.
+#include <algorithm>
+
 #include "fw_internal.h"
 #include "fw_vec.h"
 
@@ -985,30 +987,43 @@ __global__ __launch_bounds__(256) void k_pressure_planes(const StepArgs A)
     }
 }
 
-// Sources then receivers then the step counter, in one workgroup so the
-// receivers see the injected values.
-__global__ __launch_bounds__(1024) void k_src_rec(const SrcRecArgs A)
+// Sources, receivers and the step counter.  One thread per distinct
+// source/receiver cell reads p once, adds the cell's source and records the
+// result for the cell's receivers, so the receivers see the injected value
+// without a second pass.  The last workgroup to finish advances the step
+// counter (every workgroup has read it by then) and re-arms the count.
+__global__ __launch_bounds__(256) void k_src_rec(const SrcRecArgs A)
 {
+    __shared__ int s_last;
     const int64_t t = *A.step;
-    if (t < A.n_t) {
-        for (int64_t s = threadIdx.x; s < A.n_src; s += blockDim.x)
-            A.p[A.src_cell[s]] += A.waves[(int64_t)A.src_wave[s] * A.n_t + t];
-    }
-    __threadfence();
-    __syncthreads();
-    if (t < A.n_t_max) {
-        bool bad = false;
-        for (int64_t r = threadIdx.x; r < A.n_rec; r += blockDim.x) {
-            const float val = A.p[A.rec_cell[r]];
-            A.traces[t * A.n_rec + r] = val;
-            bad = bad || !isfinite(val);
+    const bool inject = t < A.n_t, record = t < A.n_t_max;
+    bool bad = false;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < A.n_cells) {
+        const SrcRecCell c = A.cells[e];
+        float v = A.p[c.cell];
+        if (inject && c.wave >= 0) {
+            v += A.waves[(int64_t)c.wave * A.n_t + t];
+            A.p[c.cell] = v;
         }
-        // finite check: every thread that saw a non-finite value writes the
-        // same row, and only while no earlier row has been flagged
-        if (bad && *A.bad_row < 0) *A.bad_row = t;
+        if (record) {
+            for (int32_t k = c.r0; k < c.r1; ++k) A.traces[t * A.n_rec + A.rec_of[k]] = v;
+            bad = c.r1 > c.r0 && !isfinite(v);
+        }
+    }
+    // finite check: every thread that saw a non-finite value writes the same
+    // row, and only while no earlier row has been flagged
+    if (bad && *A.bad_row < 0) *A.bad_row = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        s_last = atomicAdd(A.done, 1u) == gridDim.x - 1;
     }
     __syncthreads();
-    if (threadIdx.x == 0) *A.step = t + 1;
+    if (s_last && threadIdx.x == 0) {
+        *A.done = 0u;
+        *A.step = t + 1;
+    }
 }
 
 template <int NDIM, int N, int BX, int BY, int RY>
@@ -1102,7 +1117,9 @@ hipError_t launch_pressure(int ndim, int nmech, int tile_rows, int rpt, const St
 
 hipError_t launch_src_rec(const SrcRecArgs &a, hipStream_t s)
 {
-    k_src_rec<<<dim3(1), dim3(1024), 0, s>>>(a);
+    // one workgroup at least: it advances the step counter
+    const int64_t blocks = std::max<int64_t>(1, (a.n_cells + 255) / 256);
+    k_src_rec<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(a);
     return hipGetLastError();
 }
 

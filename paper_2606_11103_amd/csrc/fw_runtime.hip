@@ -92,7 +92,11 @@ struct fw_sim {
     uint64_t noise_seed = 0;
     std::vector<double> kappa, dcoef, alpha;
     // device tables
-    DevBuf d_doms, d_classes, d_pml, d_tiles, d_vtiles, d_ptiles, d_src_cell, d_src_wave, d_waves, d_rec_cell, d_traces, d_step;
+    DevBuf d_doms, d_classes, d_pml, d_tiles, d_vtiles, d_ptiles, d_waves, d_traces, d_step;
+    DevBuf d_srcrec, d_rec_of;
+    std::vector<int64_t> h_src_cell, h_rec_cell;   // global cells of the sources and the receivers
+    std::vector<int32_t> h_src_wave;               // waveform row of each source
+    int64_t n_srcrec = 0;
     DevBuf d_cadj, d_adj_cells, d_adj_off, d_adj_idx;
     DevBuf d_pold, d_partial;
     int64_t n_adj_cells = 0;
@@ -369,17 +373,17 @@ fw::SrcRecArgs srcrec_args(const fw_sim *s)
 {
     fw::SrcRecArgs a{};
     a.p = fields_of(s).p;
-    a.src_cell = s->d_src_cell.as<int64_t>();
-    a.src_wave = s->d_src_wave.as<int32_t>();
+    a.cells = s->d_srcrec.as<fw::SrcRecCell>();
+    a.n_cells = s->n_srcrec;
+    a.rec_of = s->d_rec_of.as<int32_t>();
     a.waves = s->d_waves.as<float>();
-    a.n_src = s->n_src;
     a.n_t = s->n_t;
-    a.rec_cell = s->d_rec_cell.as<int64_t>();
     a.traces = s->d_traces.as<float>();
     a.n_rec = s->n_rec;
     a.n_t_max = s->n_t_max;
     a.step = s->d_step.as<int64_t>();
     a.bad_row = s->d_step.as<int64_t>() + 1;
+    a.done = reinterpret_cast<uint32_t *>(s->d_step.as<int64_t>() + 2);
     return a;
 }
 
@@ -510,8 +514,10 @@ int fw_bind_workspace(fw_sim *sim, void *d_ptr, int64_t bytes)
     sim->ws = static_cast<char *>(d_ptr);
     HIP_OR_FAIL(hipMemset(sim->ws, 0, (size_t)sim->ws_bytes));
     // [0] step counter, [1] first trace row with a non-finite value (-1)
-    HIP_OR_FAIL(sim->d_step.ensure(2 * sizeof(int64_t)));
-    HIP_OR_FAIL(hipMemset(sim->d_step.ptr, 0, sizeof(int64_t)));
+    // step counter, first non-finite trace row (-1), workgroups finished in
+    // the running source/receiver launch (0)
+    HIP_OR_FAIL(sim->d_step.ensure(3 * sizeof(int64_t)));
+    HIP_OR_FAIL(hipMemset(sim->d_step.ptr, 0, 3 * sizeof(int64_t)));
     HIP_OR_FAIL(hipMemset(static_cast<char *>(sim->d_step.ptr) + sizeof(int64_t), 0xff, sizeof(int64_t)));
     sim->host_step = 0;
     sim->media_set = sim->table_set = false;
@@ -675,6 +681,48 @@ static int check_cells(const fw_sim *sim, int64_t n, const int32_t *domain, cons
     return FW_OK;
 }
 
+// distinct source/receiver cells (sorted), each with its source and the range
+// of its receivers in a list grouped by cell (receivers in index order)
+static int build_srcrec(fw_sim *sim)
+{
+    std::vector<int64_t> cells(sim->h_src_cell);
+    cells.insert(cells.end(), sim->h_rec_cell.begin(), sim->h_rec_cell.end());
+    std::sort(cells.begin(), cells.end());
+    cells.erase(std::unique(cells.begin(), cells.end()), cells.end());
+    std::vector<fw::SrcRecCell> tab(cells.size());
+    for (size_t e = 0; e < cells.size(); ++e) {
+        tab[e] = fw::SrcRecCell{};
+        tab[e].cell = cells[e];
+        tab[e].wave = -1;
+    }
+    auto slot = [&](int64_t c) { return (size_t)(std::lower_bound(cells.begin(), cells.end(), c) - cells.begin()); };
+    for (size_t i = 0; i < sim->h_src_cell.size(); ++i) tab[slot(sim->h_src_cell[i])].wave = sim->h_src_wave[i];
+    const int64_t n_rec = (int64_t)sim->h_rec_cell.size();
+    std::vector<int32_t> order(n_rec);
+    for (int64_t i = 0; i < n_rec; ++i) order[i] = (int32_t)i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return sim->h_rec_cell[a] < sim->h_rec_cell[b]; });
+    for (int64_t k = 0; k < n_rec;) {
+        const int64_t c = sim->h_rec_cell[order[k]];
+        int64_t k1 = k;
+        while (k1 < n_rec && sim->h_rec_cell[order[k1]] == c) ++k1;
+        fw::SrcRecCell &e = tab[slot(c)];
+        e.r0 = (int32_t)k;
+        e.r1 = (int32_t)k1;
+        k = k1;
+    }
+    sim->n_srcrec = (int64_t)tab.size();
+    if (!tab.empty()) {
+        HIP_OR_FAIL(sim->d_srcrec.ensure(tab.size() * sizeof(fw::SrcRecCell)));
+        HIP_OR_FAIL(hipMemcpy(sim->d_srcrec.ptr, tab.data(), tab.size() * sizeof(fw::SrcRecCell), hipMemcpyHostToDevice));
+    }
+    if (n_rec > 0) {
+        HIP_OR_FAIL(sim->d_rec_of.ensure(order.size() * sizeof(int32_t)));
+        HIP_OR_FAIL(hipMemcpy(sim->d_rec_of.ptr, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
+    return FW_OK;
+}
+
 int fw_set_sources(fw_sim *sim, int64_t n_src, const int32_t *domain, const int64_t *cell, const int32_t *wave_idx,
                    int n_wave, const float *waves, int n_t)
 {
@@ -703,13 +751,13 @@ int fw_set_sources(fw_sim *sim, int64_t n_src, const int32_t *domain, const int6
     sim->n_src = n_src;
     sim->n_t = n_src > 0 ? n_t : 0;
     if (n_src > 0) {
-        HIP_OR_FAIL(sim->d_src_cell.ensure(n_src * sizeof(int64_t)));
-        HIP_OR_FAIL(sim->d_src_wave.ensure(n_src * sizeof(int32_t)));
         HIP_OR_FAIL(sim->d_waves.ensure((size_t)n_wave * n_t * sizeof(float)));
-        HIP_OR_FAIL(hipMemcpy(sim->d_src_cell.ptr, g.data(), n_src * sizeof(int64_t), hipMemcpyHostToDevice));
-        HIP_OR_FAIL(hipMemcpy(sim->d_src_wave.ptr, wave_idx, n_src * sizeof(int32_t), hipMemcpyHostToDevice));
         HIP_OR_FAIL(hipMemcpy(sim->d_waves.ptr, waves, (size_t)n_wave * n_t * sizeof(float), hipMemcpyHostToDevice));
     }
+    sim->h_src_cell = g;
+    sim->h_src_wave.assign(wave_idx, wave_idx + n_src);
+    rc = build_srcrec(sim);
+    if (rc != FW_OK) return rc;
     sim->drop_graph();
     return FW_OK;
 }
@@ -727,8 +775,6 @@ int fw_set_receivers(fw_sim *sim, int64_t n_rec, const int32_t *domain, const in
     sim->n_rec = n_rec;
     sim->n_t_max = n_rec > 0 ? n_t_max : 0;
     if (n_rec > 0) {
-        HIP_OR_FAIL(sim->d_rec_cell.ensure(n_rec * sizeof(int64_t)));
-        HIP_OR_FAIL(hipMemcpy(sim->d_rec_cell.ptr, g.data(), n_rec * sizeof(int64_t), hipMemcpyHostToDevice));
         const size_t tb = (size_t)n_rec * std::max(n_t_max, 1) * sizeof(float);
         HIP_OR_FAIL(sim->d_traces.ensure(tb));
         HIP_OR_FAIL(hipMemset(sim->d_traces.ptr, 0, tb));
@@ -755,6 +801,9 @@ int fw_set_receivers(fw_sim *sim, int64_t n_rec, const int32_t *domain, const in
     } else {
         sim->n_adj_cells = 0;
     }
+    sim->h_rec_cell = g;
+    rc = build_srcrec(sim);
+    if (rc != FW_OK) return rc;
     sim->drop_graph();
     return FW_OK;
 }
