@@ -76,3 +76,33 @@ def test_sources_and_receivers_on_corners_and_faces():
     case.rec_cell = np.array(rec, np.int64)
     got = _parity(case, "corners_faces_3d")
     assert np.array_equal(got[:, -1], got[:, -2]) and np.array_equal(got[:, -1], got[:, -3])
+
+
+def test_many_sources_and_receivers_over_several_workgroups():
+    """A 1D batch of 60 domains, each with a source and 6 receivers: one on
+    the source cell (it records the injected value), one listed twice and
+    three more, 300 distinct cells, so the source/receiver step spans
+    several workgroups (256 cells each). Against the FP64 oracle; the step
+    counter stays right over graph replays and eager steps."""
+    from paper_2606_11103_amd.native import FW_OPT_GRAPH_STEPS
+    shapes = [(160 + 7 * d, 1, 1) for d in range(60)]
+    case = _tables(configs.random_small(1, shapes, 2, 2, seed=77, steps=120, pml=6, n_rec=1), "many_srcrec")
+    rd, rc = [], []
+    for d, (n, _, _) in enumerate(shapes):
+        s = int(case.src_cell[d])
+        for c in (s, n // 3, n // 3, n // 2, 2 * n // 3, n - 1):
+            rd.append(d)
+            rc.append(c)
+    case.rec_domain = np.array(rd, np.int32)
+    case.rec_cell = np.array(rc, np.int64)
+    assert len(set(zip(rd, rc))) > 256 and len(case.src_cell) == 60
+    got = _parity(case, "many_sources_receivers_1d")
+    assert np.array_equal(got[:, 1::6], got[:, 2::6])          # the repeated receiver
+    # graph replays (7 steps per graph) and eager steps give the same traces and counter
+    sim = to_simulation(case)
+    sim.set_option(FW_OPT_GRAPH_STEPS, 7)
+    sim.step(50)
+    sim.set_option(FW_OPT_GRAPH_STEPS, 0)
+    sim.step(case.n_steps - 50)
+    assert sim.get_step() == case.n_steps
+    assert np.array_equal(sim.read_receivers(), got.astype(np.float32))
