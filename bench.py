@@ -33,7 +33,7 @@ TRAFFIC_MEASURED = {
     # velocity update (single-plane kernel): FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 per launch.
     # FETCH_SIZE counts L2 misses sent to the data fabric, so it includes the z-window reads
     # that the last-level cache serves: an upper bound on the HBM bytes.
-    "49a1fe488529c5a6": {"workload": "3d_heterogeneous_960x960x720", "tile_rows": 4, "rows_per_thread": 1,
+    "e58ae9be4099ec82": {"workload": "3d_heterogeneous_960x960x720", "tile_rows": 4, "rows_per_thread": 1,
                          "bytes_per_launch": 99.26e9,
                          "profile": "profiles/step_kernels_3d_960x960x720_N4.md"},
 }
