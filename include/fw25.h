@@ -272,7 +272,8 @@ int fw_read_field(fw_sim *sim, int field, int domain, float *dst, int dst_is_dev
 /*
  * Streaming device-to-device copy of bytes bytes on hip_stream (used for
  * state snapshots and checkpoints).  16-byte aligned pointers and sizes use a
- * float4 grid-stride kernel, anything else hipMemcpyAsync.  Asynchronous.
+ * kernel with one float4 per lane, launched in pieces of at most 16 GiB;
+ * anything else hipMemcpyAsync.  Asynchronous.
  */
 int fw_device_copy(void *d_dst, const void *d_src, int64_t bytes, void *hip_stream);
 

@@ -94,9 +94,11 @@ __global__ __launch_bounds__(1024) void k_energy(const StepArgs A, const float *
 // Streaming device-to-device copy: one 16-byte non-temporal load and store
 // per lane and a grid as large as the copy (measured on MI355X: 6.6 TB/s of
 // read + write traffic, against 5.3 TB/s for a grid-stride loop over 1024
-// workgroups; larger copies than the grid limit take several launches).
+// workgroups).  A dispatch covers fewer than 2^32 work-items along x, and
+// the count wraps silently beyond that, so a launch moves at most 2^22
+// workgroups of 256 lanes (16 GiB); larger copies take several launches.
 typedef float copy_v4 __attribute__((ext_vector_type(4)));
-constexpr int64_t kCopyMaxBlocks = int64_t(1) << 30;
+constexpr int64_t kCopyMaxBlocks = int64_t(1) << 22;
 
 __global__ __launch_bounds__(256) void k_copy16(const copy_v4 *__restrict__ src, copy_v4 *__restrict__ dst, int64_t n)
 {

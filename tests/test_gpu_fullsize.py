@@ -193,3 +193,34 @@ def test_full_size_adjoint_is_independent_of_the_checkpoint_interval():
     assert np.all(np.isfinite(out[0][0])) and np.all(np.isfinite(out[0][1]))
     assert np.abs(out[0][0]).max() > 0
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+def test_full_size_3d_state_round_trip_is_bitwise():
+    """The 960 x 960 x 720, N = 4 state (about 69 GB) is larger than one
+    copy launch can cover (2^32 lanes of 16 bytes): a snapshot taken after 40
+    steps, restored after 3 more, gives the same next step bit for bit in
+    every field, and the step counter comes back with it."""
+    import torch
+    from paper_2606_11103_amd import relax
+    torch.cuda.empty_cache()
+    case = configs.heterogeneous_3d(shape=(960, 960, 720), steps=2000)
+    kappa, d, al, _ = relax.tables_for(dict(c=case.c, alpha0=case.alpha0, y=case.y), case.nmech,
+                                      allow_fit=False, dt=case.dt)
+    configs.with_table(case, kappa, d, al)
+    print("full-size 3D state round trip", case.shapes, flush=True)
+    sim = to_simulation(case)
+    assert sim.state_bytes() > 16 * 2 ** 32
+    sim.step(40)
+    buf = sim.save_state()
+    sim.step(1)
+    ref = [sim.read_field(f, device=True) for f in range(4)]
+    assert float(ref[0].abs().max()) > 0.0
+    sim.step(2)
+    sim.load_state(buf)
+    assert sim.get_step() == 40
+    sim.step(1)
+    same = [bool(torch.equal(sim.read_field(f, device=True), ref[f])) for f in range(4)]
+    report("full-size 3D state round trip (%.1f GB): fields bitwise equal %s" % (sim.state_bytes() / 1e9, same))
+    del sim, buf, ref
+    torch.cuda.empty_cache()
+    assert all(same)
