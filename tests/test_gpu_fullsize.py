@@ -26,14 +26,11 @@ from reporting import report
 pytestmark = pytest.mark.gpu
 
 
-def test_full_size_3d_workload_matches_oracle_on_the_field_support():
-    from paper_2606_11103_amd import relax
-    case = configs.heterogeneous_3d(shape=(960, 960, 720), steps=2000)
-    kappa, d, al, _ = relax.tables_for(dict(c=case.c, alpha0=case.alpha0, y=case.y), case.nmech,
-                                      allow_fit=False, dt=case.dt)
-    configs.with_table(case, kappa, d, al)
-    K = 10
-    print("full-size 3D", case.shapes, "steps", K, flush=True)
+def _support_parity(case, K, label):
+    """Run K steps on the GPU; every pressure of the box holding the field's
+    support and every receiver inside it against the FP64 oracle on that box
+    (relative L2 <= 1e-5), and exact zeros outside the box."""
+    print(label, case.shapes, "steps", K, flush=True)
     sim = to_simulation(case)
     sim.step(K)
     p = sim.read_field(0)
@@ -70,9 +67,40 @@ def test_full_size_3d_workload_matches_oracle_on_the_field_support():
     ref = orc.p.reshape(box.shape)
     rel_field = float(np.linalg.norm(box - ref) / np.linalg.norm(ref))
     rel_rec = float(np.linalg.norm(traces[:, inside] - rec) / np.linalg.norm(rec))
-    report("full-size 3D 960x960x720 N=4 after %d steps: box %s rel_L2 field=%.3e receivers(%d)=%.3e"
-            % (K, [h - l for l, h in zip(lo, hi)], rel_field, int(inside.sum()), rel_rec))
+    report("%s %s N=%d after %d steps: box %s rel_L2 field=%.3e receivers(%d)=%.3e"
+           % (label, "x".join(str(n) for n in case.shapes[0]), case.nmech, K, [h - l for l, h in zip(lo, hi)],
+              rel_field, int(inside.sum()), rel_rec))
     assert rel_field <= 1e-5 and rel_rec <= 1e-5
+
+
+def test_full_size_3d_workload_matches_oracle_on_the_field_support():
+    from paper_2606_11103_amd import relax
+    case = configs.heterogeneous_3d(shape=(960, 960, 720), steps=2000)
+    kappa, d, al, _ = relax.tables_for(dict(c=case.c, alpha0=case.alpha0, y=case.y), case.nmech,
+                                      allow_fit=False, dt=case.dt)
+    configs.with_table(case, kappa, d, al)
+    _support_parity(case, 10, "full-size 3D")
+
+
+def test_largest_admissible_domain_matches_oracle_on_the_field_support():
+    """1280^3 = 2.097e9 cells, just under the 2^31 cells a domain may hold
+    (in-domain offsets are 32-bit), with the same recipe at N = 2 (about
+    153 GB of state).  Sources and receivers are mirrored to the last planes
+    (z -> nz - 1 - z), so the checked support sits at the top of the 32-bit
+    offset range."""
+    import torch
+    torch.cuda.empty_cache()
+    case = configs.heterogeneous_3d(shape=(1280, 1280, 1280), steps=64, nmech=2)
+    assert case.cells() < 2 ** 31 and case.cells() > 2 ** 31 - 2 ** 28
+    nx, ny, nz = case.shapes[0]
+    for name in ("src_cell", "rec_cell"):
+        c = getattr(case, name)
+        z = c // (nx * ny)
+        setattr(case, name, (c - z * nx * ny + (nz - 1 - z) * nx * ny).astype(np.int64))
+    assert int(case.src_cell.min()) > case.cells() - 2 ** 26
+    configs.with_table(case, *configs.random_relaxation_table(1280, case.n_classes, case.nmech))
+    _support_parity(case, 6, "largest domain 3D")
+    torch.cuda.empty_cache()
 
 
 GOLDEN_2D = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "two_layer_2d_2048_oracle.npz")
