@@ -43,13 +43,20 @@ def _case(name):
         c = configs.random_small(1, [(300, 1, 1), (257, 1, 1), (129, 1, 1)], 2, 2, seed=3, steps=400)
     elif name == "2d_batched_N3":
         c = configs.random_small(2, [(100, 90, 1), (77, 130, 1), (65, 65, 1)], 3, 2, seed=4, steps=200)
+    elif name == "1d_batched_N4":
+        c = configs.random_small(1, [(512, 1, 1), (203, 1, 1), (77, 1, 1)], 4, 3, seed=10, steps=500)
+    elif name == "1d_N1_linear":
+        c = configs.random_small(1, [(333, 1, 1)], 1, 2, seed=11, steps=400, nonlinear=False, noise=0.0)
+    elif name == "3d_closed_N2":
+        c = configs.random_small(3, [(45, 38, 33)], 2, 3, seed=12, steps=90, pml=0)
     else:
         raise KeyError(name)
     return configs.with_table(c, *configs.random_relaxation_table(zlib.crc32(name.encode()) % 1000, c.n_classes, c.nmech))
 
 
 PARITY_CASES = ["2d_homogeneous_256", "2d_random_N4", "2d_random_N1_linear", "3d_random_N4",
-                "3d_random_N2_ragged", "3d_random_N3", "1d_batched_N2", "2d_batched_N3"]
+                "3d_random_N2_ragged", "3d_random_N3", "1d_batched_N2", "2d_batched_N3",
+                "1d_batched_N4", "1d_N1_linear", "3d_closed_N2"]
 
 
 @pytest.mark.parametrize("name", PARITY_CASES)
