@@ -33,8 +33,8 @@ TRAFFIC_MEASURED = {
     # velocity update (single-plane kernel): FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 per launch.
     # FETCH_SIZE counts L2 misses sent to the data fabric, so it includes the z-window reads
     # that the last-level cache serves: an upper bound on the HBM bytes.
-    "e58ae9be4099ec82": {"workload": "3d_heterogeneous_960x960x720", "tile_rows": 4, "rows_per_thread": 1,
-                         "bytes_per_launch": 99.26e9,
+    "f993beab3617068e": {"workload": "3d_heterogeneous_960x960x720", "tile_rows": 4, "rows_per_thread": 1,
+                         "bytes_per_launch": 99.25e9,
                          "profile": "profiles/step_kernels_3d_960x960x720_N4.md"},
 }
 
@@ -265,7 +265,8 @@ def bench_paper_shape(torch, steps=100):
 
 
 def bench_sweep(torch, steps=2000):
-    """1D sweep: 544 domains x 8192 cells, N = 2, one batched launch."""
+    """1D sweep: 544 domains x 8192 cells, N = 2, one batched launch; then
+    the same sweep with N = 4 (default launch shape)."""
     from workloads import configs
     from workloads.adapters import to_simulation
     case = configs.sweep_1d()
@@ -275,10 +276,18 @@ def bench_sweep(torch, steps=2000):
     ms_default = _time_steps(torch, sim, steps)
     cfg = _tune(sim)
     ms = _time_steps(torch, sim, steps)
+    del sim
+    case4 = configs.sweep_1d(nmech=4)
+    tab4 = _tables_or_random(case4, 3)
+    sim = to_simulation(case4)
+    sim.step(32)
+    ms4 = _time_steps(torch, sim, steps)
     return {"workload": case.name, "cells": case.cells(), "steps": steps, "tables": tab,
             "steps_of_full_run": case.n_steps,
             "gcells": round(case.cells() * steps / (ms / 1e3) / 1e9, 3), "ms_per_step": round(ms / steps, 4),
-            "launch_shape": cfg, "default_shape_gcells": round(case.cells() * steps / (ms_default / 1e3) / 1e9, 3)}
+            "launch_shape": cfg, "default_shape_gcells": round(case.cells() * steps / (ms_default / 1e3) / 1e9, 3),
+            "n4": {"tables": tab4, "gcells": round(case4.cells() * steps / (ms4 / 1e3) / 1e9, 3),
+                   "ms_per_step": round(ms4 / steps, 4)}}
 
 
 def bench_adjoint(torch, steps=3000, ckpt=55):

@@ -808,10 +808,13 @@ __global__ __launch_bounds__(256) void k_velocity_plane(const StepArgs A)
 // Pressure update on tiles of kPressurePlanes consecutive planes (3D, 64 x 4,
 // one tile per block), from a list in which XCD k owns y-band k of every
 // group of planes.  The v_z window of the group (its planes - 4 .. + 3 past
-// the last) is loaded once into registers; each plane loads its own state
-// and the x-halo of v_x and y-halo of v_y into registers, then stages the
-// halos in a double-buffered LDS tile (one barrier per plane).  Same
-// operations in the same order as k_pressure.
+// the last) is loaded once into registers; each plane loads the x-halo of
+// v_x, the y-halo of v_y and its own state into registers and stages the
+// halos in a double-buffered LDS tile.  The barrier of a plane orders LDS
+// only (the threads exchange nothing through global memory), so the loads
+// of the next plane, issued right after it, stay in flight while the
+// current plane is computed.  Same operations in the same order as
+// k_pressure.
 template <int N>
 __global__ __launch_bounds__(256) void k_pressure_planes(const StepArgs A)
 {
@@ -889,38 +892,36 @@ __global__ __launch_bounds__(256) void k_pressure_planes(const StepArgs A)
         hoff[s] = (h < NHALO && inside) ? gy * nx + gx : -1;
     }
 
-    auto load_plane = [&](int z, float (&hv)[HS], float &ox, float &oy, float &pc, int &L, float (&psc)[N],
-                          float (&ppc)[3]) {
+    // per plane: the halo share and own v_x, v_y first (the LDS staging
+    // waits for them only), then the streamed state
+    struct PlaneIn {
+        float hv[HS], ox, oy, pc, psc[N], ppc[3];
+        int L;
+    };
+    auto load_plane = [&](int z, PlaneIn &o) {
         const int zoff = z * sm;
         const int g = zoff + col;
 #pragma unroll
         for (int s = 0; s < HS; ++s)
-            hv[s] = (hli[s] == -1 || hoff[s] < 0) ? 0.0f
-                    : (hli[s] >= 0 ? Mo.v[0][zoff + hoff[s]] : Mo.v[1][zoff + hoff[s]]);
-        ox = 0.0f;
-        oy = 0.0f;
-        pc = 0.0f;
-        L = 0;
+            o.hv[s] = (hli[s] == -1 || hoff[s] < 0) ? 0.0f
+                      : (hli[s] >= 0 ? Mo.v[0][zoff + hoff[s]] : Mo.v[1][zoff + hoff[s]]);
+        o.ox = ok ? Mo.v[0][g] : 0.0f;
+        o.oy = ok ? Mo.v[1][g] : 0.0f;
+        o.pc = ok ? load1_stream(M.p + g) : 0.0f;
+        o.L = ok ? (int)M.cls[g] : 0;
+        if (ok)
+            load_stream<N>(M.psi2 + (size_t)g * N, o.psc);
+        else
 #pragma unroll
-        for (int nu = 0; nu < N; ++nu) psc[nu] = 0.0f;
+            for (int nu = 0; nu < N; ++nu) o.psc[nu] = 0.0f;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) ppc[a] = 0.0f;
-        if (ok) {
-            pc = load1_stream(M.p + g);
-            L = M.cls[g];
-            load_stream<N>(M.psi2 + (size_t)g * N, psc);
-            ox = Mo.v[0][g];
-            oy = Mo.v[1][g];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const int c = a == 0 ? x : (a == 1 ? y : z), n = a == 0 ? nx : (a == 1 ? ny : nz);
-                ppc[a] = in_slab(c, n, P) ? M.pP2[a][g] : 0.0f;
-            }
+        for (int a = 0; a < 3; ++a) {
+            const int c = a == 0 ? x : (a == 1 ? y : z), n = a == 0 ? nx : (a == 1 ? ny : nz);
+            o.ppc[a] = (ok && in_slab(c, n, P)) ? M.pP2[a][g] : 0.0f;
         }
     };
-    float hv[HS], ox, oy, pc, psc[N], ppc[3];
-    int L;
-    load_plane(T.z0, hv, ox, oy, pc, L, psc, ppc);
+    PlaneIn cur, nxt;
+    load_plane(T.z0, cur);
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
         const int z = T.z0 + j;
@@ -930,15 +931,19 @@ __global__ __launch_bounds__(256) void k_pressure_planes(const StepArgs A)
 #pragma unroll
         for (int s = 0; s < HS; ++s) {
             if (hli[s] >= 0)
-                bx[hli[s]] = hv[s];
+                bx[hli[s]] = cur.hv[s];
             else if (hli[s] <= -2)
-                by[-(hli[s] + 2)] = hv[s];
+                by[-(hli[s] + 2)] = cur.hv[s];
         }
-        bx[ty * LX + 4 + tx] = ox;
-        by[(ty + 4) * BX + tx] = oy;
-        // the buffer written here was last read in plane j - 2, before the
-        // barrier of plane j - 1 that every thread has passed
-        __syncthreads();
+        bx[ty * LX + 4 + tx] = cur.ox;
+        by[(ty + 4) * BX + tx] = cur.oy;
+        // LDS-only barrier: the loads in flight keep going.  The buffer
+        // written here was last read in plane j - 2, before every thread
+        // passed the barrier of plane j - 1
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+        if (j + 1 < NP && z + 1 < T.z1) load_plane(z + 1, nxt);
         if (ok) {   // threads outside the domain still own halo slots
             const float *sx = bx + ty * LX + 4 + tx;
             const float *sy = by + (ty + 4) * BX + tx;
@@ -948,6 +953,7 @@ __global__ __launch_bounds__(256) void k_pressure_planes(const StepArgs A)
                              sy[3 * BX] - sy[-4 * BX]);
             Dd[2] = stencil4(A.fd, vq[j + 4] - vq[j + 3], vq[j + 5] - vq[j + 2], vq[j + 6] - vq[j + 1],
                              vq[j + 7] - vq[j]);
+            const int L = cur.L;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const int c = a == 0 ? x : (a == 1 ? y : z), n = a == 0 ? nx : (a == 1 ? ny : nz);
@@ -955,7 +961,7 @@ __global__ __launch_bounds__(256) void k_pressure_planes(const StepArgs A)
                     const int32_t off = D.pml_off[a];
                     const float aC = A.pml_tab[off + 2 * n + c];
                     const float bC = A.pml_tab[off + 3 * n + c];
-                    const float qv = fmaf(aC, Dd[a], bC * ppc[a]);
+                    const float qv = fmaf(aC, Dd[a], bC * cur.ppc[a]);
                     Mo.pP2[a][g] = qv;
                     Dd[a] += qv;
                 }
@@ -964,12 +970,13 @@ __global__ __launch_bounds__(256) void k_pressure_planes(const StepArgs A)
 #pragma unroll
             for (int a = 1; a < 3; ++a) S += Dd[a];
             float Tt = s_ik[L] * S;
+            float psn[N];
 #pragma unroll
             for (int nu = 0; nu < N; ++nu) {
-                psc[nu] = fmaf(s_a[nu * C + L], S, s_b[nu * C + L] * psc[nu]);
-                Tt += psc[nu];
+                psn[nu] = fmaf(s_a[nu * C + L], S, s_b[nu * C + L] * cur.psc[nu]);
+                Tt += psn[nu];
             }
-            store_stream<N>(Mo.psi2 + (size_t)g * N, psc);
+            store_stream<N>(Mo.psi2 + (size_t)g * N, psn);
             float K = s_K[L];
             if (A.noise_amp != 0.0f) {
                 const uint64_t hsh = splitmix64(D.noise_seed ^ (uint64_t)(uint32_t)g);
@@ -978,12 +985,10 @@ __global__ __launch_bounds__(256) void k_pressure_planes(const StepArgs A)
                 const float f1 = 1.0f + e;
                 K = K * (f1 * f1);
             }
-            const float pn0 = pc;
+            const float pn0 = cur.pc;
             store1_stream(Mo.p + g, fmaf(-(A.dt * fmaf(s_tb[L], pn0, K)), Tt, pn0));
         }
-        // all of the next plane's loads are issued together, before its LDS
-        // stores (more loads in flight than staging each halo value in turn)
-        if (j + 1 < NP && z + 1 < T.z1) load_plane(z + 1, hv, ox, oy, pc, L, psc, ppc);
+        cur = nxt;
     }
 }
 
