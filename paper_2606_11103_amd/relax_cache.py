@@ -1,7 +1,7 @@
 """Fill the relaxation-table cache (data/relax_tables.json) for the named
 workloads by running the FP64 calibration (relax.fit_class) on every class
 that is not cached yet.  Usage: python -m paper_2606_11103_amd.relax_cache
-[--adjoint] [--sweep] [--library] [--tissues] [--procs=N]"""
+[--adjoint] [--sweep] [--sweep4] [--library] [--tissues] [--procs=N]"""
 import sys
 import time
 
@@ -21,6 +21,8 @@ def main():
         jobs = [("2d_adjoint", configs.adjoint_2d(n=64, n_shots=1, steps=10, n_rec=4, pml=8), 4)]
     if "--sweep" in sys.argv:
         jobs.append(("1d_sweep", configs.sweep_1d(n_cells=64, steps=10, pml=8), 2))
+    if "--sweep4" in sys.argv:
+        jobs.append(("1d_sweep_N4", configs.sweep_1d(n_cells=64, steps=10, pml=8, nmech=4), 4))
     if "--tissues" in sys.argv:
         class _Tissues:      # muscle, fat, liver of the two-layer validation (Sec. 4)
             c, alpha0, y = [1540.0] * 3, [0.15, 0.40, 0.50], [1.0, 1.1, 1.1]
