@@ -141,16 +141,17 @@ def test_step_matched_mechanisms_keep_gain_and_pole():
         assert np.all(err_m <= err_r)
 
 
-def test_step_matched_sweep_fits_meet_the_simulated_bar():
+@pytest.mark.parametrize("nmech", [2, 4])
+def test_step_matched_sweep_fits_meet_the_simulated_bar(nmech):
     """The attenuation the scheme realises with the step-matched tables --
     the exact discrete 1D wavenumber of the leapfrog staggered scheme with
     the recursions' response, which the GPU run reproduces to 0.2 % -- meets
     the 3 % mean NRMSE bar over the cached sweep fits (16 points per
-    wavelength at 20 MHz, CFL 0.2)."""
+    wavelength at 20 MHz, CFL 0.2), with N = 2 and with N = 4 mechanisms."""
     from oracle import fdcoef
     cache = relax.load_cache()
     fits = [relax.effective(f) for f in cache.values()]
-    fits = [f for f in fits if f["nmech"] == 2 and abs(f["c"] - 1540.0) < 1e-9 and not f["failed"]]
+    fits = [f for f in fits if f["nmech"] == nmech and abs(f["c"] - 1540.0) < 1e-9 and not f["failed"]]
     if len(fits) < 20:
         pytest.skip("sweep fits not cached")
     dx = 1540.0 / (16 * 20e6)
