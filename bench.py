@@ -33,8 +33,8 @@ TRAFFIC_MEASURED = {
     # velocity update (single-plane kernel): FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 per launch.
     # FETCH_SIZE counts L2 misses sent to the data fabric, so it includes the z-window reads
     # that the last-level cache serves: an upper bound on the HBM bytes.
-    "f993beab3617068e": {"workload": "3d_heterogeneous_960x960x720", "tile_rows": 4, "rows_per_thread": 1,
-                         "bytes_per_launch": 99.25e9,
+    "01996d664e447147": {"workload": "3d_heterogeneous_960x960x720", "tile_rows": 4, "rows_per_thread": 1,
+                         "bytes_per_launch": 99.24e9,
                          "profile": "profiles/step_kernels_3d_960x960x720_N4.md"},
 }
 
@@ -259,9 +259,12 @@ def bench_paper_shape(torch, steps=100):
     tab = _tables_or_random(case, 5)
     sim = to_simulation(case)
     sim.step(32)                    # untimed: captures the step graph
+    ms_default = _time_steps(torch, sim, steps)
+    cfg = _tune(sim)
     ms = _time_steps(torch, sim, steps)
     return {"workload": case.name, "cells": case.cells(), "steps": steps, "tables": tab,
-            "gcells": round(case.cells() * steps / (ms / 1e3) / 1e9, 3), "ms_per_step": round(ms / steps, 4)}
+            "gcells": round(case.cells() * steps / (ms / 1e3) / 1e9, 3), "ms_per_step": round(ms / steps, 4),
+            "launch_shape": cfg, "default_shape_gcells": round(case.cells() * steps / (ms_default / 1e3) / 1e9, 3)}
 
 
 def bench_sweep(torch, steps=2000):

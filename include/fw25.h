@@ -291,8 +291,8 @@ int fw_device_copy(void *d_dst, const void *d_src, int64_t bytes, void *hip_stre
  *   FW_OPT_TILE_ORDER    order of the marching tiles: 0 = x fastest within a
  *                        chunk (default), 1 = y fastest, 2 = plane-major with
  *                        XCD k owning y-band k of every chunk (3D).
- *   FW_OPT_PLANE_KERNELS 3D: 1 = the velocity update runs on 64 x 4
- *                        tiles of one plane and the pressure update on 64 x 4
+ *   FW_OPT_PLANE_KERNELS 3D: 1 = the velocity update runs on 64 x R
+ *                        tiles of one plane and the pressure update on 64 x R
  *                        tiles of 4 planes, plane-major with XCD k owning
  *                        y-band k of every plane (the z stencil reads its
  *                        eight-plane window from memory: it stays in the
@@ -300,10 +300,14 @@ int fw_device_copy(void *d_dst, const void *d_src, int64_t bytes, void *hip_stre
  *                        options above; -1 (default) = the pressure update
  *                        always, the velocity update with N >= 2 mechanisms.
  *                        Not used with a persistent grid.
+ *   FW_OPT_PLANE_ROWS    rows of the plane kernels' tiles along y: 4
+ *                        (default) or 8.  Eight halve the y-halo reads per
+ *                        cell; which is faster depends on the grid (the
+ *                        autotuner times both).
  * Options change the work decomposition only, never the results.
  */
 enum { FW_OPT_GRAPH_STEPS = 1, FW_OPT_MARCH_CHUNK = 2, FW_OPT_TILE_ROWS = 3, FW_OPT_ROWS_PER_THREAD = 4,
-       FW_OPT_PERSISTENT = 5, FW_OPT_TILE_ORDER = 6, FW_OPT_PLANE_KERNELS = 7 };
+       FW_OPT_PERSISTENT = 5, FW_OPT_TILE_ORDER = 6, FW_OPT_PLANE_KERNELS = 7, FW_OPT_PLANE_ROWS = 8 };
 int fw_set_option(fw_sim *sim, int key, int64_t value);
 
 #ifdef __cplusplus

@@ -1,6 +1,6 @@
 """Launch-shape autotuner for a Simulation.
 
-Every option it touches (3D plane kernels, tile rows, rows per thread,
+Every option it touches (3D plane kernels and their tile rows, tile rows, rows per thread,
 marching chunk, persistent grid) changes only the work decomposition -- results are bitwise
 identical -- so candidates are timed on the live state: the state is saved,
 each candidate runs a few steps with per-kernel HIP events, and the state is
@@ -12,12 +12,13 @@ import json
 import math
 import os
 
-from .native import (FW_OPT_MARCH_CHUNK, FW_OPT_PERSISTENT, FW_OPT_PLANE_KERNELS, FW_OPT_ROWS_PER_THREAD,
-                     FW_OPT_TILE_ROWS)
+from .native import (FW_OPT_MARCH_CHUNK, FW_OPT_PERSISTENT, FW_OPT_PLANE_KERNELS, FW_OPT_PLANE_ROWS,
+                     FW_OPT_ROWS_PER_THREAD, FW_OPT_TILE_ROWS)
 
 CACHE_PATH = os.path.join(os.path.expanduser("~"), ".cache", "fw25_autotune.json")
 
-DEFAULT = {"plane_kernels": -1, "tile_rows": 4, "rows_per_thread": 1, "march_chunk": 0, "persistent": 0}
+DEFAULT = {"plane_kernels": -1, "plane_rows": 4, "tile_rows": 4, "rows_per_thread": 1, "march_chunk": 0,
+           "persistent": 0}
 
 
 def candidates(ndim):
@@ -26,8 +27,9 @@ def candidates(ndim):
         # the plane kernels ignore the marching shape; -1 picks them per update
         # (with N = 1 the velocity update then marches the default shape)
         for plane in (-1, 1):
-            out.append({"plane_kernels": plane, "tile_rows": 4, "rows_per_thread": 1, "march_chunk": 0,
-                        "persistent": 0})
+            for prow in (4, 8):
+                out.append({"plane_kernels": plane, "plane_rows": prow, "tile_rows": 4, "rows_per_thread": 1,
+                            "march_chunk": 0, "persistent": 0})
         for rows, rpt in ((4, 1), (8, 1), (16, 1), (16, 2), (8, 2)):
             for persistent in (0, 4):
                 for chunk in (0, 24, 96):
@@ -42,6 +44,7 @@ def candidates(ndim):
 
 def apply(sim, cfg):
     sim.set_option(FW_OPT_PLANE_KERNELS, cfg.get("plane_kernels", -1))
+    sim.set_option(FW_OPT_PLANE_ROWS, cfg.get("plane_rows", 4))
     # rows per thread first when shrinking to 4-row tiles is requested
     sim.set_option(FW_OPT_ROWS_PER_THREAD, 1)
     sim.set_option(FW_OPT_TILE_ROWS, cfg["tile_rows"])

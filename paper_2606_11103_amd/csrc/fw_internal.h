@@ -67,7 +67,8 @@ struct StepArgs {
     int32_t tile_rows;         // rows of a 3D tile along y
     int32_t plane;             // 1: the 3D velocity update runs its plane kernel on vtiles
     int32_t plane_p;           // 1: the 3D pressure update runs its plane kernel on ptiles
-    const Tile *vtiles;        // velocity: 64 x 4 tiles of kVelocityPlanes planes, plane-major, XCD k owning y-band k
+    int32_t plane_rows;        // rows (4 or 8) of the plane kernels' tiles
+    const Tile *vtiles;        // velocity: 64 x plane_rows tiles of kVelocityPlanes planes, plane-major, XCD k owning y-band k
     int32_t n_vtiles;
     int32_t vtiles_per_xcd;
     const Tile *ptiles;        // pressure: 64 x 4 tiles of kPressurePlanes planes, same banding

@@ -643,8 +643,8 @@ __global__ __launch_bounds__(BX *BY) void k_pressure(const StepArgs A)
 }
 
 // ---------------------------------------------------------------------------
-// Plane velocity update (3D, 64 x 4 tiles of kVelocityPlanes planes, one
-// tile per block).  Its tile list is plane-major and XCD k owns y-band k of
+// Plane velocity update (3D, 64 x TY tiles of kVelocityPlanes planes, TY = 4
+// or 8 rows, one tile per block).  Its tile list is plane-major and XCD k owns y-band k of
 // every plane, so all XCDs work on the same few planes: the window of the z
 // stencil stays in the last-level cache and is read straight from memory
 // instead of being carried in a register queue, and the concurrent tiles
@@ -653,12 +653,12 @@ __global__ __launch_bounds__(BX *BY) void k_pressure(const StepArgs A)
 // latency.  Each output is computed with the same operations, in the same
 // order, as in k_velocity, so the two give identical bits.
 // ---------------------------------------------------------------------------
-template <int N>
-__global__ __launch_bounds__(256) void k_velocity_plane(const StepArgs A)
+template <int N, int TY>
+__global__ __launch_bounds__(64 * TY) void k_velocity_plane(const StepArgs A)
 {
     constexpr int NP = kVelocityPlanes;
     constexpr int NB = NP > 1 ? 2 : 1;      // LDS buffers
-    constexpr int BX = 64, TY = 4, LX = BX + 8, LY = TY + 8, NT = BX * TY, CX = BX + 1;
+    constexpr int BX = 64, LX = BX + 8, LY = TY + 8, NT = BX * TY, CX = BX + 1;
     // halo cells the stencils read: 3 rows above and 4 below the tile over
     // its own columns, 3 columns left and 4 right over its own rows (LDS row
     // hy holds y0 - 4 + hy, column hx holds x0 - 4 + hx; corners never read)
@@ -805,8 +805,8 @@ __global__ __launch_bounds__(256) void k_velocity_plane(const StepArgs A)
     }
 }
 
-// Pressure update on tiles of kPressurePlanes consecutive planes (3D, 64 x 4,
-// one tile per block), from a list in which XCD k owns y-band k of every
+// Pressure update on tiles of kPressurePlanes consecutive planes (3D, 64 x TY
+// with TY = 4 or 8 rows, one tile per block), from a list in which XCD k owns y-band k of every
 // group of planes.  The v_z window of the group (its planes - 4 .. + 3 past
 // the last) is loaded once into registers; each plane loads the x-halo of
 // v_x, the y-halo of v_y and its own state into registers and stages the
@@ -815,11 +815,11 @@ __global__ __launch_bounds__(256) void k_velocity_plane(const StepArgs A)
 // of the next plane, issued right after it, stay in flight while the
 // current plane is computed.  Same operations in the same order as
 // k_pressure.
-template <int N>
-__global__ __launch_bounds__(256) void k_pressure_planes(const StepArgs A)
+template <int N, int TY>
+__global__ __launch_bounds__(64 * TY) void k_pressure_planes(const StepArgs A)
 {
     constexpr int NP = kPressurePlanes;
-    constexpr int BX = 64, TY = 4, LX = BX + 8, LY = TY + 8, NT = BX * TY;
+    constexpr int BX = 64, LX = BX + 8, LY = TY + 8, NT = BX * TY;
     // halo cells the stencils read: x-4 .. x-1 and x+64 .. x+66 of v_x over
     // the tile's rows, y-4 .. y-1 and y+4 .. y+6 of v_y over its columns
     constexpr int NHALO = 7 * TY + 7 * BX;
@@ -1051,12 +1051,18 @@ hipError_t launch_nd(bool velocity, int tile_rows, int rpt, const StepArgs &a, h
     if constexpr (NDIM == 3) {
         if (velocity && a.plane) {
             const size_t lds = (size_t)a.class_cap * (2 + 2 * N) * sizeof(float);
-            k_velocity_plane<N><<<dim3(8 * a.vtiles_per_xcd), dim3(64, 4), lds, s>>>(a);
+            if (a.plane_rows == 8)
+                k_velocity_plane<N, 8><<<dim3(8 * a.vtiles_per_xcd), dim3(64, 8), lds, s>>>(a);
+            else
+                k_velocity_plane<N, 4><<<dim3(8 * a.vtiles_per_xcd), dim3(64, 4), lds, s>>>(a);
             return hipGetLastError();
         }
         if (!velocity && a.plane_p) {
             const size_t lds = (size_t)a.class_cap * (3 + 2 * N) * sizeof(float);
-            k_pressure_planes<N><<<dim3(8 * a.ptiles_per_xcd), dim3(64, 4), lds, s>>>(a);
+            if (a.plane_rows == 8)
+                k_pressure_planes<N, 8><<<dim3(8 * a.ptiles_per_xcd), dim3(64, 8), lds, s>>>(a);
+            else
+                k_pressure_planes<N, 4><<<dim3(8 * a.ptiles_per_xcd), dim3(64, 4), lds, s>>>(a);
             return hipGetLastError();
         }
         if (tile_rows == 4) return launch_pair<3, N, 64, 4, 1>(velocity, a, s);

@@ -106,7 +106,7 @@ struct fw_sim {
     int n_t = 0, n_t_max = 0;
     // options
     int graph_steps = 16, march_chunk = 0, tile_rows = 4, rows_per_thread = 1, persistent = 0, tile_order = 0,
-        plane_kernels = -1;
+        plane_kernels = -1, plane_rows = 4;
     // stepping
     int64_t host_step = 0;
     hipStream_t cap_stream = nullptr;
@@ -322,11 +322,11 @@ int build_tiles(fw_sim *s)
     }
     int rc = upload_tiles(tiles, s->d_tiles, &s->n_tiles, &s->tiles_per_xcd);
     if (rc != FW_OK) return rc;
-    // plane-kernel tiles (3D): 64 x 4, kVelocityPlanes planes each for the
+    // plane-kernel tiles (3D): 64 x plane_rows, kVelocityPlanes planes each for the
     // velocity update, kPressurePlanes for the pressure update
     std::vector<fw::Tile> vt, pt;
-    if (plane_velocity_on(s)) vt = banded_tiles(s, 64, 4, fw::kVelocityPlanes);
-    if (plane_pressure_on(s)) pt = banded_tiles(s, 64, 4, fw::kPressurePlanes);
+    if (plane_velocity_on(s)) vt = banded_tiles(s, 64, s->plane_rows, fw::kVelocityPlanes);
+    if (plane_pressure_on(s)) pt = banded_tiles(s, 64, s->plane_rows, fw::kPressurePlanes);
     rc = upload_tiles(vt, s->d_vtiles, &s->n_vtiles, &s->vtiles_per_xcd);
     if (rc != FW_OK) return rc;
     rc = upload_tiles(pt, s->d_ptiles, &s->n_ptiles, &s->ptiles_per_xcd);
@@ -357,6 +357,7 @@ fw::StepArgs step_args(const fw_sim *s)
     // the plane kernels take one tile per block: not with a persistent grid
     a.plane = (plane_velocity_on(s) && s->persistent == 0 && s->n_vtiles > 0) ? 1 : 0;
     a.plane_p = (plane_pressure_on(s) && s->persistent == 0 && s->n_ptiles > 0) ? 1 : 0;
+    a.plane_rows = s->plane_rows;
     a.vtiles = s->d_vtiles.as<fw::Tile>();
     a.n_vtiles = s->n_vtiles;
     a.vtiles_per_xcd = s->vtiles_per_xcd;
@@ -1205,6 +1206,11 @@ int fw_set_option(fw_sim *sim, int key, int64_t value)
     case FW_OPT_PLANE_KERNELS:
         if (value < -1 || value > 1) return fail(FW_EINVAL, "plane kernels must be -1 (auto), 0 or 1");
         sim->plane_kernels = (int)value;
+        sim->tiles_dirty = true;
+        return FW_OK;
+    case FW_OPT_PLANE_ROWS:
+        if (value != 4 && value != 8) return fail(FW_EINVAL, "plane-kernel tile rows must be 4 or 8");
+        sim->plane_rows = (int)value;
         sim->tiles_dirty = true;
         return FW_OK;
     case FW_OPT_ROWS_PER_THREAD:

@@ -109,6 +109,11 @@ def test_tiling_does_not_change_results():
             opts[FW_OPT_MARCH_CHUNK] = chunk
         _, got = _run(case, opts=opts)
         assert np.array_equal(ref, got), (rows, rpt, chunk, pers, order, plane)
+    # 8-row tiles of the plane kernels (both updates, and pressure only)
+    from paper_2606_11103_amd.native import FW_OPT_PLANE_ROWS
+    for plane in (1, -1):
+        _, got = _run(case, opts={FW_OPT_PLANE_KERNELS: plane, FW_OPT_PLANE_ROWS: 8})
+        assert np.array_equal(ref, got), ("plane rows 8", plane)
 
 
 def test_persistent_grid_on_batched_2d_and_1d():
