@@ -93,10 +93,11 @@ def _selection_stats(fits, nr, dp):
     return j_sim, j_mod, nr[rows, j_sim], nr[rows, j_mod], dp[rows, j_sim], ok
 
 
-def test_weight_selection_over_the_sweep():
+@pytest.mark.parametrize("nmech", [2, 4])
+def test_weight_selection_over_the_sweep(nmech):
     case = configs.sweep_1d(n_cells=64, steps=10, pml=8)
     cache = relax.load_cache()
-    keys = [relax._key(c, a0, y, 2, 50000) for c, a0, y in zip(case.c, case.alpha0, case.y)]
+    keys = [relax._key(c, a0, y, nmech, 50000) for c, a0, y in zip(case.c, case.alpha0, case.y)]
     if any(k not in cache or "cands" not in cache[k] for k in keys):
         pytest.skip("sweep fits with per-weight candidates are not cached")
     fits = [relax.effective(cache[k]) for k in keys]
@@ -104,11 +105,12 @@ def test_weight_selection_over_the_sweep():
     j_sim, j_mod, nr_sim, nr_mod, dp_sim, ok = _selection_stats(fits, nr, dp)
     assert np.array_equal(j_sim, [[cd["w"] for cd in f["cands"]].index(c["w"]) for f, c in zip(fits, chosen)])
     ok_mod = np.array([relax.passes(nr[i, j], dp[i, j]) for i, j in enumerate(j_mod)])
-    report("weight selection %d classes x %d weights: within both bars %d (closed-form choice: %d), "
+    report("weight selection N=%d, %d classes x %d weights: within both bars %d (closed-form choice: %d), "
             "simulated NRMSE mean %.4f sd %.4f (closed-form choice %.4f), dispersion mean %.3f m/s"
-            % (len(fits), nr.shape[1], ok.sum(), ok_mod.sum(), nr_sim[ok].mean(), nr_sim[ok].std(),
+            % (nmech, len(fits), nr.shape[1], ok.sum(), ok_mod.sum(), nr_sim[ok].mean(), nr_sim[ok].std(),
                nr_mod[ok_mod].mean(), dp_sim[ok].mean()))
-    save("weight_selection.npy", np.stack([case.alpha0, case.y, nr_sim, nr_mod, ok]))
+    save("weight_selection.npy" if nmech == 2 else "weight_selection_N%d.npy" % nmech,
+         np.stack([case.alpha0, case.y, nr_sim, nr_mod, ok]))
     assert ok.sum() >= ok_mod.sum()
     assert ok.sum() >= 0.7 * len(fits)
     assert nr_sim[ok].mean() < 0.03
