@@ -30,7 +30,7 @@ from .analytic import recursion_coefficients
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_lib = None
+_libs = {}
 
 
 def build(force=False):
@@ -45,14 +45,20 @@ def build(force=False):
     return LIB_PATH
 
 
-def _load():
-    global _lib
-    if _lib is None:
-        build()
-        _lib = ctypes.CDLL(LIB_PATH)
-        _lib.oracle_steps.restype = ctypes.c_int
-        _lib.oracle_adjoint_step.restype = ctypes.c_int
-    return _lib
+def _load(path=None):
+    """The compiled stepping engine: the library built from fdtd_oracle.c, or
+    another build of that source named by path (tests that plant a mistake
+    in a copy of the engine load it this way)."""
+    key = path or LIB_PATH
+    lib = _libs.get(key)
+    if lib is None:
+        if path is None:
+            build()
+        lib = ctypes.CDLL(key)
+        lib.oracle_steps.restype = ctypes.c_int
+        lib.oracle_adjoint_step.restype = ctypes.c_int
+        _libs[key] = lib
+    return lib
 
 
 class _Sim(ctypes.Structure):
@@ -140,7 +146,9 @@ class OracleSim:
 
     def __init__(self, ndim, shape, dx, dt, nmech, class_map, c, rho, beta,
                  kappa, d, alpha, pml_cells=0, pml_R0=1e-4, pml_f_alpha=1e6, pml_c_ref=None,
-                 noise_amp=0.0, noise_seed=0, d_scale=None, noise_index=None, axis_full=None):
+                 noise_amp=0.0, noise_seed=0, d_scale=None, noise_index=None, axis_full=None,
+                 engine=None):
+        self.engine = engine
         self.ndim = int(ndim)
         nx, ny, nz = (list(shape) + [1, 1, 1])[:3]
         self.shape = (int(nx), int(ny), int(nz))
@@ -241,7 +249,7 @@ class OracleSim:
     def run(self, n_steps, src_cell=(), src_wave=None, rec_cell=(), energy=False):
         """Advance n_steps.  src_wave is [n_src][n_t] (sample t is added at the
         end of global step t).  Returns (receivers [n_steps][n_rec], energy or None)."""
-        lib = _load()
+        lib = _load(self.engine)
         src_cell = np.ascontiguousarray(np.asarray(src_cell, dtype=np.int64).reshape(-1))
         rec_cell = np.ascontiguousarray(np.asarray(rec_cell, dtype=np.int64).reshape(-1))
         n_src = src_cell.size
@@ -267,7 +275,7 @@ class OracleSim:
     def adjoint_step(self, lam, gK, gs):
         """Apply the transposed step to lam (dict of adjoint arrays shaped like
         the state), using the forward state currently held (u^n)."""
-        lib = _load()
+        lib = _load(self.engine)
         st = self._struct()
         c = self.coef
         rc = lib.oracle_adjoint_step(ctypes.byref(st),
