@@ -48,7 +48,10 @@ def build(force=False):
 def _load(path=None):
     """The compiled stepping engine: the library built from fdtd_oracle.c, or
     another build of that source named by path (tests that plant a mistake
-    in a copy of the engine load it this way)."""
+    in a copy of the engine load it this way) or by the environment variable
+    ORACLE_ENGINE (the sanitizer test runs the oracle pins on an
+    instrumented build this way)."""
+    path = path or os.environ.get("ORACLE_ENGINE") or None
     key = path or LIB_PATH
     lib = _libs.get(key)
     if lib is None:
