@@ -309,6 +309,7 @@ def bench_adjoint(torch, steps=3000, ckpt=55):
     del true
     case.c = case.c * 0.99
     sim = to_simulation(case)
+    sim.set_class_alpha0(case.alpha0)
     sim.step(32)                    # untimed: captures the step graph
     sim.reset()
     ms_fwd = _time_steps(torch, sim, steps)
@@ -320,8 +321,8 @@ def bench_adjoint(torch, steps=3000, ckpt=55):
         sim.forward_checkpointed(steps, ckpt, work)
         tr = sim.read_receivers_device()
         res = case.dt * (tr - obs)
-        gK, gs = sim.adjoint(steps, ckpt, work, res)
-        return tr, gK, gs
+        gc, ga = sim.adjoint(steps, ckpt, work, res)
+        return tr, gc, ga
 
     gradient()                      # untimed pass: first touch of the workspace
     torch.cuda.synchronize()

@@ -141,6 +141,9 @@ int fw_set_relaxation_table(fw_sim *sim, int n_classes, const double *kappa,
                             const double *d, const double *alpha);
 
 /*
+ * Sources (Sec. 4.1: plane-wave sources of Gaussian-modulated sinusoidal
+ * pulses; Sec. 4.5: transducer elements; the paper does not state how a
+ * source enters the scheme, the reading here is an additive soft source).
  * Additive pressure sources: after the pressure update of step t (0-based,
  * counted from the last reset), p[domain[s], cell[s]] += waves[wave_idx[s]][t]
  * for t < n_t.  cell = domain-local linear index.  Each (domain, cell) pair
@@ -150,6 +153,8 @@ int fw_set_sources(fw_sim *sim, int64_t n_src, const int32_t *domain, const int6
                    const int32_t *wave_idx, int n_wave, const float *waves, int n_t);
 
 /*
+ * Receivers (Sec. 4.1: receiver pixels recording the pressure wavefield,
+ * Sec. 4.3 and Sec. 4.5: incident/reflected pressure and RF traces).
  * Receivers: after step t's sources, trace[t][r] = p[domain[r], cell[r]]
  * for t < n_t_max (later steps are not recorded).  Allocates the device
  * trace buffer [n_t_max][n_rec] (zeroed).  n_rec = 0 clears.
@@ -158,6 +163,9 @@ int fw_set_receivers(fw_sim *sim, int64_t n_rec, const int32_t *domain, const in
                      int n_t_max);
 
 /*
+ * The FDTD step of Sec. 3.3 applied to Eqs. (wave1)/(wave2) of Sec. 2.1,
+ * with the memory variables of Eq. (relaxation_psi) (staggered stencil of
+ * order 8 in space, leapfrog in time).
  * Advance every domain by n_steps time steps on hip_stream (asynchronous).
  * One step = velocity update (gradient, N memory variables per axis, CPML)
  * -> pressure update (divergence, N memory variables, CPML, nonlinearity)
@@ -168,6 +176,7 @@ int fw_set_receivers(fw_sim *sim, int64_t n_rec, const int32_t *domain, const in
 int fw_step(fw_sim *sim, int n_steps, void *hip_stream);
 
 /*
+ * The simulation's output, the receiver pressure traces (Sec. 4.1, Sec. 4.5).
  * Copy n_elems floats of the trace buffer ([n_t_max][n_rec], row-major) to
  * dst (device memory if dst_is_device, else host).  Synchronises the stream.
  */
@@ -181,6 +190,8 @@ int fw_reset_state(fw_sim *sim, void *hip_stream);
 int fw_get_step(const fw_sim *sim, int64_t *step);
 
 /*
+ * Instability monitor (Sec. 4.6 and Sec. 5.5 watch the recorded wavefield
+ * for NaN or Inf at every step to detect divergence).
  * Finite check of every step: the source/receiver kernel (part of every
  * step, inside captured graphs too, no extra launch) flags the first trace
  * row, i.e. the 0-based step index as in fw_read_receivers, that holds a
@@ -190,50 +201,83 @@ int fw_get_step(const fw_sim *sim, int64_t *step);
  */
 int fw_first_nonfinite_step(fw_sim *sim, int64_t *row, void *hip_stream);
 
-/* Bytes of a full state snapshot (fields, memory variables, CPML variables
- * and the step counter); -1 on a NULL sim. */
+/* Bytes of a full state snapshot (fields, memory variables, CPML variables,
+ * the step counter and the first non-finite trace row of
+ * fw_first_nonfinite_step); -1 on a NULL sim. */
 int64_t fw_state_bytes(const fw_sim *sim);
 
 /* Copy the full state into / out of a caller-owned device buffer of
  * fw_state_bytes bytes (asynchronous, device-to-device).  Resuming from a
- * saved state reproduces the uninterrupted run bit for bit. */
+ * saved state reproduces the uninterrupted run bit for bit; loading a state
+ * also restores the non-finite row it was saved with, so a row flagged after
+ * the save is forgotten. */
 int fw_save_state(fw_sim *sim, void *d_dst, void *hip_stream);
 int fw_load_state(fw_sim *sim, const void *d_src, void *hip_stream);
 
 /*
+ * Power-law attenuation coefficient alpha0 of each class (Sec. 3.1, the
+ * alpha0 of alpha(f) = alpha0 f^y that the class's relaxation table was
+ * fitted to), host double [n_classes], every value finite and > 0
+ * (FW_EINVAL otherwise: a class without attenuation has no relaxation
+ * strength to scale).  Used only by fw_adjoint's dJ/dalpha0, whose units
+ * are those of J per unit of the alpha0 given here.  Requires fw_set_media.
+ */
+int fw_set_class_alpha0(fw_sim *sim, int n_classes, const double *alpha0);
+
+/*
  * Discrete adjoint with checkpointed recomputation (linear media: beta = 0).
+ * The paper has no adjoint; this differentiates the scheme of Sec. 2.1 and
+ * Sec. 3.3 (the transposed velocity and pressure updates, memory-variable
+ * and CPML recursions included, applied to every step in reverse order).
  *
  * Misfit J is any function of the receiver traces; the caller supplies
- * d_adj_src[t][r] = dJ/d trace[t][r] (device float [n_steps][n_rec]).  The
- * adjoint of every forward step (transposed velocity and pressure updates,
- * memory-variable and CPML recursions included) is applied in reverse order,
- * accumulating (+=) per cell, in the caller's unpadded cell layout (domains
- * concatenated, each in its own linear order):
- *   d_grad_K[x] = dJ/dK(x), K = rho c^2 (1 + eps)^2 the bulk modulus, and
- *   d_grad_s[x] = dJ/ds(x), s(x) a scale of every relaxation coefficient d of
- *                 the cell (d -> s d, kappa and alpha fixed).
- * Then dJ/dc = 2 rho c (1 + eps)^2 dJ/dK and, when d is taken proportional to
- * alpha0 within a class, dJ/dalpha0 = dJ/ds / alpha0.
+ * d_adj_src[t][r] = dJ/d trace[t][r] (device float [n_steps][n_rec]).
+ * Gradients are accumulated (+=) per cell in the caller's unpadded cell
+ * layout (domains concatenated, each in its own linear order):
+ *   d_grad_c[x]      = dJ/dc(x) of the cell's sound speed, with the cell's
+ *                      modulus K = rho c^2 (1 + eps)^2 (eps the speed
+ *                      perturbation of fw_set_media), i.e. 2 rho c (1 + eps)^2
+ *                      dJ/dK(x);
+ *   d_grad_alpha0[x] = dJ/dalpha0(x) when the relaxation strengths d of the
+ *                      cell scale with its alpha0 (kappa and alpha fixed:
+ *                      d(x) = d_class alpha0(x) / alpha0_class), i.e.
+ *                      dJ/ds(x) / alpha0_class for the scale s of every d of
+ *                      the cell.  May be NULL; otherwise fw_set_class_alpha0
+ *                      must have been called (FW_ESTATE).
+ * The chain rule runs on the device (the speed perturbation is evaluated as
+ * in the forward step); rho, c and alpha0 are those of the cell's class.
  *
  * d_work is a caller-owned, 256-byte aligned device buffer of
  * fw_adjoint_workspace_bytes bytes (FW_EINVAL if misaligned, FW_ENOMEM if
  * smaller) holding ceil(n_steps / ckpt_every) state checkpoints,
  * ckpt_every + 1 recomputed states, the adjoint state and scratch.
- * d_grad_K and d_grad_s are accumulated into (the caller zeroes them); they
- * and d_adj_src must be 4-byte aligned device buffers.
+ * d_grad_c, d_grad_alpha0 and d_adj_src must be 4-byte aligned device
+ * buffers of the sizes above; the gradients are accumulated into (the caller
+ * zeroes them).
  * fw_forward_checkpointed resets the state, runs n_steps (recording the
  * traces) and stores the checkpoints; fw_adjoint then sweeps the segments
  * last to first, recomputing each segment's states from its checkpoint into
  * d_work.  fw_adjoint leaves the simulation's own state and step counter as
  * they were (the recompute rewrites the traces of steps < n_steps with the
- * same values), so stepping can continue after it.
+ * same values), so stepping can continue after it.  fw_adjoint synchronises
+ * the stream before it returns.
  * Returns FW_EUNSUPPORTED if any class has beta != 0.
  */
 int64_t fw_adjoint_workspace_bytes(const fw_sim *sim, int n_steps, int ckpt_every);
 int fw_forward_checkpointed(fw_sim *sim, int n_steps, int ckpt_every, void *d_work, int64_t bytes,
                             void *hip_stream);
 int fw_adjoint(fw_sim *sim, int n_steps, int ckpt_every, void *d_work, int64_t bytes,
-               const float *d_adj_src, float *d_grad_K, float *d_grad_s, void *hip_stream);
+               const float *d_adj_src, float *d_grad_c, float *d_grad_alpha0, void *hip_stream);
+
+/*
+ * The same reverse sweep as fw_adjoint, returning the gradients before the
+ * chain rule (asynchronous): d_grad_K[x] += dJ/dK(x), the cell's bulk
+ * modulus, and d_grad_s[x] += dJ/ds(x), s a scale of every relaxation
+ * strength d of the cell (d -> s d, kappa and alpha fixed).  Same workspace,
+ * layout and errors as fw_adjoint.
+ */
+int fw_adjoint_modulus(fw_sim *sim, int n_steps, int ckpt_every, void *d_work, int64_t bytes,
+                       const float *d_adj_src, float *d_grad_K, float *d_grad_s, void *hip_stream);
 
 /*
  * Advance n_steps steps like fw_step, but launch every kernel eagerly with a
@@ -245,6 +289,9 @@ int fw_adjoint(fw_sim *sim, int n_steps, int ckpt_every, void *d_work, int64_t b
 int fw_time_kernels(fw_sim *sim, int n_steps, void *hip_stream, double *avg_ms);
 
 /*
+ * Diagnostics of one step (Sec. 2.1: the lossless limit of Eqs. (wave1)/
+ * (wave2) conserves acoustic energy; Sec. 4.6: the peak pressure of every
+ * step is watched for instability).
  * One full step (like fw_step(sim, 1, ...)) that also evaluates, per domain,
  * out[3 d + 0] = E^{n+1/2} = 1/2 sum_faces rho_f |v^{n+1/2}|^2
  *                           + 1/2 sum_cells p^{n+1} p^n / K,

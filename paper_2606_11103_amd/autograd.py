@@ -13,12 +13,11 @@ The forward run groups voxels into classes by (label, c, alpha0); a class
 keeps its label's kappa and alpha and scales the label's d by
 alpha0 / alpha0_label (Sec. 2.1 parameters; d-scaling keeps the relaxation
 times and scales the relaxation strength).  At most 256 distinct classes per
-domain are allowed, so continuous maps must be quantised first.  The
-backward pass feeds dJ/d traces to the HIP adjoint and returns
-  dJ/dc(x)      = 2 rho c (1 + eps)^2 dJ/dK(x),
-  dJ/dalpha0(x) = dJ/ds(x) / alpha0(x),
-with eps the per-voxel speed perturbation of the problem (0 when off).
-Linear media only (beta = 0), as the adjoint is.
+domain are allowed, so continuous maps must be quantised first, and every
+alpha0 must be > 0.  The backward pass feeds dJ/d traces to the HIP adjoint
+(fw_adjoint), which returns dJ/dc(x) and dJ/dalpha0(x) per voxel; this
+module only marshals arrays.  Linear media only (beta = 0), as the adjoint
+is.
 """
 import dataclasses
 from typing import List, Optional
@@ -56,32 +55,9 @@ class Problem:
     pml_params: Optional[tuple] = None
 
 
-def _splitmix64(x):
-    with np.errstate(over="ignore"):
-        z = x + np.uint64(0x9E3779B97F4A7C15)
-        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
-        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
-        return z ^ (z >> np.uint64(31))
-
-
-def speed_perturbation(problem):
-    """eps per voxel (unpadded layout), the definition documented for
-    fw_set_media: amp (2u - 1), u = (SplitMix64(seed ^ local index) >> 40) 2^-24."""
-    out = []
-    for shp in problem.shapes:
-        n = int(np.prod(shp))
-        if problem.noise_amp == 0.0:
-            out.append(np.zeros(n))
-            continue
-        idx = np.arange(n, dtype=np.uint64) ^ np.uint64(problem.noise_seed)
-        u = (_splitmix64(idx) >> np.uint64(40)).astype(np.float64) * 2.0 ** -24
-        out.append(problem.noise_amp * (2.0 * u - 1.0))
-    return np.concatenate(out)
-
-
 def _classes(problem, c, a0):
     """Group voxels into classes by (label, c, alpha0) per domain."""
-    maps, base, cls_c, cls_rho, cls_k, cls_d, cls_al = [], [], [], [], [], [], []
+    maps, base, cls_c, cls_rho, cls_k, cls_d, cls_al, cls_a0 = [], [], [], [], [], [], [], []
     pos = 0
     nb = 0
     for dom, shp in enumerate(problem.shapes):
@@ -101,9 +77,11 @@ def _classes(problem, c, a0):
             cls_k.append(problem.kappa[L])
             cls_d.append(problem.d[L] * (aa / problem.alpha0_ref[L]))
             cls_al.append(problem.alpha[L])
+            cls_a0.append(aa)
         nb += len(uniq)
         pos += n
-    return maps, base, np.array(cls_c), np.array(cls_rho), np.array(cls_k), np.array(cls_d), np.array(cls_al)
+    return (maps, base, np.array(cls_c), np.array(cls_rho), np.array(cls_k), np.array(cls_d), np.array(cls_al),
+            np.array(cls_a0))
 
 
 class FDTDFunction(torch.autograd.Function):
@@ -111,30 +89,27 @@ class FDTDFunction(torch.autograd.Function):
     def forward(ctx, c_map, alpha0_map, problem):
         c = c_map.detach().double().cpu().numpy().reshape(-1)
         a0 = alpha0_map.detach().double().cpu().numpy().reshape(-1)
-        maps, base, cc, rho, kap, d, al = _classes(problem, c, a0)
+        if not np.all(a0 > 0):
+            raise ValueError("alpha0 must be > 0 in every voxel (the relaxation strengths scale with it)")
+        maps, base, cc, rho, kap, d, al, ca0 = _classes(problem, c, a0)
         sim = Simulation(problem.ndim, problem.shapes, problem.dx, problem.dt, problem.nmech, problem.pml_cells,
                          pml_params=problem.pml_params)
         sim.set_media(maps, base, cc, rho, np.zeros(len(cc)), problem.noise_amp, problem.noise_seed)
         sim.set_relaxation_table(kap, d, al)
+        sim.set_class_alpha0(ca0)
         sim.set_sources(problem.src_domain, problem.src_cell, problem.src_wave, problem.waves)
         sim.set_receivers(problem.rec_domain, problem.rec_cell, problem.n_steps)
         work = sim.adjoint_workspace(problem.n_steps, problem.ckpt_every)
         sim.forward_checkpointed(problem.n_steps, problem.ckpt_every, work)
         traces = sim.read_receivers_device()
         ctx.sim, ctx.work, ctx.problem = sim, work, problem
-        ctx.c, ctx.a0 = c, a0
-        ctx.rho_voxel = np.concatenate([rho[base[k] + m.reshape(-1)] for k, m in enumerate(maps)])
         ctx.in_device = c_map.device
         return traces
 
     @staticmethod
     def backward(ctx, grad_traces):
         sim, work, problem = ctx.sim, ctx.work, ctx.problem
-        gK, gs = sim.adjoint(problem.n_steps, problem.ckpt_every, work, grad_traces.detach().float())
-        eps = speed_perturbation(problem)
-        scale_c = torch.as_tensor(2.0 * ctx.rho_voxel * ctx.c * (1.0 + eps) ** 2, device=gK.device)
-        grad_c = (gK.double() * scale_c).float()
-        grad_a0 = (gs.double() / torch.as_tensor(ctx.a0, device=gs.device)).float()
+        grad_c, grad_a0 = sim.adjoint(problem.n_steps, problem.ckpt_every, work, grad_traces.detach().float())
         ctx.sim = ctx.work = None
         return grad_c.to(ctx.in_device), grad_a0.to(ctx.in_device), None
 

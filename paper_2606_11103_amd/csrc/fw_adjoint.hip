@@ -436,6 +436,37 @@ hipError_t adj_launch(int which, const AdjArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
+// dJ/dc and dJ/dalpha0 per cell (one thread per cell of the unpadded
+// layout).  The speed perturbation is evaluated exactly as in the forward
+// pressure update (same hash, same FP32 operations), so (1 + eps)^2 matches
+// the factor the modulus of the run was built with.
+__global__ __launch_bounds__(256) void k_adj_chain(const AdjChainArgs A)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= A.n_packed) return;
+    int lo = 0, hi = A.n_domains - 1;   // domain holding unpadded cell i
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (A.doms[mid].packed_off <= i)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const DomainDesc &D = A.doms[lo];
+    const int64_t g = i - D.packed_off;
+    const float2 ch = A.chain[D.class_base + A.cls[D.cell_off + g]];
+    float f2 = 1.0f;
+    if (A.noise_amp != 0.0f) {
+        const uint64_t h = splitmix64_a(D.noise_seed ^ (uint64_t)(uint32_t)g);
+        const float u = (float)(h >> 40) * 0x1.0p-24f;
+        const float e = A.noise_amp * fmaf(2.0f, u, -1.0f);
+        const float f1 = 1.0f + e;
+        f2 = f1 * f1;
+    }
+    A.grad_c[i] = fmaf(ch.x * f2, A.gK[i], A.grad_c[i]);
+    if (A.grad_a0) A.grad_a0[i] = fmaf(A.gs[i], ch.y, A.grad_a0[i]);
+}
+
 template <int NDIM>
 hipError_t adj_launch_n(int which, int nmech, const AdjArgs &a, hipStream_t s)
 {
@@ -470,6 +501,15 @@ hipError_t launch_adjoint_finish(int ndim, const AdjArgs &a, hipStream_t s)
 {
     if (a.s.n_tiles <= 0) return hipSuccess;
     return adj_launch_dim(2, ndim, 1, a, s);
+}
+
+hipError_t launch_adjoint_chain(const AdjChainArgs &a, hipStream_t s)
+{
+    if (a.n_packed <= 0) return hipSuccess;
+    const int64_t blocks = (a.n_packed + 255) / 256;
+    if (blocks > (int64_t(1) << 31) - 1) return hipErrorInvalidValue;
+    k_adj_chain<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(a);
+    return hipGetLastError();
 }
 
 hipError_t launch_adjoint_inject(const AdjInjectArgs &a, hipStream_t s)

@@ -130,7 +130,24 @@ struct AdjInjectArgs {
     int64_t step;
 };
 
+// Chain rule of the adjoint from the modulus and d-scale gradients to the
+// gradients of the sound speed and of the attenuation coefficient alpha0:
+//   dJ/dc(x)      = 2 rho c (1 + eps(x))^2 dJ/dK(x)   (K = rho c^2 (1 + eps)^2),
+//   dJ/dalpha0(x) = dJ/ds(x) / alpha0                 (d proportional to alpha0),
+// with rho, c, alpha0 of the cell's class and eps its speed perturbation.
+struct AdjChainArgs {
+    const DomainDesc *doms;
+    int32_t n_domains;
+    float noise_amp;
+    const uint8_t *cls;        // class map (padded layout: doms[d].cell_off + local index)
+    const float2 *chain;       // per global class: (2 rho c, 1 / alpha0)
+    const float *gK, *gs;      // dJ/dK, dJ/ds in the unpadded layout
+    float *grad_c, *grad_a0;   // accumulated (+=), unpadded layout; grad_a0 may be NULL
+    int64_t n_packed;
+};
+
 hipError_t launch_copy(void *dst, const void *src, int64_t bytes, hipStream_t s);
+hipError_t launch_adjoint_chain(const AdjChainArgs &a, hipStream_t s);
 hipError_t launch_energy(int ndim, const StepArgs &a, const float *p_old, double *partial, hipStream_t s);
 // one reverse step: transpose of the pressure update (applying a pending
 // lamD1 first when a.fold_div is set), then of the velocity update

@@ -91,17 +91,19 @@ struct fw_sim {
     double noise_amp = 0;
     uint64_t noise_seed = 0;
     std::vector<double> kappa, dcoef, alpha;
+    std::vector<double> alpha0;          // power-law coefficient per class (fw_set_class_alpha0)
     // device tables
     DevBuf d_doms, d_classes, d_pml, d_tiles, d_vtiles, d_ptiles, d_waves, d_traces, d_step;
     DevBuf d_srcrec, d_rec_of;
     std::vector<int64_t> h_src_cell, h_rec_cell;   // global cells of the sources and the receivers
     std::vector<int32_t> h_src_wave;               // waveform row of each source
     int64_t n_srcrec = 0;
-    DevBuf d_cadj, d_adj_cells, d_adj_off, d_adj_idx;
+    DevBuf d_cadj, d_adj_cells, d_adj_off, d_adj_idx, d_chain;
     DevBuf d_pold, d_partial;
     int64_t n_adj_cells = 0;
     int64_t total_packed = 0;
     int n_tiles = 0, tiles_per_xcd = 0, n_vtiles = 0, vtiles_per_xcd = 0, n_ptiles = 0, ptiles_per_xcd = 0;
+    std::vector<int32_t> h_tile_dom;     // domain of each marching tile (energy partial sums)
     int64_t n_src = 0, n_rec = 0;
     int n_t = 0, n_t_max = 0;
     // options
@@ -322,6 +324,8 @@ int build_tiles(fw_sim *s)
     }
     int rc = upload_tiles(tiles, s->d_tiles, &s->n_tiles, &s->tiles_per_xcd);
     if (rc != FW_OK) return rc;
+    s->h_tile_dom.resize(tiles.size());
+    for (size_t t = 0; t < tiles.size(); ++t) s->h_tile_dom[t] = tiles[t].dom;
     // plane-kernel tiles (3D): 64 x plane_rows, kVelocityPlanes planes each for the
     // velocity update, kPressurePlanes for the pressure update
     std::vector<fw::Tile> vt, pt;
@@ -431,7 +435,7 @@ extern "C" {
 
 const char *fw_last_error(void) { return g_err.c_str(); }
 
-int fw_abi_version(void) { return 1; }
+int fw_abi_version(void) { return 2; }
 
 int fw_create_grid(fw_sim **out, int ndim, int n_domains, const int64_t *shape, double dx, double dt, int n_mech,
                    int pml_cells, const double *pml_params)
@@ -897,7 +901,8 @@ int fw_save_state(fw_sim *sim, void *d_dst, void *hip_stream)
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     char *dst = static_cast<char *>(d_dst);
     HIP_OR_FAIL(fw::launch_copy(dst, sim->ws, sim->state_end, st));
-    HIP_OR_FAIL(hipMemcpyAsync(dst + sim->state_end, sim->d_step.ptr, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+    // the step counter and the first non-finite trace row travel together
+    HIP_OR_FAIL(hipMemcpyAsync(dst + sim->state_end, sim->d_step.ptr, 2 * sizeof(int64_t), hipMemcpyDeviceToDevice, st));
     return FW_OK;
 }
 
@@ -909,7 +914,7 @@ int fw_load_state(fw_sim *sim, const void *d_src, void *hip_stream)
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     const char *src = static_cast<const char *>(d_src);
     HIP_OR_FAIL(fw::launch_copy(sim->ws, src, sim->state_end, st));
-    HIP_OR_FAIL(hipMemcpyAsync(sim->d_step.ptr, src + sim->state_end, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+    HIP_OR_FAIL(hipMemcpyAsync(sim->d_step.ptr, src + sim->state_end, 2 * sizeof(int64_t), hipMemcpyDeviceToDevice, st));
     int64_t step = 0;
     HIP_OR_FAIL(hipMemcpyAsync(&step, src + sim->state_end, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     HIP_OR_FAIL(hipStreamSynchronize(st));
@@ -964,6 +969,33 @@ int fw_time_kernels(fw_sim *sim, int n_steps, void *hip_stream, double *avg_ms)
 }
 
 
+// One step plus the energy diagnostics, with p^n kept in pold (total_cells
+// floats) and the per-tile partial sums in partial (n_tiles x 3 doubles).
+static int energy_step_impl(fw_sim *sim, double *out, hipStream_t st, float *pold, double *partial)
+{
+    const fw::StepArgs a = step_args(sim);
+    const fw::SrcRecArgs r = srcrec_args(sim);
+    HIP_OR_FAIL(fw::launch_velocity(sim->ndim, sim->nmech, sim->tile_rows, sim->rows_per_thread, a, st));
+    HIP_OR_FAIL(fw::launch_copy(pold, a.f.p, sim->total_cells * (int64_t)sizeof(float), st));
+    HIP_OR_FAIL(fw::launch_pressure(sim->ndim, sim->nmech, sim->tile_rows, sim->rows_per_thread, a, st));
+    HIP_OR_FAIL(fw::launch_src_rec(r, st));
+    HIP_OR_FAIL(fw::launch_energy(sim->ndim, a, pold, partial, st));
+    std::vector<double> part((size_t)sim->n_tiles * 3);
+    HIP_OR_FAIL(hipMemcpyAsync(part.data(), partial, part.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_OR_FAIL(hipStreamSynchronize(st));
+    for (int d = 0; d < sim->n_domains; ++d) out[3 * d] = out[3 * d + 1] = out[3 * d + 2] = 0.0;
+    for (int t = 0; t < sim->n_tiles; ++t) {
+        double *o = out + 3 * sim->h_tile_dom[t];
+        o[0] += part[3 * (size_t)t];
+        o[1] = std::max(o[1], part[3 * (size_t)t + 1]);
+        o[2] += part[3 * (size_t)t + 2];
+    }
+    sim->host_step += 1;
+    for (int d = 0; d < sim->n_domains; ++d)
+        if (out[3 * d + 2] > 0) return fail(FW_ENONFINITE, "domain %d: %.0f non-finite pressure values", d, out[3 * d + 2]);
+    return FW_OK;
+}
+
 extern "C" int fw_energy_step(fw_sim *sim, double *out, void *hip_stream)
 {
     g_err.clear();
@@ -973,32 +1005,10 @@ extern "C" int fw_energy_step(fw_sim *sim, double *out, void *hip_stream)
         int rc = build_tiles(sim);
         if (rc != FW_OK) return rc;
     }
-    hipStream_t st = static_cast<hipStream_t>(hip_stream);
     HIP_OR_FAIL(sim->d_pold.ensure((size_t)sim->total_cells * sizeof(float)));
     HIP_OR_FAIL(sim->d_partial.ensure((size_t)sim->n_tiles * 3 * sizeof(double)));
-    const fw::StepArgs a = step_args(sim);
-    const fw::SrcRecArgs r = srcrec_args(sim);
-    HIP_OR_FAIL(fw::launch_velocity(sim->ndim, sim->nmech, sim->tile_rows, sim->rows_per_thread, a, st));
-    HIP_OR_FAIL(fw::launch_copy(sim->d_pold.ptr, a.f.p, sim->total_cells * (int64_t)sizeof(float), st));
-    HIP_OR_FAIL(fw::launch_pressure(sim->ndim, sim->nmech, sim->tile_rows, sim->rows_per_thread, a, st));
-    HIP_OR_FAIL(fw::launch_src_rec(r, st));
-    HIP_OR_FAIL(fw::launch_energy(sim->ndim, a, sim->d_pold.as<float>(), sim->d_partial.as<double>(), st));
-    std::vector<double> part((size_t)sim->n_tiles * 3);
-    HIP_OR_FAIL(hipMemcpyAsync(part.data(), sim->d_partial.ptr, part.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_OR_FAIL(hipStreamSynchronize(st));
-    std::vector<fw::Tile> tiles(sim->n_tiles);
-    HIP_OR_FAIL(hipMemcpy(tiles.data(), sim->d_tiles.ptr, tiles.size() * sizeof(fw::Tile), hipMemcpyDeviceToHost));
-    for (int d = 0; d < sim->n_domains; ++d) out[3 * d] = out[3 * d + 1] = out[3 * d + 2] = 0.0;
-    for (int t = 0; t < sim->n_tiles; ++t) {
-        double *o = out + 3 * tiles[t].dom;
-        o[0] += part[3 * (size_t)t];
-        o[1] = std::max(o[1], part[3 * (size_t)t + 1]);
-        o[2] += part[3 * (size_t)t + 2];
-    }
-    sim->host_step += 1;
-    for (int d = 0; d < sim->n_domains; ++d)
-        if (out[3 * d + 2] > 0) return fail(FW_ENONFINITE, "domain %d: %.0f non-finite pressure values", d, out[3 * d + 2]);
-    return FW_OK;
+    return energy_step_impl(sim, out, static_cast<hipStream_t>(hip_stream), sim->d_pold.as<float>(),
+                            sim->d_partial.as<double>());
 }
 
 // ------------------------------------------------------------------ adjoint --
@@ -1013,7 +1023,10 @@ static int adj_layout(const fw_sim *s, int n_steps, int ckpt_every, int64_t *n_c
     *off_seg = *n_ck * SB;
     *off_lam = *off_seg + (int64_t)(std::min(ckpt_every, n_steps) + 1) * SB;
     *off_scr = *off_lam + SB;
-    *total = *off_scr + align_up(2LL * 3 * s->total_cells * 4, kAlignBytes);
+    // scratch: the six pending-derivative fields, then dJ/dK and dJ/ds of
+    // fw_adjoint (unpadded layout) before its chain rule
+    *total = *off_scr + align_up(2LL * 3 * s->total_cells * 4, kAlignBytes) +
+             2 * align_up(s->total_packed * 4, kAlignBytes);
     return FW_OK;
 }
 
@@ -1057,11 +1070,11 @@ extern "C" int fw_forward_checkpointed(fw_sim *sim, int n_steps, int ckpt_every,
     return FW_OK;
 }
 
-extern "C" int fw_adjoint(fw_sim *sim, int n_steps, int ckpt_every, void *d_work, int64_t bytes, const float *d_adj_src,
-                          float *d_grad_K, float *d_grad_s, void *hip_stream)
+// The reverse sweep shared by fw_adjoint and fw_adjoint_modulus: accumulates
+// dJ/dK into d_grad_K and dJ/ds into d_grad_s (unpadded layout).
+static int adjoint_sweep(fw_sim *sim, int n_steps, int ckpt_every, void *d_work, int64_t bytes,
+                         const float *d_adj_src, float *d_grad_K, float *d_grad_s, void *hip_stream)
 {
-    g_err.clear();
-    if (!sim || !d_work || !d_adj_src || !d_grad_K || !d_grad_s) return fail(FW_EINVAL, "NULL argument");
     int64_t nck, os, ol, oc, tot;
     int rc = adj_layout(sim, n_steps, ckpt_every, &nck, &os, &ol, &oc, &tot);
     if (rc != FW_OK) return rc;
@@ -1136,6 +1149,75 @@ extern "C" int fw_adjoint(fw_sim *sim, int n_steps, int ckpt_every, void *d_work
     }
     if (A.fold_div) HIP_OR_FAIL(fw::launch_adjoint_finish(sim->ndim, A, st));
     HIP_OR_FAIL(hipMemcpyAsync(sim->d_step.ptr, lam + sim->state_end, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+    return FW_OK;
+}
+
+extern "C" int fw_adjoint_modulus(fw_sim *sim, int n_steps, int ckpt_every, void *d_work, int64_t bytes,
+                                  const float *d_adj_src, float *d_grad_K, float *d_grad_s, void *hip_stream)
+{
+    g_err.clear();
+    if (!sim || !d_work || !d_adj_src || !d_grad_K || !d_grad_s) return fail(FW_EINVAL, "NULL argument");
+    return adjoint_sweep(sim, n_steps, ckpt_every, d_work, bytes, d_adj_src, d_grad_K, d_grad_s, hip_stream);
+}
+
+extern "C" int fw_set_class_alpha0(fw_sim *sim, int n_classes, const double *alpha0)
+{
+    g_err.clear();
+    if (!sim || !alpha0) return fail(FW_EINVAL, "NULL argument");
+    if (!sim->media_set) return fail(FW_ESTATE, "call fw_set_media first");
+    if (n_classes != sim->n_classes) return fail(FW_EINVAL, "n_classes %d != %d of fw_set_media", n_classes, sim->n_classes);
+    for (int k = 0; k < n_classes; ++k)
+        if (!(alpha0[k] > 0.0) || !std::isfinite(alpha0[k]))
+            return fail(FW_EINVAL, "class %d: alpha0 must be finite and > 0 (got %g); a class without attenuation has "
+                        "no relaxation strength to scale", k, alpha0[k]);
+    sim->alpha0.assign(alpha0, alpha0 + n_classes);
+    return FW_OK;
+}
+
+extern "C" int fw_adjoint(fw_sim *sim, int n_steps, int ckpt_every, void *d_work, int64_t bytes, const float *d_adj_src,
+                          float *d_grad_c, float *d_grad_alpha0, void *hip_stream)
+{
+    g_err.clear();
+    if (!sim || !d_work || !d_adj_src || !d_grad_c) return fail(FW_EINVAL, "NULL argument");
+    if (d_grad_alpha0 && (int)sim->alpha0.size() != sim->n_classes)
+        return fail(FW_ESTATE, "dJ/dalpha0 needs the class alpha0 values (fw_set_class_alpha0)");
+    int64_t nck, os, ol, oc, tot;
+    int rc = adj_layout(sim, n_steps, ckpt_every, &nck, &os, &ol, &oc, &tot);
+    if (rc != FW_OK) return rc;
+    if (bytes < tot) return fail(FW_ENOMEM, "adjoint workspace too small: %lld < %lld", (long long)bytes, (long long)tot);
+    if ((reinterpret_cast<uintptr_t>(d_work) % kAlignBytes) != 0)
+        return fail(FW_EINVAL, "adjoint workspace must be 256-byte aligned");
+    if (!sim->ws || !sim->media_set || !sim->table_set) return fail(FW_ESTATE, "set up the simulation first");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    char *w = static_cast<char *>(d_work);
+    const int64_t gbytes = align_up(sim->total_packed * 4, kAlignBytes);
+    float *gK = reinterpret_cast<float *>(w + tot - 2 * gbytes);
+    float *gs = reinterpret_cast<float *>(w + tot - gbytes);
+    HIP_OR_FAIL(hipMemsetAsync(gK, 0, (size_t)(2 * gbytes), st));
+    rc = adjoint_sweep(sim, n_steps, ckpt_every, d_work, bytes, d_adj_src, gK, gs, hip_stream);
+    if (rc != FW_OK) return rc;
+    // per class (2 rho c, 1 / alpha0) in FP64, rounded once
+    std::vector<float> chain(2 * (size_t)sim->n_classes);
+    for (int k = 0; k < sim->n_classes; ++k) {
+        chain[2 * k] = (float)(2.0 * sim->rho[k] * sim->c[k]);
+        chain[2 * k + 1] = d_grad_alpha0 ? (float)(1.0 / sim->alpha0[k]) : 0.0f;
+    }
+    HIP_OR_FAIL(sim->d_chain.ensure(chain.size() * sizeof(float)));
+    HIP_OR_FAIL(hipMemcpyAsync(sim->d_chain.ptr, chain.data(), chain.size() * sizeof(float), hipMemcpyHostToDevice, st));
+    fw::AdjChainArgs C{};
+    C.doms = sim->d_doms.as<fw::DomainDesc>();
+    C.n_domains = sim->n_domains;
+    C.noise_amp = (float)sim->noise_amp;
+    C.cls = fields_of(sim).cls;
+    C.chain = sim->d_chain.as<float2>();
+    C.gK = gK;
+    C.gs = gs;
+    C.grad_c = d_grad_c;
+    C.grad_a0 = d_grad_alpha0;
+    C.n_packed = sim->total_packed;
+    HIP_OR_FAIL(fw::launch_adjoint_chain(C, st));
+    // the host table must outlive the asynchronous upload
+    HIP_OR_FAIL(hipStreamSynchronize(st));
     return FW_OK;
 }
 

@@ -52,6 +52,8 @@ SIGNATURES = {
     "fw_read_field": (_I, [_P, _I, _I, _P, _I, _P]),
     "fw_forward_checkpointed": (_I, [_P, _I, _I, _P, _L, _P]),
     "fw_adjoint": (_I, [_P, _I, _I, _P, _L, _P, _P, _P, _P]),
+    "fw_adjoint_modulus": (_I, [_P, _I, _I, _P, _L, _P, _P, _P, _P]),
+    "fw_set_class_alpha0": (_I, [_P, _I, _P]),
 }
 
 

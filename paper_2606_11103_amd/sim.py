@@ -176,26 +176,53 @@ class Simulation:
         check(lib.fw_forward_checkpointed(self._h, int(n_steps), int(ckpt_every), ctypes.c_void_p(work.data_ptr()),
                                           int(work.numel()), self._stream(stream)))
 
-    def adjoint(self, n_steps, ckpt_every, work, adj_src, grad_K=None, grad_s=None, stream=None):
-        """Reverse sweep; adj_src is a device float tensor [n_steps][n_rec]
-        (dJ/d trace).  Returns (grad_K, grad_s) per cell, unpadded layout."""
+    def _grad_buffer(self, g, ncell):
         torch = self.torch
-        ncell = sum(int(np.prod(s)) for s in self.shapes)
-        if grad_K is None:
-            grad_K = torch.zeros(ncell, dtype=torch.float32, device=self.device)
-        if grad_s is None:
-            grad_s = torch.zeros(ncell, dtype=torch.float32, device=self.device)
-        for g in (grad_K, grad_s):
-            if g.dtype != torch.float32 or not g.is_contiguous() or g.numel() != ncell or g.device != self.device:
-                raise ValueError("gradient buffers must be contiguous float32 tensors of %d cells on %s"
-                                 % (ncell, self.device))
-        adj_src = adj_src.to(device=self.device, dtype=torch.float32).contiguous()
+        if g is None:
+            return torch.zeros(ncell, dtype=torch.float32, device=self.device)
+        if g.dtype != torch.float32 or not g.is_contiguous() or g.numel() != ncell or g.device != self.device:
+            raise ValueError("gradient buffers must be contiguous float32 tensors of %d cells on %s"
+                             % (ncell, self.device))
+        return g
+
+    def _adj_source(self, adj_src, n_steps):
+        adj_src = adj_src.to(device=self.device, dtype=self.torch.float32).contiguous()
         if adj_src.numel() < min(int(n_steps), self.n_t_max) * self.n_rec:
             raise ValueError("adj_src needs [n_steps][n_rec] values")
+        return adj_src
+
+    def set_class_alpha0(self, alpha0):
+        """Power-law alpha0 per class (for dJ/dalpha0 of adjoint)."""
+        a0 = np.ascontiguousarray(np.asarray(alpha0, dtype=np.float64).reshape(-1))
+        check(lib.fw_set_class_alpha0(self._h, int(a0.size), _ptr(a0)))
+
+    def adjoint(self, n_steps, ckpt_every, work, adj_src, grad_c=None, grad_alpha0=None, with_alpha0=True,
+                stream=None):
+        """Reverse sweep; adj_src is a device float tensor [n_steps][n_rec]
+        (dJ/d trace).  Returns (dJ/dc, dJ/dalpha0) per cell, unpadded layout
+        (dJ/dalpha0 is None when with_alpha0 is False)."""
+        ncell = sum(int(np.prod(s)) for s in self.shapes)
+        grad_c = self._grad_buffer(grad_c, ncell)
+        if with_alpha0:
+            grad_alpha0 = self._grad_buffer(grad_alpha0, ncell)
+        adj_src = self._adj_source(adj_src, n_steps)
         check(lib.fw_adjoint(self._h, int(n_steps), int(ckpt_every), ctypes.c_void_p(work.data_ptr()),
                              int(work.numel()), ctypes.c_void_p(adj_src.data_ptr()),
-                             ctypes.c_void_p(grad_K.data_ptr()), ctypes.c_void_p(grad_s.data_ptr()),
+                             ctypes.c_void_p(grad_c.data_ptr()),
+                             ctypes.c_void_p(grad_alpha0.data_ptr() if with_alpha0 else None),
                              self._stream(stream)))
+        return grad_c, (grad_alpha0 if with_alpha0 else None)
+
+    def adjoint_modulus(self, n_steps, ckpt_every, work, adj_src, grad_K=None, grad_s=None, stream=None):
+        """The same sweep before the chain rule: (dJ/dK, dJ/ds) per cell."""
+        ncell = sum(int(np.prod(s)) for s in self.shapes)
+        grad_K = self._grad_buffer(grad_K, ncell)
+        grad_s = self._grad_buffer(grad_s, ncell)
+        adj_src = self._adj_source(adj_src, n_steps)
+        check(lib.fw_adjoint_modulus(self._h, int(n_steps), int(ckpt_every), ctypes.c_void_p(work.data_ptr()),
+                                     int(work.numel()), ctypes.c_void_p(adj_src.data_ptr()),
+                                     ctypes.c_void_p(grad_K.data_ptr()), ctypes.c_void_p(grad_s.data_ptr()),
+                                     self._stream(stream)))
         return grad_K, grad_s
 
     def set_option(self, key, value):

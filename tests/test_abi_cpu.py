@@ -23,7 +23,7 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(native.lib, n), n
         assert n in native.SIGNATURES, n
-    assert native.lib.fw_abi_version() == 1
+    assert native.lib.fw_abi_version() == 2
 
 
 def _create(ndim=2, shapes=((64, 48, 1),), dx=1e-4, dt=1e-8, nmech=2, pml=6, params=None):
@@ -78,6 +78,29 @@ def _media(h, cls, base, c, rho, beta, amp=0.0):
     ptrs = [ctypes.c_void_p(a.ctypes.data) for a in arrs]
     return native.lib.fw_set_media(h, ptrs[0], ptrs[1], len(arrs[2]), ptrs[2], ptrs[3], ptrs[4], amp,
                                    ctypes.c_uint64(1))
+
+
+def test_adjoint_calls_validate_without_gpu():
+    """The adjoint's entry points check their arguments and the call order on
+    the host: NULL pointers (FW_EINVAL), the class alpha0 values before the
+    media (FW_ESTATE), and a workspace request with n_steps < 1 (-1)."""
+    from paper_2606_11103_amd import native
+    lib = native.lib
+    rc, h = _create()
+    assert rc == 0
+    a0 = np.ones(2)
+    assert lib.fw_set_class_alpha0(h, 2, ctypes.c_void_p(a0.ctypes.data)) == native.FW_ESTATE
+    assert lib.fw_set_class_alpha0(h, 2, None) == native.FW_EINVAL
+    assert lib.fw_adjoint_workspace_bytes(h, 0, 10) == -1
+    nb = lib.fw_adjoint_workspace_bytes(h, 100, 10)
+    assert nb > 10 * lib.fw_state_bytes(h)
+    buf = ctypes.c_void_p(256)
+    assert lib.fw_adjoint(h, 100, 10, None, nb, buf, buf, buf, None) == native.FW_EINVAL
+    assert lib.fw_adjoint(h, 100, 10, buf, nb, buf, None, buf, None) == native.FW_EINVAL
+    assert lib.fw_adjoint_modulus(h, 100, 10, buf, nb, buf, buf, None, None) == native.FW_EINVAL
+    # dJ/dalpha0 requested before fw_set_class_alpha0
+    assert lib.fw_adjoint(h, 100, 10, buf, nb, buf, buf, buf, None) == native.FW_ESTATE
+    assert lib.fw_destroy(h) == 0
 
 
 def test_set_media_validation_without_gpu():

@@ -35,8 +35,22 @@ def _gpu_gradient(case, ckpt, obs, opts=None):
     sim.forward_checkpointed(n, ckpt, work)
     tr = sim.read_receivers_device()
     res = (case.dt * (tr.double() - torch.as_tensor(obs, device=tr.device))).float()
-    gK, gs = sim.adjoint(n, ckpt, work, res)
+    gK, gs = sim.adjoint_modulus(n, ckpt, work, res)
     return sim.read_receivers(), gK.cpu().numpy(), gs.cpu().numpy()
+
+
+def _gpu_gradient_c_alpha0(case, ckpt, obs):
+    """fw_adjoint: dJ/dc and dJ/dalpha0 per cell, chain rule in the library."""
+    import torch
+    sim = to_simulation(case)
+    sim.set_class_alpha0(case.alpha0)
+    n = case.n_steps
+    work = sim.adjoint_workspace(n, ckpt)
+    sim.forward_checkpointed(n, ckpt, work)
+    tr = sim.read_receivers_device()
+    res = (case.dt * (tr.double() - torch.as_tensor(obs, device=tr.device))).float()
+    gc, ga = sim.adjoint(n, ckpt, work, res)
+    return gc.cpu().numpy(), ga.cpu().numpy()
 
 
 def _oracle_gradient(case, obs):
@@ -69,6 +83,60 @@ def test_adjoint_gradients_match_fp64_adjoint(ndim, nmech, shapes, steps):
     report("adjoint %dD N=%d shapes=%s rel_L2 gK=%.3e gs=%.3e" % (ndim, nmech, case.shapes, rK, rs))
     assert np.abs(oK).max() > 0 and np.abs(os_).max() > 0
     assert rK <= 1e-4 and rs <= 1e-4
+
+
+@pytest.mark.parametrize("ndim,nmech,shapes,steps", [
+    (2, 4, [(64, 64, 1), (48, 72, 1)], 160), (3, 2, [(36, 30, 28), (21, 26, 33)], 120)])
+def test_speed_and_alpha0_gradients_match_fp64_adjoint(ndim, nmech, shapes, steps):
+    """fw_adjoint's dJ/dc and dJ/dalpha0 (chain rule on the device, with the
+    +-1 % speed perturbation) against the FP64 adjoint's dJ/dK and dJ/ds taken
+    through dK/dc = 2 rho c (1 + eps)^2 and ds/dalpha0 = 1/alpha0 in FP64."""
+    from oracle.solver import speed_noise
+    case = _case(ndim, nmech, seed=40 + ndim, steps=steps, shapes=shapes)
+    assert case.noise_amp > 0
+    obs = np.zeros((case.n_steps, len(case.rec_cell)))
+    gc, ga = _gpu_gradient_c_alpha0(case, 29, obs)
+    oK, os_ = _oracle_gradient(case, obs)
+    oc, oa = [], []
+    pos = 0
+    for dom, m in enumerate(case.class_maps):
+        lab = case.class_base[dom] + m.reshape(-1).astype(np.int64)
+        eps = speed_noise(lab.size, case.noise_amp, case.noise_seed)
+        sl = slice(pos, pos + lab.size)
+        oc.append(2.0 * case.rho[lab] * case.c[lab] * (1.0 + eps) ** 2 * oK[sl])
+        oa.append(os_[sl] / case.alpha0[lab])
+        pos += lab.size
+    oc, oa = np.concatenate(oc), np.concatenate(oa)
+    rc_, ra = _rel(gc, oc), _rel(ga, oa)
+    report("adjoint dJ/dc, dJ/dalpha0 %dD N=%d shapes=%s rel_L2 %.3e %.3e" % (ndim, nmech, case.shapes, rc_, ra))
+    assert np.abs(oc).max() > 0 and np.abs(oa).max() > 0
+    assert rc_ <= 1e-4 and ra <= 1e-4
+
+
+def test_adjoint_alpha0_arguments():
+    """dJ/dalpha0 needs the class alpha0 values (FW_ESTATE without them);
+    alpha0 <= 0 is rejected (FW_EINVAL); dJ/dc alone needs neither."""
+    import torch
+    from paper_2606_11103_amd.native import FW_EINVAL, FW_ESTATE, FWError
+    case = _case(2, 2, seed=3, steps=30)
+    sim = to_simulation(case)
+    work = sim.adjoint_workspace(30, 10)
+    sim.forward_checkpointed(30, 10, work)
+    res = torch.ones((30, len(case.rec_cell)), dtype=torch.float32, device="cuda")
+    with pytest.raises(FWError) as ei:
+        sim.adjoint(30, 10, work, res)
+    assert ei.value.code == FW_ESTATE
+    gc, ga = sim.adjoint(30, 10, work, res, with_alpha0=False)
+    assert ga is None and bool(torch.isfinite(gc).all()) and float(gc.abs().max()) > 0
+    bad = np.array(case.alpha0, dtype=np.float64)
+    bad[0] = 0.0
+    with pytest.raises(FWError) as ei:
+        sim.set_class_alpha0(bad)
+    assert ei.value.code == FW_EINVAL
+    sim.set_class_alpha0(case.alpha0)
+    gc2, ga2 = sim.adjoint(30, 10, work, res)
+    assert np.array_equal(gc.cpu().numpy(), gc2.cpu().numpy())
+    assert bool(torch.isfinite(ga2).all())
 
 
 def test_checkpoint_interval_does_not_change_gradients():
@@ -110,7 +178,7 @@ def test_stepping_continues_after_the_adjoint():
     work = sim.adjoint_workspace(n, 30)
     sim.forward_checkpointed(n, 30, work)
     res = torch.ones((case.n_steps, len(case.rec_cell)), dtype=torch.float32, device="cuda")
-    sim.adjoint(n, 30, work, res)
+    sim.adjoint_modulus(n, 30, work, res)
     assert sim.get_step() == n
     sim.step(case.n_steps - n)
     assert np.array_equal(sim.read_receivers(), full)
@@ -128,7 +196,7 @@ def test_adjoint_central_difference_on_gpu():
     case.pml_params = (1e-4, 1e6, float(case.c.max()) * 1.01)
     rng = np.random.default_rng(0)
     obs = np.zeros((case.n_steps, len(case.rec_cell)))
-    rec, gK, gs = _gpu_gradient(case, 50, obs)
+    gc, ga = _gpu_gradient_c_alpha0(case, 50, obs)
     lab = case.class_maps[0].reshape(-1)
 
     def J_of(cs):
@@ -142,21 +210,22 @@ def test_adjoint_central_difference_on_gpu():
         if not m.any():
             continue
         c0 = case.c[k]
-        adj_c = float(np.sum(2.0 * case.rho[k] * c0 * gK[m].astype(np.float64)))
+        adj_c = float(np.sum(gc[m].astype(np.float64)))
         h = 1e-3 * c0
         cp, cm = copy.deepcopy(case), copy.deepcopy(case)
         cp.c[k] += h
         cm.c[k] -= h
         fd_c = (J_of(cp) - J_of(cm)) / (2 * h)
-        adj_s = float(np.sum(gs[m].astype(np.float64)))
+        # d proportional to alpha0 within the class: alpha0 (1 +- h) scales d by 1 +- h
+        adj_a = float(np.sum(ga[m].astype(np.float64)))
         hs = 1e-2
         sp_, sm_ = copy.deepcopy(case), copy.deepcopy(case)
         sp_.d[k] *= 1 + hs
         sm_.d[k] *= 1 - hs
-        fd_s = (J_of(sp_) - J_of(sm_)) / (2 * hs)
-        report("adjoint FD class %d dJ/dc adj=%.6e fd=%.6e  dJ/ds adj=%.6e fd=%.6e" % (k, adj_c, fd_c, adj_s, fd_s))
+        fd_a = (J_of(sp_) - J_of(sm_)) / (2 * hs * case.alpha0[k])
+        report("adjoint FD class %d dJ/dc adj=%.6e fd=%.6e  dJ/dalpha0 adj=%.6e fd=%.6e" % (k, adj_c, fd_c, adj_a, fd_a))
         assert abs(adj_c - fd_c) <= 1e-2 * abs(fd_c)
-        assert abs(adj_s - fd_s) <= 2e-2 * abs(fd_s) + 1e-3 * abs(adj_c * c0)
+        assert abs(adj_a - fd_a) <= 2e-2 * abs(fd_a) + 1e-3 * abs(adj_c * c0) / case.alpha0[k]
 
 
 def test_autograd_function_gradients():
@@ -215,15 +284,18 @@ def test_adjoint_error_returns():
     res = torch.zeros((40, len(case.rec_cell)), dtype=torch.float32, device="cuda")
     sim.forward_checkpointed(40, 20, work)
     with pytest.raises(FWError) as ei:
-        sim.adjoint(40, 20, work[:-256], res)
+        sim.adjoint_modulus(40, 20, work[:-256], res)
     assert ei.value.code == FW_ENOMEM
     with pytest.raises(FWError) as ei:
-        sim.adjoint(40, 20, work[4:], res)
+        sim.adjoint(40, 20, work[:-256], res, with_alpha0=False)
+    assert ei.value.code == FW_ENOMEM
+    with pytest.raises(FWError) as ei:
+        sim.adjoint_modulus(40, 20, work[4:], res)
     assert ei.value.code in (FW_EINVAL, FW_ENOMEM)
     big = sim.adjoint_workspace(40, 20)
     pad = torch.empty(big.numel() + 256, dtype=torch.uint8, device="cuda")
     with pytest.raises(FWError) as ei:
-        sim.adjoint(40, 20, pad[4:4 + big.numel()], res)
+        sim.adjoint_modulus(40, 20, pad[4:4 + big.numel()], res)
     assert ei.value.code == FW_EINVAL
     nl = configs.random_small(2, [(64, 64, 1)], 2, 3, seed=3, steps=40, pml=8, nonlinear=True)
     configs.with_table(nl, *configs.random_relaxation_table(103, nl.n_classes, nl.nmech))
@@ -231,5 +303,8 @@ def test_adjoint_error_returns():
     w2 = sim2.adjoint_workspace(40, 20)
     sim2.forward_checkpointed(40, 20, w2)
     with pytest.raises(FWError) as ei:
-        sim2.adjoint(40, 20, w2, res)
+        sim2.adjoint_modulus(40, 20, w2, res)
+    assert ei.value.code == FW_EUNSUPPORTED
+    with pytest.raises(FWError) as ei:
+        sim2.adjoint(40, 20, w2, res, with_alpha0=False)
     assert ei.value.code == FW_EUNSUPPORTED

@@ -111,9 +111,14 @@ def test_weight_selection_over_the_sweep(nmech):
                nr_mod[ok_mod].mean(), dp_sim[ok].mean()))
     save("weight_selection.npy" if nmech == 2 else "weight_selection_N%d.npy" % nmech,
          np.stack([case.alpha0, case.y, nr_sim, nr_mod, ok]))
+    # floors a few cells under the measured figures (N = 2: 504 of 544 within
+    # both bars, mean 1.19 %; N = 4: 507, 1.21 %), so that a regression of
+    # the fits, the batched 1D launch or the measurement shows; selection by
+    # simulation never passes fewer cells than the closed-form choice
+    floor = {2: 500, 4: 503}[nmech]
+    assert ok.sum() >= floor
     assert ok.sum() >= ok_mod.sum()
-    assert ok.sum() >= 0.7 * len(fits)
-    assert nr_sim[ok].mean() < 0.03
+    assert nr_sim[ok].mean() < 0.014
 
 
 def test_weight_selection_over_the_library():

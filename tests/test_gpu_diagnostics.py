@@ -68,3 +68,26 @@ def test_non_finite_pressure_is_reported():
     assert sim.first_nonfinite_step() == bad_rows[0]
     sim.reset()
     assert sim.first_nonfinite_step() == -1
+
+
+def test_loading_a_state_restores_the_non_finite_row():
+    """A snapshot carries the first non-finite trace row with the step
+    counter: reloading a state saved before the overflow forgets the row
+    flagged after it, and stepping on flags it again."""
+    case = configs.random_small(2, [(64, 64, 1)], 1, 2, seed=2, steps=20, nonlinear=False)
+    configs.with_table(case, *configs.random_relaxation_table(2, case.n_classes, case.nmech))
+    case.waves = case.waves.copy()
+    case.waves[0, 3] = np.float32(3e38)       # finite input that overflows p to inf
+    case.waves[0, 4] = np.float32(3e38)
+    sim = to_simulation(case)
+    sim.step(2)
+    buf = sim.save_state()
+    assert sim.first_nonfinite_step() == -1
+    sim.step(case.n_steps - 2)
+    flagged = sim.first_nonfinite_step()
+    assert flagged >= 3
+    sim.load_state(buf)
+    assert sim.get_step() == 2
+    assert sim.first_nonfinite_step() == -1
+    sim.step(case.n_steps - 2)
+    assert sim.first_nonfinite_step() == flagged
