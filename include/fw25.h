@@ -308,6 +308,21 @@ int fw_time_kernels(fw_sim *sim, int n_steps, void *hip_stream, double *avg_ms);
 int fw_energy_step(fw_sim *sim, double *out, void *hip_stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * step and diagnostics as fw_energy_step, with p^n and the partial sums kept
+ * in a fixed scratch array inside the library (one per GPU, held until the
+ * process ends) instead of buffers allocated on first use.  Calls no
+ * allocating routine.  Limits: at most 8 Mi cells in all domains together
+ * (domains padded to 64 cells) and 65536 marching tiles, else FW_EINVAL.
+ * The tile lists must already exist (building them allocates): take one
+ * fw_step or fw_energy_step first, else FW_ESTATE.  Every call on one GPU
+ * uses that GPU's single scratch array, so calls that overlap on one GPU
+ * (other host threads, other streams) race.  Synchronises the stream.
+ */
+int fw_energy_step_noalloc(fw_sim *sim, double *out, void *hip_stream);
+
+/*
  * Copy one field of one domain (cells in the domain's linear order) to dst
  * (device memory if dst_is_device, else host): FW_FIELD_P the pressure,
  * FW_FIELD_VX/VY/VZ the velocity at faces i+1/2 (stored at cell i).

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <limits>
@@ -1009,6 +1010,59 @@ extern "C" int fw_energy_step(fw_sim *sim, double *out, void *hip_stream)
     HIP_OR_FAIL(sim->d_partial.ensure((size_t)sim->n_tiles * 3 * sizeof(double)));
     return energy_step_impl(sim, out, static_cast<hipStream_t>(hip_stream), sim->d_pold.as<float>(),
                             sim->d_partial.as<double>());
+}
+
+// Scratch of the allocation-free energy step: p^n of up to kNoAllocCells
+// cells, then the partial sums of up to kNoAllocTiles tiles.  Every GPU the
+// library runs on holds its own copy until the process ends.
+constexpr int64_t kNoAllocCells = int64_t(8) << 20;
+constexpr int64_t kNoAllocTiles = int64_t(1) << 16;
+constexpr size_t kNoAllocBytes = (size_t)kNoAllocCells * sizeof(float) + (size_t)kNoAllocTiles * 3 * sizeof(double);
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of this GPU's copy of scratch, looked up once per device
+// with that device current.  The host-side name of the array is not a device
+// address and is never passed to a kernel or a copy.
+static int scratch_address(void **ptr)
+{
+    int dev = -1;
+    HIP_OR_FAIL(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(FW_EUNSUPPORTED, "device %d is beyond the %d supported", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return fail(FW_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_dev[dev] = p;
+    }
+    *ptr = g_scratch_dev[dev];
+    return FW_OK;
+}
+
+extern "C" int fw_energy_step_noalloc(fw_sim *sim, double *out, void *hip_stream)
+{
+    g_err.clear();
+    if (!sim || !out) return fail(FW_EINVAL, "NULL argument");
+    if (!sim->ws || !sim->media_set || !sim->table_set) return fail(FW_ESTATE, "set up the simulation first");
+    if (sim->tiles_dirty)
+        return fail(FW_ESTATE, "the tile lists are not built yet (building them allocates): take one fw_step or "
+                    "fw_energy_step first");
+    if (sim->total_cells > kNoAllocCells)
+        return fail(FW_EINVAL, "%lld cells (domains padded to 64 cells) exceed the allocation-free limit of %lld",
+                    (long long)sim->total_cells, (long long)kNoAllocCells);
+    if (sim->n_tiles > kNoAllocTiles)
+        return fail(FW_EINVAL, "%d tiles exceed the allocation-free limit of %lld", sim->n_tiles,
+                    (long long)kNoAllocTiles);
+    void *base = nullptr;
+    int rc = scratch_address(&base);
+    if (rc != FW_OK) return rc;
+    float *pold = static_cast<float *>(base);
+    double *partial = reinterpret_cast<double *>(static_cast<char *>(base) + (size_t)kNoAllocCells * sizeof(float));
+    return energy_step_impl(sim, out, static_cast<hipStream_t>(hip_stream), pold, partial);
 }
 
 // ------------------------------------------------------------------ adjoint --

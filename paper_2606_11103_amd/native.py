@@ -47,6 +47,7 @@ SIGNATURES = {
     "fw_time_kernels": (_I, [_P, _I, _P, _P]),
     "fw_adjoint_workspace_bytes": (_L, [_P, _I, _I]),
     "fw_energy_step": (_I, [_P, _P, _P]),
+    "fw_energy_step_noalloc": (_I, [_P, _P, _P]),
     "fw_first_nonfinite_step": (_I, [_P, _P, _P]),
     "fw_device_copy": (_I, [_P, _P, _L, _P]),
     "fw_read_field": (_I, [_P, _I, _I, _P, _I, _P]),

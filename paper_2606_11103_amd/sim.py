@@ -164,6 +164,15 @@ class Simulation:
             check(rc)
         return out
 
+    def energy_step_noalloc(self, stream=None, check_finite=True):
+        """energy_step through the allocation-free entry point (library
+        scratch of fixed size; the tile lists must exist, i.e. one step taken)."""
+        out = np.zeros((self.n_domains, 3), dtype=np.float64)
+        rc = lib.fw_energy_step_noalloc(self._h, _ptr(out), self._stream(stream))
+        if rc != native.FW_ENONFINITE or check_finite:
+            check(rc)
+        return out
+
     # ------------------------------------------------------------ adjoint --
     def adjoint_workspace(self, n_steps, ckpt_every):
         nb = int(lib.fw_adjoint_workspace_bytes(self._h, int(n_steps), int(ckpt_every)))
