@@ -1,7 +1,8 @@
 """Fill the relaxation-table cache (data/relax_tables.json) for the named
 workloads by running the FP64 calibration (relax.fit_class) on every class
 that is not cached yet.  Usage: python -m paper_2606_11103_amd.relax_cache
-[--adjoint] [--sweep] [--sweep4] [--library] [--tissues] [--procs=N]"""
+[--adjoint] [--sweep] [--sweep4] [--library] [--tissues] [--pml-reference]
+[--procs=N]"""
 import sys
 import time
 
@@ -27,6 +28,10 @@ def main():
         class _Tissues:      # muscle, fat, liver of the two-layer validation (Sec. 4)
             c, alpha0, y = [1540.0] * 3, [0.15, 0.40, 0.50], [1.0, 1.1, 1.1]
         jobs = [("tissue_layers", _Tissues, 2)]
+    if "--pml-reference" in sys.argv:
+        class _Ref:          # the fixed tissue of the homogeneous absorbing layers (Sec. 4.6)
+            c, alpha0, y = [1540.0], [0.5], [1.0]
+        jobs = [("pml_reference", _Ref, 2), ("pml_reference", _Ref, 4)]
     if "--library" in sys.argv:
         lib = configs.library_classes()
 
