@@ -9,6 +9,7 @@ import pytest
 from workloads import configs, linear_index
 from workloads.adapters import oracle_traces, to_simulation
 from reporting import report
+from parity_metrics import check_traces
 
 pytestmark = pytest.mark.gpu
 
@@ -24,9 +25,9 @@ def _parity(case, name):
     sim.step(case.n_steps)
     got = sim.read_receivers().astype(np.float64)
     ref = oracle_traces(case)
-    rel = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
-    report("edge %s rel_L2=%.3e steps=%d receivers=%d" % (name, rel, case.n_steps, len(case.rec_cell)))
-    assert np.abs(ref).max() > 0 and rel <= 1e-4
+    glob, worst, n = check_traces(got, ref)
+    report("edge %s rel_L2=%.3e worst_receiver=%.3e (%d of %d reached) steps=%d"
+           % (name, glob, worst, n, len(case.rec_cell), case.n_steps))
     return got
 
 

@@ -22,6 +22,7 @@ import pytest
 from workloads import configs
 from workloads.adapters import to_oracle_crop, to_simulation
 from reporting import report
+from parity_metrics import check_traces
 
 pytestmark = pytest.mark.gpu
 
@@ -124,15 +125,11 @@ def test_full_size_two_layer_2d_matches_stored_oracle_traces():
     tr = sim.read_receivers()[:steps].astype(np.float64)
     del sim
     ref = g["traces"].astype(np.float64)
-    rel = float(np.linalg.norm(tr - ref) / np.linalg.norm(ref))
-    reached = np.linalg.norm(ref, axis=0) > 0
-    worst = float(np.max(np.linalg.norm((tr - ref)[:, reached], axis=0) / np.linalg.norm(ref[:, reached], axis=0)))
-    assert np.all(tr[:, ~reached] == 0.0)
+    zero = np.linalg.norm(ref, axis=0) == 0
+    assert np.all(tr[:, zero] == 0.0)
+    rel, worst, n = check_traces(tr, ref)
     report("full-size 2D two-layer 2048x2048 N=4 nonlinear, %d steps x %d receivers (%d reached): rel_L2 %.3e "
-            "(worst receiver %.3e), peak |p| %.3g Pa" % (steps, tr.shape[1], int(reached.sum()), rel, worst,
-                                                         np.abs(ref).max()))
-    assert np.all(np.isfinite(tr))
-    assert rel <= 1e-4
+           "(worst receiver %.3e), peak |p| %.3g Pa" % (steps, tr.shape[1], n, rel, worst, np.abs(ref).max()))
 
 
 def test_full_size_3d_run_is_finite_and_loses_energy_after_the_source():
@@ -213,7 +210,7 @@ def test_full_size_adjoint_is_independent_of_the_checkpoint_interval():
         work = sim.adjoint_workspace(110, ck)
         sim.forward_checkpointed(110, ck, work)
         tr = sim.read_receivers_device()
-        gK, gs = sim.adjoint(110, ck, work, case.dt * tr)
+        gK, gs = sim.adjoint_modulus(110, ck, work, case.dt * tr)
         out.append((gK.cpu().numpy(), gs.cpu().numpy()))
         del work
         torch.cuda.empty_cache()
