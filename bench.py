@@ -343,6 +343,27 @@ def bench_adjoint(torch, steps=3000, ckpt=55):
             "misfit": misfit, "gradients_finite": finite}
 
 
+def bench_strength_map(torch, steps=100):
+    """The benchmark workload with a per-voxel relaxation strength map (4 bytes
+    per cell more for each update to read): Gcell-updates/s beside the plain
+    run of the same case (the map's values do not change the traffic)."""
+    from workloads.adapters import to_simulation
+    case = bench_case()
+    fill_tables(case)
+    sim = to_simulation(case)
+    sim.step(32)
+    ms_plain = _time_steps(torch, sim, steps)
+    sim.set_strength_map(torch.full((case.cells(),), 0.7, dtype=torch.float32, device="cuda"))
+    sim.step(32)                    # untimed: re-captures the step graph
+    ms_map = _time_steps(torch, sim, steps)
+    cells = case.cells()
+    return {"workload": case.name + " + strength map", "steps": steps,
+            "gcells": round(cells * steps / (ms_map / 1e3) / 1e9, 3),
+            "gcells_without_map": round(cells * steps / (ms_plain / 1e3) / 1e9, 3),
+            "ms_per_step": round(ms_map / steps, 4), "ms_per_step_without_map": round(ms_plain / steps, 4),
+            "extra_bytes_per_cell": 8}
+
+
 def copy_probe(torch, gib, reps):
     """Plain copies of a known size (gib GiB read + gib GiB written per launch):
     the library's streaming copy kernel and torch's copy_.  Used to scale the
@@ -384,7 +405,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched, adjoint, two-layer 2D and 1D sweep workloads")
-    ap.add_argument("--only", choices=("batched", "adjoint", "two_layer", "sweep", "paper_shape"), default=None,
+    ap.add_argument("--only", choices=("batched", "adjoint", "two_layer", "sweep", "paper_shape", "strength_map"),
+                    default=None,
                     help="run only one comparison workload and print its JSON (profiling)")
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--march-chunk", type=int, default=0)
@@ -411,7 +433,8 @@ def main():
     if args.only:
         torch.cuda.set_device(0)
         fn = dict(batched=bench_batched, adjoint=lambda t: bench_adjoint(t, steps=args.adjoint_steps),
-                  two_layer=bench_two_layer, sweep=bench_sweep, paper_shape=bench_paper_shape)[args.only]
+                  two_layer=bench_two_layer, sweep=bench_sweep, paper_shape=bench_paper_shape,
+                  strength_map=bench_strength_map)[args.only]
         print(json.dumps(fn(torch)), flush=True)
         return
     from paper_2606_11103_amd.native import FW_OPT_MARCH_CHUNK, FW_OPT_ROWS_PER_THREAD, FW_OPT_TILE_ROWS

@@ -124,6 +124,26 @@ int fw_set_media(fw_sim *sim, const uint8_t *h_class, const int32_t *class_base,
                  double c_noise_amp, uint64_t noise_seed);
 
 /*
+ * Per-voxel attenuation within a class (Sec. 1 and Sec. 4.5: attenuation
+ * that varies from voxel to voxel; the paper assigns relaxation parameters
+ * per pixel).  d_scale is a caller-owned device float array over all cells
+ * (unpadded layout: domains concatenated, each in its own linear order),
+ * borrowed until replaced or cleared (NULL), with values s(x) in [0, 1]:
+ * the memory-variable coefficients a of both operators of the cell become
+ * s(x) a (the relaxation times, i.e. b, stay those of the class), so the
+ * relaxation strength of the class is scaled down voxel by voxel; for
+ * relaxation strengths small against the medium's stiffness the attenuation
+ * scales the same way, alpha(x, f) ~ s(x) alpha_class(f).  The class table
+ * thus describes the most attenuating voxels of the class, and s = 1
+ * reproduces it bit for bit.  The values are checked on the device
+ * (FW_EINVAL if any is not a finite number in [0, 1]; synchronises the
+ * stream).  The strength map adds 4 bytes per cell to each update's reads.
+ * The adjoint calls return FW_EUNSUPPORTED while a map is set.
+ * Requires fw_set_media.
+ */
+int fw_set_strength_map(fw_sim *sim, const float *d_scale, void *hip_stream);
+
+/*
  * Relaxation parameters per class (Sec. 2.1, Table 2 variables), FP64 in:
  *   kappa [n_classes][2], d [n_classes][2][N], alpha [n_classes][2][N]
  *   (index 0: gradient operator nabla_1, index 1: divergence nabla_2).

@@ -144,13 +144,15 @@ class OracleSim:
     shape (nz, ny, nx); per-class arrays c, rho, beta [C] (beta = 0 is the
     linear medium, see beta_from_b_over_a); kappa [C][2],
     d and alpha [C][2][N] (index 0 for the gradient operator, 1 for the
-    divergence operator).
+    divergence operator).  a_scale (per voxel, optional) multiplies both
+    operators' recursion coefficients a of the voxel (its relaxation
+    strength; b, the relaxation times, unchanged).
     """
 
     def __init__(self, ndim, shape, dx, dt, nmech, class_map, c, rho, beta,
                  kappa, d, alpha, pml_cells=0, pml_R0=1e-4, pml_f_alpha=1e6, pml_c_ref=None,
                  noise_amp=0.0, noise_seed=0, d_scale=None, noise_index=None, axis_full=None,
-                 engine=None):
+                 engine=None, a_scale=None):
         self.engine = engine
         self.ndim = int(ndim)
         nx, ny, nz = (list(shape) + [1, 1, 1])[:3]
@@ -186,6 +188,10 @@ class OracleSim:
             dv = d[cls, i, :].T * s[None, :]
             av = alpha[cls, i, :].T
             a_, b_ = recursion_coefficients(kv, dv, av, self.dt)
+            if a_scale is not None:
+                # per-voxel relaxation strength: both operators' coefficients a
+                # of the voxel scaled by s(x), the relaxation times (b) kept
+                a_ = a_ * np.asarray(a_scale, dtype=np.float64).reshape(1, -1)
             # derivative with respect to s of a(s d), b(s d): (1/s) * [d da/dd]
             as_, bs_ = recursion_scale_derivatives(kv, dv, av, self.dt)
             self.coef["a" + nm] = np.ascontiguousarray(a_)

@@ -106,7 +106,32 @@ __global__ __launch_bounds__(256) void k_copy16(const copy_v4 *__restrict__ src,
     if (i < n) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
+// Validation of a caller's map: one grid-stride pass, one atomic per block.
+__global__ __launch_bounds__(256) void k_count_outside_unit(const float *__restrict__ x, int64_t n,
+                                                            unsigned long long *count)
+{
+    __shared__ unsigned int s_bad;
+    if (threadIdx.x == 0) s_bad = 0;
+    __syncthreads();
+    unsigned int bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const float v = x[i];
+        if (!(v >= 0.0f && v <= 1.0f)) ++bad;      // NaN fails both comparisons
+    }
+    if (bad) atomicAdd(&s_bad, bad);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_bad) atomicAdd(count, (unsigned long long)s_bad);
+}
+
 }  // namespace
+
+hipError_t launch_count_outside_unit(const float *x, int64_t n, unsigned long long *count, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>(8192, (n + 255) / 256);
+    k_count_outside_unit<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(x, n, count);
+    return hipGetLastError();
+}
 
 hipError_t launch_copy(void *dst, const void *src, int64_t bytes, hipStream_t s)
 {

@@ -77,6 +77,10 @@ struct StepArgs {
     float fd[4];               // staggered coefficients c_m / dx
     float dt;
     float noise_amp;
+    // optional per-voxel relaxation strength scale s(x) in [0, 1] (NULL: 1
+    // everywhere), unpadded layout (DomainDesc::packed_off + local index):
+    // the memory-variable coefficients a of both operators are multiplied by s
+    const float *amap;
 };
 
 // One distinct source or receiver cell: the waveform row of its source (-1:
@@ -147,6 +151,8 @@ struct AdjChainArgs {
 };
 
 hipError_t launch_copy(void *dst, const void *src, int64_t bytes, hipStream_t s);
+// *count += number of the n values that are not finite numbers in [0, 1]
+hipError_t launch_count_outside_unit(const float *x, int64_t n, unsigned long long *count, hipStream_t s);
 hipError_t launch_adjoint_chain(const AdjChainArgs &a, hipStream_t s);
 hipError_t launch_energy(int ndim, const StepArgs &a, const float *p_old, double *partial, hipStream_t s);
 // one reverse step: transpose of the pressure update (applying a pending

@@ -58,6 +58,13 @@ __device__ __forceinline__ int tile_index(const StepArgs &A, int it)
 
 __device__ __forceinline__ bool in_slab(int64_t c, int64_t n, int P) { return P > 0 && (c < P || c >= n - P); }
 
+// Relaxation strength scale of a cell (1 without a strength map).  With the
+// scale the coefficient is s * a; s = 1 reproduces a exactly.
+__device__ __forceinline__ float strength(const StepArgs &A, const DomainDesc &D, int g)
+{
+    return A.amap ? A.amap[D.packed_off + g] : 1.0f;
+}
+
 // sum_m c_m d_m with an explicit fused-multiply-add chain.  The library is
 // compiled without implicit contraction, so every instantiation (tile shape,
 // batching) performs the same rounding sequence.
@@ -318,6 +325,7 @@ __global__ __launch_bounds__(BX *BY) void k_velocity(const StepArgs A)
             const float *sr = spb + (NDIM == 3 ? row + 4 : 0) * LX + 4 + tx;
             const int g = G.col[r] + z * G.sm;
             const int L = cq[r][0];
+            const float ms = strength(A, D, g);
             float Dv[3];
             int Ln[3];
             Dv[0] = stencil4(A.fd, sr[1] - sr[0], sr[2] - sr[-1], sr[3] - sr[-2], sr[4] - sr[-3]);
@@ -350,7 +358,7 @@ __global__ __launch_bounds__(BX *BY) void k_velocity(const StepArgs A)
                 float s = s_ik[L] * Da;
 #pragma unroll
                 for (int nu = 0; nu < N; ++nu) {
-                    pc[r][a][nu] = fmaf(s_a[nu * C + L], Da, s_b[nu * C + L] * pc[r][a][nu]);
+                    pc[r][a][nu] = fmaf(ms * s_a[nu * C + L], Da, s_b[nu * C + L] * pc[r][a][nu]);
                     s += pc[r][a][nu];
                 }
                 store_stream<N>(Mo.psi1[a] + (size_t)g * N, pc[r][a]);
@@ -598,10 +606,11 @@ __global__ __launch_bounds__(BX *BY) void k_pressure(const StepArgs A)
 #pragma unroll
             for (int a = 1; a < NDIM; ++a) S += Dd[a];
             const int L = cc_[r];
+            const float ms = strength(A, D, g);
             float Tt = s_ik[L] * S;
 #pragma unroll
             for (int nu = 0; nu < N; ++nu) {
-                psc[r][nu] = fmaf(s_a[nu * C + L], S, s_b[nu * C + L] * psc[r][nu]);
+                psc[r][nu] = fmaf(ms * s_a[nu * C + L], S, s_b[nu * C + L] * psc[r][nu]);
                 Tt += psc[r][nu];
             }
             store_stream<N>(Mo.psi2 + (size_t)g * N, psc[r]);
@@ -755,7 +764,9 @@ __global__ __launch_bounds__(64 * TY) void k_velocity_plane(const StepArgs A)
             if (hli[s] >= 0) bp[hli[s]] = hoff[s] >= 0 ? M.p[zoff + hoff[s]] : 0.0f;
         if (cli >= 0) bc[cli] = coff >= 0 ? M.cls[zoff + coff] : (uint8_t)0;
         float vc[3], pc[3][N], ppc[3];
+        float ms = 1.0f;
         if (ok) {
+            ms = strength(A, D, g);
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const int c = a == 0 ? x : (a == 1 ? y : z), n = a == 0 ? nx : (a == 1 ? ny : nz);
@@ -796,7 +807,7 @@ __global__ __launch_bounds__(64 * TY) void k_velocity_plane(const StepArgs A)
             float sacc = s_ik[L] * Da;
 #pragma unroll
             for (int nu = 0; nu < N; ++nu) {
-                pc[a][nu] = fmaf(s_a[nu * C + L], Da, s_b[nu * C + L] * pc[a][nu]);
+                pc[a][nu] = fmaf(ms * s_a[nu * C + L], Da, s_b[nu * C + L] * pc[a][nu]);
                 sacc += pc[a][nu];
             }
             store_stream<N>(Mo.psi1[a] + (size_t)g * N, pc[a]);
@@ -895,7 +906,7 @@ __global__ __launch_bounds__(64 * TY) void k_pressure_planes(const StepArgs A)
     // per plane: the halo share and own v_x, v_y first (the LDS staging
     // waits for them only), then the streamed state
     struct PlaneIn {
-        float hv[HS], ox, oy, pc, psc[N], ppc[3];
+        float hv[HS], ox, oy, pc, psc[N], ppc[3], ms;
         int L;
     };
     auto load_plane = [&](int z, PlaneIn &o) {
@@ -909,6 +920,7 @@ __global__ __launch_bounds__(64 * TY) void k_pressure_planes(const StepArgs A)
         o.oy = ok ? Mo.v[1][g] : 0.0f;
         o.pc = ok ? load1_stream(M.p + g) : 0.0f;
         o.L = ok ? (int)M.cls[g] : 0;
+        o.ms = ok ? strength(A, D, g) : 1.0f;
         if (ok)
             load_stream<N>(M.psi2 + (size_t)g * N, o.psc);
         else
@@ -973,7 +985,7 @@ __global__ __launch_bounds__(64 * TY) void k_pressure_planes(const StepArgs A)
             float psn[N];
 #pragma unroll
             for (int nu = 0; nu < N; ++nu) {
-                psn[nu] = fmaf(s_a[nu * C + L], S, s_b[nu * C + L] * cur.psc[nu]);
+                psn[nu] = fmaf(cur.ms * s_a[nu * C + L], S, s_b[nu * C + L] * cur.psc[nu]);
                 Tt += psn[nu];
             }
             store_stream<N>(Mo.psi2 + (size_t)g * N, psn);

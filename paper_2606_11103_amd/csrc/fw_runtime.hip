@@ -90,6 +90,7 @@ struct fw_sim {
     int n_classes = 0;
     std::vector<double> c, rho, beta;
     double noise_amp = 0;
+    const float *amap = nullptr;         // caller's per-voxel strength scale (fw_set_strength_map), borrowed
     uint64_t noise_seed = 0;
     std::vector<double> kappa, dcoef, alpha;
     std::vector<double> alpha0;          // power-law coefficient per class (fw_set_class_alpha0)
@@ -100,7 +101,7 @@ struct fw_sim {
     std::vector<int32_t> h_src_wave;               // waveform row of each source
     int64_t n_srcrec = 0;
     DevBuf d_cadj, d_adj_cells, d_adj_off, d_adj_idx, d_chain;
-    DevBuf d_pold, d_partial;
+    DevBuf d_pold, d_partial, d_check;
     int64_t n_adj_cells = 0;
     int64_t total_packed = 0;
     int n_tiles = 0, tiles_per_xcd = 0, n_vtiles = 0, vtiles_per_xcd = 0, n_ptiles = 0, ptiles_per_xcd = 0;
@@ -372,6 +373,7 @@ fw::StepArgs step_args(const fw_sim *s)
     for (int m = 0; m < 4; ++m) a.fd[m] = (float)(kFD[m] / s->dx);
     a.dt = (float)s->dt;
     a.noise_amp = (float)s->noise_amp;
+    a.amap = s->amap;
     return a;
 }
 
@@ -1138,6 +1140,7 @@ static int adjoint_sweep(fw_sim *sim, int n_steps, int ckpt_every, void *d_work,
     if (!sim->ws || !sim->media_set || !sim->table_set) return fail(FW_ESTATE, "set up the simulation first");
     for (double b : sim->beta)
         if (b != 0.0) return fail(FW_EUNSUPPORTED, "the adjoint supports linear media only (beta = 0 in every class)");
+    if (sim->amap) return fail(FW_EUNSUPPORTED, "the adjoint does not support a relaxation strength map");
     if (sim->tiles_dirty) {
         rc = build_tiles(sim);
         if (rc != FW_OK) return rc;
@@ -1272,6 +1275,32 @@ extern "C" int fw_adjoint(fw_sim *sim, int n_steps, int ckpt_every, void *d_work
     HIP_OR_FAIL(fw::launch_adjoint_chain(C, st));
     // the host table must outlive the asynchronous upload
     HIP_OR_FAIL(hipStreamSynchronize(st));
+    return FW_OK;
+}
+
+int fw_set_strength_map(fw_sim *sim, const float *d_scale, void *hip_stream)
+{
+    g_err.clear();
+    if (!sim) return fail(FW_EINVAL, "sim is NULL");
+    if (!sim->ws || !sim->media_set) return fail(FW_ESTATE, "call fw_set_media first");
+    sim->drop_graph();            // captured steps hold the previous map pointer
+    if (!d_scale) {
+        sim->amap = nullptr;
+        return FW_OK;
+    }
+    if ((reinterpret_cast<uintptr_t>(d_scale) & 3) != 0) return fail(FW_EINVAL, "the strength map must be 4-byte aligned");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    HIP_OR_FAIL(sim->d_check.ensure(sizeof(unsigned long long)));
+    HIP_OR_FAIL(hipMemsetAsync(sim->d_check.ptr, 0, sizeof(unsigned long long), st));
+    HIP_OR_FAIL(fw::launch_count_outside_unit(d_scale, sim->total_packed, sim->d_check.as<unsigned long long>(), st));
+    unsigned long long bad = 0;
+    HIP_OR_FAIL(hipMemcpyAsync(&bad, sim->d_check.ptr, sizeof(bad), hipMemcpyDeviceToHost, st));
+    HIP_OR_FAIL(hipStreamSynchronize(st));
+    if (bad) {
+        sim->amap = nullptr;
+        return fail(FW_EINVAL, "%llu strength values are not finite numbers in [0, 1]", bad);
+    }
+    sim->amap = d_scale;
     return FW_OK;
 }
 

@@ -55,6 +55,7 @@ SIGNATURES = {
     "fw_adjoint": (_I, [_P, _I, _I, _P, _L, _P, _P, _P, _P]),
     "fw_adjoint_modulus": (_I, [_P, _I, _I, _P, _L, _P, _P, _P, _P]),
     "fw_set_class_alpha0": (_I, [_P, _I, _P]),
+    "fw_set_strength_map": (_I, [_P, _P, _P]),
 }
 
 

@@ -200,6 +200,21 @@ class Simulation:
             raise ValueError("adj_src needs [n_steps][n_rec] values")
         return adj_src
 
+    def set_strength_map(self, scale, stream=None):
+        """Per-voxel relaxation strength scale s(x) in [0, 1] (a device float
+        tensor over all cells, unpadded layout), or None to clear it.  The
+        tensor is borrowed: the Simulation keeps a reference."""
+        if scale is None:
+            self._strength = None
+            check(lib.fw_set_strength_map(self._h, None, self._stream(stream)))
+            return
+        ncell = sum(int(np.prod(s)) for s in self.shapes)
+        t = scale.to(device=self.device, dtype=self.torch.float32).contiguous()
+        if t.numel() != ncell:
+            raise ValueError("the strength map needs %d values" % ncell)
+        check(lib.fw_set_strength_map(self._h, ctypes.c_void_p(t.data_ptr()), self._stream(stream)))
+        self._strength = t
+
     def set_class_alpha0(self, alpha0):
         """Power-law alpha0 per class (for dJ/dalpha0 of adjoint)."""
         a0 = np.ascontiguousarray(np.asarray(alpha0, dtype=np.float64).reshape(-1))

@@ -79,6 +79,17 @@ def smoothed_label_field(shape_zyx, n_classes, seed, coarse=4, sigma=5.0):
     return np.ascontiguousarray(lab)
 
 
+def smooth_unit_field(shape_zyx, seed, lo=0.2, hi=1.0, sigma=3.0):
+    """Smooth random field with values in [lo, hi]: an iid N(0, 1) field,
+    Gaussian-smoothed (sigma cells), rescaled to its own min..max and mapped
+    onto [lo, hi]; float32 (the values both sides read)."""
+    from scipy.ndimage import gaussian_filter
+    rng = np.random.default_rng(seed)
+    f = gaussian_filter(rng.standard_normal(shape_zyx), sigma, mode="wrap")
+    f = (f - f.min()) / max(f.max() - f.min(), 1e-300)
+    return np.ascontiguousarray((lo + (hi - lo) * f).astype(np.float32))
+
+
 def layered_labels(shape_zyx, boundaries, axis):
     """Piecewise-constant labels along one axis: class k between
     boundaries[k-1] and boundaries[k] (cell indices)."""

@@ -20,6 +20,10 @@ def to_simulation(case, **kw):
         sim.set_sources(case.src_domain, case.src_cell, case.src_wave, case.waves)
     if len(case.rec_cell):
         sim.set_receivers(case.rec_domain, case.rec_cell, case.n_steps)
+    if case.strength is not None:
+        import torch
+        flat = np.concatenate([np.asarray(m, np.float32).reshape(-1) for m in case.strength])
+        sim.set_strength_map(torch.from_numpy(flat).to(sim.device))
     return sim
 
 
@@ -32,6 +36,8 @@ def to_oracle(case, domain=0, **kw):
     beta = beta_from_b_over_a(case.b_over_a[sl]) if case.nonlinear else np.zeros(nloc)
     pp = case.pml_params or (1e-4, 1e6, 0.0)
     cref = pp[2] if pp[2] > 0 else float(np.max(case.c))
+    if case.strength is not None and "a_scale" not in kw:
+        kw["a_scale"] = np.asarray(case.strength[domain], np.float64).reshape(-1)
     return OracleSim(case.ndim, case.shapes[domain], case.dx, case.dt, case.nmech, case.class_maps[domain],
                      case.c[sl], case.rho[sl], beta, case.kappa[sl], case.d[sl], case.alpha[sl],
                      pml_cells=case.pml_cells, pml_R0=pp[0], pml_f_alpha=pp[1], pml_c_ref=cref,

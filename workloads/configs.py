@@ -46,6 +46,7 @@ class Case:
     kappa: Optional[np.ndarray] = None  # [C][2]
     d: Optional[np.ndarray] = None      # [C][2][N]
     alpha: Optional[np.ndarray] = None  # [C][2][N]
+    strength: Optional[List[np.ndarray]] = None   # per-voxel strength scale in [0, 1] per domain (float32)
 
     @property
     def n_classes(self):
@@ -66,6 +67,14 @@ def random_relaxation_table(seed, n_classes, nmech):
     strength = 10.0 ** rng.uniform(-4.0, math.log10(3e-2), size=(n_classes, 2, nmech))
     d = strength * kappa[:, :, None] * alpha / (1.0 - strength)
     return kappa, d, alpha
+
+
+def with_strength(case, seed, lo=0.2, hi=1.0):
+    """Attach a smooth seeded per-voxel strength map to every domain of the
+    case (see workloads.smooth_unit_field)."""
+    from . import smooth_unit_field
+    case.strength = [smooth_unit_field(m.shape, seed + 31 * k, lo, hi) for k, m in enumerate(case.class_maps)]
+    return case
 
 
 def with_table(case, kappa, d, alpha):
