@@ -386,10 +386,17 @@ int fw_device_copy(void *d_dst, const void *d_src, int64_t bytes, void *hip_stre
  *                        (default) or 8.  Eight halve the y-halo reads per
  *                        cell; which is faster depends on the grid (the
  *                        autotuner times both).
+ *   FW_OPT_VEL_PLANES    planes per tile of the velocity plane kernel: 1
+ *                        (default) or 2 (more loads in flight per thread).
+ *   FW_OPT_PRS_PLANES    planes per tile of the pressure plane kernel: 2, 4
+ *                        or 8 (a longer tile re-reads the v_z window less
+ *                        often, a shorter one needs fewer registers); default
+ *                        2 with N >= 3 mechanisms, 8 with N <= 2.
  * Options change the work decomposition only, never the results.
  */
 enum { FW_OPT_GRAPH_STEPS = 1, FW_OPT_MARCH_CHUNK = 2, FW_OPT_TILE_ROWS = 3, FW_OPT_ROWS_PER_THREAD = 4,
-       FW_OPT_PERSISTENT = 5, FW_OPT_TILE_ORDER = 6, FW_OPT_PLANE_KERNELS = 7, FW_OPT_PLANE_ROWS = 8 };
+       FW_OPT_PERSISTENT = 5, FW_OPT_TILE_ORDER = 6, FW_OPT_PLANE_KERNELS = 7, FW_OPT_PLANE_ROWS = 8,
+       FW_OPT_VEL_PLANES = 9, FW_OPT_PRS_PLANES = 10 };
 int fw_set_option(fw_sim *sim, int key, int64_t value);
 
 #ifdef __cplusplus

@@ -13,12 +13,12 @@ import math
 import os
 
 from .native import (FW_OPT_MARCH_CHUNK, FW_OPT_PERSISTENT, FW_OPT_PLANE_KERNELS, FW_OPT_PLANE_ROWS,
-                     FW_OPT_ROWS_PER_THREAD, FW_OPT_TILE_ROWS)
+                     FW_OPT_PRS_PLANES, FW_OPT_ROWS_PER_THREAD, FW_OPT_TILE_ROWS, FW_OPT_VEL_PLANES)
 
 CACHE_PATH = os.path.join(os.path.expanduser("~"), ".cache", "fw25_autotune.json")
 
 DEFAULT = {"plane_kernels": -1, "plane_rows": 4, "tile_rows": 4, "rows_per_thread": 1, "march_chunk": 0,
-           "persistent": 0}
+           "persistent": 0, "vel_planes": 1, "prs_planes": 0}    # prs_planes 0: the library's default for N
 
 
 def candidates(ndim):
@@ -28,8 +28,11 @@ def candidates(ndim):
         # (with N = 1 the velocity update then marches the default shape)
         for plane in (-1, 1):
             for prow in (4, 8):
-                out.append({"plane_kernels": plane, "plane_rows": prow, "tile_rows": 4, "rows_per_thread": 1,
-                            "march_chunk": 0, "persistent": 0})
+                for vp in (1, 2):
+                    for pp in (2, 4, 8):
+                        out.append({"plane_kernels": plane, "plane_rows": prow, "tile_rows": 4,
+                                    "rows_per_thread": 1, "march_chunk": 0, "persistent": 0,
+                                    "vel_planes": vp, "prs_planes": pp})
         for rows, rpt in ((4, 1), (8, 1), (16, 1), (16, 2), (8, 2)):
             for persistent in (0, 4):
                 for chunk in (0, 24, 96):
@@ -45,6 +48,9 @@ def candidates(ndim):
 def apply(sim, cfg):
     sim.set_option(FW_OPT_PLANE_KERNELS, cfg.get("plane_kernels", -1))
     sim.set_option(FW_OPT_PLANE_ROWS, cfg.get("plane_rows", 4))
+    sim.set_option(FW_OPT_VEL_PLANES, cfg.get("vel_planes", 1))
+    pp = cfg.get("prs_planes", 0)
+    sim.set_option(FW_OPT_PRS_PLANES, pp if pp else (2 if sim.n_mech >= 3 else 8))
     # rows per thread first when shrinking to 4-row tiles is requested
     sim.set_option(FW_OPT_ROWS_PER_THREAD, 1)
     sim.set_option(FW_OPT_TILE_ROWS, cfg["tile_rows"])

@@ -49,7 +49,7 @@ struct Fields {
 // planes per tile of the 3D plane kernels (measured on 960 x 960 x 720, N = 4:
 // velocity 14.95 / 15.7 / 16.3 ms with 1 / 2 / 4 planes, pressure 7.59 /
 // 7.16 / 7.04 / 7.13 ms with 1 / 2 / 4 / 8)
-constexpr int kVelocityPlanes = 1;
+constexpr int kVelocityPlanes = 1;      // defaults; FW_OPT_VEL_PLANES / FW_OPT_PRS_PLANES pick others
 constexpr int kPressurePlanes = 4;
 
 struct StepArgs {
@@ -68,6 +68,8 @@ struct StepArgs {
     int32_t plane;             // 1: the 3D velocity update runs its plane kernel on vtiles
     int32_t plane_p;           // 1: the 3D pressure update runs its plane kernel on ptiles
     int32_t plane_rows;        // rows (4 or 8) of the plane kernels' tiles
+    int32_t vel_planes;        // planes per velocity plane-kernel tile (1 or 2)
+    int32_t prs_planes;        // planes per pressure plane-kernel tile (2, 4 or 8)
     const Tile *vtiles;        // velocity: 64 x plane_rows tiles of kVelocityPlanes planes, plane-major, XCD k owning y-band k
     int32_t n_vtiles;
     int32_t vtiles_per_xcd;

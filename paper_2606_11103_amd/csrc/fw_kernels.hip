@@ -652,7 +652,7 @@ __global__ __launch_bounds__(BX *BY) void k_pressure(const StepArgs A)
 }
 
 // ---------------------------------------------------------------------------
-// Plane velocity update (3D, 64 x TY tiles of kVelocityPlanes planes, TY = 4
+// Plane velocity update (3D, 64 x TY tiles of NP planes (1 or 2), TY = 4
 // or 8 rows, one tile per block).  Its tile list is plane-major and XCD k owns y-band k of
 // every plane, so all XCDs work on the same few planes: the window of the z
 // stencil stays in the last-level cache and is read straight from memory
@@ -662,10 +662,9 @@ __global__ __launch_bounds__(BX *BY) void k_pressure(const StepArgs A)
 // latency.  Each output is computed with the same operations, in the same
 // order, as in k_velocity, so the two give identical bits.
 // ---------------------------------------------------------------------------
-template <int N, int TY>
+template <int N, int TY, int NP, bool SMAP>
 __global__ __launch_bounds__(64 * TY) void k_velocity_plane(const StepArgs A)
 {
-    constexpr int NP = kVelocityPlanes;
     constexpr int NB = NP > 1 ? 2 : 1;      // LDS buffers
     constexpr int BX = 64, LX = BX + 8, LY = TY + 8, NT = BX * TY, CX = BX + 1;
     // halo cells the stencils read: 3 rows above and 4 below the tile over
@@ -764,9 +763,7 @@ __global__ __launch_bounds__(64 * TY) void k_velocity_plane(const StepArgs A)
             if (hli[s] >= 0) bp[hli[s]] = hoff[s] >= 0 ? M.p[zoff + hoff[s]] : 0.0f;
         if (cli >= 0) bc[cli] = coff >= 0 ? M.cls[zoff + coff] : (uint8_t)0;
         float vc[3], pc[3][N], ppc[3];
-        float ms = 1.0f;
         if (ok) {
-            ms = strength(A, D, g);
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const int c = a == 0 ? x : (a == 1 ? y : z), n = a == 0 ? nx : (a == 1 ? ny : nz);
@@ -782,6 +779,7 @@ __global__ __launch_bounds__(64 * TY) void k_velocity_plane(const StepArgs A)
         __syncthreads();
         if (!ok) continue;
         const int L = cz[j];
+        const float ms = SMAP ? A.amap[D.packed_off + g] : 1.0f;   // strength map: a separate instantiation
         const float *sr = bp + (ty + 4) * LX + 4 + tx;
         float Dv[3];
         int Ln[3];
@@ -816,7 +814,7 @@ __global__ __launch_bounds__(64 * TY) void k_velocity_plane(const StepArgs A)
     }
 }
 
-// Pressure update on tiles of kPressurePlanes consecutive planes (3D, 64 x TY
+// Pressure update on tiles of NP consecutive planes (2, 4 or 8; 3D, 64 x TY
 // with TY = 4 or 8 rows, one tile per block), from a list in which XCD k owns y-band k of every
 // group of planes.  The v_z window of the group (its planes - 4 .. + 3 past
 // the last) is loaded once into registers; each plane loads the x-halo of
@@ -826,10 +824,9 @@ __global__ __launch_bounds__(64 * TY) void k_velocity_plane(const StepArgs A)
 // of the next plane, issued right after it, stay in flight while the
 // current plane is computed.  Same operations in the same order as
 // k_pressure.
-template <int N, int TY>
+template <int N, int TY, int NP, bool SMAP>
 __global__ __launch_bounds__(64 * TY) void k_pressure_planes(const StepArgs A)
 {
-    constexpr int NP = kPressurePlanes;
     constexpr int BX = 64, LX = BX + 8, LY = TY + 8, NT = BX * TY;
     // halo cells the stencils read: x-4 .. x-1 and x+64 .. x+66 of v_x over
     // the tile's rows, y-4 .. y-1 and y+4 .. y+6 of v_y over its columns
@@ -906,7 +903,7 @@ __global__ __launch_bounds__(64 * TY) void k_pressure_planes(const StepArgs A)
     // per plane: the halo share and own v_x, v_y first (the LDS staging
     // waits for them only), then the streamed state
     struct PlaneIn {
-        float hv[HS], ox, oy, pc, psc[N], ppc[3], ms;
+        float hv[HS], ox, oy, pc, psc[N], ppc[3];
         int L;
     };
     auto load_plane = [&](int z, PlaneIn &o) {
@@ -920,7 +917,6 @@ __global__ __launch_bounds__(64 * TY) void k_pressure_planes(const StepArgs A)
         o.oy = ok ? Mo.v[1][g] : 0.0f;
         o.pc = ok ? load1_stream(M.p + g) : 0.0f;
         o.L = ok ? (int)M.cls[g] : 0;
-        o.ms = ok ? strength(A, D, g) : 1.0f;
         if (ok)
             load_stream<N>(M.psi2 + (size_t)g * N, o.psc);
         else
@@ -983,9 +979,12 @@ __global__ __launch_bounds__(64 * TY) void k_pressure_planes(const StepArgs A)
             for (int a = 1; a < 3; ++a) S += Dd[a];
             float Tt = s_ik[L] * S;
             float psn[N];
+            // strength map (a separate instantiation): read here rather than
+            // with the prefetched state
+            const float ms = SMAP ? A.amap[D.packed_off + g] : 1.0f;
 #pragma unroll
             for (int nu = 0; nu < N; ++nu) {
-                psn[nu] = fmaf(cur.ms * s_a[nu * C + L], S, s_b[nu * C + L] * cur.psc[nu]);
+                psn[nu] = fmaf(ms * s_a[nu * C + L], S, s_b[nu * C + L] * cur.psc[nu]);
                 Tt += psn[nu];
             }
             store_stream<N>(Mo.psi2 + (size_t)g * N, psn);
@@ -1056,6 +1055,47 @@ hipError_t launch_pair(bool velocity, const StepArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
+// plane kernels: tile rows (4 or 8) x planes per tile
+template <int N, bool SMAP>
+hipError_t launch_velocity_plane(const StepArgs &a, size_t lds, hipStream_t s)
+{
+    const dim3 grid(8 * a.vtiles_per_xcd);
+    if (a.plane_rows == 8) {
+        if (a.vel_planes == 2)
+            k_velocity_plane<N, 8, 2, SMAP><<<grid, dim3(64, 8), lds, s>>>(a);
+        else
+            k_velocity_plane<N, 8, 1, SMAP><<<grid, dim3(64, 8), lds, s>>>(a);
+    } else {
+        if (a.vel_planes == 2)
+            k_velocity_plane<N, 4, 2, SMAP><<<grid, dim3(64, 4), lds, s>>>(a);
+        else
+            k_velocity_plane<N, 4, 1, SMAP><<<grid, dim3(64, 4), lds, s>>>(a);
+    }
+    return hipGetLastError();
+}
+
+template <int N, bool SMAP>
+hipError_t launch_pressure_planes(const StepArgs &a, size_t lds, hipStream_t s)
+{
+    const dim3 grid(8 * a.ptiles_per_xcd);
+    if (a.plane_rows == 8) {
+        if (a.prs_planes == 8)
+            k_pressure_planes<N, 8, 8, SMAP><<<grid, dim3(64, 8), lds, s>>>(a);
+        else if (a.prs_planes == 2)
+            k_pressure_planes<N, 8, 2, SMAP><<<grid, dim3(64, 8), lds, s>>>(a);
+        else
+            k_pressure_planes<N, 8, 4, SMAP><<<grid, dim3(64, 8), lds, s>>>(a);
+    } else {
+        if (a.prs_planes == 8)
+            k_pressure_planes<N, 4, 8, SMAP><<<grid, dim3(64, 4), lds, s>>>(a);
+        else if (a.prs_planes == 2)
+            k_pressure_planes<N, 4, 2, SMAP><<<grid, dim3(64, 4), lds, s>>>(a);
+        else
+            k_pressure_planes<N, 4, 4, SMAP><<<grid, dim3(64, 4), lds, s>>>(a);
+    }
+    return hipGetLastError();
+}
+
 // 3D launch shapes: (tile rows along y, rows per thread) -> block (64, rows / rpt)
 template <int NDIM, int N>
 hipError_t launch_nd(bool velocity, int tile_rows, int rpt, const StepArgs &a, hipStream_t s)
@@ -1063,19 +1103,11 @@ hipError_t launch_nd(bool velocity, int tile_rows, int rpt, const StepArgs &a, h
     if constexpr (NDIM == 3) {
         if (velocity && a.plane) {
             const size_t lds = (size_t)a.class_cap * (2 + 2 * N) * sizeof(float);
-            if (a.plane_rows == 8)
-                k_velocity_plane<N, 8><<<dim3(8 * a.vtiles_per_xcd), dim3(64, 8), lds, s>>>(a);
-            else
-                k_velocity_plane<N, 4><<<dim3(8 * a.vtiles_per_xcd), dim3(64, 4), lds, s>>>(a);
-            return hipGetLastError();
+            return a.amap ? launch_velocity_plane<N, true>(a, lds, s) : launch_velocity_plane<N, false>(a, lds, s);
         }
         if (!velocity && a.plane_p) {
             const size_t lds = (size_t)a.class_cap * (3 + 2 * N) * sizeof(float);
-            if (a.plane_rows == 8)
-                k_pressure_planes<N, 8><<<dim3(8 * a.ptiles_per_xcd), dim3(64, 8), lds, s>>>(a);
-            else
-                k_pressure_planes<N, 4><<<dim3(8 * a.ptiles_per_xcd), dim3(64, 4), lds, s>>>(a);
-            return hipGetLastError();
+            return a.amap ? launch_pressure_planes<N, true>(a, lds, s) : launch_pressure_planes<N, false>(a, lds, s);
         }
         if (tile_rows == 4) return launch_pair<3, N, 64, 4, 1>(velocity, a, s);
         if (tile_rows == 8 && rpt == 2) return launch_pair<3, N, 64, 4, 2>(velocity, a, s);

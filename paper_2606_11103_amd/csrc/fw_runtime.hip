@@ -110,7 +110,7 @@ struct fw_sim {
     int n_t = 0, n_t_max = 0;
     // options
     int graph_steps = 16, march_chunk = 0, tile_rows = 4, rows_per_thread = 1, persistent = 0, tile_order = 0,
-        plane_kernels = -1, plane_rows = 4;
+        plane_kernels = -1, plane_rows = 4, vel_planes = fw::kVelocityPlanes, prs_planes = fw::kPressurePlanes;
     // stepping
     int64_t host_step = 0;
     hipStream_t cap_stream = nullptr;
@@ -331,8 +331,8 @@ int build_tiles(fw_sim *s)
     // plane-kernel tiles (3D): 64 x plane_rows, kVelocityPlanes planes each for the
     // velocity update, kPressurePlanes for the pressure update
     std::vector<fw::Tile> vt, pt;
-    if (plane_velocity_on(s)) vt = banded_tiles(s, 64, s->plane_rows, fw::kVelocityPlanes);
-    if (plane_pressure_on(s)) pt = banded_tiles(s, 64, s->plane_rows, fw::kPressurePlanes);
+    if (plane_velocity_on(s)) vt = banded_tiles(s, 64, s->plane_rows, s->vel_planes);
+    if (plane_pressure_on(s)) pt = banded_tiles(s, 64, s->plane_rows, s->prs_planes);
     rc = upload_tiles(vt, s->d_vtiles, &s->n_vtiles, &s->vtiles_per_xcd);
     if (rc != FW_OK) return rc;
     rc = upload_tiles(pt, s->d_ptiles, &s->n_ptiles, &s->ptiles_per_xcd);
@@ -364,6 +364,8 @@ fw::StepArgs step_args(const fw_sim *s)
     a.plane = (plane_velocity_on(s) && s->persistent == 0 && s->n_vtiles > 0) ? 1 : 0;
     a.plane_p = (plane_pressure_on(s) && s->persistent == 0 && s->n_ptiles > 0) ? 1 : 0;
     a.plane_rows = s->plane_rows;
+    a.vel_planes = s->vel_planes;
+    a.prs_planes = s->prs_planes;
     a.vtiles = s->d_vtiles.as<fw::Tile>();
     a.n_vtiles = s->n_vtiles;
     a.vtiles_per_xcd = s->vtiles_per_xcd;
@@ -458,6 +460,11 @@ int fw_create_grid(fw_sim **out, int ndim, int n_domains, const int64_t *shape, 
     s->ndim = ndim;
     s->n_domains = n_domains;
     s->nmech = n_mech;
+    // pressure plane-kernel tile depth by mechanism count (measured on
+    // 960 x 960 x 720: N = 4, 6.77 / 6.97 / 7.05 ms with 2 / 4 / 8 planes, the
+    // 2-plane kernel fitting 8 waves per SIMD; N = 2, 5.54 / 5.78 / 5.65 ms
+    // and 3.13 / 3.14 / 3.17 ms on 499 x 499 x 1247 with 8 / 4 / 2)
+    s->prs_planes = n_mech >= 3 ? 2 : 8;
     s->pml = pml_cells;
     s->dx = dx;
     s->dt = dt;
@@ -1376,6 +1383,17 @@ int fw_set_option(fw_sim *sim, int key, int64_t value)
     case FW_OPT_PLANE_ROWS:
         if (value != 4 && value != 8) return fail(FW_EINVAL, "plane-kernel tile rows must be 4 or 8");
         sim->plane_rows = (int)value;
+        sim->tiles_dirty = true;
+        return FW_OK;
+    case FW_OPT_VEL_PLANES:
+        if (value != 1 && value != 2) return fail(FW_EINVAL, "velocity plane-kernel tiles hold 1 or 2 planes");
+        sim->vel_planes = (int)value;
+        sim->tiles_dirty = true;
+        return FW_OK;
+    case FW_OPT_PRS_PLANES:
+        if (value != 2 && value != 4 && value != 8)
+            return fail(FW_EINVAL, "pressure plane-kernel tiles hold 2, 4 or 8 planes");
+        sim->prs_planes = (int)value;
         sim->tiles_dirty = true;
         return FW_OK;
     case FW_OPT_ROWS_PER_THREAD:
