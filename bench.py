@@ -368,6 +368,28 @@ def bench_strength_map(torch, steps=100):
             "extra_bytes_per_cell": 8}
 
 
+def stream_probe(torch, reps=5):
+    """Memory-traffic probes on the benchmark grid (fw_stream_probe): the
+    velocity update's streams, the pressure update's, and a fused single
+    pass, each as one flat sweep and as 64 x 4 tiles marching 48 planes."""
+    from workloads.adapters import to_simulation
+    case = bench_case()
+    from workloads import configs
+    configs.with_table(case, *configs.random_relaxation_table(1, case.n_classes, case.nmech))
+    sim = to_simulation(case)
+    cells = case.cells()
+    N = case.nmech
+    per_cell = {0: 4 + 1 + 3 * 8 + 3 * 8 * N, 1: 3 * 4 + 8 + 1 + 8 * N, 2: (1 + 3 + 4 * N) * 8 + 1}
+    out = {"workload": case.name + " (state streams only, no CPML)", "reps": reps}
+    for mode, name in ((0, "velocity_streams"), (1, "pressure_streams"), (2, "fused_single_pass")):
+        for order, oname in ((0, "flat"), (1, "marching_64x4x48")):
+            ms = sim.stream_probe(mode, order, reps)
+            out["%s_%s" % (name, oname)] = {"bytes_per_cell": per_cell[mode], "ms": round(ms, 3),
+                                             "GBps": round(per_cell[mode] * cells / (ms / 1e3) / 1e9, 1)}
+            print("# probe %s %s: %.3f ms" % (name, oname, ms), file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+
+
 def copy_probe(torch, gib, reps):
     """Plain copies of a known size (gib GiB read + gib GiB written per launch):
     the library's streaming copy kernel and torch's copy_.  Used to scale the
@@ -415,6 +437,8 @@ def main():
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--march-chunk", type=int, default=0)
     ap.add_argument("--rows-per-thread", type=int, default=0)
+    ap.add_argument("--stream-probe", action="store_true",
+                    help="only run the memory-traffic probes of the step's streams (fused-schedule bound)")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="only run a plain device-to-device copy of this many GiB (HBM counter calibration)")
     ap.add_argument("--adjoint-steps", type=int, default=3000,
@@ -433,6 +457,10 @@ def main():
     import torch
     if args.copy_probe > 0:
         copy_probe(torch, args.copy_probe, max(args.steps, 1))
+        return
+    if args.stream_probe:
+        torch.cuda.set_device(0)
+        stream_probe(torch)
         return
     if args.only:
         torch.cuda.set_device(0)

@@ -352,6 +352,24 @@ enum { FW_FIELD_P = 0, FW_FIELD_VX = 1, FW_FIELD_VY = 2, FW_FIELD_VZ = 3 };
 int fw_read_field(fw_sim *sim, int field, int domain, float *dst, int dst_is_device, void *hip_stream);
 
 /*
+ * Memory-traffic probe (measurement only; Sec. 3.3's step is bound by memory
+ * bandwidth, and this measures what a schedule of it can reach): moves the
+ * per-cell state streams of one 3D domain with none of the method's
+ * arithmetic, writing every value back unchanged, reps times, and returns the
+ * average milliseconds per pass in *avg_ms.
+ *   mode 0: the velocity update's streams (p, class map, v and the 3N face
+ *           memory variables read; v and the memory variables written);
+ *   mode 1: the pressure update's (v, p, class map, N cell memory variables
+ *           read; p and the memory variables written);
+ *   mode 2: the whole state read and written once (a fused update's pass).
+ *   order 0: one flat sweep (neighbouring cells in concurrent workgroups);
+ *   order 1: 64 x 4 tiles each marching 48 planes along z.
+ * CPML variables are not moved.  Requires one 3D domain (FW_EUNSUPPORTED
+ * otherwise) and fw_set_media.  Synchronises the stream.
+ */
+int fw_stream_probe(fw_sim *sim, int mode, int order, int reps, void *hip_stream, double *avg_ms);
+
+/*
  * Streaming device-to-device copy of bytes bytes on hip_stream (used for
  * state snapshots and checkpoints).  16-byte aligned pointers and sizes use a
  * kernel with one float4 per lane, launched in pieces of at most 16 GiB;

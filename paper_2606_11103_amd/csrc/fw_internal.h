@@ -153,6 +153,10 @@ struct AdjChainArgs {
 };
 
 hipError_t launch_copy(void *dst, const void *src, int64_t bytes, hipStream_t s);
+// memory-traffic probe of one 3D domain: mode 0 velocity streams, 1 pressure
+// streams, 2 both in one pass; order 0 flat sweep, 1 64 x 4 tiles marching 48 planes
+hipError_t launch_stream_probe(int nmech, int mode, int order, const Fields &F, int64_t nx, int64_t ny, int64_t nz,
+                               hipStream_t s);
 // *count += number of the n values that are not finite numbers in [0, 1]
 hipError_t launch_count_outside_unit(const float *x, int64_t n, unsigned long long *count, hipStream_t s);
 hipError_t launch_adjoint_chain(const AdjChainArgs &a, hipStream_t s);

@@ -1285,6 +1285,35 @@ extern "C" int fw_adjoint(fw_sim *sim, int n_steps, int ckpt_every, void *d_work
     return FW_OK;
 }
 
+int fw_stream_probe(fw_sim *sim, int mode, int order, int reps, void *hip_stream, double *avg_ms)
+{
+    g_err.clear();
+    if (!sim || !avg_ms) return fail(FW_EINVAL, "NULL argument");
+    if (!sim->ws || !sim->media_set) return fail(FW_ESTATE, "set up the simulation first");
+    if (sim->ndim != 3 || sim->n_domains != 1) return fail(FW_EUNSUPPORTED, "the probe runs on one 3D domain");
+    if (mode < 0 || mode > 2 || order < 0 || order > 1 || reps < 1)
+        return fail(FW_EINVAL, "mode must be 0..2, order 0..1, reps >= 1");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const fw::Fields f = fields_of(sim);
+    const fw::DomainDesc &D = sim->doms[0];
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_OR_FAIL(hipEventCreate(&e0));
+    HIP_OR_FAIL(hipEventCreate(&e1));
+    hipError_t err = fw::launch_stream_probe(sim->nmech, mode, order, f, D.n[0], D.n[1], D.n[2], st);   // warm-up
+    if (err == hipSuccess) err = hipEventRecord(e0, st);
+    for (int r = 0; r < reps && err == hipSuccess; ++r)
+        err = fw::launch_stream_probe(sim->nmech, mode, order, f, D.n[0], D.n[1], D.n[2], st);
+    if (err == hipSuccess) err = hipEventRecord(e1, st);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float ms = 0;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return fail(FW_EHIP, "stream probe: %s", hipGetErrorString(err));
+    *avg_ms = ms / reps;
+    return FW_OK;
+}
+
 int fw_set_strength_map(fw_sim *sim, const float *d_scale, void *hip_stream)
 {
     g_err.clear();

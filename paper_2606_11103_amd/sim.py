@@ -155,6 +155,12 @@ class Simulation:
         check(lib.fw_time_kernels(self._h, int(n_steps), self._stream(stream), _ptr(out)))
         return out
 
+    def stream_probe(self, mode, order, reps=5, stream=None):
+        """Average ms of the memory-traffic probe (see fw_stream_probe)."""
+        out = np.zeros(1, dtype=np.float64)
+        check(lib.fw_stream_probe(self._h, int(mode), int(order), int(reps), self._stream(stream), _ptr(out)))
+        return float(out[0])
+
     def energy_step(self, stream=None, check_finite=True):
         """One full step that also returns, per domain, (E^{n+1/2}, max|p|,
         number of non-finite pressures) with FP64 sums."""
