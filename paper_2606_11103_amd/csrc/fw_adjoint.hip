@@ -50,9 +50,10 @@ __device__ __forceinline__ float st4(const float (&c)[4], float d1, float d2, fl
 
 struct Geo {
     int n[3];       // nx, ny, nz
-    int st[3];      // strides of x, y, z
+    int st[3];      // strides of x, y, z in the stored layout (rows D.pitch apart)
     int c[3];       // coordinates of the cell
-    int g;          // domain-local linear index
+    int g;          // domain-local stored index
+    int u;          // domain-local unpadded index (rows nx apart): gradients, speed perturbation
 };
 
 // staggered gradient (cell field -> face i+1/2 of axis a), zero beyond the grid
@@ -101,8 +102,8 @@ __device__ __forceinline__ bool column(const Tile &T, const DomainDesc &D, Geo &
     G.n[1] = (int)D.n[1];
     G.n[2] = (int)D.n[2];
     G.st[0] = 1;
-    G.st[1] = G.n[0];
-    G.st[2] = G.n[0] * G.n[1];
+    G.st[1] = D.pitch;
+    G.st[2] = D.pitch * G.n[1];
     G.c[0] = T.x0 + (int)threadIdx.x;
     G.c[1] = NDIM == 3 ? T.y0 + (int)threadIdx.y : 0;
     G.c[2] = 0;
@@ -115,7 +116,8 @@ __device__ __forceinline__ void at_plane(Geo &G, int z)
 {
     if (NDIM == 3) G.c[2] = z;
     if (NDIM == 2) G.c[1] = z;
-    G.g = (G.c[2] * G.n[1] + G.c[1]) * G.n[0] + G.c[0];
+    G.g = (G.c[2] * G.n[1] + G.c[1]) * G.st[1] + G.c[0];
+    G.u = (G.c[2] * G.n[1] + G.c[1]) * G.n[0] + G.c[0];
 }
 
 __device__ __forceinline__ bool slab(int c, int n, int P) { return P > 0 && (c < P || c >= n - P); }
@@ -133,7 +135,7 @@ struct March {
     int col, stride, n;
     __device__ __forceinline__ void init(const Geo &G)
     {
-        col = G.c[0] + (NDIM == 3 ? G.c[1] * G.n[0] : 0);
+        col = G.c[0] + (NDIM == 3 ? G.c[1] * G.st[1] : 0);
         stride = G.st[axis];
         n = G.n[axis];
     }
@@ -248,13 +250,13 @@ __global__ void k_adj_pressure(const AdjArgs A)
         for (int nu = 0; nu < N; ++nu) Tt += psn[nu];
         float K = s_K[L];
         if (A.s.noise_amp != 0.0f) {
-            const uint64_t h = splitmix64_a(D.noise_seed ^ (uint64_t)(uint32_t)g);
+            const uint64_t h = splitmix64_a(D.noise_seed ^ (uint64_t)(uint32_t)G.u);
             const float u = (float)(h >> 40) * 0x1.0p-24f;
             const float e = A.s.noise_amp * fmaf(2.0f, u, -1.0f);
             const float f1 = 1.0f + e;
             K = K * (f1 * f1);
         }
-        const int64_t pk = D.packed_off + g;
+        const int64_t pk = D.packed_off + G.u;
         const float gk0 = A.gK[pk];
         A.gK[pk] = gk0 + lp * (-dt * Tt);
         const float q = -dt * K * lp;
@@ -383,7 +385,7 @@ __global__ void k_adj_velocity(const AdjArgs A)
             Q.push(qp, pf0, z + 5);
             Q.push(ql, ld2m, z + 5);
         }
-        const int64_t pk = D.packed_off + g;
+        const int64_t pk = D.packed_off + G.u;
         const float gs0 = A.gs[pk];
         A.gs[pk] = gs0 + gsum;
     }
@@ -453,8 +455,10 @@ __global__ __launch_bounds__(256) void k_adj_chain(const AdjChainArgs A)
             hi = mid - 1;
     }
     const DomainDesc &D = A.doms[lo];
-    const int64_t g = i - D.packed_off;
-    const float2 ch = A.chain[D.class_base + A.cls[D.cell_off + g]];
+    const int64_t g = i - D.packed_off;                       // unpadded local index
+    const int64_t nx = D.n[0];
+    const int64_t stored = (g / nx) * D.pitch + g % nx;       // its place in the padded rows
+    const float2 ch = A.chain[D.class_base + A.cls[D.cell_off + stored]];
     float f2 = 1.0f;
     if (A.noise_amp != 0.0f) {
         const uint64_t h = splitmix64_a(D.noise_seed ^ (uint64_t)(uint32_t)g);

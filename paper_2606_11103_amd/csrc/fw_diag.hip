@@ -31,8 +31,8 @@ __global__ __launch_bounds__(1024) void k_energy(const StepArgs A, const float *
     if (ti >= A.n_tiles) return;
     const Tile T = A.tiles[ti];
     const DomainDesc D = A.doms[T.dom];
-    const int nx = (int)D.n[0], ny = (int)D.n[1], nz = (int)D.n[2];
-    const int st[3] = {1, nx, nx * ny};
+    const int nx = (int)D.n[0], ny = (int)D.n[1], nz = (int)D.n[2], px = D.pitch;
+    const int st[3] = {1, px, px * ny};
     const int nn[3] = {nx, ny, nz};
     const int64_t o = D.cell_off;
     const int tid = threadIdx.y * blockDim.x + threadIdx.x;
@@ -47,12 +47,13 @@ __global__ __launch_bounds__(1024) void k_energy(const StepArgs A, const float *
             int c[3] = {x, y, 0};
             if (NDIM == 3) c[2] = z;
             if (NDIM == 2) c[1] = z;
-            const int g = (c[2] * ny + c[1]) * nx + c[0];
+            const int g = (c[2] * ny + c[1]) * px + c[0];        // stored index
+            const int u = (c[2] * ny + c[1]) * nx + c[0];        // unpadded index (speed perturbation)
             const int L = A.f.cls[o + g];
             const ClassCoef &cc = A.classes[D.class_base + L];
             float K = cc.K;
             if (A.noise_amp != 0.0f) {
-                const uint64_t h = splitmix64_d(D.noise_seed ^ (uint64_t)(uint32_t)g);
+                const uint64_t h = splitmix64_d(D.noise_seed ^ (uint64_t)(uint32_t)u);
                 const float u = (float)(h >> 40) * 0x1.0p-24f;
                 const float ep = A.noise_amp * fmaf(2.0f, u, -1.0f);
                 const float f1 = 1.0f + ep;

@@ -27,7 +27,8 @@ struct DomainDesc {
     int32_t class_base;    // first global class of the domain
     int32_t n_classes;     // number of local classes
     int32_t pml_off[3];    // offset of the per-axis CPML tables [aF|bF|aC|bC] x n[a]
-    int32_t pad;
+    int32_t pitch;         // row stride in cells: nx rounded up to 32 cells (128 B) in 2D/3D, nx in 1D;
+                           // cell (x, y, z) is stored at cell_off + (z*ny + y)*pitch + x
     uint64_t noise_seed;
     int64_t packed_off;    // first cell of the domain in the unpadded (caller) layout
 };
@@ -155,8 +156,8 @@ struct AdjChainArgs {
 hipError_t launch_copy(void *dst, const void *src, int64_t bytes, hipStream_t s);
 // memory-traffic probe of one 3D domain: mode 0 velocity streams, 1 pressure
 // streams, 2 both in one pass; order 0 flat sweep, 1 64 x 4 tiles marching 48 planes
-hipError_t launch_stream_probe(int nmech, int mode, int order, const Fields &F, int64_t nx, int64_t ny, int64_t nz,
-                               hipStream_t s);
+hipError_t launch_stream_probe(int nmech, int mode, int order, const Fields &F, int64_t nx, int64_t px, int64_t ny,
+                               int64_t nz, hipStream_t s);
 // *count += number of the n values that are not finite numbers in [0, 1]
 hipError_t launch_count_outside_unit(const float *x, int64_t n, unsigned long long *count, hipStream_t s);
 hipError_t launch_adjoint_chain(const AdjChainArgs &a, hipStream_t s);

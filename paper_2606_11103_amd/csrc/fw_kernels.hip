@@ -60,9 +60,9 @@ __device__ __forceinline__ bool in_slab(int64_t c, int64_t n, int P) { return P 
 
 // Relaxation strength scale of a cell (1 without a strength map).  With the
 // scale the coefficient is s * a; s = 1 reproduces a exactly.
-__device__ __forceinline__ float strength(const StepArgs &A, const DomainDesc &D, int g)
+__device__ __forceinline__ float strength(const StepArgs &A, const DomainDesc &D, int u)
 {
-    return A.amap ? A.amap[D.packed_off + g] : 1.0f;
+    return A.amap ? A.amap[D.packed_off + u] : 1.0f;
 }
 
 // sum_m c_m d_m with an explicit fused-multiply-add chain.  The library is
@@ -103,23 +103,29 @@ __device__ __forceinline__ DomPtrs dom_ptrs(const Fields &F, const DomainDesc &D
 }
 
 // Geometry of a tile as seen by one thread (32-bit domain-local indices).
+// Stored index g = col + z * sm (rows px cells apart); the caller's unpadded
+// index u = ucol + z * usm (rows nx apart) keys the speed perturbation and
+// the strength map.
 template <int NDIM, int BX, int BY, int RY>
 struct TileGeom {
-    int nx, ny, nmarch, sm, x;
-    int yr[RY], col[RY];
+    int nx, ny, px, nmarch, sm, usm, x;
+    int yr[RY], col[RY], ucol[RY];
     bool ok[RY];
     __device__ __forceinline__ void init(const Tile &T, const DomainDesc &D)
     {
         nx = (int)D.n[0];
         ny = (int)D.n[1];
+        px = D.pitch;
         nmarch = NDIM == 3 ? (int)D.n[2] : (NDIM == 2 ? (int)D.n[1] : 1);
-        sm = NDIM == 3 ? nx * ny : nx;
+        sm = NDIM == 3 ? px * ny : px;
+        usm = NDIM == 3 ? nx * ny : nx;
         x = T.x0 + (int)threadIdx.x;
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             yr[r] = NDIM == 3 ? T.y0 + (int)threadIdx.y * RY + r : 0;
             ok[r] = x < nx && (NDIM < 3 || yr[r] < ny);
-            col[r] = (NDIM == 3 ? yr[r] * nx : 0) + x;
+            col[r] = (NDIM == 3 ? yr[r] * px : 0) + x;
+            ucol[r] = (NDIM == 3 ? yr[r] * nx : 0) + x;
         }
     }
 };
@@ -208,7 +214,7 @@ __global__ __launch_bounds__(BX *BY) void k_velocity(const StepArgs A)
         const int gy = NDIM == 3 ? T.y0 - 4 + hy : 0;
         const bool inside = gx >= 0 && gx < G.nx && (NDIM < 3 || (gy >= 0 && gy < G.ny));
         hli[s] = h < NHALO ? hy * LX + hx : -1;
-        hoff[s] = (h < NHALO && inside) ? (NDIM == 3 ? gy * G.nx : 0) + gx : -1;
+        hoff[s] = (h < NHALO && inside) ? (NDIM == 3 ? gy * G.px : 0) + gx : -1;
     }
     int coff[CS], cli[CS];
 #pragma unroll
@@ -226,7 +232,7 @@ __global__ __launch_bounds__(BX *BY) void k_velocity(const StepArgs A)
         }
         const bool inside = gx < G.nx && (NDIM < 3 || gy < G.ny);
         cli[s] = h < NCH ? li : -1;
-        coff[s] = (h < NCH && inside) ? (NDIM == 3 ? gy * G.nx : 0) + gx : -1;
+        coff[s] = (h < NCH && inside) ? (NDIM == 3 ? gy * G.px : 0) + gx : -1;
     }
 
     // registers: pressure queue, class queue, current-plane private state
@@ -325,7 +331,7 @@ __global__ __launch_bounds__(BX *BY) void k_velocity(const StepArgs A)
             const float *sr = spb + (NDIM == 3 ? row + 4 : 0) * LX + 4 + tx;
             const int g = G.col[r] + z * G.sm;
             const int L = cq[r][0];
-            const float ms = strength(A, D, g);
+            const float ms = strength(A, D, G.ucol[r] + z * G.usm);
             float Dv[3];
             int Ln[3];
             Dv[0] = stencil4(A.fd, sr[1] - sr[0], sr[2] - sr[-1], sr[3] - sr[-2], sr[4] - sr[-3]);
@@ -482,7 +488,7 @@ __global__ __launch_bounds__(BX *BY) void k_pressure(const StepArgs A)
         }
         const bool inside = gx >= 0 && gx < G.nx && (NDIM < 3 || (gy >= 0 && gy < G.ny));
         hli[s] = h < NHALO ? li : -1;
-        hoff[s] = (h < NHALO && inside) ? (NDIM == 3 ? gy * G.nx : 0) + gx : -1;
+        hoff[s] = (h < NHALO && inside) ? (NDIM == 3 ? gy * G.px : 0) + gx : -1;
     }
     auto halo_load = [&](int s, int zoff) -> float {
         if (hoff[s] < 0) return 0.0f;
@@ -606,7 +612,8 @@ __global__ __launch_bounds__(BX *BY) void k_pressure(const StepArgs A)
 #pragma unroll
             for (int a = 1; a < NDIM; ++a) S += Dd[a];
             const int L = cc_[r];
-            const float ms = strength(A, D, g);
+            const int u = G.ucol[r] + z * G.usm;
+            const float ms = strength(A, D, u);
             float Tt = s_ik[L] * S;
 #pragma unroll
             for (int nu = 0; nu < N; ++nu) {
@@ -616,7 +623,7 @@ __global__ __launch_bounds__(BX *BY) void k_pressure(const StepArgs A)
             store_stream<N>(Mo.psi2 + (size_t)g * N, psc[r]);
             float K = s_K[L];
             if (A.noise_amp != 0.0f) {
-                const uint64_t hsh = splitmix64(D.noise_seed ^ (uint64_t)(uint32_t)g);
+                const uint64_t hsh = splitmix64(D.noise_seed ^ (uint64_t)(uint32_t)u);
                 const float u = (float)(hsh >> 40) * 0x1.0p-24f;
                 const float e = A.noise_amp * fmaf(2.0f, u, -1.0f);
                 const float f1 = 1.0f + e;
@@ -695,10 +702,10 @@ __global__ __launch_bounds__(64 * TY) void k_velocity_plane(const StepArgs A)
             s_b[nu * C + c] = cc.b1[nu];
         }
     }
-    const int nx = (int)D.n[0], ny = (int)D.n[1], nz = (int)D.n[2], sm = nx * ny;
+    const int nx = (int)D.n[0], ny = (int)D.n[1], nz = (int)D.n[2], px = D.pitch, sm = px * ny;
     const int x = T.x0 + tx, y = T.y0 + ty;
     const bool ok = x < nx && y < ny;
-    const int col = y * nx + x;
+    const int col = y * px + x;
     const DomPtrs M = dom_ptrs<N>(A.f, D);
     const DomPtrs Mo = dom_ptrs<N>(A.fo, D);
     const int P = A.pml;
@@ -734,7 +741,7 @@ __global__ __launch_bounds__(64 * TY) void k_velocity_plane(const StepArgs A)
         const int gx = T.x0 - 4 + hx, gy = T.y0 - 4 + hy;
         const bool inside = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
         hli[s] = h < NHALO ? hy * LX + hx : -1;
-        hoff[s] = (h < NHALO && inside) ? gy * nx + gx : -1;
+        hoff[s] = (h < NHALO && inside) ? gy * px + gx : -1;
     }
     int coff = -1, cli = -1;
     if (tid < NCH) {
@@ -748,7 +755,7 @@ __global__ __launch_bounds__(64 * TY) void k_velocity_plane(const StepArgs A)
             gy = T.y0 + TY;
             cli = TY * CX + (tid - TY);
         }
-        coff = (gx < nx && gy < ny) ? gy * nx + gx : -1;
+        coff = (gx < nx && gy < ny) ? gy * px + gx : -1;
     }
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
@@ -779,7 +786,8 @@ __global__ __launch_bounds__(64 * TY) void k_velocity_plane(const StepArgs A)
         __syncthreads();
         if (!ok) continue;
         const int L = cz[j];
-        const float ms = SMAP ? A.amap[D.packed_off + g] : 1.0f;   // strength map: a separate instantiation
+        // strength map (a separate instantiation), keyed by the unpadded index
+        const float ms = SMAP ? A.amap[D.packed_off + (int64_t)(z * ny + y) * nx + x] : 1.0f;
         const float *sr = bp + (ty + 4) * LX + 4 + tx;
         float Dv[3];
         int Ln[3];
@@ -856,7 +864,7 @@ __global__ __launch_bounds__(64 * TY) void k_pressure_planes(const StepArgs A)
             s_b[nu * C + c] = cc.b2[nu];
         }
     }
-    const int nx = (int)D.n[0], ny = (int)D.n[1], nz = (int)D.n[2], sm = nx * ny;
+    const int nx = (int)D.n[0], ny = (int)D.n[1], nz = (int)D.n[2], px = D.pitch, sm = px * ny;
     const int x = T.x0 + tx, y = T.y0 + ty;
     const bool ok = x < nx && y < ny;
     // p and the memory variables read from A.f, the new velocity and every
@@ -864,7 +872,7 @@ __global__ __launch_bounds__(64 * TY) void k_pressure_planes(const StepArgs A)
     const DomPtrs M = dom_ptrs<N>(A.f, D);
     const DomPtrs Mo = dom_ptrs<N>(A.fo, D);
     const int P = A.pml;
-    const int col = y * nx + x;
+    const int col = y * px + x;
 
     // v_z of the group's window: planes z0 - 4 .. z0 + NP + 2, zero outside
     float vq[NP + 7];
@@ -897,7 +905,7 @@ __global__ __launch_bounds__(64 * TY) void k_pressure_planes(const StepArgs A)
         }
         const bool inside = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
         hli[s] = h < NHALO ? li : -1;
-        hoff[s] = (h < NHALO && inside) ? gy * nx + gx : -1;
+        hoff[s] = (h < NHALO && inside) ? gy * px + gx : -1;
     }
 
     // per plane: the halo share and own v_x, v_y first (the LDS staging
@@ -980,8 +988,10 @@ __global__ __launch_bounds__(64 * TY) void k_pressure_planes(const StepArgs A)
             float Tt = s_ik[L] * S;
             float psn[N];
             // strength map (a separate instantiation): read here rather than
-            // with the prefetched state
-            const float ms = SMAP ? A.amap[D.packed_off + g] : 1.0f;
+            // with the prefetched state; speed perturbation and map are keyed
+            // by the unpadded index
+            const int u = (z * ny + y) * nx + x;
+            const float ms = SMAP ? A.amap[D.packed_off + u] : 1.0f;
 #pragma unroll
             for (int nu = 0; nu < N; ++nu) {
                 psn[nu] = fmaf(ms * s_a[nu * C + L], S, s_b[nu * C + L] * cur.psc[nu]);
@@ -990,7 +1000,7 @@ __global__ __launch_bounds__(64 * TY) void k_pressure_planes(const StepArgs A)
             store_stream<N>(Mo.psi2 + (size_t)g * N, psn);
             float K = s_K[L];
             if (A.noise_amp != 0.0f) {
-                const uint64_t hsh = splitmix64(D.noise_seed ^ (uint64_t)(uint32_t)g);
+                const uint64_t hsh = splitmix64(D.noise_seed ^ (uint64_t)(uint32_t)u);
                 const float u = (float)(hsh >> 40) * 0x1.0p-24f;
                 const float e = A.noise_amp * fmaf(2.0f, u, -1.0f);
                 const float f1 = 1.0f + e;

@@ -62,7 +62,7 @@ __global__ __launch_bounds__(256) void k_probe_flat(const Fields F, int64_t n)
 // 64 x 4 tiles marching `chunk` planes; XCD k (block % 8) takes a contiguous
 // run of the tile list, x fastest, then y, then the chunk
 template <int N, int MODE>
-__global__ __launch_bounds__(256) void k_probe_march(const Fields F, int nx, int ny, int nz, int chunk,
+__global__ __launch_bounds__(256) void k_probe_march(const Fields F, int nx, int px, int ny, int nz, int chunk,
                                                      int n_tiles, int per_xcd)
 {
     const int b = blockIdx.x;
@@ -73,14 +73,15 @@ __global__ __launch_bounds__(256) void k_probe_march(const Fields F, int nx, int
     const int x = tx * 64 + (int)threadIdx.x, y = ty * 4 + (int)threadIdx.y;
     if (x >= nx || y >= ny) return;
     const int z0 = tz * chunk, z1 = min(nz, z0 + chunk);
-    for (int z = z0; z < z1; ++z) probe_cell<N, MODE>(F, ((int64_t)z * ny + y) * nx + x);
+    for (int z = z0; z < z1; ++z) probe_cell<N, MODE>(F, ((int64_t)z * ny + y) * px + x);
 }
 
 template <int N>
-hipError_t probe_n(int mode, int order, const Fields &F, int64_t nx, int64_t ny, int64_t nz, hipStream_t s)
+hipError_t probe_n(int mode, int order, const Fields &F, int64_t nx, int64_t px, int64_t ny, int64_t nz,
+                   hipStream_t s)
 {
     if (order == 0) {
-        const int64_t n = nx * ny * nz;
+        const int64_t n = px * ny * nz;          // every stored cell, row padding included
         const dim3 grid((unsigned)((n + 255) / 256));
         if (mode == 0) k_probe_flat<N, 0><<<grid, dim3(256), 0, s>>>(F, n);
         if (mode == 1) k_probe_flat<N, 1><<<grid, dim3(256), 0, s>>>(F, n);
@@ -90,24 +91,24 @@ hipError_t probe_n(int mode, int order, const Fields &F, int64_t nx, int64_t ny,
         const int64_t tiles = ((nx + 63) / 64) * ((ny + 3) / 4) * ((nz + chunk - 1) / chunk);
         const int per_xcd = (int)((tiles + 7) / 8);
         const dim3 grid((unsigned)(8 * per_xcd)), block(64, 4);
-        if (mode == 0) k_probe_march<N, 0><<<grid, block, 0, s>>>(F, (int)nx, (int)ny, (int)nz, chunk, (int)tiles, per_xcd);
-        if (mode == 1) k_probe_march<N, 1><<<grid, block, 0, s>>>(F, (int)nx, (int)ny, (int)nz, chunk, (int)tiles, per_xcd);
-        if (mode == 2) k_probe_march<N, 2><<<grid, block, 0, s>>>(F, (int)nx, (int)ny, (int)nz, chunk, (int)tiles, per_xcd);
+        if (mode == 0) k_probe_march<N, 0><<<grid, block, 0, s>>>(F, (int)nx, (int)px, (int)ny, (int)nz, chunk, (int)tiles, per_xcd);
+        if (mode == 1) k_probe_march<N, 1><<<grid, block, 0, s>>>(F, (int)nx, (int)px, (int)ny, (int)nz, chunk, (int)tiles, per_xcd);
+        if (mode == 2) k_probe_march<N, 2><<<grid, block, 0, s>>>(F, (int)nx, (int)px, (int)ny, (int)nz, chunk, (int)tiles, per_xcd);
     }
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_stream_probe(int nmech, int mode, int order, const Fields &F, int64_t nx, int64_t ny, int64_t nz,
-                               hipStream_t s)
+hipError_t launch_stream_probe(int nmech, int mode, int order, const Fields &F, int64_t nx, int64_t px, int64_t ny,
+                               int64_t nz, hipStream_t s)
 {
     if (mode < 0 || mode > 2 || order < 0 || order > 1) return hipErrorInvalidValue;
     switch (nmech) {
-    case 1: return probe_n<1>(mode, order, F, nx, ny, nz, s);
-    case 2: return probe_n<2>(mode, order, F, nx, ny, nz, s);
-    case 3: return probe_n<3>(mode, order, F, nx, ny, nz, s);
-    case 4: return probe_n<4>(mode, order, F, nx, ny, nz, s);
+    case 1: return probe_n<1>(mode, order, F, nx, px, ny, nz, s);
+    case 2: return probe_n<2>(mode, order, F, nx, px, ny, nz, s);
+    case 3: return probe_n<3>(mode, order, F, nx, px, ny, nz, s);
+    case 4: return probe_n<4>(mode, order, F, nx, px, ny, nz, s);
     default: return hipErrorInvalidValue;
     }
 }

