@@ -399,11 +399,14 @@ int fw_device_copy(void *d_dst, const void *d_src, int64_t bytes, void *hip_stre
  *                        last-level cache); 0 = both march the tiles set by the
  *                        options above; -1 (default) = the pressure update
  *                        always, the velocity update with N >= 2 mechanisms.
- *                        Not used with a persistent grid.
- *   FW_OPT_PLANE_ROWS    rows of the plane kernels' tiles along y: 4
- *                        (default) or 8.  Eight halve the y-halo reads per
- *                        cell; which is faster depends on the grid (the
- *                        autotuner times both).
+ *                        2D: 1 or -1 (default) = both updates run on 64 x R
+ *                        tiles, one per block, with both stencils read from
+ *                        LDS; 0 = both march along y.  Not used with a
+ *                        persistent grid.
+ *   FW_OPT_PLANE_ROWS    rows R of those tiles along y: 4 (3D default) or 8
+ *                        (2D default); 16 in 2D.  More rows mean fewer y-halo
+ *                        reads per cell; which is faster depends on the grid
+ *                        (the autotuner times them).
  *   FW_OPT_VEL_PLANES    planes per tile of the velocity plane kernel: 1
  *                        (default) or 2 (more loads in flight per thread).
  *   FW_OPT_PRS_PLANES    planes per tile of the pressure plane kernel: 2, 4

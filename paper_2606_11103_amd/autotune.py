@@ -1,6 +1,6 @@
 """Launch-shape autotuner for a Simulation.
 
-Every option it touches (3D plane kernels and their tile rows, tile rows, rows per thread,
+Every option it touches (3D plane kernels and 2D tile kernels and their tile rows, tile rows, rows per thread,
 marching chunk, persistent grid) changes only the work decomposition -- results are bitwise
 identical -- so candidates are timed on the live state: the state is saved,
 each candidate runs a few steps with per-kernel HIP events, and the state is
@@ -17,6 +17,7 @@ from .native import (FW_OPT_MARCH_CHUNK, FW_OPT_PERSISTENT, FW_OPT_PLANE_KERNELS
 
 CACHE_PATH = os.path.join(os.path.expanduser("~"), ".cache", "fw25_autotune.json")
 
+# the library's defaults (3D; 2D grids default to 8-row tile kernels)
 DEFAULT = {"plane_kernels": -1, "plane_rows": 4, "tile_rows": 4, "rows_per_thread": 1, "march_chunk": 0,
            "persistent": 0, "vel_planes": 1, "prs_planes": 0}    # prs_planes 0: the library's default for N
 
@@ -39,15 +40,21 @@ def candidates(ndim):
                     out.append({"plane_kernels": 0, "tile_rows": rows, "rows_per_thread": rpt, "march_chunk": chunk,
                                 "persistent": persistent})
     else:
+        if ndim == 2:
+            # 2D tile kernels (64 x R tiles, one per block) ignore the marching shape
+            for prow in (4, 8, 16):
+                out.append({"plane_kernels": 1, "plane_rows": prow, "tile_rows": 4, "rows_per_thread": 1,
+                            "march_chunk": 0, "persistent": 0})
         for persistent in (0, 2, 4, 8):
             for chunk in ((0, 16, 32) if ndim == 2 else (0,)):
-                out.append({"tile_rows": 4, "rows_per_thread": 1, "march_chunk": chunk, "persistent": persistent})
+                out.append({"plane_kernels": 0, "tile_rows": 4, "rows_per_thread": 1, "march_chunk": chunk,
+                            "persistent": persistent})
     return out
 
 
 def apply(sim, cfg):
     sim.set_option(FW_OPT_PLANE_KERNELS, cfg.get("plane_kernels", -1))
-    sim.set_option(FW_OPT_PLANE_ROWS, cfg.get("plane_rows", 4))
+    sim.set_option(FW_OPT_PLANE_ROWS, cfg.get("plane_rows", 8 if sim.ndim == 2 else 4))
     sim.set_option(FW_OPT_VEL_PLANES, cfg.get("vel_planes", 1))
     pp = cfg.get("prs_planes", 0)
     sim.set_option(FW_OPT_PRS_PLANES, pp if pp else (2 if sim.n_mech >= 3 else 8))

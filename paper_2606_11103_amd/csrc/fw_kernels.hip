@@ -19,12 +19,14 @@
 // dispatched round-robin over the XCDs), keeping neighbouring tiles and their
 // halos in one L2.
 //
-// 3D grids use the plane kernels at the end of this file instead (by default
-// the pressure one always, the velocity one from N = 2 memory variables on):
-// short tiles (one plane for the velocity update, four for the pressure
-// update) on plane-major lists in which XCD k owns y-band k of every plane,
-// with the z stencil read from memory; they compute the same operations in
-// the same order.
+// 3D grids use the plane kernels further down instead (by default the
+// pressure one always, the velocity one from N = 2 memory variables on):
+// short tiles (one plane for the velocity update, two to eight for the
+// pressure update) on plane-major lists in which XCD k owns y-band k of every
+// plane, with the z stencil read from memory.  2D grids use the 2D tile
+// kernels by default: one 64 x R tile per block, both stencils from LDS.  All
+// of them compute the same operations in the same order as the marching
+// kernels.
 #include <algorithm>
 
 #include "fw_internal.h"
@@ -1013,6 +1015,276 @@ __global__ __launch_bounds__(64 * TY) void k_pressure_planes(const StepArgs A)
     }
 }
 
+// ---------------------------------------------------------------------------
+// 2D tile kernels: one 64 x TY tile of a 2D grid per block (TY = 4, 8 or 16
+// rows, one cell per thread), from a list in which XCD k owns y-band k of
+// every domain.  Both stencils read an LDS tile holding the halo cells they
+// use, so a thread keeps only its own cell's state: no register queue and no
+// prefetched row, which leaves room for about twice the waves per SIMD of the
+// marching kernels.  The halo rows are rows of the neighbouring tiles of the
+// same band, read again from L2.  Same operations in the same order as
+// k_velocity / k_pressure in 2D, so the results are identical.
+// ---------------------------------------------------------------------------
+template <int N, int TY, bool SMAP>
+__global__ __launch_bounds__(64 * TY) void k_velocity_tile2d(const StepArgs A)
+{
+    constexpr int BX = 64, LX = BX + 8, LY = TY + 8, NT = BX * TY, CX = BX + 1;
+    // p halo the stencils read: 3 rows above and 4 below the tile over its
+    // columns, 3 columns left and 4 right over its rows (LDS row hy holds
+    // y0 - 4 + hy, column hx holds x0 - 4 + hx; corners never read)
+    constexpr int NHALO = 7 * BX + 7 * TY;
+    constexpr int HS = (NHALO + NT - 1) / NT;
+    constexpr int NCH = TY + BX;
+    __shared__ float sp[LY * LX];
+    __shared__ uint8_t scl[(TY + 1) * CX];
+    extern __shared__ float s_dyn[];
+    const int C = A.class_cap;
+    float *s_ik = s_dyn, *s_rho = s_dyn + C, *s_a = s_dyn + 2 * C, *s_b = s_dyn + (2 + N) * C;
+    const int b = blockIdx.x;
+    const int ti = (b & 7) * A.vtiles_per_xcd + (b >> 3);
+    if (ti >= A.n_vtiles) return;
+    const Tile T = A.vtiles[ti];
+    if (T.z1 <= T.z0) return;      // padding of the banded list
+    const DomainDesc D = A.doms[T.dom];
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * BX + tx;
+    for (int c = tid; c < D.n_classes; c += NT) {
+        const ClassCoef &cc = A.classes[D.class_base + c];
+        s_ik[c] = cc.ik1;
+        s_rho[c] = cc.rho;
+#pragma unroll
+        for (int nu = 0; nu < N; ++nu) {
+            s_a[nu * C + c] = cc.a1[nu];
+            s_b[nu * C + c] = cc.b1[nu];
+        }
+    }
+    const int nx = (int)D.n[0], ny = (int)D.n[1], px = D.pitch;
+    const int x = T.x0 + tx, y = T.y0 + ty;
+    const bool ok = x < nx && y < ny;
+    const int g = y * px + x;
+    const DomPtrs M = dom_ptrs<N>(A.f, D);
+    const DomPtrs Mo = dom_ptrs<N>(A.fo, D);
+    const int P = A.pml;
+    // the tile's p and classes, and the halo
+    const float p0 = ok ? M.p[g] : 0.0f;
+    const int L0 = ok ? (int)M.cls[g] : 0;
+    float hv[HS];
+    int hli[HS];
+#pragma unroll
+    for (int s = 0; s < HS; ++s) {
+        const int h = tid + s * NT;
+        int hy = 0, hx = 0;
+        if (h < 7 * BX) {
+            const int rr = h / BX;
+            hy = rr < 3 ? rr + 1 : TY + 1 + rr;
+            hx = 4 + h - rr * BX;
+        } else {
+            const int hh = h - 7 * BX;
+            hy = 4 + hh / 7;
+            const int k = hh - (hh / 7) * 7;
+            hx = k < 3 ? k + 1 : BX + 1 + k;
+        }
+        const int gx = T.x0 - 4 + hx, gy = T.y0 - 4 + hy;
+        const bool inside = h < NHALO && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+        hli[s] = h < NHALO ? hy * LX + hx : -1;
+        hv[s] = inside ? M.p[gy * px + gx] : 0.0f;
+    }
+    int cli = -1;
+    uint8_t cv = 0;
+    if (tid < NCH) {
+        int gx, gy;
+        if (tid < TY) {
+            gx = T.x0 + BX;
+            gy = T.y0 + tid;
+            cli = tid * CX + BX;
+        } else {
+            gx = T.x0 + (tid - TY);
+            gy = T.y0 + TY;
+            cli = TY * CX + (tid - TY);
+        }
+        if (gx < nx && gy < ny) cv = M.cls[gy * px + gx];
+    }
+    // the cell's own streamed state
+    float vc[2], pc[2][N], ppc[2];
+    if (ok) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const int c = a == 0 ? x : y, n = a == 0 ? nx : ny;
+            vc[a] = load1_stream(M.v[a] + g);
+            load_stream<N>(M.psi1[a] + (size_t)g * N, pc[a]);
+            ppc[a] = in_slab(c, n, P) ? M.pP1[a][g] : 0.0f;
+        }
+    }
+    sp[(ty + 4) * LX + 4 + tx] = p0;
+    scl[ty * CX + tx] = (uint8_t)L0;
+#pragma unroll
+    for (int s = 0; s < HS; ++s)
+        if (hli[s] >= 0) sp[hli[s]] = hv[s];
+    if (cli >= 0) scl[cli] = cv;
+    __syncthreads();
+    if (!ok) return;
+    const int L = L0;
+    const float ms = SMAP ? A.amap[D.packed_off + y * nx + x] : 1.0f;
+    const float *sr = sp + (ty + 4) * LX + 4 + tx;
+    float Dv[2];
+    int Ln[2];
+    Dv[0] = stencil4(A.fd, sr[1] - sr[0], sr[2] - sr[-1], sr[3] - sr[-2], sr[4] - sr[-3]);
+    Ln[0] = (x + 1 < nx) ? scl[ty * CX + tx + 1] : L;
+    Dv[1] = stencil4(A.fd, sr[LX] - sr[0], sr[2 * LX] - sr[-LX], sr[3 * LX] - sr[-2 * LX], sr[4 * LX] - sr[-3 * LX]);
+    Ln[1] = (y + 1 < ny) ? scl[(ty + 1) * CX + tx] : L;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        float Da = Dv[a];
+        const int c = a == 0 ? x : y, n = a == 0 ? nx : ny;
+        if (in_slab(c, n, P)) {
+            const int32_t off = D.pml_off[a];
+            const float aF = A.pml_tab[off + c];
+            const float bF = A.pml_tab[off + n + c];
+            const float qv = fmaf(aF, Da, bF * ppc[a]);
+            Mo.pP1[a][g] = qv;
+            Da += qv;
+        }
+        const float m = 2.0f * A.dt / (s_rho[L] + s_rho[Ln[a]]);
+        float sacc = s_ik[L] * Da;
+#pragma unroll
+        for (int nu = 0; nu < N; ++nu) {
+            pc[a][nu] = fmaf(ms * s_a[nu * C + L], Da, s_b[nu * C + L] * pc[a][nu]);
+            sacc += pc[a][nu];
+        }
+        store_stream<N>(Mo.psi1[a] + (size_t)g * N, pc[a]);
+        store1_stream(Mo.v[a] + g, fmaf(-m, sacc, vc[a]));
+    }
+}
+
+template <int N, int TY, bool SMAP>
+__global__ __launch_bounds__(64 * TY) void k_pressure_tile2d(const StepArgs A)
+{
+    constexpr int BX = 64, LX = BX + 8, LY = TY + 8, NT = BX * TY;
+    // halo cells the stencils read: x-4 .. x-1 and x+64 .. x+66 of v_x over
+    // the tile's rows, y-4 .. y-1 and y+TY .. y+TY+2 of v_y over its columns
+    constexpr int NHALO = 7 * TY + 7 * BX;
+    constexpr int HS = (NHALO + NT - 1) / NT;
+    __shared__ float svx[TY * LX];
+    __shared__ float svy[LY * BX];
+    extern __shared__ float s_dyn[];
+    const int C = A.class_cap;
+    float *s_ik = s_dyn, *s_K = s_dyn + C, *s_tb = s_dyn + 2 * C, *s_a = s_dyn + 3 * C, *s_b = s_dyn + (3 + N) * C;
+    const int b = blockIdx.x;
+    const int ti = (b & 7) * A.ptiles_per_xcd + (b >> 3);
+    if (ti >= A.n_ptiles) return;
+    const Tile T = A.ptiles[ti];
+    if (T.z1 <= T.z0) return;      // padding of the banded list
+    const DomainDesc D = A.doms[T.dom];
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * BX + tx;
+    for (int c = tid; c < D.n_classes; c += NT) {
+        const ClassCoef &cc = A.classes[D.class_base + c];
+        s_ik[c] = cc.ik2;
+        s_K[c] = cc.K;
+        s_tb[c] = cc.twobeta;
+#pragma unroll
+        for (int nu = 0; nu < N; ++nu) {
+            s_a[nu * C + c] = cc.a2[nu];
+            s_b[nu * C + c] = cc.b2[nu];
+        }
+    }
+    const int nx = (int)D.n[0], ny = (int)D.n[1], px = D.pitch;
+    const int x = T.x0 + tx, y = T.y0 + ty;
+    const bool ok = x < nx && y < ny;
+    const int g = y * px + x;
+    // p and the memory variables read from A.f, the new velocity and every
+    // write in A.fo (the same buffers when stepping in place)
+    const DomPtrs M = dom_ptrs<N>(A.f, D);
+    const DomPtrs Mo = dom_ptrs<N>(A.fo, D);
+    const int P = A.pml;
+    const float ox = ok ? Mo.v[0][g] : 0.0f;
+    const float oy = ok ? Mo.v[1][g] : 0.0f;
+    // halo: target >= 0 an svx index, <= -2 the svy index -(li + 2), -1 none
+    float hv[HS];
+    int hli[HS];
+#pragma unroll
+    for (int s = 0; s < HS; ++s) {
+        const int h = tid + s * NT;
+        int gx, gy, li;
+        if (h < 7 * TY) {
+            const int row = h / 7, k = h - (h / 7) * 7;
+            const int hx = k < 4 ? k : BX + k;
+            gx = T.x0 - 4 + hx;
+            gy = T.y0 + row;
+            li = row * LX + hx;
+        } else {
+            const int hh = h - 7 * TY;
+            const int rr = hh / BX;
+            const int hy = rr < 4 ? rr : TY + rr;
+            const int hx = hh - rr * BX;
+            gx = T.x0 + hx;
+            gy = T.y0 - 4 + hy;
+            li = -(hy * BX + hx) - 2;
+        }
+        const bool inside = h < NHALO && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+        hli[s] = h < NHALO ? li : -1;
+        hv[s] = inside ? (li >= 0 ? Mo.v[0][gy * px + gx] : Mo.v[1][gy * px + gx]) : 0.0f;
+    }
+    // the cell's own streamed state
+    float pc = 0.0f, psc[N], ppc[2];
+    int L = 0;
+    if (ok) {
+        pc = load1_stream(M.p + g);
+        L = M.cls[g];
+        load_stream<N>(M.psi2 + (size_t)g * N, psc);
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const int c = a == 0 ? x : y, n = a == 0 ? nx : ny;
+            ppc[a] = in_slab(c, n, P) ? M.pP2[a][g] : 0.0f;
+        }
+    }
+    svx[ty * LX + 4 + tx] = ox;
+    svy[(ty + 4) * BX + tx] = oy;
+#pragma unroll
+    for (int s = 0; s < HS; ++s) {
+        if (hli[s] >= 0)
+            svx[hli[s]] = hv[s];
+        else if (hli[s] <= -2)
+            svy[-(hli[s] + 2)] = hv[s];
+    }
+    __syncthreads();
+    if (!ok) return;
+    const float *sx = svx + ty * LX + 4 + tx;
+    const float *sy = svy + (ty + 4) * BX + tx;
+    float Dd[2];
+    Dd[0] = stencil4(A.fd, sx[0] - sx[-1], sx[1] - sx[-2], sx[2] - sx[-3], sx[3] - sx[-4]);
+    Dd[1] = stencil4(A.fd, sy[0] - sy[-BX], sy[BX] - sy[-2 * BX], sy[2 * BX] - sy[-3 * BX], sy[3 * BX] - sy[-4 * BX]);
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const int c = a == 0 ? x : y, n = a == 0 ? nx : ny;
+        if (in_slab(c, n, P)) {
+            const int32_t off = D.pml_off[a];
+            const float aC = A.pml_tab[off + 2 * n + c];
+            const float bC = A.pml_tab[off + 3 * n + c];
+            const float qv = fmaf(aC, Dd[a], bC * ppc[a]);
+            Mo.pP2[a][g] = qv;
+            Dd[a] += qv;
+        }
+    }
+    const float S = Dd[0] + Dd[1];
+    float Tt = s_ik[L] * S;
+    const int u = y * nx + x;
+    const float ms = SMAP ? A.amap[D.packed_off + u] : 1.0f;
+#pragma unroll
+    for (int nu = 0; nu < N; ++nu) {
+        psc[nu] = fmaf(ms * s_a[nu * C + L], S, s_b[nu * C + L] * psc[nu]);
+        Tt += psc[nu];
+    }
+    store_stream<N>(Mo.psi2 + (size_t)g * N, psc);
+    float K = s_K[L];
+    if (A.noise_amp != 0.0f) {
+        const uint64_t hsh = splitmix64(D.noise_seed ^ (uint64_t)(uint32_t)u);
+        const float uu = (float)(hsh >> 40) * 0x1.0p-24f;
+        const float e = A.noise_amp * fmaf(2.0f, uu, -1.0f);
+        const float f1 = 1.0f + e;
+        K = K * (f1 * f1);
+    }
+    store1_stream(Mo.p + g, fmaf(-(A.dt * fmaf(s_tb[L], pc, K)), Tt, pc));
+}
+
 // Sources, receivers and the step counter.  One thread per distinct
 // source/receiver cell reads p once, adds the cell's source and records the
 // result for the cell's receivers, so the receivers see the injected value
@@ -1106,6 +1378,31 @@ hipError_t launch_pressure_planes(const StepArgs &a, size_t lds, hipStream_t s)
     return hipGetLastError();
 }
 
+// 2D tile kernels: 64 x plane_rows tiles (4, 8 or 16 rows), one per block
+template <int N, bool SMAP>
+hipError_t launch_tile2d(bool velocity, const StepArgs &a, size_t lds, hipStream_t s)
+{
+    const dim3 grid(8 * (velocity ? a.vtiles_per_xcd : a.ptiles_per_xcd));
+    const dim3 block(64, a.plane_rows);
+    if (a.plane_rows == 16) {
+        if (velocity)
+            k_velocity_tile2d<N, 16, SMAP><<<grid, block, lds, s>>>(a);
+        else
+            k_pressure_tile2d<N, 16, SMAP><<<grid, block, lds, s>>>(a);
+    } else if (a.plane_rows == 8) {
+        if (velocity)
+            k_velocity_tile2d<N, 8, SMAP><<<grid, block, lds, s>>>(a);
+        else
+            k_pressure_tile2d<N, 8, SMAP><<<grid, block, lds, s>>>(a);
+    } else {
+        if (velocity)
+            k_velocity_tile2d<N, 4, SMAP><<<grid, dim3(64, 4), lds, s>>>(a);
+        else
+            k_pressure_tile2d<N, 4, SMAP><<<grid, dim3(64, 4), lds, s>>>(a);
+    }
+    return hipGetLastError();
+}
+
 // 3D launch shapes: (tile rows along y, rows per thread) -> block (64, rows / rpt)
 template <int NDIM, int N>
 hipError_t launch_nd(bool velocity, int tile_rows, int rpt, const StepArgs &a, hipStream_t s)
@@ -1125,6 +1422,10 @@ hipError_t launch_nd(bool velocity, int tile_rows, int rpt, const StepArgs &a, h
         if (rpt == 2) return launch_pair<3, N, 64, 8, 2>(velocity, a, s);
         return launch_pair<3, N, 64, 16, 1>(velocity, a, s);
     } else if constexpr (NDIM == 2) {
+        if ((velocity && a.plane) || (!velocity && a.plane_p)) {
+            const size_t lds = (size_t)a.class_cap * (velocity ? 2 + 2 * N : 3 + 2 * N) * sizeof(float);
+            return a.amap ? launch_tile2d<N, true>(velocity, a, lds, s) : launch_tile2d<N, false>(velocity, a, lds, s);
+        }
         return launch_pair<2, N, 64, 1, 1>(velocity, a, s);
     } else {
         return launch_pair<1, N, 256, 1, 1>(velocity, a, s);

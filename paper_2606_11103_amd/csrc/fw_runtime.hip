@@ -47,6 +47,12 @@ double fd_abs_sum() { return std::fabs(kFD[0]) + std::fabs(kFD[1]) + std::fabs(k
 constexpr int64_t kAlignCells = 64;
 constexpr int64_t kRowCells = 32;        // row pitch granule of 2D/3D domains: one 128-byte line
 constexpr int64_t kAlignBytes = 256;
+// 2D grids: tile kernels (64 x plane_rows tiles, LDS halos, one tile per block)
+// rather than the marching kernels when the plane-kernel option is auto.
+// Measured per step, marching against 8-row tiles: 1.768 / 1.509 ms on 64
+// ragged shots of 384^2..1536^2 (N = 4), 0.424 / 0.340 ms on 16 x 1024^2,
+// 0.120 / 0.092 ms on 2048^2 (N = 4), 0.102 / 0.068 ms on 2048^2 (N = 2)
+constexpr bool kTile2dDefault = true;
 
 int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
@@ -272,7 +278,8 @@ static int upload_tiles(const std::vector<fw::Tile> &tiles, DevBuf &buf, int *n,
     return FW_OK;
 }
 
-// plane kernels in use for the 3D updates: option 1 for both, 0 for neither;
+// plane kernels in use for the 3D updates (2D: the tile kernels): option 1
+// for both, 0 for neither;
 // -1 (auto) picks per update from measurements on 960 x 960 x 720: the
 // pressure plane kernel wins at every N (N = 1: 4.28 against 4.97 ms), the
 // velocity plane kernel from N = 2 on (N = 2: 10.55 / 10.63 ms, N = 4: 14.96 /
@@ -280,11 +287,13 @@ static int upload_tiles(const std::vector<fw::Tile> &tiles, DevBuf &buf, int *n,
 // axis the z-window reads weigh too much)
 static bool plane_velocity_on(const fw_sim *s)
 {
+    if (s->ndim == 2) return s->plane_kernels == 1 || (s->plane_kernels < 0 && kTile2dDefault);
     return s->ndim == 3 && (s->plane_kernels == 1 || (s->plane_kernels < 0 && s->nmech >= 2));
 }
 
 static bool plane_pressure_on(const fw_sim *s)
 {
+    if (s->ndim == 2) return s->plane_kernels == 1 || (s->plane_kernels < 0 && kTile2dDefault);
     return s->ndim == 3 && s->plane_kernels != 0;
 }
 
@@ -473,6 +482,10 @@ int fw_create_grid(fw_sim **out, int ndim, int n_domains, const int64_t *shape, 
     // 2-plane kernel fitting 8 waves per SIMD; N = 2, 5.54 / 5.78 / 5.65 ms
     // and 3.13 / 3.14 / 3.17 ms on 499 x 499 x 1247 with 8 / 4 / 2)
     s->prs_planes = n_mech >= 3 ? 2 : 8;
+    // 2D tile kernels: 8-row tiles (measured against 4 / 16 rows: 0.340 /
+    // 0.351 / 0.343 ms per step on 16 shots of 1024^2 at N = 4, 0.068 / 0.071 /
+    // 0.072 ms on 2048^2 at N = 2, equal on the 64-shot ragged batch)
+    if (ndim == 2) s->plane_rows = 8;
     s->pml = pml_cells;
     s->dx = dx;
     s->dt = dt;
@@ -1426,7 +1439,8 @@ int fw_set_option(fw_sim *sim, int key, int64_t value)
         sim->tiles_dirty = true;
         return FW_OK;
     case FW_OPT_PLANE_ROWS:
-        if (value != 4 && value != 8) return fail(FW_EINVAL, "plane-kernel tile rows must be 4 or 8");
+        if (sim->ndim == 2 ? (value != 4 && value != 8 && value != 16) : (value != 4 && value != 8))
+            return fail(FW_EINVAL, "plane-kernel tile rows must be 4 or 8 (2D tile kernels: 4, 8 or 16)");
         sim->plane_rows = (int)value;
         sim->tiles_dirty = true;
         return FW_OK;

@@ -164,6 +164,25 @@ def test_adjoint_tiling_does_not_change_gradients():
         assert np.array_equal(k0, k1) and np.array_equal(s0, s1), opts
 
 
+@pytest.mark.parametrize("nmech", [1, 4])
+def test_2d_adjoint_tile_kernels_equal_marching(nmech):
+    """2D: the reverse-step tile kernels (64 x R tiles with LDS halos, the
+    default) against the marching ones on a ragged batch (widths 70, 33, 130,
+    heights not multiples of the tile heights, CPML on every side): bitwise
+    equal gradients for R = 4, 8 and 16 (a nonzero misfit, so the folded
+    divergence and every CPML transpose are exercised)."""
+    from paper_2606_11103_amd.native import FW_OPT_PLANE_KERNELS, FW_OPT_PLANE_ROWS
+    case = _case(2, nmech, seed=60 + nmech, steps=140, shapes=[(70, 37, 1), (33, 45, 1), (130, 51, 1)])
+    rng = np.random.default_rng(nmech)
+    obs = 1e3 * rng.standard_normal((case.n_steps, len(case.rec_cell)))
+    print("2D adjoint tile kernels, N=%d" % nmech, flush=True)
+    _, k0, s0 = _gpu_gradient(case, 31, obs, {FW_OPT_PLANE_KERNELS: 0})
+    assert np.abs(k0).max() > 0 and np.abs(s0).max() > 0
+    for rows in (4, 8, 16):
+        _, k1, s1 = _gpu_gradient(case, 31, obs, {FW_OPT_PLANE_KERNELS: 1, FW_OPT_PLANE_ROWS: rows})
+        assert np.array_equal(k0, k1) and np.array_equal(s0, s1), rows
+
+
 def test_stepping_continues_after_the_adjoint():
     """fw_adjoint leaves the state and the step counter of the forward run:
     steps taken after it continue the forward run bit for bit (the sources

@@ -148,6 +148,37 @@ def test_plane_kernels_on_a_ragged_3d_batch():
            % (glob, worst, n))
 
 
+@pytest.mark.parametrize("nmech", [1, 2, 3, 4])
+def test_2d_tile_kernels_on_a_ragged_batch(nmech):
+    """Five 2D domains of different shapes (widths 70, 33, 130, 64 and 65
+    cells: partial last tiles, one exactly full, one a single cell past a
+    tile; heights not multiples of any tile height) in one launch: the 2D
+    tile kernels with 4-, 8- and 16-row tiles bitwise equal to the marching
+    kernels, with and without a strength map, and to the FP64 oracle within
+    the bar."""
+    from paper_2606_11103_amd.native import FW_OPT_PLANE_KERNELS, FW_OPT_PLANE_ROWS
+    shapes = [(70, 21, 1), (33, 38, 1), (130, 97, 1), (64, 61, 1), (65, 19, 1)]
+    case = configs.random_small(2, shapes, nmech, 3, seed=50 + nmech, steps=160, pml=5)
+    case = configs.with_table(case, *configs.random_relaxation_table(150 + nmech, case.n_classes, case.nmech))
+    print("2D tile kernels, N=%d" % nmech, flush=True)
+    _, march = _run(case, opts={FW_OPT_PLANE_KERNELS: 0})
+    for rows in (4, 8, 16):
+        _, tile = _run(case, opts={FW_OPT_PLANE_KERNELS: 1, FW_OPT_PLANE_ROWS: rows})
+        assert np.array_equal(march, tile), rows
+    _, auto = _run(case)
+    assert np.array_equal(march, auto)
+    ref = oracle_traces(case)
+    glob, worst, n = check_traces(tile, ref)
+    report("2D tile kernels, ragged 2D batch of 5, N=%d: rel L2 vs FP64 oracle = %.3e, worst receiver %.3e "
+           "(%d reached)" % (nmech, glob, worst, n))
+    if nmech == 4:
+        smap = configs.with_strength(case, 7, 0.2, 1.0)
+        _, march_s = _run(smap, opts={FW_OPT_PLANE_KERNELS: 0})
+        _, tile_s = _run(smap, opts={FW_OPT_PLANE_KERNELS: 1, FW_OPT_PLANE_ROWS: 8})
+        assert np.array_equal(march_s, tile_s)
+        assert not np.array_equal(march_s, march)
+
+
 def test_default_kernel_choice_with_one_mechanism():
     """N = 1 in 3D: by default the marching velocity kernel and the plane
     pressure kernel; bitwise equal to marching both, and to the oracle within
