@@ -184,6 +184,35 @@ def _tune(sim):
     return cfg
 
 
+def bench_batched_launch(torch, steps=200, plane_kernels=None, plane_rows=None):
+    """The 64-shot batched 2D launch alone, in the library's default launch
+    shape (or with the given tile-kernel options): graph-replayed steps, then
+    per-kernel HIP-event times, each against its algorithmic bytes (profiling
+    the batched kernels in isolation)."""
+    from paper_2606_11103_amd.native import FW_OPT_PLANE_KERNELS, FW_OPT_PLANE_ROWS
+    from workloads import configs
+    from workloads.adapters import to_simulation
+    case = configs.batched_2d(steps=steps + 32)
+    configs.with_table(case, *configs.random_relaxation_table(4000, case.n_classes, case.nmech))
+    sim = to_simulation(case)
+    if plane_kernels is not None:
+        sim.set_option(FW_OPT_PLANE_KERNELS, plane_kernels)
+    if plane_rows is not None:
+        sim.set_option(FW_OPT_PLANE_ROWS, plane_rows)
+    sim.step(32)                    # untimed: captures the step graph
+    ms = _time_steps(torch, sim, steps) / steps
+    sim.time_kernels(2)
+    kern = sim.time_kernels(20)
+    cells = case.cells()
+    vb, pb, sb = algorithmic_bytes(case)
+    frac = lambda b, t: round(b * cells / (t / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+    return {"workload": case.name, "cells": cells, "steps": steps, "ms_per_step": round(ms, 4),
+            "gcells": round(cells / ms / 1e6, 3), "bytes_per_cell": {"velocity": round(vb, 2), "pressure": round(pb, 2),
+                                                                     "step": round(sb, 2)},
+            "step_frac": frac(sb, ms), "velocity_ms": round(kern[0], 4), "velocity_frac": frac(vb, kern[0]),
+            "pressure_ms": round(kern[1], 4), "pressure_frac": frac(pb, kern[1])}
+
+
 def bench_batched(torch, steps=200):
     """64 ragged 2D shots (384^2..1536^2, N = 4, 4-layer media) advanced
     together in one tile list, vs the same shots run one at a time."""
@@ -431,9 +460,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched, adjoint, two-layer 2D and 1D sweep workloads")
-    ap.add_argument("--only", choices=("batched", "adjoint", "two_layer", "sweep", "paper_shape", "strength_map"),
+    ap.add_argument("--only", choices=("batched", "batched_launch", "adjoint", "two_layer", "sweep", "paper_shape",
+                                       "strength_map"),
                     default=None,
                     help="run only one comparison workload and print its JSON (profiling)")
+    ap.add_argument("--plane-kernels", type=int, default=None,
+                    help="--only batched_launch: FW_OPT_PLANE_KERNELS (2D: 0 marching, 1 tile kernels)")
+    ap.add_argument("--plane-rows", type=int, default=None,
+                    help="--only batched_launch: FW_OPT_PLANE_ROWS (2D tile rows: 4, 8 or 16)")
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--march-chunk", type=int, default=0)
     ap.add_argument("--rows-per-thread", type=int, default=0)
@@ -464,7 +498,10 @@ def main():
         return
     if args.only:
         torch.cuda.set_device(0)
-        fn = dict(batched=bench_batched, adjoint=lambda t: bench_adjoint(t, steps=args.adjoint_steps),
+        fn = dict(batched=bench_batched,
+                  batched_launch=lambda t: bench_batched_launch(t, steps=args.steps, plane_kernels=args.plane_kernels,
+                                                                plane_rows=args.plane_rows),
+                  adjoint=lambda t: bench_adjoint(t, steps=args.adjoint_steps),
                   two_layer=bench_two_layer, sweep=bench_sweep, paper_shape=bench_paper_shape,
                   strength_map=bench_strength_map)[args.only]
         print(json.dumps(fn(torch)), flush=True)
