@@ -37,8 +37,8 @@ TRAFFIC_MEASURED = {
     # tiles, 2 planes) + sources/receivers; FETCH_SIZE counts L2 misses sent to
     # the data fabric, so the z-window reads served by the last-level cache are
     # included: an upper bound on the HBM bytes
-    "6037ca6edd759955": {"workload": "3d_heterogeneous_960x960x720", "step_bytes": 144.81e9,
-                         "velocity_bytes": 99.24e9,
+    "85f89d8818da03cb": {"workload": "3d_heterogeneous_960x960x720", "step_bytes": 144.87e9,
+                         "velocity_bytes": 99.30e9,
                          "profile": "profiles/step_kernels_3d_960x960x720_N4.md"},
 }
 
@@ -78,10 +78,14 @@ def algorithmic_bytes(case):
     return vel, prs, step
 
 
-def bench_case(full=True):
+def bench_case(full=True, shape=None, nmech=4):
+    """The benchmark workload (3D heterogeneous recipe, 960 x 960 x 720, N = 4);
+    shape / nmech select the same recipe on another grid or mechanism count
+    (profiling runs, not the benchmark)."""
     from workloads import configs
-    shape = (960, 960, 720) if full else (192, 160, 128)
-    return configs.heterogeneous_3d(shape=shape, steps=2000)
+    if shape is None:
+        shape = (960, 960, 720) if full else (192, 160, 128)
+    return configs.heterogeneous_3d(shape=tuple(shape), steps=2000, nmech=nmech)
 
 
 def fill_tables(case, allow_fit=True):
@@ -465,9 +469,15 @@ def main():
                     default=None,
                     help="run only one comparison workload and print its JSON (profiling)")
     ap.add_argument("--plane-kernels", type=int, default=None,
-                    help="--only batched_launch: FW_OPT_PLANE_KERNELS (2D: 0 marching, 1 tile kernels)")
+                    help="FW_OPT_PLANE_KERNELS for the headline run or --only batched_launch")
     ap.add_argument("--plane-rows", type=int, default=None,
-                    help="--only batched_launch: FW_OPT_PLANE_ROWS (2D tile rows: 4, 8 or 16)")
+                    help="FW_OPT_PLANE_ROWS for the headline run or --only batched_launch")
+    ap.add_argument("--vel-planes", type=int, default=None, help="FW_OPT_VEL_PLANES for the headline run")
+    ap.add_argument("--prs-planes", type=int, default=None, help="FW_OPT_PRS_PLANES for the headline run")
+    ap.add_argument("--grid", type=int, nargs=3, default=None, metavar=("NX", "NY", "NZ"),
+                    help="the benchmark recipe on another grid (profiling; not the benchmark line)")
+    ap.add_argument("--nmech", type=int, default=4,
+                    help="the benchmark recipe with another mechanism count (profiling; not the benchmark line)")
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--march-chunk", type=int, default=0)
     ap.add_argument("--rows-per-thread", type=int, default=0)
@@ -511,7 +521,7 @@ def main():
 
     torch.cuda.set_device(0)
     t0 = time.time()
-    case = bench_case(full=not args.small)
+    case = bench_case(full=not args.small, shape=args.grid, nmech=args.nmech)
     fill_tables(case)
     print("# workload %s built in %.1f s" % (case.name, time.time() - t0), file=sys.stderr, flush=True)
     sim = to_simulation(case)
@@ -523,6 +533,12 @@ def main():
         sim.set_option(FW_OPT_ROWS_PER_THREAD, 2)
     if args.march_chunk:
         sim.set_option(FW_OPT_MARCH_CHUNK, args.march_chunk)
+    from paper_2606_11103_amd.native import (FW_OPT_PLANE_KERNELS, FW_OPT_PLANE_ROWS, FW_OPT_PRS_PLANES,
+                                             FW_OPT_VEL_PLANES)
+    for key, val in ((FW_OPT_PLANE_KERNELS, args.plane_kernels), (FW_OPT_PLANE_ROWS, args.plane_rows),
+                     (FW_OPT_VEL_PLANES, args.vel_planes), (FW_OPT_PRS_PLANES, args.prs_planes)):
+        if val is not None:
+            sim.set_option(key, val)
     print("# simulation ready (%.1f GB workspace)" % (sim.workspace.numel() / 1e9), file=sys.stderr, flush=True)
 
     stream = torch.cuda.current_stream()
@@ -561,12 +577,14 @@ def main():
     ach_step = b_step * cells / (ms_step / 1e3) / 1e9
     meas = TRAFFIC_MEASURED.get(kernel_source_hash())
     traffic = traffic_vel = None
-    if meas is not None and not args.small and meas["workload"] == case.name and not (
-            args.tile_rows or args.rows_per_thread or args.march_chunk):
+    shape_opts = (args.tile_rows or args.rows_per_thread or args.march_chunk or
+                  any(v is not None for v in (args.plane_kernels, args.plane_rows, args.vel_planes, args.prs_planes)))
+    if meas is not None and not args.small and meas["workload"] == case.name and not (args.grid or args.nmech != 4) \
+            and not shape_opts:
         traffic = round(meas["step_bytes"] / (ms_step / 1e3) / 1e9, 1)
         traffic_vel = round(meas["velocity_bytes"] / (kern_ms[0] / 1e3) / 1e9, 1)
     out = {
-        "metric": "Gcell-updates/s (3D heterogeneous, 4 mechanisms)",
+        "metric": "Gcell-updates/s (3D heterogeneous, %d mechanisms)" % case.nmech,
         "value": round(value, 4),
         "unit": "Gcell-updates/s",
         "n_gpus": 1,
@@ -578,7 +596,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": case.name if not args.small else case.name + " (reduced, not the benchmark)",
+        "config": {"workload": case.name if not (args.small or args.grid or args.nmech != 4)
+                   else case.name + " (not the benchmark)",
                    "cells": cells, "nmech": case.nmech, "pml_cells": case.pml_cells, "classes": case.n_classes,
                    "steps_of_full_run": case.n_steps, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": "whole step (velocity + pressure + sources/receivers kernels, "

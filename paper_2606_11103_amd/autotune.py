@@ -17,7 +17,8 @@ from .native import (FW_OPT_MARCH_CHUNK, FW_OPT_PERSISTENT, FW_OPT_PLANE_KERNELS
 
 CACHE_PATH = os.path.join(os.path.expanduser("~"), ".cache", "fw25_autotune.json")
 
-# the library's defaults (3D; 2D grids default to 8-row tile kernels)
+# the library's defaults (3D with N >= 3; 2D grids default to 8-row tile
+# kernels, 3D grids with N <= 2 to 8-row tiles of 2 velocity planes)
 DEFAULT = {"plane_kernels": -1, "plane_rows": 4, "tile_rows": 4, "rows_per_thread": 1, "march_chunk": 0,
            "persistent": 0, "vel_planes": 1, "prs_planes": 0}    # prs_planes 0: the library's default for N
 
@@ -29,7 +30,7 @@ def candidates(ndim):
         # (with N = 1 the velocity update then marches the default shape)
         for plane in (-1, 1):
             for prow in (4, 8):
-                for vp in (1, 2):
+                for vp in (1, 2, 4):
                     for pp in (2, 4, 8):
                         out.append({"plane_kernels": plane, "plane_rows": prow, "tile_rows": 4,
                                     "rows_per_thread": 1, "march_chunk": 0, "persistent": 0,
@@ -52,10 +53,18 @@ def candidates(ndim):
     return out
 
 
+def _default_rows_planes(sim):
+    """The library's default tile rows and velocity planes for this grid."""
+    if sim.ndim == 2:
+        return 8, 1
+    return (8, 2) if (sim.ndim == 3 and sim.n_mech <= 2) else (4, 1)
+
+
 def apply(sim, cfg):
+    rows, vp = _default_rows_planes(sim)
     sim.set_option(FW_OPT_PLANE_KERNELS, cfg.get("plane_kernels", -1))
-    sim.set_option(FW_OPT_PLANE_ROWS, cfg.get("plane_rows", 8 if sim.ndim == 2 else 4))
-    sim.set_option(FW_OPT_VEL_PLANES, cfg.get("vel_planes", 1))
+    sim.set_option(FW_OPT_PLANE_ROWS, cfg.get("plane_rows", rows))
+    sim.set_option(FW_OPT_VEL_PLANES, cfg.get("vel_planes", vp))
     pp = cfg.get("prs_planes", 0)
     sim.set_option(FW_OPT_PRS_PLANES, pp if pp else (2 if sim.n_mech >= 3 else 8))
     # rows per thread first when shrinking to 4-row tiles is requested

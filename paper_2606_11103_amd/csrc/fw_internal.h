@@ -66,15 +66,16 @@ struct StepArgs {
     int32_t pml;               // CPML width P
     int32_t class_cap;         // entries per LDS class table (>= classes of any domain)
     int32_t tile_rows;         // rows of a 3D tile along y
-    int32_t plane;             // 1: the 3D velocity update runs its plane kernel on vtiles
-    int32_t plane_p;           // 1: the 3D pressure update runs its plane kernel on ptiles
-    int32_t plane_rows;        // rows (4 or 8) of the plane kernels' tiles
-    int32_t vel_planes;        // planes per velocity plane-kernel tile (1 or 2)
+    int32_t plane;             // 1: the velocity update runs its plane kernel (2D: tile kernel) on vtiles
+    int32_t plane_p;           // 1: the pressure update runs its plane kernel (2D: tile kernel) on ptiles
+    int32_t plane_rows;        // rows of the plane kernels' tiles (3D: 4 or 8; 2D tile kernels: 4, 8 or 16)
+    int32_t vel_planes;        // planes per velocity plane-kernel tile (1, 2 or 4)
     int32_t prs_planes;        // planes per pressure plane-kernel tile (2, 4 or 8)
-    const Tile *vtiles;        // velocity: 64 x plane_rows tiles of kVelocityPlanes planes, plane-major, XCD k owning y-band k
+    const Tile *vtiles;        // velocity (2D: also the adjoint's tiles): 64 x plane_rows tiles of vel_planes planes,
+                               // plane-major, XCD k owning y-band k
     int32_t n_vtiles;
     int32_t vtiles_per_xcd;
-    const Tile *ptiles;        // pressure: 64 x 4 tiles of kPressurePlanes planes, same banding
+    const Tile *ptiles;        // pressure: 64 x plane_rows tiles of prs_planes planes, same banding
     int32_t n_ptiles;
     int32_t ptiles_per_xcd;
     float fd[4];               // staggered coefficients c_m / dx

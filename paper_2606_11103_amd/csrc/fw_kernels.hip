@@ -1343,12 +1343,16 @@ hipError_t launch_velocity_plane(const StepArgs &a, size_t lds, hipStream_t s)
 {
     const dim3 grid(8 * a.vtiles_per_xcd);
     if (a.plane_rows == 8) {
-        if (a.vel_planes == 2)
+        if (a.vel_planes == 4)
+            k_velocity_plane<N, 8, 4, SMAP><<<grid, dim3(64, 8), lds, s>>>(a);
+        else if (a.vel_planes == 2)
             k_velocity_plane<N, 8, 2, SMAP><<<grid, dim3(64, 8), lds, s>>>(a);
         else
             k_velocity_plane<N, 8, 1, SMAP><<<grid, dim3(64, 8), lds, s>>>(a);
     } else {
-        if (a.vel_planes == 2)
+        if (a.vel_planes == 4)
+            k_velocity_plane<N, 4, 4, SMAP><<<grid, dim3(64, 4), lds, s>>>(a);
+        else if (a.vel_planes == 2)
             k_velocity_plane<N, 4, 2, SMAP><<<grid, dim3(64, 4), lds, s>>>(a);
         else
             k_velocity_plane<N, 4, 1, SMAP><<<grid, dim3(64, 4), lds, s>>>(a);

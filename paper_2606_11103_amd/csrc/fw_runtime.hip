@@ -345,8 +345,8 @@ int build_tiles(fw_sim *s)
     if (rc != FW_OK) return rc;
     s->h_tile_dom.resize(tiles.size());
     for (size_t t = 0; t < tiles.size(); ++t) s->h_tile_dom[t] = tiles[t].dom;
-    // plane-kernel tiles (3D): 64 x plane_rows, kVelocityPlanes planes each for the
-    // velocity update, kPressurePlanes for the pressure update
+    // plane-kernel tiles (3D; 2D tile kernels): 64 x plane_rows, vel_planes planes
+    // each for the velocity update, prs_planes for the pressure update (2D: one)
     std::vector<fw::Tile> vt, pt;
     if (plane_velocity_on(s)) vt = banded_tiles(s, 64, s->plane_rows, s->vel_planes);
     if (plane_pressure_on(s)) pt = banded_tiles(s, 64, s->plane_rows, s->prs_planes);
@@ -486,6 +486,15 @@ int fw_create_grid(fw_sim **out, int ndim, int n_domains, const int64_t *shape, 
     // 0.351 / 0.343 ms per step on 16 shots of 1024^2 at N = 4, 0.068 / 0.071 /
     // 0.072 ms on 2048^2 at N = 2, equal on the 64-shot ragged batch)
     if (ndim == 2) s->plane_rows = 8;
+    // 3D plane kernels at N <= 2: 8-row tiles, two planes per velocity tile
+    // (measured, step ms with rows 4 / 8 and 1 / 2 / 4 velocity planes:
+    // 960 x 960 x 720 15.83 15.76 15.94 / 16.02 15.56 15.71; 499 x 499 x 1247
+    // 8.13 7.97 7.88 / 7.93 7.69 7.60; at N = 4 the 4-row, 1-plane default is
+    // fastest: 21.79 against 22.05-23.44)
+    if (ndim == 3 && n_mech <= 2) {
+        s->plane_rows = 8;
+        s->vel_planes = 2;
+    }
     s->pml = pml_cells;
     s->dx = dx;
     s->dt = dt;
@@ -1445,7 +1454,8 @@ int fw_set_option(fw_sim *sim, int key, int64_t value)
         sim->tiles_dirty = true;
         return FW_OK;
     case FW_OPT_VEL_PLANES:
-        if (value != 1 && value != 2) return fail(FW_EINVAL, "velocity plane-kernel tiles hold 1 or 2 planes");
+        if (value != 1 && value != 2 && value != 4)
+            return fail(FW_EINVAL, "velocity plane-kernel tiles hold 1, 2 or 4 planes");
         sim->vel_planes = (int)value;
         sim->tiles_dirty = true;
         return FW_OK;

@@ -113,10 +113,11 @@ def test_tiling_does_not_change_results():
     for plane in (1, -1):
         _, got = _run(case, opts={FW_OPT_PLANE_KERNELS: plane, FW_OPT_PLANE_ROWS: 8})
         assert np.array_equal(ref, got), ("plane rows 8", plane)
-    # plane-kernel tile depths: 2-plane velocity tiles, 2/4/8-plane pressure
-    # tiles (29 planes: a ragged last tile for each), with 4- and 8-row tiles
+    # plane-kernel tile depths: 2- and 4-plane velocity tiles, 2/4/8-plane
+    # pressure tiles (29 planes: a ragged last tile for each), with 4- and
+    # 8-row tiles
     from paper_2606_11103_amd.native import FW_OPT_PRS_PLANES, FW_OPT_VEL_PLANES
-    for prow, vp, pp in ((4, 2, 2), (8, 2, 8), (4, 1, 4), (8, 1, 2), (4, 2, 8)):
+    for prow, vp, pp in ((4, 2, 2), (8, 2, 8), (4, 1, 4), (8, 1, 2), (4, 2, 8), (4, 4, 2), (8, 4, 8), (8, 4, 4)):
         _, got = _run(case, opts={FW_OPT_PLANE_KERNELS: 1, FW_OPT_PLANE_ROWS: prow, FW_OPT_VEL_PLANES: vp,
                                   FW_OPT_PRS_PLANES: pp})
         assert np.array_equal(ref, got), ("plane depths", prow, vp, pp)
