@@ -826,16 +826,25 @@ __global__ __launch_bounds__(64 * TY) void k_velocity_plane(const StepArgs A)
 
 // Pressure update on tiles of NP consecutive planes (2, 4 or 8; 3D, 64 x TY
 // with TY = 4 or 8 rows, one tile per block), from a list in which XCD k owns y-band k of every
-// group of planes.  The v_z window of the group (its planes - 4 .. + 3 past
-// the last) is loaded once into registers; each plane loads the x-halo of
-// v_x, the y-halo of v_y and its own state into registers and stages the
-// halos in a double-buffered LDS tile.  The barrier of a plane orders LDS
+// group of planes.  The v_z window of the current plane (planes - 4 .. + 3)
+// is carried in registers as a queue: seven planes are loaded before the
+// first plane and the eighth with each plane's own operands.  Each plane
+// loads the x-halo of v_x, the y-halo of v_y and its own state into
+// registers and stages the halos in a double-buffered LDS tile.  The barrier of a plane orders LDS
 // only (the threads exchange nothing through global memory), so the loads
 // of the next plane, issued right after it, stay in flight while the
 // current plane is computed.  Same operations in the same order as
 // k_pressure.
+// Asking the compiler for 8 waves per SIMD where that fits without scratch
+// spills (2-plane tiles, and N <= 2): 6.64 against 6.69 ms at N = 4 and 5.08
+// against 5.21 ms at N = 2 on 960 x 960 x 720; the 4- and 8-plane tiles at
+// N >= 3 would spill and run slower (7.4-7.5 ms), so they keep 7.
+template <int N, int NP>
+constexpr int kPressureMinWaves = (NP == 2 || N <= 2) ? 8 : 1;
+
 template <int N, int TY, int NP, bool SMAP>
-__global__ __launch_bounds__(64 * TY) void k_pressure_planes(const StepArgs A)
+__global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(kPressureMinWaves<N, NP>)))
+void k_pressure_planes(const StepArgs A)
 {
     constexpr int BX = 64, LX = BX + 8, LY = TY + 8, NT = BX * TY;
     // halo cells the stencils read: x-4 .. x-1 and x+64 .. x+66 of v_x over
@@ -877,9 +886,9 @@ __global__ __launch_bounds__(64 * TY) void k_pressure_planes(const StepArgs A)
     const int col = y * px + x;
 
     // v_z of the group's window: planes z0 - 4 .. z0 + NP + 2, zero outside
-    float vq[NP + 7];
+    float vq[7];
 #pragma unroll
-    for (int j = 0; j < NP + 7; ++j) {
+    for (int j = 0; j < 7; ++j) {
         const int zz = T.z0 - 4 + j;
         vq[j] = (ok && zz >= 0 && zz < nz) ? Mo.v[2][col + zz * sm] : 0.0f;
     }
@@ -913,12 +922,14 @@ __global__ __launch_bounds__(64 * TY) void k_pressure_planes(const StepArgs A)
     // per plane: the halo share and own v_x, v_y first (the LDS staging
     // waits for them only), then the streamed state
     struct PlaneIn {
-        float hv[HS], ox, oy, pc, psc[N], ppc[3];
+        float hv[HS], ox, oy, pc, psc[N], ppc[3], vzt;
         int L;
     };
     auto load_plane = [&](int z, PlaneIn &o) {
         const int zoff = z * sm;
         const int g = zoff + col;
+        // top of plane z's v_z window (plane z + 3); the rest is carried over
+        o.vzt = (ok && z + 3 < nz) ? Mo.v[2][col + (z + 3) * sm] : 0.0f;
 #pragma unroll
         for (int s = 0; s < HS; ++s)
             o.hv[s] = (hli[s] == -1 || hoff[s] < 0) ? 0.0f
@@ -969,8 +980,7 @@ __global__ __launch_bounds__(64 * TY) void k_pressure_planes(const StepArgs A)
             Dd[0] = stencil4(A.fd, sx[0] - sx[-1], sx[1] - sx[-2], sx[2] - sx[-3], sx[3] - sx[-4]);
             Dd[1] = stencil4(A.fd, sy[0] - sy[-BX], sy[BX] - sy[-2 * BX], sy[2 * BX] - sy[-3 * BX],
                              sy[3 * BX] - sy[-4 * BX]);
-            Dd[2] = stencil4(A.fd, vq[j + 4] - vq[j + 3], vq[j + 5] - vq[j + 2], vq[j + 6] - vq[j + 1],
-                             vq[j + 7] - vq[j]);
+            Dd[2] = stencil4(A.fd, vq[4] - vq[3], vq[5] - vq[2], vq[6] - vq[1], cur.vzt - vq[0]);
             const int L = cur.L;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
@@ -1011,6 +1021,10 @@ __global__ __launch_bounds__(64 * TY) void k_pressure_planes(const StepArgs A)
             const float pn0 = cur.pc;
             store1_stream(Mo.p + g, fmaf(-(A.dt * fmaf(s_tb[L], pn0, K)), Tt, pn0));
         }
+        // advance the window: planes z - 3 .. z + 3 kept, z + 4 arrives with nxt
+#pragma unroll
+        for (int i = 0; i < 6; ++i) vq[i] = vq[i + 1];
+        vq[6] = cur.vzt;
         cur = nxt;
     }
 }

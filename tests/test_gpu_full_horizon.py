@@ -4,9 +4,9 @@ traces (both <= 1e-4), in the launch configuration the benchmark uses.
 
 * 3D heterogeneous recipe (8 calibrated step-matched classes, focused array,
   +-1 % speed perturbation, nonlinear, N = 4, 24-cell CPML, 2000 steps) on a
-  128 x 128 x 96 instance (oracle live, about 30 s on 16 host cores) and on
-  a 256 x 256 x 192 instance (oracle traces stored by
-  tests/golden/make_3d_instance_traces.py);
+  128 x 128 x 96 instance (oracle live, about 30 s on 16 host cores), the
+  same with N = 2, and on a 256 x 256 x 192 instance (oracle traces stored
+  by tests/golden/make_3d_instance_traces.py);
 * the 64-shot batched 2D launch over all 3000 steps: the smallest, the
   largest and two middle shots against the oracle;
 * the 544-domain 1D sweep over its full 14 800 steps: eight domains spanning
@@ -63,6 +63,18 @@ def test_3d_recipe_128x128x96_all_2000_steps():
     _, ref = _oracle_domain(case, 0)
     glob, worst, n = check_traces(got, ref)
     report("full horizon: 3D heterogeneous 128x128x96 N=4 nonlinear noise, 2000 steps: rel_L2 %.3e, worst receiver "
+           "%.3e (%d of %d reached), peak %.3g Pa" % (glob, worst, n, ref.shape[1], np.abs(ref).max()))
+
+
+def test_3d_recipe_at_the_papers_n2_128x128x96_all_2000_steps():
+    """The 3D recipe with N = 2 (the paper's mechanism count and the library's
+    N <= 2 launch shape: 8-row plane tiles, two planes per velocity tile)."""
+    case = _calibrated(configs.heterogeneous_3d(shape=(128, 128, 96), steps=2000, n_elem=16, nmech=2))
+    print("3D instance N=2", case.shapes, "steps", case.n_steps, flush=True)
+    got = _gpu(case)
+    _, ref = _oracle_domain(case, 0)
+    glob, worst, n = check_traces(got, ref)
+    report("full horizon: 3D heterogeneous 128x128x96 N=2 nonlinear noise, 2000 steps: rel_L2 %.3e, worst receiver "
            "%.3e (%d of %d reached), peak %.3g Pa" % (glob, worst, n, ref.shape[1], np.abs(ref).max()))
 
 
