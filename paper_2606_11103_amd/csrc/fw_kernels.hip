@@ -671,8 +671,16 @@ __global__ __launch_bounds__(BX *BY) void k_pressure(const StepArgs A)
 // latency.  Each output is computed with the same operations, in the same
 // order, as in k_velocity, so the two give identical bits.
 // ---------------------------------------------------------------------------
+// Tiles of 2 or 4 planes need about 105 scalar registers, which alone limits
+// a SIMD to 7 waves; at N <= 2 their vector registers leave room for 8, so
+// the compiler is asked for 8 there (it keeps the extra scalars in vector
+// lanes).
+template <int N, int NP>
+constexpr int kVelocityMinWaves = (NP >= 2 && N <= 2) ? 8 : 1;
+
 template <int N, int TY, int NP, bool SMAP>
-__global__ __launch_bounds__(64 * TY) void k_velocity_plane(const StepArgs A)
+__global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(kVelocityMinWaves<N, NP>)))
+void k_velocity_plane(const StepArgs A)
 {
     constexpr int NB = NP > 1 ? 2 : 1;      // LDS buffers
     constexpr int BX = 64, LX = BX + 8, LY = TY + 8, NT = BX * TY, CX = BX + 1;
