@@ -96,9 +96,11 @@ def fill_tables(case, allow_fit=True):
     return fits
 
 
-def cpu_baseline(seconds_target=20.0):
+def cpu_baseline(seconds_target=20.0, gpu=False):
     """The FP64 oracle as it stands, on a 128 x 128 x 96 crop-sized instance of
-    the same recipe (same classes, tables, noise, source), timed on the host."""
+    the same recipe (same classes, tables, noise, source), timed on the host;
+    with gpu, the library then runs the same instance for the same steps and
+    its receiver traces are compared with the oracle's ("parity")."""
     from workloads import configs
     from workloads.adapters import to_oracle
     case = configs.heterogeneous_3d(shape=(128, 128, 96), steps=2000, n_elem=16)
@@ -106,9 +108,11 @@ def cpu_baseline(seconds_target=20.0):
     sim = to_oracle(case)
     waves = case.waves.astype(np.float64)[case.src_wave]
     steps = 0
+    traces = []
     t0 = time.perf_counter()
     while True:
-        sim.run(10, case.src_cell, waves, case.rec_cell)
+        rec, _ = sim.run(10, case.src_cell, waves, case.rec_cell)
+        traces.append(np.asarray(rec, np.float64))
         steps += 10
         el = time.perf_counter() - t0
         if el >= seconds_target or steps >= 2000:
@@ -116,9 +120,60 @@ def cpu_baseline(seconds_target=20.0):
     cells = case.cells()
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     cores = min(cores, os.cpu_count() or cores)
-    return dict(value=cells * steps / el / 1e9, unit="Gcell-updates/s", cores=cores, kind="oracle",
-                sample="FP64 oracle, 128x128x96 instance of the 3D heterogeneous recipe (N=4, CPML 24, "
-                       "noise, nonlinear), %d steps in %.1f s" % (steps, el))
+    out = dict(value=cells * steps / el / 1e9, unit="Gcell-updates/s", cores=cores, kind="oracle",
+               sample="FP64 oracle, 128x128x96 instance of the 3D heterogeneous recipe (N=4, CPML 24, "
+                      "noise, nonlinear), %d steps in %.1f s" % (steps, el))
+    if gpu:
+        # the library on the same instance and steps, against the oracle's traces
+        from workloads.adapters import to_simulation
+        ref = np.concatenate(traces)[:steps]
+        lib = to_simulation(case)
+        lib.step(steps)
+        got = lib.read_receivers()[:steps].astype(np.float64)
+        del lib
+        out["parity"] = dict(zip(("rel_l2", "worst_receiver_rel_l2", "receivers_reached"),
+                                 trace_errors(got, ref)), steps=steps)
+    return out
+
+
+def trace_errors(got, ref, reach=1e-3):
+    """Relative L2 of the receiver traces [steps][receivers] over all of them,
+    the worst relative L2 of one receiver among those whose peak reaches
+    `reach` of the strongest, and the number of those receivers."""
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    glob = float(np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300))
+    peak = np.abs(ref).max(axis=0)
+    reached = peak >= reach * max(peak.max(), 1e-300)
+    worst = 0.0
+    for r in np.nonzero(reached)[0]:
+        worst = max(worst, float(np.linalg.norm(got[:, r] - ref[:, r]) / np.linalg.norm(ref[:, r])))
+    return round(glob, 10), round(worst, 10), int(reached.sum())
+
+
+def bench_record(out, kernel_hash):
+    """One JSONL record of a benchmark run: a hash of its configuration, the
+    throughput, the roofline figures, the oracle beside it and the parity of
+    the oracle's sample."""
+    import datetime
+    import hashlib
+    import platform
+    cfg = json.dumps(out.get("config", {}), sort_keys=True)
+    r = out.get("roofline", {})
+    cb = out.get("cpu_baseline") or {}
+    return {
+        "time": datetime.datetime.now(datetime.timezone.utc).isoformat(timespec="seconds"),
+        "host": platform.node(),
+        "config_hash": hashlib.sha256(cfg.encode()).hexdigest()[:16],
+        "kernel_source_hash": kernel_hash,
+        "workload": out.get("config", {}).get("workload"),
+        "metric": out.get("metric"), "value": out.get("value"), "unit": out.get("unit"),
+        "ms_per_step": out.get("ms_per_step"),
+        "roofline_frac": r.get("frac"), "algorithmic_GBps": r.get("achieved"), "counted_GBps": r.get("traffic"),
+        "dominant_kernel_frac": (r.get("dominant_kernel") or {}).get("frac"),
+        "oracle_gcells": cb.get("value"), "oracle_cores": cb.get("cores"),
+        "parity": cb.get("parity"),
+    }
 
 
 def oracle_timings(seconds=8.0):
@@ -458,6 +513,8 @@ def copy_probe(torch, gib, reps):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--record", default=None,
+                    help="append a JSONL record of the run (config hash, throughput, roofline, oracle, parity)")
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--small", action="store_true", help="reduced grid for quick checks (not the benchmark)")
@@ -637,8 +694,11 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         print("# cpu baseline ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(gpu=True)
     print(json.dumps(out), flush=True)
+    if args.record:
+        with open(args.record, "a") as fh:
+            fh.write(json.dumps(bench_record(out, kernel_source_hash())) + "\n")
 
 
 if __name__ == "__main__":

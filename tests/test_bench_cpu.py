@@ -31,3 +31,32 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_trace_errors_and_the_jsonl_record():
+    """The parity figures of the record: relative L2 over all traces, the worst
+    reached receiver (peak >= 1e-3 of the strongest), the count of those; and
+    a record that carries them with a configuration hash that depends on the
+    configuration only."""
+    import json
+    import numpy as np
+    import bench
+    rng = np.random.default_rng(0)
+    ref = rng.standard_normal((50, 4))
+    ref[:, 3] *= 1e-6                         # below the reach: not counted
+    got = ref.copy()
+    got[:, 1] *= 1.01                         # one receiver 1 % off
+    glob, worst, n = bench.trace_errors(got, ref)
+    assert n == 3
+    assert worst == pytest.approx(0.01, rel=1e-7)         # figures are rounded to 1e-10
+    assert glob == pytest.approx(0.01 * np.linalg.norm(ref[:, 1]) / np.linalg.norm(ref), rel=1e-7)
+    out = {"metric": "m", "value": 1.5, "unit": "u", "ms_per_step": 2.0,
+           "config": {"workload": "w", "cells": 10},
+           "roofline": {"frac": 0.6, "achieved": 4800.0, "traffic": 6000.0, "dominant_kernel": {"frac": 0.7}},
+           "cpu_baseline": {"value": 0.1, "cores": 16, "parity": {"rel_l2": glob}}}
+    r1 = bench.bench_record(out, "abc")
+    r2 = bench.bench_record(dict(out, value=9.0), "abc")
+    r3 = bench.bench_record(dict(out, config={"workload": "w", "cells": 11}), "abc")
+    assert r1["config_hash"] == r2["config_hash"] != r3["config_hash"]
+    assert r1["parity"]["rel_l2"] == glob and r1["oracle_cores"] == 16 and r1["roofline_frac"] == 0.6
+    json.dumps(r1)
