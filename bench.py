@@ -456,20 +456,22 @@ def bench_strength_map(torch, steps=100):
             "extra_bytes_per_cell": 8}
 
 
-def stream_probe(torch, reps=5):
+def stream_probe(torch, reps=5, nmech=4):
     """Memory-traffic probes on the benchmark grid (fw_stream_probe): the
     velocity update's streams, the pressure update's, and a fused single
     pass, each as one flat sweep and as 64 x 4 tiles marching 48 planes."""
     from workloads.adapters import to_simulation
-    case = bench_case()
+    case = bench_case(nmech=nmech)
     from workloads import configs
     configs.with_table(case, *configs.random_relaxation_table(1, case.n_classes, case.nmech))
     sim = to_simulation(case)
     cells = case.cells()
     N = case.nmech
-    per_cell = {0: 4 + 1 + 3 * 8 + 3 * 8 * N, 1: 3 * 4 + 8 + 1 + 8 * N, 2: (1 + 3 + 4 * N) * 8 + 1}
+    vel = 4 + 1 + 3 * 8 + 3 * 8 * N
+    per_cell = {0: vel, 1: 3 * 4 + 8 + 1 + 8 * N, 2: (1 + 3 + 4 * N) * 8 + 1, 3: vel, 4: vel}
     out = {"workload": case.name + " (state streams only, no CPML)", "reps": reps}
-    for mode, name in ((0, "velocity_streams"), (1, "pressure_streams"), (2, "fused_single_pass")):
+    for mode, name in ((0, "velocity_streams"), (1, "pressure_streams"), (2, "fused_single_pass"),
+                       (3, "velocity_streams_psi1_interleaved"), (4, "velocity_streams_psi1_v_interleaved")):
         for order, oname in ((0, "flat"), (1, "marching_64x4x48")):
             ms = sim.stream_probe(mode, order, reps)
             out["%s_%s" % (name, oname)] = {"bytes_per_cell": per_cell[mode], "ms": round(ms, 3),
@@ -561,7 +563,7 @@ def main():
         return
     if args.stream_probe:
         torch.cuda.set_device(0)
-        stream_probe(torch)
+        stream_probe(torch, nmech=args.nmech)
         return
     if args.only:
         torch.cuda.set_device(0)

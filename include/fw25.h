@@ -361,7 +361,12 @@ int fw_read_field(fw_sim *sim, int field, int domain, float *dst, int dst_is_dev
  *           memory variables read; v and the memory variables written);
  *   mode 1: the pressure update's (v, p, class map, N cell memory variables
  *           read; p and the memory variables written);
- *   mode 2: the whole state read and written once (a fused update's pass).
+ *   mode 2: the whole state read and written once (a fused update's pass);
+ *   mode 3: mode 0 with the three per-axis face memory-variable groups of a
+ *           cell read and written as one [cell][axis][N] stream over the
+ *           memory of the three arrays (a layout the step does not use;
+ *           every address still gets back the value read from it);
+ *   mode 4: mode 3 with v read and written as one [cell][axis] stream too.
  *   order 0: one flat sweep (neighbouring cells in concurrent workgroups);
  *   order 1: 64 x 4 tiles each marching 48 planes along z.
  * CPML variables are not moved.  Requires one 3D domain (FW_EUNSUPPORTED

@@ -18,20 +18,28 @@ namespace {
 // MODE 0: velocity streams (read p, class, v, psi1; write v, psi1)
 // MODE 1: pressure streams (read v, p, class, psi2; write p, psi2)
 // MODE 2: both in one pass (every state float read and written once)
+// MODE 3: MODE 0 with the three per-axis psi1 groups of a cell stored together
+//         ([cell][axis][N] over the psi1 arrays' memory), one stream instead of three
+// MODE 4: MODE 3 with v stored [cell][axis] as well
 template <int N, int MODE>
 __device__ __forceinline__ void probe_cell(const Fields &F, int64_t g)
 {
     // every load first (the stores may alias them), then every store
-    float *vp[3] = {F.vx, F.vy, F.vz};
-    float *psi1[3] = {F.psi1x, F.psi1y, F.psi1z};
+    constexpr bool ILV1 = MODE >= 3, ILV_V = MODE == 4;
+    float *vp[3], *psi1[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        vp[a] = ILV_V ? F.vx + g * 3 + a : (a == 0 ? F.vx : (a == 1 ? F.vy : F.vz)) + g;
+        psi1[a] = ILV1 ? F.psi1x + (g * 3 + a) * N : (a == 0 ? F.psi1x : (a == 1 ? F.psi1y : F.psi1z)) + g * N;
+    }
     const float p = load1_stream(F.p + g);
     const float c = (float)F.cls[g];
     float v[3], q1[3][N], q2[N];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) v[a] = load1_stream(vp[a] + g);
+    for (int a = 0; a < 3; ++a) v[a] = load1_stream(vp[a]);
     if constexpr (MODE != 1) {
 #pragma unroll
-        for (int a = 0; a < 3; ++a) load_stream<N>(psi1[a] + g * N, q1[a]);
+        for (int a = 0; a < 3; ++a) load_stream<N>(psi1[a], q1[a]);
     }
     if constexpr (MODE != 0) load_stream<N>(F.psi2 + g * N, q2);
     // x + 0 * y cannot be folded away (NaN), so each store keeps its load
@@ -40,8 +48,8 @@ __device__ __forceinline__ void probe_cell(const Fields &F, int64_t g)
         for (int a = 0; a < 3; ++a) {
 #pragma unroll
             for (int i = 0; i < N; ++i) q1[a][i] = fmaf(0.0f, p, q1[a][i]);
-            store_stream<N>(psi1[a] + g * N, q1[a]);
-            store1_stream(vp[a] + g, fmaf(0.0f, p + c, v[a]));
+            store_stream<N>(psi1[a], q1[a]);
+            store1_stream(vp[a], fmaf(0.0f, p + c, v[a]));
         }
     }
     if constexpr (MODE != 0) {
@@ -86,6 +94,8 @@ hipError_t probe_n(int mode, int order, const Fields &F, int64_t nx, int64_t px,
         if (mode == 0) k_probe_flat<N, 0><<<grid, dim3(256), 0, s>>>(F, n);
         if (mode == 1) k_probe_flat<N, 1><<<grid, dim3(256), 0, s>>>(F, n);
         if (mode == 2) k_probe_flat<N, 2><<<grid, dim3(256), 0, s>>>(F, n);
+        if (mode == 3) k_probe_flat<N, 3><<<grid, dim3(256), 0, s>>>(F, n);
+        if (mode == 4) k_probe_flat<N, 4><<<grid, dim3(256), 0, s>>>(F, n);
     } else {
         const int chunk = 48;
         const int64_t tiles = ((nx + 63) / 64) * ((ny + 3) / 4) * ((nz + chunk - 1) / chunk);
@@ -94,6 +104,8 @@ hipError_t probe_n(int mode, int order, const Fields &F, int64_t nx, int64_t px,
         if (mode == 0) k_probe_march<N, 0><<<grid, block, 0, s>>>(F, (int)nx, (int)px, (int)ny, (int)nz, chunk, (int)tiles, per_xcd);
         if (mode == 1) k_probe_march<N, 1><<<grid, block, 0, s>>>(F, (int)nx, (int)px, (int)ny, (int)nz, chunk, (int)tiles, per_xcd);
         if (mode == 2) k_probe_march<N, 2><<<grid, block, 0, s>>>(F, (int)nx, (int)px, (int)ny, (int)nz, chunk, (int)tiles, per_xcd);
+        if (mode == 3) k_probe_march<N, 3><<<grid, block, 0, s>>>(F, (int)nx, (int)px, (int)ny, (int)nz, chunk, (int)tiles, per_xcd);
+        if (mode == 4) k_probe_march<N, 4><<<grid, block, 0, s>>>(F, (int)nx, (int)px, (int)ny, (int)nz, chunk, (int)tiles, per_xcd);
     }
     return hipGetLastError();
 }
@@ -103,7 +115,7 @@ hipError_t probe_n(int mode, int order, const Fields &F, int64_t nx, int64_t px,
 hipError_t launch_stream_probe(int nmech, int mode, int order, const Fields &F, int64_t nx, int64_t px, int64_t ny,
                                int64_t nz, hipStream_t s)
 {
-    if (mode < 0 || mode > 2 || order < 0 || order > 1) return hipErrorInvalidValue;
+    if (mode < 0 || mode > 4 || order < 0 || order > 1) return hipErrorInvalidValue;
     switch (nmech) {
     case 1: return probe_n<1>(mode, order, F, nx, px, ny, nz, s);
     case 2: return probe_n<2>(mode, order, F, nx, px, ny, nz, s);

@@ -1328,11 +1328,17 @@ int fw_stream_probe(fw_sim *sim, int mode, int order, int reps, void *hip_stream
     if (!sim || !avg_ms) return fail(FW_EINVAL, "NULL argument");
     if (!sim->ws || !sim->media_set) return fail(FW_ESTATE, "set up the simulation first");
     if (sim->ndim != 3 || sim->n_domains != 1) return fail(FW_EUNSUPPORTED, "the probe runs on one 3D domain");
-    if (mode < 0 || mode > 2 || order < 0 || order > 1 || reps < 1)
-        return fail(FW_EINVAL, "mode must be 0..2, order 0..1, reps >= 1");
+    if (mode < 0 || mode > 4 || order < 0 || order > 1 || reps < 1)
+        return fail(FW_EINVAL, "mode must be 0..4, order 0..1, reps >= 1");
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     const fw::Fields f = fields_of(sim);
     const fw::DomainDesc &D = sim->doms[0];
+    // modes 3 and 4 read the three per-axis arrays as one interleaved array:
+    // they must lie back to back, each holding at least the stored cells
+    const int64_t stored = sim->stored(0);
+    if (mode >= 3 && (sim->off_psi2 - sim->off_psi1[0] < 3 * stored * sim->nmech * (int64_t)sizeof(float) ||
+                      sim->off_psi1[0] - sim->off_v[0] < 3 * stored * (int64_t)sizeof(float)))
+        return fail(FW_EUNSUPPORTED, "interleaved probe modes need the per-axis arrays back to back");
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_OR_FAIL(hipEventCreate(&e0));
     HIP_OR_FAIL(hipEventCreate(&e1));
