@@ -44,11 +44,11 @@ TRAFFIC_MEASURED = {
 
 
 def kernel_source_hash():
-    """SHA-256 prefix of the step kernels' sources (kernel file and the device
-    helper header it includes)."""
+    """SHA-256 prefix of the step kernels' sources (the kernel file and the two
+    headers it includes: argument structures and device helpers)."""
     import hashlib
     h = hashlib.sha256()
-    for name in ("fw_kernels.hip", "fw_vec.h"):
+    for name in ("fw_kernels.hip", "fw_internal.h", "fw_vec.h"):
         with open(os.path.join(ROOT, "paper_2606_11103_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

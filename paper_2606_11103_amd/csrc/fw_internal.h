@@ -47,12 +47,6 @@ struct Fields {
     uint8_t *cls;
 };
 
-// planes per tile of the 3D plane kernels (measured on 960 x 960 x 720, N = 4:
-// velocity 14.95 / 15.7 / 16.3 ms with 1 / 2 / 4 planes, pressure 7.59 /
-// 7.16 / 7.04 / 7.13 ms with 1 / 2 / 4 / 8)
-constexpr int kVelocityPlanes = 1;      // defaults; FW_OPT_VEL_PLANES / FW_OPT_PRS_PLANES pick others
-constexpr int kPressurePlanes = 4;
-
 struct StepArgs {
     Fields f;                  // state read by the step
     Fields fo;                 // state written by the step (== f: in place)

@@ -117,7 +117,7 @@ struct fw_sim {
     int n_t = 0, n_t_max = 0;
     // options
     int graph_steps = 16, march_chunk = 0, tile_rows = 4, rows_per_thread = 1, persistent = 0, tile_order = 0,
-        plane_kernels = -1, plane_rows = 4, vel_planes = fw::kVelocityPlanes, prs_planes = fw::kPressurePlanes;
+        plane_kernels = -1, plane_rows = 4, vel_planes = 1, prs_planes = 2;   // per dimension and N: fw_create_grid
     // stepping
     int64_t host_step = 0;
     hipStream_t cap_stream = nullptr;
