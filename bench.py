@@ -311,9 +311,16 @@ def bench_batched(torch, steps=200):
     plain = cells * steps / (tot / 1e3) / 1e9
     return {"workload": case.name, "cells": case.cells(), "steps": steps,
             "batched_gcells": round(batched, 3), "ms_per_step": round(ms / steps, 4),
+            "step_frac": _step_frac(case, ms / steps),
             "launch_shape": cfg, "default_shape_gcells": round(case.cells() * steps / (ms_default / 1e3) / 1e9, 3),
             "plain_single_shot_gcells": round(plain, 3), "batched_vs_plain": round(batched / plain, 3),
             "plain_sample": "8 of the 64 shots, one simulation each"}
+
+
+def _step_frac(case, ms_per_step):
+    """Whole-step algorithmic bytes of the case over the step time, as a
+    fraction of the 8 TB/s HBM peak."""
+    return round(algorithmic_bytes(case)[2] * case.cells() / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
 
 
 def _tables_or_random(case, seed):
@@ -338,7 +345,8 @@ def bench_two_layer(torch, steps=400):
     sim.step(32)                    # untimed: captures the step graph
     ms = _time_steps(torch, sim, steps)
     return {"workload": case.name, "cells": case.cells(), "steps": steps, "tables": tab,
-            "gcells": round(case.cells() * steps / (ms / 1e3) / 1e9, 3), "ms_per_step": round(ms / steps, 4)}
+            "gcells": round(case.cells() * steps / (ms / 1e3) / 1e9, 3), "ms_per_step": round(ms / steps, 4),
+            "step_frac": _step_frac(case, ms / steps)}
 
 
 def bench_paper_shape(torch, steps=100):
@@ -356,6 +364,7 @@ def bench_paper_shape(torch, steps=100):
     ms = _time_steps(torch, sim, steps)
     return {"workload": case.name, "cells": case.cells(), "steps": steps, "tables": tab,
             "gcells": round(case.cells() * steps / (ms / 1e3) / 1e9, 3), "ms_per_step": round(ms / steps, 4),
+            "step_frac": _step_frac(case, ms / steps),
             "launch_shape": cfg, "default_shape_gcells": round(case.cells() * steps / (ms_default / 1e3) / 1e9, 3)}
 
 
