@@ -177,10 +177,24 @@ int fw_set_sources(fw_sim *sim, int64_t n_src, const int32_t *domain, const int6
  * Sec. 4.3 and Sec. 4.5: incident/reflected pressure and RF traces).
  * Receivers: after step t's sources, trace[t][r] = p[domain[r], cell[r]]
  * for t < n_t_max (later steps are not recorded).  Allocates the device
- * trace buffer [n_t_max][n_rec] (zeroed).  n_rec = 0 clears.
+ * trace buffer [n_t_max][n_rec] (zeroed); fw_set_receivers_into takes a
+ * caller-owned one instead.  n_rec = 0 clears.
  */
 int fw_set_receivers(fw_sim *sim, int64_t n_rec, const int32_t *domain, const int64_t *cell,
                      int n_t_max);
+
+/*
+ * The same receivers (Sec. 4.1), recorded into a caller-owned device buffer
+ * d_traces of `capacity` floats instead of one the library allocates: the
+ * library zeroes its first n_rec * max(n_t_max, 1) floats ([n_t_max][n_rec],
+ * row-major) and writes the traces there at every step; fw_read_receivers
+ * and fw_reset_state use it.  The caller keeps it alive and unmodified while
+ * the simulation steps (the library only borrows it), until receivers are
+ * set again.  FW_EINVAL if d_traces is NULL with n_rec > 0 or capacity is
+ * too small.  The small per-cell receiver tables are still the library's.
+ */
+int fw_set_receivers_into(fw_sim *sim, int64_t n_rec, const int32_t *domain, const int64_t *cell,
+                          int n_t_max, float *d_traces, int64_t capacity);
 
 /*
  * The FDTD step of Sec. 3.3 applied to Eqs. (wave1)/(wave2) of Sec. 2.1,

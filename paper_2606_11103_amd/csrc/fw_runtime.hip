@@ -103,6 +103,8 @@ struct fw_sim {
     std::vector<double> alpha0;          // power-law coefficient per class (fw_set_class_alpha0)
     // device tables
     DevBuf d_doms, d_classes, d_pml, d_tiles, d_vtiles, d_ptiles, d_waves, d_traces, d_step;
+    float *traces_ext = nullptr;         // caller-owned trace buffer (fw_set_receivers_into), borrowed
+    float *traces() const { return traces_ext ? traces_ext : d_traces.as<float>(); }
     DevBuf d_srcrec, d_rec_of;
     std::vector<int64_t> h_src_cell, h_rec_cell;   // global cells of the sources and the receivers
     std::vector<int32_t> h_src_wave;               // waveform row of each source
@@ -405,7 +407,7 @@ fw::SrcRecArgs srcrec_args(const fw_sim *s)
     a.rec_of = s->d_rec_of.as<int32_t>();
     a.waves = s->d_waves.as<float>();
     a.n_t = s->n_t;
-    a.traces = s->d_traces.as<float>();
+    a.traces = s->traces();
     a.n_rec = s->n_rec;
     a.n_t_max = s->n_t_max;
     a.step = s->d_step.as<int64_t>();
@@ -814,22 +816,30 @@ int fw_set_sources(fw_sim *sim, int64_t n_src, const int32_t *domain, const int6
     return FW_OK;
 }
 
-int fw_set_receivers(fw_sim *sim, int64_t n_rec, const int32_t *domain, const int64_t *cell, int n_t_max)
+// Receivers recording into the library's trace buffer (ext == NULL) or into
+// the caller's (ext, cap floats).
+static int set_receivers_impl(fw_sim *sim, int64_t n_rec, const int32_t *domain, const int64_t *cell, int n_t_max,
+                              float *ext, int64_t cap, bool caller_buffer)
 {
     g_err.clear();
     if (!sim) return fail(FW_EINVAL, "sim is NULL");
     if (n_rec < 0 || n_t_max < 0) return fail(FW_EINVAL, "n_rec and n_t_max must be >= 0");
     if (n_rec > 0 && (!domain || !cell)) return fail(FW_EINVAL, "NULL array argument");
+    const int64_t need = n_rec > 0 ? n_rec * std::max<int64_t>(n_t_max, 1) : 0;
+    if (caller_buffer && n_rec > 0 && !ext) return fail(FW_EINVAL, "d_traces is NULL");
+    if (caller_buffer && cap < need)
+        return fail(FW_EINVAL, "trace buffer holds %lld floats, %lld needed", (long long)cap, (long long)need);
     std::vector<int64_t> g;
     int rc = check_cells(sim, n_rec, domain, cell, g, "receiver");
     if (rc != FW_OK) return rc;
     if (!sim->ws) return fail(FW_ESTATE, "fw_bind_workspace must come first");
     sim->n_rec = n_rec;
     sim->n_t_max = n_rec > 0 ? n_t_max : 0;
+    sim->traces_ext = caller_buffer ? ext : nullptr;
     if (n_rec > 0) {
-        const size_t tb = (size_t)n_rec * std::max(n_t_max, 1) * sizeof(float);
-        HIP_OR_FAIL(sim->d_traces.ensure(tb));
-        HIP_OR_FAIL(hipMemset(sim->d_traces.ptr, 0, tb));
+        const size_t tb = (size_t)need * sizeof(float);
+        if (!caller_buffer) HIP_OR_FAIL(sim->d_traces.ensure(tb));
+        HIP_OR_FAIL(hipMemset(sim->traces(), 0, tb));
         // receivers grouped by distinct cell, for the adjoint source injection
         std::vector<int32_t> order(n_rec);
         for (int64_t i = 0; i < n_rec; ++i) order[i] = (int32_t)i;
@@ -858,6 +868,17 @@ int fw_set_receivers(fw_sim *sim, int64_t n_rec, const int32_t *domain, const in
     if (rc != FW_OK) return rc;
     sim->drop_graph();
     return FW_OK;
+}
+
+int fw_set_receivers(fw_sim *sim, int64_t n_rec, const int32_t *domain, const int64_t *cell, int n_t_max)
+{
+    return set_receivers_impl(sim, n_rec, domain, cell, n_t_max, nullptr, 0, false);
+}
+
+int fw_set_receivers_into(fw_sim *sim, int64_t n_rec, const int32_t *domain, const int64_t *cell, int n_t_max,
+                          float *d_traces, int64_t capacity)
+{
+    return set_receivers_impl(sim, n_rec, domain, cell, n_t_max, d_traces, capacity, true);
 }
 
 int fw_step(fw_sim *sim, int n_steps, void *hip_stream)
@@ -898,7 +919,7 @@ int fw_read_receivers(fw_sim *sim, float *dst, int64_t n_elems, int dst_is_devic
                     (long long)(sim->n_rec * (int64_t)sim->n_t_max));
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     if (n_elems > 0)
-        HIP_OR_FAIL(hipMemcpyAsync(dst, sim->d_traces.ptr, (size_t)n_elems * sizeof(float),
+        HIP_OR_FAIL(hipMemcpyAsync(dst, sim->traces(), (size_t)n_elems * sizeof(float),
                                    dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
     HIP_OR_FAIL(hipStreamSynchronize(st));
     return FW_OK;
@@ -914,7 +935,7 @@ int fw_reset_state(fw_sim *sim, void *hip_stream)
     HIP_OR_FAIL(hipMemsetAsync(sim->d_step.ptr, 0, sizeof(int64_t), st));
     HIP_OR_FAIL(hipMemsetAsync(static_cast<char *>(sim->d_step.ptr) + sizeof(int64_t), 0xff, sizeof(int64_t), st));
     if (sim->n_rec > 0)
-        HIP_OR_FAIL(hipMemsetAsync(sim->d_traces.ptr, 0, (size_t)sim->n_rec * std::max(sim->n_t_max, 1) * sizeof(float), st));
+        HIP_OR_FAIL(hipMemsetAsync(sim->traces(), 0, (size_t)sim->n_rec * std::max(sim->n_t_max, 1) * sizeof(float), st));
     sim->host_step = 0;
     return FW_OK;
 }

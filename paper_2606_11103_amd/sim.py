@@ -77,10 +77,20 @@ class Simulation:
         check(lib.fw_set_sources(self._h, int(cell.size), _ptr(domain), _ptr(cell), _ptr(wave_idx),
                                  int(waves.shape[0]), _ptr(waves), int(waves.shape[1])))
 
-    def set_receivers(self, domain, cell, n_t_max):
+    def set_receivers(self, domain, cell, n_t_max, out=None):
+        """Receivers; with out (a contiguous float32 tensor on the simulation's
+        device, at least n_t_max x n_rec elements) the traces are recorded
+        into it (fw_set_receivers_into) instead of a library buffer."""
         domain = np.ascontiguousarray(np.asarray(domain, dtype=np.int32).reshape(-1))
         cell = np.ascontiguousarray(np.asarray(cell, dtype=np.int64).reshape(-1))
-        check(lib.fw_set_receivers(self._h, int(cell.size), _ptr(domain), _ptr(cell), int(n_t_max)))
+        if out is None:
+            check(lib.fw_set_receivers(self._h, int(cell.size), _ptr(domain), _ptr(cell), int(n_t_max)))
+        else:
+            if out.dtype != self.torch.float32 or not out.is_contiguous() or out.device != self.device:
+                raise ValueError("out must be a contiguous float32 tensor on %s" % self.device)
+            check(lib.fw_set_receivers_into(self._h, int(cell.size), _ptr(domain), _ptr(cell), int(n_t_max),
+                                            ctypes.c_void_p(out.data_ptr()), int(out.numel())))
+        self._trace_buf = out          # borrowed by the library while set
         self.n_rec = int(cell.size)
         self.n_t_max = int(n_t_max)
 

@@ -143,6 +143,11 @@ def test_sources_and_receivers_validation_without_gpu():
     dom_bad = np.array([0, 1], np.int32)                 # only one domain
     assert lib.fw_set_receivers(h, 2, P(dom_bad), P(cells), 10) == native.FW_EINVAL
     assert lib.fw_set_receivers(h, 2, P(dom), P(cells), 10) == native.FW_ESTATE   # no workspace
+    # caller-owned trace buffer: NULL or too small is rejected before anything else
+    assert lib.fw_set_receivers_into(h, 2, P(dom), P(cells), 10, None, 20) == native.FW_EINVAL
+    fake = ctypes.c_void_p(0x1000)                       # never dereferenced: the call stops first
+    assert lib.fw_set_receivers_into(h, 2, P(dom), P(cells), 10, fake, 19) == native.FW_EINVAL
+    assert lib.fw_set_receivers_into(h, 2, P(dom), P(cells), 10, fake, 20) == native.FW_ESTATE
     assert lib.fw_set_option(h, native.FW_OPT_TILE_ROWS, 12) == native.FW_EINVAL
     assert lib.fw_set_option(h, native.FW_OPT_ROWS_PER_THREAD, 3) == native.FW_EINVAL
     assert lib.fw_set_option(h, native.FW_OPT_MARCH_CHUNK, -1) == native.FW_EINVAL

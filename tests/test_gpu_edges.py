@@ -107,3 +107,37 @@ def test_many_sources_and_receivers_over_several_workgroups():
     sim.step(case.n_steps - 50)
     assert sim.get_step() == case.n_steps
     assert np.array_equal(sim.read_receivers(), got.astype(np.float32))
+
+
+def test_receivers_into_a_caller_buffer():
+    """fw_set_receivers_into: the traces land in the caller's device tensor,
+    bit for bit the library-buffer traces; read-back and reset use it; once
+    receivers are set again with the library's buffer the tensor is no longer
+    written."""
+    import torch
+    case = _tables(configs.random_small(2, [(70, 50, 1), (40, 45, 1)], 3, 2, seed=71, steps=120, pml=6), "into")
+    ref_sim = to_simulation(case)
+    ref_sim.step(case.n_steps)
+    ref = ref_sim.read_receivers()
+    sim = to_simulation(case)
+    n_rec = len(case.rec_cell)
+    buf = torch.full((case.n_steps + 5, n_rec), 7.0, dtype=torch.float32, device=sim.device)   # larger than needed
+    sim.set_receivers(case.rec_domain, case.rec_cell, case.n_steps, out=buf)
+    assert float(buf[: case.n_steps].abs().max()) == 0.0          # zeroed by the library
+    sim.step(case.n_steps)
+    torch.cuda.synchronize()
+    got = buf[: case.n_steps].cpu().numpy()
+    assert np.array_equal(got, ref)
+    assert np.array_equal(sim.read_receivers(), ref)
+    assert float(buf[case.n_steps:].sub(7.0).abs().max()) == 0.0   # past the traces: untouched
+    sim.reset()
+    torch.cuda.synchronize()
+    assert float(buf[: case.n_steps].abs().max()) == 0.0
+    sim.set_receivers(case.rec_domain, case.rec_cell, case.n_steps)
+    buf.fill_(3.0)
+    sim.step(10)
+    torch.cuda.synchronize()
+    assert float(buf.sub(3.0).abs().max()) == 0.0
+    with pytest.raises(Exception):
+        sim.set_receivers(case.rec_domain, case.rec_cell, case.n_steps,
+                          out=torch.zeros(case.n_steps * n_rec - 1, dtype=torch.float32, device=sim.device))
