@@ -37,8 +37,8 @@ TRAFFIC_MEASURED = {
     # tiles, 2 planes) + sources/receivers; FETCH_SIZE counts L2 misses sent to
     # the data fabric, so the z-window reads served by the last-level cache are
     # included: an upper bound on the HBM bytes
-    "ebf6e44ff35a3a7b": {"workload": "3d_heterogeneous_960x960x720", "step_bytes": 144.77e9,
-                         "velocity_bytes": 99.24e9,
+    "326671e25f45c411": {"workload": "3d_heterogeneous_960x960x720", "step_bytes": 144.78e9,
+                         "velocity_bytes": 99.25e9,
                          "profile": "profiles/step_kernels_3d_960x960x720_N4.md"},
 }
 
