@@ -29,18 +29,42 @@ HBM_PEAK_GBS = 8000.0
 
 # Counted bytes of the benchmark's kernels measured with rocprofv3 --pmc
 # (FETCH_SIZE x 2.000 and WRITE_SIZE x 1.000 per dispatch, factors from the
-# library's plain copy kernel): per step (all kernels of one step) and per
-# velocity launch, keyed by the SHA-256 prefix of the kernel sources they were
-# taken on; any other kernel source reports traffic as null.
+# library's plain copy kernel): per step, of all kernels of one step and of
+# its velocity launches, keyed by the SHA-256 prefix of the kernel sources they
+# were taken on and by the step's schedule (planes per chunk of the interleaved
+# schedule, 0 for whole-grid launches); any other kernel source or schedule
+# reports traffic as null.
 TRAFFIC_MEASURED = {
     # velocity plane kernel (64 x 4 tiles, 1 plane) + pressure plane kernel (64 x 4
     # tiles, 2 planes) + sources/receivers; FETCH_SIZE counts L2 misses sent to
     # the data fabric, so the z-window reads served by the last-level cache are
     # included: an upper bound on the HBM bytes
-    "326671e25f45c411": {"workload": "3d_heterogeneous_960x960x720", "step_bytes": 144.78e9,
-                         "velocity_bytes": 99.25e9,
-                         "profile": "profiles/step_kernels_3d_960x960x720_N4.md"},
+    ("326671e25f45c411", 0): {"workload": "3d_heterogeneous_960x960x720", "step_bytes": 144.78e9,
+                              "velocity_bytes": 99.25e9,
+                              "profile": "profiles/step_kernels_3d_960x960x720_N4.md"},
+    # the same kernels in the interleaved schedule (6 chunks of 120 planes per step)
+    ("326671e25f45c411", 120): {"workload": "3d_heterogeneous_960x960x720", "step_bytes": 144.83e9,
+                                "velocity_bytes": 99.28e9,
+                                "profile": "profiles/step_kernels_3d_960x960x720_N4.md"},
 }
+
+# The library's automatic choice of the interleaved schedule (FW_OPT_STEP_CHUNK
+# -1): 3D grids with both plane kernels, at least 480 planes and a plane of at
+# least 200 k cells run 120-plane chunks.
+AUTO_CHUNK, AUTO_CHUNK_MIN_PLANES, AUTO_CHUNK_MIN_PLANE_CELLS = 120, 480, 200000
+
+
+def step_chunk_planes(case, step_chunk=None):
+    """Planes per chunk of the step's interleaved schedule for this case and
+    FW_OPT_STEP_CHUNK value (None: the default), 0 for whole-grid launches.
+    Plane kernels are assumed on (the 3D default)."""
+    if case.ndim != 3 or step_chunk == 0:
+        return 0
+    if step_chunk is not None and step_chunk > 0:
+        return int(step_chunk)
+    nz = max(int(s[2]) for s in case.shapes)
+    plane = max(int(s[0]) * int(s[1]) for s in case.shapes)
+    return AUTO_CHUNK if nz >= AUTO_CHUNK_MIN_PLANES and plane >= AUTO_CHUNK_MIN_PLANE_CELLS else 0
 
 
 def kernel_source_hash():
@@ -477,10 +501,11 @@ def stream_probe(torch, reps=5, nmech=4):
     cells = case.cells()
     N = case.nmech
     vel = 4 + 1 + 3 * 8 + 3 * 8 * N
-    per_cell = {0: vel, 1: 3 * 4 + 8 + 1 + 8 * N, 2: (1 + 3 + 4 * N) * 8 + 1, 3: vel, 4: vel}
+    per_cell = {0: vel, 1: 3 * 4 + 8 + 1 + 8 * N, 2: (1 + 3 + 4 * N) * 8 + 1, 3: vel, 4: vel, 5: vel, 6: vel}
     out = {"workload": case.name + " (state streams only, no CPML)", "reps": reps}
     for mode, name in ((0, "velocity_streams"), (1, "pressure_streams"), (2, "fused_single_pass"),
-                       (3, "velocity_streams_psi1_interleaved"), (4, "velocity_streams_psi1_v_interleaved")):
+                       (3, "velocity_streams_psi1_interleaved"), (4, "velocity_streams_psi1_v_interleaved"),
+                       (5, "velocity_streams_psi1_blocked64"), (6, "velocity_streams_psi1_v_blocked64")):
         for order, oname in ((0, "flat"), (1, "marching_64x4x48")):
             ms = sim.stream_probe(mode, order, reps)
             out["%s_%s" % (name, oname)] = {"bytes_per_cell": per_cell[mode], "ms": round(ms, 3),
@@ -542,6 +567,8 @@ def main():
                     help="FW_OPT_PLANE_ROWS for the headline run or --only batched_launch")
     ap.add_argument("--vel-planes", type=int, default=None, help="FW_OPT_VEL_PLANES for the headline run")
     ap.add_argument("--prs-planes", type=int, default=None, help="FW_OPT_PRS_PLANES for the headline run")
+    ap.add_argument("--step-chunk", type=int, default=None,
+                    help="FW_OPT_STEP_CHUNK for the headline run (0: whole-grid launches, -1: automatic)")
     ap.add_argument("--grid", type=int, nargs=3, default=None, metavar=("NX", "NY", "NZ"),
                     help="the benchmark recipe on another grid (profiling; not the benchmark line)")
     ap.add_argument("--nmech", type=int, default=4,
@@ -602,9 +629,10 @@ def main():
     if args.march_chunk:
         sim.set_option(FW_OPT_MARCH_CHUNK, args.march_chunk)
     from paper_2606_11103_amd.native import (FW_OPT_PLANE_KERNELS, FW_OPT_PLANE_ROWS, FW_OPT_PRS_PLANES,
-                                             FW_OPT_VEL_PLANES)
+                                             FW_OPT_STEP_CHUNK, FW_OPT_VEL_PLANES)
     for key, val in ((FW_OPT_PLANE_KERNELS, args.plane_kernels), (FW_OPT_PLANE_ROWS, args.plane_rows),
-                     (FW_OPT_VEL_PLANES, args.vel_planes), (FW_OPT_PRS_PLANES, args.prs_planes)):
+                     (FW_OPT_VEL_PLANES, args.vel_planes), (FW_OPT_PRS_PLANES, args.prs_planes),
+                     (FW_OPT_STEP_CHUNK, args.step_chunk)):
         if val is not None:
             sim.set_option(key, val)
     print("# simulation ready (%.1f GB workspace)" % (sim.workspace.numel() / 1e9), file=sys.stderr, flush=True)
@@ -643,7 +671,9 @@ def main():
     ach_vel = b_vel * cells / (kern_ms[0] / 1e3) / 1e9
     ach_prs = b_prs * cells / (kern_ms[1] / 1e3) / 1e9
     ach_step = b_step * cells / (ms_step / 1e3) / 1e9
-    meas = TRAFFIC_MEASURED.get(kernel_source_hash())
+    chunk = step_chunk_planes(case, args.step_chunk)
+    n_vel_launches = 1 if chunk == 0 else -(-max(int(s[2]) for s in case.shapes) // chunk)
+    meas = TRAFFIC_MEASURED.get((kernel_source_hash(), chunk))
     traffic = traffic_vel = None
     shape_opts = (args.tile_rows or args.rows_per_thread or args.march_chunk or
                   any(v is not None for v in (args.plane_kernels, args.plane_rows, args.vel_planes, args.prs_planes)))
@@ -675,9 +705,13 @@ def main():
                      "traffic_note": "FETCH_SIZE x 2 + WRITE_SIZE bytes of the step's kernels per step (L2 misses "
                                      "to the fabric: includes last-level-cache hits) / live step time, see profile",
                      "bytes_per_cell": round(b_step, 2), "avg_ms": round(ms_step, 4),
+                     "step_schedule": ("whole-grid launches" if chunk == 0 else
+                                       "interleaved velocity/pressure chunks of %d planes" % chunk),
                      "dominant_kernel": {"kernel": "velocity update", "achieved": round(ach_vel, 1),
                                          "frac": round(ach_vel / HBM_PEAK_GBS, 4), "traffic": traffic_vel,
-                                         "bytes_per_cell": round(b_vel, 2), "avg_ms": round(kern_ms[0], 4)},
+                                         "bytes_per_cell": round(b_vel, 2), "avg_ms": round(kern_ms[0], 4),
+                                         "launches_per_step": n_vel_launches,
+                                         "avg_ms_per_launch": round(kern_ms[0] / n_vel_launches, 4)},
                      "pressure_kernel": {"achieved": round(ach_prs, 1), "frac": round(ach_prs / HBM_PEAK_GBS, 4),
                                          "bytes_per_cell": round(b_prs, 2), "avg_ms": round(kern_ms[1], 4)}},
         "kernels_ms": {"velocity": round(kern_ms[0], 4), "pressure": round(kern_ms[1], 4),

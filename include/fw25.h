@@ -316,9 +316,12 @@ int fw_adjoint_modulus(fw_sim *sim, int n_steps, int ckpt_every, void *d_work, i
 /*
  * Advance n_steps steps like fw_step, but launch every kernel eagerly with a
  * HIP event before and after it on hip_stream, wait for completion, and
- * return the average duration in milliseconds of each kernel kind:
+ * return the average time per step in milliseconds of each kernel kind:
  * avg_ms[0] velocity update, avg_ms[1] pressure update, avg_ms[2] sources and
- * receivers.  Used for per-kernel roofline figures; the state advances.
+ * receivers.  The launches are those of fw_step: with the interleaved chunk
+ * schedule (FW_OPT_STEP_CHUNK) a kind's figure is the sum over its chunk
+ * launches of one step.  Used for per-kernel roofline figures; the state
+ * advances.
  */
 int fw_time_kernels(fw_sim *sim, int n_steps, void *hip_stream, double *avg_ms);
 
@@ -380,7 +383,11 @@ int fw_read_field(fw_sim *sim, int field, int domain, float *dst, int dst_is_dev
  *           cell read and written as one [cell][axis][N] stream over the
  *           memory of the three arrays (a layout the step does not use;
  *           every address still gets back the value read from it);
- *   mode 4: mode 3 with v read and written as one [cell][axis] stream too.
+ *   mode 4: mode 3 with v read and written as one [cell][axis] stream too;
+ *   mode 5: mode 0 with the face memory variables blocked by 64 cells,
+ *           [cell / 64][axis][cell % 64][N] (needs a multiple of 64 stored
+ *           cells, FW_EUNSUPPORTED otherwise);
+ *   mode 6: mode 5 with v blocked the same way, [cell / 64][axis][cell % 64].
  *   order 0: one flat sweep (neighbouring cells in concurrent workgroups);
  *   order 1: 64 x 4 tiles each marching 48 planes along z.
  * CPML variables are not moved.  Requires one 3D domain (FW_EUNSUPPORTED
@@ -426,8 +433,19 @@ int fw_device_copy(void *d_dst, const void *d_src, int64_t bytes, void *hip_stre
  *                        (2D default); 16 in 2D.  More rows mean fewer y-halo
  *                        reads per cell; which is faster depends on the grid
  *                        (the autotuner times them).
- *   FW_OPT_VEL_PLANES    planes per tile of the velocity plane kernel: 1
- *                        (default) or 2 (more loads in flight per thread).
+ *   FW_OPT_STEP_CHUNK    3D with both plane kernels: C >= 4 = the step runs
+ *                        the velocity update over planes [cC, (c+1)C) then the
+ *                        pressure update over [cC-3, (c+1)C-3), chunk after
+ *                        chunk (same results); 0 = each update runs once over
+ *                        the whole grid; -1 (default) = 120-plane chunks on
+ *                        grids of at least 480 planes of 200 k cells, whole-
+ *                        grid launches otherwise.  fw_time_kernels follows
+ *                        the same schedule; the energy step and the adjoint
+ *                        run whole-grid launches.
+ *   FW_OPT_VEL_PLANES    planes per tile of the velocity plane kernel: 1, 2
+ *                        or 4 (more loads in flight per thread, more
+ *                        registers); default 1 with N >= 3 mechanisms, 2 with
+ *                        N <= 2.
  *   FW_OPT_PRS_PLANES    planes per tile of the pressure plane kernel: 2, 4
  *                        or 8 (a longer tile re-reads the v_z window less
  *                        often, a shorter one needs fewer registers); default
@@ -436,7 +454,7 @@ int fw_device_copy(void *d_dst, const void *d_src, int64_t bytes, void *hip_stre
  */
 enum { FW_OPT_GRAPH_STEPS = 1, FW_OPT_MARCH_CHUNK = 2, FW_OPT_TILE_ROWS = 3, FW_OPT_ROWS_PER_THREAD = 4,
        FW_OPT_PERSISTENT = 5, FW_OPT_TILE_ORDER = 6, FW_OPT_PLANE_KERNELS = 7, FW_OPT_PLANE_ROWS = 8,
-       FW_OPT_VEL_PLANES = 9, FW_OPT_PRS_PLANES = 10 };
+       FW_OPT_VEL_PLANES = 9, FW_OPT_PRS_PLANES = 10, FW_OPT_STEP_CHUNK = 11 };
 int fw_set_option(fw_sim *sim, int key, int64_t value);
 
 #ifdef __cplusplus

@@ -21,16 +21,26 @@ namespace {
 // MODE 3: MODE 0 with the three per-axis psi1 groups of a cell stored together
 //         ([cell][axis][N] over the psi1 arrays' memory), one stream instead of three
 // MODE 4: MODE 3 with v stored [cell][axis] as well
+// MODE 5: MODE 0 with the psi1 arrays blocked by 64 cells: [cell / 64][axis]
+//         [cell % 64][N], so a wave's three axis groups are 3 KB in a row
+//         (one stream, every load instruction on whole lines)
+// MODE 6: MODE 5 with v blocked the same way ([cell / 64][axis][cell % 64])
 template <int N, int MODE>
 __device__ __forceinline__ void probe_cell(const Fields &F, int64_t g)
 {
     // every load first (the stores may alias them), then every store
-    constexpr bool ILV1 = MODE >= 3, ILV_V = MODE == 4;
+    constexpr bool ILV1 = MODE == 3 || MODE == 4, ILV_V = MODE == 4;
+    constexpr bool BLK1 = MODE >= 5, BLK_V = MODE == 6;
+    const int64_t blk = g >> 6, lane = g & 63;
     float *vp[3], *psi1[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        vp[a] = ILV_V ? F.vx + g * 3 + a : (a == 0 ? F.vx : (a == 1 ? F.vy : F.vz)) + g;
-        psi1[a] = ILV1 ? F.psi1x + (g * 3 + a) * N : (a == 0 ? F.psi1x : (a == 1 ? F.psi1y : F.psi1z)) + g * N;
+        vp[a] = ILV_V ? F.vx + g * 3 + a
+              : BLK_V ? F.vx + (blk * 3 + a) * 64 + lane
+                      : (a == 0 ? F.vx : (a == 1 ? F.vy : F.vz)) + g;
+        psi1[a] = ILV1 ? F.psi1x + (g * 3 + a) * N
+                : BLK1 ? F.psi1x + ((blk * 3 + a) * 64 + lane) * N
+                       : (a == 0 ? F.psi1x : (a == 1 ? F.psi1y : F.psi1z)) + g * N;
     }
     const float p = load1_stream(F.p + g);
     const float c = (float)F.cls[g];
@@ -96,6 +106,8 @@ hipError_t probe_n(int mode, int order, const Fields &F, int64_t nx, int64_t px,
         if (mode == 2) k_probe_flat<N, 2><<<grid, dim3(256), 0, s>>>(F, n);
         if (mode == 3) k_probe_flat<N, 3><<<grid, dim3(256), 0, s>>>(F, n);
         if (mode == 4) k_probe_flat<N, 4><<<grid, dim3(256), 0, s>>>(F, n);
+        if (mode == 5) k_probe_flat<N, 5><<<grid, dim3(256), 0, s>>>(F, n);
+        if (mode == 6) k_probe_flat<N, 6><<<grid, dim3(256), 0, s>>>(F, n);
     } else {
         const int chunk = 48;
         const int64_t tiles = ((nx + 63) / 64) * ((ny + 3) / 4) * ((nz + chunk - 1) / chunk);
@@ -106,6 +118,8 @@ hipError_t probe_n(int mode, int order, const Fields &F, int64_t nx, int64_t px,
         if (mode == 2) k_probe_march<N, 2><<<grid, block, 0, s>>>(F, (int)nx, (int)px, (int)ny, (int)nz, chunk, (int)tiles, per_xcd);
         if (mode == 3) k_probe_march<N, 3><<<grid, block, 0, s>>>(F, (int)nx, (int)px, (int)ny, (int)nz, chunk, (int)tiles, per_xcd);
         if (mode == 4) k_probe_march<N, 4><<<grid, block, 0, s>>>(F, (int)nx, (int)px, (int)ny, (int)nz, chunk, (int)tiles, per_xcd);
+        if (mode == 5) k_probe_march<N, 5><<<grid, block, 0, s>>>(F, (int)nx, (int)px, (int)ny, (int)nz, chunk, (int)tiles, per_xcd);
+        if (mode == 6) k_probe_march<N, 6><<<grid, block, 0, s>>>(F, (int)nx, (int)px, (int)ny, (int)nz, chunk, (int)tiles, per_xcd);
     }
     return hipGetLastError();
 }
@@ -115,7 +129,7 @@ hipError_t probe_n(int mode, int order, const Fields &F, int64_t nx, int64_t px,
 hipError_t launch_stream_probe(int nmech, int mode, int order, const Fields &F, int64_t nx, int64_t px, int64_t ny,
                                int64_t nz, hipStream_t s)
 {
-    if (mode < 0 || mode > 4 || order < 0 || order > 1) return hipErrorInvalidValue;
+    if (mode < 0 || mode > 6 || order < 0 || order > 1) return hipErrorInvalidValue;
     switch (nmech) {
     case 1: return probe_n<1>(mode, order, F, nx, px, ny, nz, s);
     case 2: return probe_n<2>(mode, order, F, nx, px, ny, nz, s);

@@ -104,6 +104,15 @@ struct fw_sim {
     // device tables
     DevBuf d_doms, d_classes, d_pml, d_tiles, d_vtiles, d_ptiles, d_waves, d_traces, d_step;
     float *traces_ext = nullptr;         // caller-owned trace buffer (fw_set_receivers_into), borrowed
+    // interleaved 3D schedule (FW_OPT_STEP_CHUNK): per chunk, the velocity
+    // tiles of planes [cC, (c+1)C) and the pressure tiles of [cC-3, (c+1)C-3)
+    struct ChunkList {
+        int64_t voff, poff;
+        int32_t vn, vper, pn, pper;
+    };
+    int step_chunk = -1;                 // -1: automatic (kStepChunk on large grids), 0: off
+    std::vector<ChunkList> chunks;
+    DevBuf d_vchunks, d_pchunks;
     float *traces() const { return traces_ext ? traces_ext : d_traces.as<float>(); }
     DevBuf d_srcrec, d_rec_of;
     std::vector<int64_t> h_src_cell, h_rec_cell;   // global cells of the sources and the receivers
@@ -232,7 +241,9 @@ int stability_check(const fw_sim *s, double min_kappa_prod)
 // Plane-major tile list in 8 segments, one per XCD: segment k holds y-band k
 // (of the y-tiles) of every chunk of planes, domain by domain; segments are
 // padded with empty tiles (z1 == z0, skipped by every kernel) to one length.
-static std::vector<fw::Tile> banded_tiles(const fw_sim *s, int tx, int ty, int64_t chunk_or_auto)
+// Only planes [zlo, zhi) of each domain when given (the interleaved schedule).
+static std::vector<fw::Tile> banded_tiles(const fw_sim *s, int tx, int ty, int64_t chunk_or_auto, int64_t zlo = 0,
+                                          int64_t zhi = std::numeric_limits<int64_t>::max())
 {
     std::vector<fw::Tile> seg[8];
     for (int d = 0; d < s->n_domains; ++d) {
@@ -244,7 +255,8 @@ static std::vector<fw::Tile> banded_tiles(const fw_sim *s, int tx, int ty, int64
             chunk = (nz + nch - 1) / nch;
         }
         chunk = std::max<int64_t>(1, std::min<int64_t>(chunk, nz));
-        for (int64_t z0 = 0; z0 < nz; z0 += chunk)
+        const int64_t za = std::max<int64_t>(0, zlo), zb = std::min(nz, zhi);
+        for (int64_t z0 = za; z0 < zb; z0 += chunk)
             for (int k = 0; k < 8; ++k)
                 for (int64_t yt = k * nytile / 8; yt < (k + 1) * nytile / 8; ++yt)
                     for (int64_t xt = 0; xt < nxtile; ++xt) {
@@ -253,7 +265,7 @@ static std::vector<fw::Tile> banded_tiles(const fw_sim *s, int tx, int ty, int64
                         t.x0 = (int32_t)(xt * tx);
                         t.y0 = (int32_t)(yt * ty);
                         t.z0 = (int32_t)z0;
-                        t.z1 = (int32_t)std::min(nz, z0 + chunk);
+                        t.z1 = (int32_t)std::min(zb, z0 + chunk);
                         seg[k].push_back(t);
                     }
     }
@@ -297,6 +309,64 @@ static bool plane_pressure_on(const fw_sim *s)
 {
     if (s->ndim == 2) return s->plane_kernels == 1 || (s->plane_kernels < 0 && kTile2dDefault);
     return s->ndim == 3 && s->plane_kernels != 0;
+}
+
+// Interleaved schedule: velocity over planes [cC, (c+1)C), then pressure
+// over [cC - 3, (c+1)C - 3) (from 0 for the first chunk, to the last plane for
+// the last).  The pressure update of plane j reads v_z of planes up to j + 3,
+// all updated by then; the velocity update of plane j reads p of planes down
+// to j - 3, none of which an earlier pressure chunk has written.  So every
+// cell sees the same operands as in the two whole-grid launches (same bits),
+// while the planes the pressure update reads again were touched one chunk
+// earlier.
+// Automatic choice (measured, per graph-replayed step, whole-grid / 120-plane
+// chunks): 960 x 960 x 720 N = 4 21.65 / 21.45 ms, 499 x 499 x 1247 N = 2
+// 7.41 / 7.27 ms, 512^3 N = 4 4.38 / 4.33 ms; on 256^3 the chunks' extra
+// launch tails cost more than they save (0.537 / 0.553 ms with 128 planes),
+// so grids of fewer than 480 planes or 200 k cells per plane keep whole-grid
+// launches.
+constexpr int64_t kStepChunk = 120, kChunkMinPlanes = 480, kChunkMinPlaneCells = 200000;
+
+static int build_chunk_lists(fw_sim *s)
+{
+    s->chunks.clear();
+    if (s->step_chunk == 0 || s->ndim != 3 || !plane_velocity_on(s) || !plane_pressure_on(s)) return FW_OK;
+    int64_t nzmax = 0, plane_max = 0;
+    for (const auto &d : s->doms) {
+        nzmax = std::max<int64_t>(nzmax, d.n[2]);
+        plane_max = std::max<int64_t>(plane_max, d.n[0] * d.n[1]);
+    }
+    if (s->step_chunk < 0 && (nzmax < kChunkMinPlanes || plane_max < kChunkMinPlaneCells)) return FW_OK;
+    const int64_t C = s->step_chunk < 0 ? kStepChunk : s->step_chunk;
+    const int64_t nch = (nzmax + C - 1) / C;
+    std::vector<fw::Tile> va, pa;
+    for (int64_t c = 0; c < nch; ++c) {
+        const int64_t plo = c == 0 ? 0 : c * C - 3;
+        const int64_t phi = c + 1 == nch ? nzmax : (c + 1) * C - 3;
+        std::vector<fw::Tile> v = banded_tiles(s, 64, s->plane_rows, s->vel_planes, c * C, (c + 1) * C);
+        std::vector<fw::Tile> p = banded_tiles(s, 64, s->plane_rows, s->prs_planes, plo, phi);
+        fw_sim::ChunkList L{};
+        L.voff = (int64_t)va.size();
+        L.vn = (int32_t)v.size();
+        L.vper = (L.vn + 7) / 8;
+        L.poff = (int64_t)pa.size();
+        L.pn = (int32_t)p.size();
+        L.pper = (L.pn + 7) / 8;
+        va.insert(va.end(), v.begin(), v.end());
+        pa.insert(pa.end(), p.begin(), p.end());
+        s->chunks.push_back(L);
+    }
+    if (va.size() > (size_t)std::numeric_limits<int32_t>::max() || pa.size() > (size_t)std::numeric_limits<int32_t>::max())
+        return fail(FW_EINVAL, "too many tiles in the interleaved schedule");
+    if (!va.empty()) {
+        HIP_OR_FAIL(s->d_vchunks.ensure(va.size() * sizeof(fw::Tile)));
+        HIP_OR_FAIL(hipMemcpy(s->d_vchunks.ptr, va.data(), va.size() * sizeof(fw::Tile), hipMemcpyHostToDevice));
+    }
+    if (!pa.empty()) {
+        HIP_OR_FAIL(s->d_pchunks.ensure(pa.size() * sizeof(fw::Tile)));
+        HIP_OR_FAIL(hipMemcpy(s->d_pchunks.ptr, pa.data(), pa.size() * sizeof(fw::Tile), hipMemcpyHostToDevice));
+    }
+    return FW_OK;
 }
 
 int build_tiles(fw_sim *s)
@@ -355,6 +425,8 @@ int build_tiles(fw_sim *s)
     rc = upload_tiles(vt, s->d_vtiles, &s->n_vtiles, &s->vtiles_per_xcd);
     if (rc != FW_OK) return rc;
     rc = upload_tiles(pt, s->d_ptiles, &s->n_ptiles, &s->ptiles_per_xcd);
+    if (rc != FW_OK) return rc;
+    rc = build_chunk_lists(s);
     if (rc != FW_OK) return rc;
     s->tiles_dirty = false;
     s->drop_graph();
@@ -416,13 +488,42 @@ fw::SrcRecArgs srcrec_args(const fw_sim *s)
     return a;
 }
 
+// The step's arguments restricted to one chunk of the interleaved schedule.
+static fw::StepArgs chunk_args(const fw_sim *s, const fw::StepArgs &a, const fw_sim::ChunkList &L)
+{
+    fw::StepArgs c = a;
+    c.vtiles = s->d_vchunks.as<fw::Tile>() + L.voff;
+    c.n_vtiles = L.vn;
+    c.vtiles_per_xcd = L.vper;
+    c.ptiles = s->d_pchunks.as<fw::Tile>() + L.poff;
+    c.n_ptiles = L.pn;
+    c.ptiles_per_xcd = L.pper;
+    return c;
+}
+
+static bool interleaved_on(const fw_sim *s, const fw::StepArgs &a)
+{
+    return !s->chunks.empty() && a.plane && a.plane_p;
+}
+
 int enqueue_steps(fw_sim *s, int n, hipStream_t st)
 {
     const fw::StepArgs a = step_args(s);
     const fw::SrcRecArgs r = srcrec_args(s);
+    const bool interleaved = interleaved_on(s, a);
     for (int i = 0; i < n; ++i) {
-        HIP_OR_FAIL(fw::launch_velocity(s->ndim, s->nmech, s->tile_rows, s->rows_per_thread, a, st));
-        HIP_OR_FAIL(fw::launch_pressure(s->ndim, s->nmech, s->tile_rows, s->rows_per_thread, a, st));
+        if (interleaved) {
+            for (const auto &L : s->chunks) {
+                const fw::StepArgs c = chunk_args(s, a, L);
+                if (L.vn > 0)
+                    HIP_OR_FAIL(fw::launch_velocity(s->ndim, s->nmech, s->tile_rows, s->rows_per_thread, c, st));
+                if (L.pn > 0)
+                    HIP_OR_FAIL(fw::launch_pressure(s->ndim, s->nmech, s->tile_rows, s->rows_per_thread, c, st));
+            }
+        } else {
+            HIP_OR_FAIL(fw::launch_velocity(s->ndim, s->nmech, s->tile_rows, s->rows_per_thread, a, st));
+            HIP_OR_FAIL(fw::launch_pressure(s->ndim, s->nmech, s->tile_rows, s->rows_per_thread, a, st));
+        }
         HIP_OR_FAIL(fw::launch_src_rec(r, st));
     }
     return FW_OK;
@@ -1003,18 +1104,37 @@ int fw_time_kernels(fw_sim *sim, int n_steps, void *hip_stream, double *avg_ms)
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     const fw::StepArgs a = step_args(sim);
     const fw::SrcRecArgs r = srcrec_args(sim);
-    std::vector<hipEvent_t> ev((size_t)n_steps * 4, nullptr);
+    // the launches of one step in the order fw_step issues them, each with
+    // the update it belongs to (0 velocity, 1 pressure, 2 sources/receivers)
+    std::vector<std::pair<int, fw::StepArgs>> plan;
+    if (interleaved_on(sim, a)) {
+        for (const auto &L : sim->chunks) {
+            const fw::StepArgs c = chunk_args(sim, a, L);
+            if (L.vn > 0) plan.emplace_back(0, c);
+            if (L.pn > 0) plan.emplace_back(1, c);
+        }
+    } else {
+        plan.emplace_back(0, a);
+        plan.emplace_back(1, a);
+    }
+    plan.emplace_back(2, a);
+    const size_t per = plan.size() + 1;
+    std::vector<hipEvent_t> ev((size_t)n_steps * per, nullptr);
     for (auto &e : ev) HIP_OR_FAIL(hipEventCreate(&e));
     int rc = FW_OK;
     for (int i = 0; i < n_steps && rc == FW_OK; ++i) {
-        hipEvent_t *e = &ev[(size_t)i * 4];
+        hipEvent_t *e = &ev[(size_t)i * per];
         hipError_t err = hipEventRecord(e[0], st);
-        if (err == hipSuccess) err = fw::launch_velocity(sim->ndim, sim->nmech, sim->tile_rows, sim->rows_per_thread, a, st);
-        if (err == hipSuccess) err = hipEventRecord(e[1], st);
-        if (err == hipSuccess) err = fw::launch_pressure(sim->ndim, sim->nmech, sim->tile_rows, sim->rows_per_thread, a, st);
-        if (err == hipSuccess) err = hipEventRecord(e[2], st);
-        if (err == hipSuccess) err = fw::launch_src_rec(r, st);
-        if (err == hipSuccess) err = hipEventRecord(e[3], st);
+        for (size_t k = 0; k < plan.size() && err == hipSuccess; ++k) {
+            const fw::StepArgs &c = plan[k].second;
+            if (plan[k].first == 0)
+                err = fw::launch_velocity(sim->ndim, sim->nmech, sim->tile_rows, sim->rows_per_thread, c, st);
+            else if (plan[k].first == 1)
+                err = fw::launch_pressure(sim->ndim, sim->nmech, sim->tile_rows, sim->rows_per_thread, c, st);
+            else
+                err = fw::launch_src_rec(r, st);
+            if (err == hipSuccess) err = hipEventRecord(e[k + 1], st);
+        }
         if (err != hipSuccess) rc = fail(FW_EHIP, "timed launch: %s", hipGetErrorString(err));
     }
     double tot[3] = {0, 0, 0};
@@ -1022,11 +1142,11 @@ int fw_time_kernels(fw_sim *sim, int n_steps, void *hip_stream, double *avg_ms)
         hipError_t err = hipStreamSynchronize(st);
         if (err != hipSuccess) rc = fail(FW_EHIP, "hipStreamSynchronize: %s", hipGetErrorString(err));
         for (int i = 0; i < n_steps && rc == FW_OK; ++i)
-            for (int k = 0; k < 3; ++k) {
+            for (size_t k = 0; k < plan.size() && rc == FW_OK; ++k) {
                 float ms = 0;
-                err = hipEventElapsedTime(&ms, ev[(size_t)i * 4 + k], ev[(size_t)i * 4 + k + 1]);
+                err = hipEventElapsedTime(&ms, ev[(size_t)i * per + k], ev[(size_t)i * per + k + 1]);
                 if (err != hipSuccess) rc = fail(FW_EHIP, "hipEventElapsedTime: %s", hipGetErrorString(err));
-                tot[k] += ms;
+                tot[plan[k].first] += ms;
             }
     }
     for (auto &e : ev) (void)hipEventDestroy(e);
@@ -1349,14 +1469,17 @@ int fw_stream_probe(fw_sim *sim, int mode, int order, int reps, void *hip_stream
     if (!sim || !avg_ms) return fail(FW_EINVAL, "NULL argument");
     if (!sim->ws || !sim->media_set) return fail(FW_ESTATE, "set up the simulation first");
     if (sim->ndim != 3 || sim->n_domains != 1) return fail(FW_EUNSUPPORTED, "the probe runs on one 3D domain");
-    if (mode < 0 || mode > 4 || order < 0 || order > 1 || reps < 1)
-        return fail(FW_EINVAL, "mode must be 0..4, order 0..1, reps >= 1");
+    if (mode < 0 || mode > 6 || order < 0 || order > 1 || reps < 1)
+        return fail(FW_EINVAL, "mode must be 0..6, order 0..1, reps >= 1");
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     const fw::Fields f = fields_of(sim);
     const fw::DomainDesc &D = sim->doms[0];
-    // modes 3 and 4 read the three per-axis arrays as one interleaved array:
-    // they must lie back to back, each holding at least the stored cells
+    // modes 3 to 6 read the three per-axis arrays as one interleaved or
+    // blocked array: they must lie back to back, each holding at least the
+    // stored cells; the 64-cell blocks of modes 5 and 6 must tile them
     const int64_t stored = sim->stored(0);
+    if (mode >= 5 && stored % 64 != 0)
+        return fail(FW_EUNSUPPORTED, "blocked probe modes need a multiple of 64 stored cells");
     if (mode >= 3 && (sim->off_psi2 - sim->off_psi1[0] < 3 * stored * sim->nmech * (int64_t)sizeof(float) ||
                       sim->off_psi1[0] - sim->off_v[0] < 3 * stored * (int64_t)sizeof(float)))
         return fail(FW_EUNSUPPORTED, "interleaved probe modes need the per-axis arrays back to back");
@@ -1490,6 +1613,12 @@ int fw_set_option(fw_sim *sim, int key, int64_t value)
         if (value != 2 && value != 4 && value != 8)
             return fail(FW_EINVAL, "pressure plane-kernel tiles hold 2, 4 or 8 planes");
         sim->prs_planes = (int)value;
+        sim->tiles_dirty = true;
+        return FW_OK;
+    case FW_OPT_STEP_CHUNK:
+        if (value != -1 && value != 0 && (value < 4 || value > 65536))
+            return fail(FW_EINVAL, "interleaved chunk must be -1 (auto), 0 (off) or 4..65536 planes");
+        sim->step_chunk = (int)value;
         sim->tiles_dirty = true;
         return FW_OK;
     case FW_OPT_ROWS_PER_THREAD:

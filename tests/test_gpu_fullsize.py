@@ -249,3 +249,33 @@ def test_full_size_3d_state_round_trip_is_bitwise():
     del sim, buf, ref
     torch.cuda.empty_cache()
     assert all(same)
+
+
+def test_full_size_interleaved_schedule_equals_whole_grid_launches():
+    """On the 960 x 960 x 720, N = 4 grid the step runs by default as
+    interleaved velocity/pressure chunks of 120 planes (pressure lagging 3
+    planes); 60 steps of it give the same pressure and velocity fields, bit for
+    bit, as 60 steps of the two whole-grid launches (FW_OPT_STEP_CHUNK 0)."""
+    import torch
+    from paper_2606_11103_amd import relax
+    from paper_2606_11103_amd.native import FW_OPT_STEP_CHUNK
+    torch.cuda.empty_cache()
+    case = configs.heterogeneous_3d(shape=(960, 960, 720), steps=2000)
+    kappa, d, al, _ = relax.tables_for(dict(c=case.c, alpha0=case.alpha0, y=case.y), case.nmech,
+                                      allow_fit=False, dt=case.dt)
+    configs.with_table(case, kappa, d, al)
+    print("full-size 3D interleaved schedule", case.shapes, flush=True)
+    sim = to_simulation(case)
+    sim.set_option(FW_OPT_STEP_CHUNK, 0)
+    sim.step(60)
+    ref = [sim.read_field(f, device=True) for f in range(4)]
+    del sim
+    torch.cuda.empty_cache()
+    assert float(ref[0].abs().max()) > 0.0
+    sim = to_simulation(case)
+    sim.step(60)
+    same = [bool(torch.equal(sim.read_field(f, device=True), ref[f])) for f in range(4)]
+    report("full-size 3D interleaved chunks vs whole-grid launches, 60 steps: fields bitwise equal %s" % (same,))
+    del sim, ref
+    torch.cuda.empty_cache()
+    assert all(same)

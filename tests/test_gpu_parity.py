@@ -149,6 +149,24 @@ def test_plane_kernels_on_a_ragged_3d_batch():
            % (glob, worst, n))
 
 
+def test_interleaved_chunk_schedule_is_bitwise_equal():
+    """FW_OPT_STEP_CHUNK: velocity and pressure plane kernels interleaved in
+    chunks of C planes (pressure lagging 3 planes) give the same bits as the
+    two whole-grid launches, on a ragged 3D batch whose domains end at
+    different planes (17, 18 and 21), with chunk sizes that do and do not
+    divide them, 1- and 2-plane velocity tiles and 2/8-plane pressure tiles,
+    through graph replay and eager steps."""
+    from paper_2606_11103_amd.native import (FW_OPT_GRAPH_STEPS, FW_OPT_PLANE_KERNELS, FW_OPT_PRS_PLANES,
+                                             FW_OPT_STEP_CHUNK, FW_OPT_VEL_PLANES)
+    case = configs.random_small(3, [(70, 17, 21), (33, 38, 17), (130, 97, 18)], 2, 3, seed=44, steps=70, pml=4)
+    case = configs.with_table(case, *configs.random_relaxation_table(144, case.n_classes, case.nmech))
+    _, ref = _run(case, opts={FW_OPT_PLANE_KERNELS: 1, FW_OPT_STEP_CHUNK: 0})
+    for chunk, vp, pp, gs in ((4, 1, 2, 16), (5, 2, 8, 16), (7, 1, 8, 0), (16, 2, 2, 7), (64, 1, 2, 16)):
+        _, got = _run(case, opts={FW_OPT_PLANE_KERNELS: 1, FW_OPT_STEP_CHUNK: chunk, FW_OPT_VEL_PLANES: vp,
+                                  FW_OPT_PRS_PLANES: pp, FW_OPT_GRAPH_STEPS: gs})
+        assert np.array_equal(ref, got), (chunk, vp, pp, gs)
+
+
 @pytest.mark.parametrize("nmech", [1, 2, 3, 4])
 def test_2d_tile_kernels_on_a_ragged_batch(nmech):
     """Five 2D domains of different shapes (widths 70, 33, 130, 64 and 65
