@@ -54,11 +54,11 @@ TRAFFIC_MEASURED = {
 AUTO_CHUNK, AUTO_CHUNK_MIN_PLANES, AUTO_CHUNK_MIN_PLANE_CELLS = 120, 480, 200000
 
 
-def step_chunk_planes(case, step_chunk=None):
-    """Planes per chunk of the step's interleaved schedule for this case and
-    FW_OPT_STEP_CHUNK value (None: the default), 0 for whole-grid launches.
-    Plane kernels are assumed on (the 3D default)."""
-    if case.ndim != 3 or step_chunk == 0:
+def step_chunk_planes(case, step_chunk=None, plane_kernels=None):
+    """Planes per chunk of the step's interleaved schedule for this case,
+    FW_OPT_STEP_CHUNK value (None: the default) and FW_OPT_PLANE_KERNELS value
+    (None: the default, plane kernels in 3D), 0 for whole-grid launches."""
+    if case.ndim != 3 or step_chunk == 0 or plane_kernels == 0:
         return 0
     if step_chunk is not None and step_chunk > 0:
         return int(step_chunk)
@@ -246,7 +246,9 @@ def oracle_timings(seconds=8.0):
 
 
 def _time_steps(torch, sim, steps):
-    """Milliseconds for `steps` full steps through fw_step (graph replay)."""
+    """Milliseconds for `steps` full steps through fw_step (graph replay; the
+    graph is captured before the timed region)."""
+    sim.prepare()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
@@ -639,6 +641,7 @@ def main():
 
     stream = torch.cuda.current_stream()
     sim.step(args.warmup)
+    sim.prepare()                   # untimed: tile lists and the step graph's capture
     torch.cuda.synchronize()
     print("# warmup done", file=sys.stderr, flush=True)
 
@@ -671,7 +674,7 @@ def main():
     ach_vel = b_vel * cells / (kern_ms[0] / 1e3) / 1e9
     ach_prs = b_prs * cells / (kern_ms[1] / 1e3) / 1e9
     ach_step = b_step * cells / (ms_step / 1e3) / 1e9
-    chunk = step_chunk_planes(case, args.step_chunk)
+    chunk = step_chunk_planes(case, args.step_chunk, args.plane_kernels)
     n_vel_launches = 1 if chunk == 0 else -(-max(int(s[2]) for s in case.shapes) // chunk)
     meas = TRAFFIC_MEASURED.get((kernel_source_hash(), chunk))
     traffic = traffic_vel = None

@@ -197,6 +197,18 @@ int fw_set_receivers_into(fw_sim *sim, int64_t n_rec, const int32_t *domain, con
                           int n_t_max, float *d_traces, int64_t capacity);
 
 /*
+ * Set-up only (the step itself is that of fw_step, Sec. 3.3).
+ * Do now the set-up work the next fw_step would do first: build the tile
+ * lists if an option or the media changed them, and capture and instantiate
+ * the graph of FW_OPT_GRAPH_STEPS steps if it is not current, so that the
+ * following fw_step calls only launch (for callers that time steps or must
+ * keep set-up out of a latency-bound loop).  Launches no kernel and leaves
+ * the state unchanged.  FW_ESTATE before the workspace, media and relaxation
+ * table are set; FW_EHIP if capture fails.
+ */
+int fw_prepare(fw_sim *sim);
+
+/*
  * The FDTD step of Sec. 3.3 applied to Eqs. (wave1)/(wave2) of Sec. 2.1,
  * with the memory variables of Eq. (relaxation_psi) (staggered stencil of
  * order 8 in space, leapfrog in time).
@@ -417,14 +429,13 @@ int fw_device_copy(void *d_dst, const void *d_src, int64_t bytes, void *hip_stre
  *   FW_OPT_TILE_ORDER    order of the marching tiles: 0 = x fastest within a
  *                        chunk (default), 1 = y fastest, 2 = plane-major with
  *                        XCD k owning y-band k of every chunk (3D).
- *   FW_OPT_PLANE_KERNELS 3D: 1 = the velocity update runs on 64 x R
- *                        tiles of one plane and the pressure update on 64 x R
- *                        tiles of 4 planes, plane-major with XCD k owning
+ *   FW_OPT_PLANE_KERNELS 3D: 1 or -1 (default) = both updates run on 64 x R
+ *                        tiles of a few planes (FW_OPT_VEL_PLANES,
+ *                        FW_OPT_PRS_PLANES), plane-major with XCD k owning
  *                        y-band k of every plane (the z stencil reads its
  *                        eight-plane window from memory: it stays in the
  *                        last-level cache); 0 = both march the tiles set by the
- *                        options above; -1 (default) = the pressure update
- *                        always, the velocity update with N >= 2 mechanisms.
+ *                        options above.
  *                        2D: 1 or -1 (default) = both updates run on 64 x R
  *                        tiles, one per block, with both stencils read from
  *                        LDS; 0 = both march along y.  Not used with a

@@ -26,9 +26,8 @@ DEFAULT = {"plane_kernels": -1, "plane_rows": 4, "tile_rows": 4, "rows_per_threa
 def candidates(ndim):
     out = []
     if ndim == 3:
-        # the plane kernels ignore the marching shape; -1 picks them per update
-        # (with N = 1 the velocity update then marches the default shape)
-        for plane in (-1, 1):
+        # the plane kernels ignore the marching shape
+        for plane in (-1,):
             for prow in (4, 8):
                 for vp in (1, 2, 4):
                     for pp in (2, 4, 8):

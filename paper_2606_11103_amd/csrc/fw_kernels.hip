@@ -19,8 +19,7 @@
 // dispatched round-robin over the XCDs), keeping neighbouring tiles and their
 // halos in one L2.
 //
-// 3D grids use the plane kernels further down instead (by default the
-// pressure one always, the velocity one from N = 2 memory variables on):
+// 3D grids use the plane kernels further down instead (by default):
 // short tiles (one plane for the velocity update, two to eight for the
 // pressure update) on plane-major lists in which XCD k owns y-band k of every
 // plane, with the z stencil read from memory.  2D grids use the 2D tile

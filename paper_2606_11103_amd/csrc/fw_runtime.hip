@@ -293,16 +293,14 @@ static int upload_tiles(const std::vector<fw::Tile> &tiles, DevBuf &buf, int *n,
 }
 
 // plane kernels in use for the 3D updates (2D: the tile kernels): option 1
-// for both, 0 for neither;
-// -1 (auto) picks per update from measurements on 960 x 960 x 720: the
-// pressure plane kernel wins at every N (N = 1: 4.28 against 4.97 ms), the
-// velocity plane kernel from N = 2 on (N = 2: 10.55 / 10.63 ms, N = 4: 14.96 /
-// 16.70 ms) but not at N = 1 (9.05 / 7.89 ms: with one memory variable per
-// axis the z-window reads weigh too much)
+// or -1 (default) for both, 0 for neither.  On 960 x 960 x 720 the plane
+// kernels take the step from 24.13 to 21.54 ms at N = 4, 20.31 to 18.42 at
+// N = 3, 16.65 to 15.06 at N = 2 and 13.70 to 11.71 at N = 1 (marching
+// velocity with plane pressure: 12.64)
 static bool plane_velocity_on(const fw_sim *s)
 {
     if (s->ndim == 2) return s->plane_kernels == 1 || (s->plane_kernels < 0 && kTile2dDefault);
-    return s->ndim == 3 && (s->plane_kernels == 1 || (s->plane_kernels < 0 && s->nmech >= 2));
+    return s->ndim == 3 && s->plane_kernels != 0;
 }
 
 static bool plane_pressure_on(const fw_sim *s)
@@ -980,6 +978,19 @@ int fw_set_receivers_into(fw_sim *sim, int64_t n_rec, const int32_t *domain, con
                           float *d_traces, int64_t capacity)
 {
     return set_receivers_impl(sim, n_rec, domain, cell, n_t_max, d_traces, capacity, true);
+}
+
+int fw_prepare(fw_sim *sim)
+{
+    g_err.clear();
+    if (!sim) return fail(FW_EINVAL, "sim is NULL");
+    if (!sim->ws || !sim->media_set || !sim->table_set)
+        return fail(FW_ESTATE, "bind the workspace, then set media and the relaxation table before preparing");
+    if (sim->tiles_dirty) {
+        int rc = build_tiles(sim);
+        if (rc != FW_OK) return rc;
+    }
+    return sim->graph_steps > 0 ? ensure_graph(sim, sim->graph_steps) : FW_OK;
 }
 
 int fw_step(fw_sim *sim, int n_steps, void *hip_stream)

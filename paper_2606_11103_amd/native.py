@@ -38,6 +38,7 @@ SIGNATURES = {
     "fw_set_sources": (_I, [_P, _L, _P, _P, _P, _I, _P, _I]),
     "fw_set_receivers": (_I, [_P, _L, _P, _P, _I]),
     "fw_set_receivers_into": (_I, [_P, _L, _P, _P, _I, _P, _L]),
+    "fw_prepare": (_I, [_P]),
     "fw_step": (_I, [_P, _I, _P]),
     "fw_read_receivers": (_I, [_P, _P, _L, _I, _P]),
     "fw_reset_state": (_I, [_P, _P]),

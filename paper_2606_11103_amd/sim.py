@@ -94,6 +94,11 @@ class Simulation:
         self.n_rec = int(cell.size)
         self.n_t_max = int(n_t_max)
 
+    def prepare(self):
+        """Build the tile lists and capture the step graph now (fw_prepare),
+        so that following step() calls only launch."""
+        check(lib.fw_prepare(self._h))
+
     def step(self, n_steps, stream=None):
         check(lib.fw_step(self._h, int(n_steps), self._stream(stream)))
 

@@ -64,6 +64,8 @@ def test_workspace_bytes_and_state_order():
     assert lib.fw_state_bytes(h) > 0
     # stepping before anything is set up
     assert lib.fw_step(h, 1, None) == native.FW_ESTATE
+    assert lib.fw_prepare(h) == native.FW_ESTATE
+    assert lib.fw_prepare(None) == native.FW_EINVAL
     k = np.ones(4)
     assert lib.fw_set_relaxation_table(h, 2, ctypes.c_void_p(k.ctypes.data), ctypes.c_void_p(k.ctypes.data),
                                        ctypes.c_void_p(k.ctypes.data)) == native.FW_ESTATE

@@ -77,3 +77,5 @@ def test_step_chunk_planes_follows_the_automatic_rule():
     assert bench.step_chunk_planes(flat) == 0
     assert bench.step_chunk_planes(big, 0) == 0
     assert bench.step_chunk_planes(small, 16) == 16
+    assert bench.step_chunk_planes(big, None, 0) == 0
+    assert bench.step_chunk_planes(big, None, 1) == 120

@@ -88,6 +88,20 @@ def test_graph_and_eager_paths_are_bitwise_identical():
     _, b = _run(case, opts={FW_OPT_GRAPH_STEPS: 16})
     _, c = _run(case, opts={FW_OPT_GRAPH_STEPS: 7})
     assert np.array_equal(a, b) and np.array_equal(a, c)
+    # fw_prepare captures the graph ahead (twice: the second call finds it
+    # current) and leaves the state alone; an option change after it rebuilds
+    sim = to_simulation(case)
+    sim.prepare()
+    sim.prepare()
+    assert sim.get_step() == 0
+    sim.step(case.n_steps)
+    assert np.array_equal(a, sim.read_receivers())
+    sim = to_simulation(case)
+    sim.prepare()
+    sim.set_option(FW_OPT_GRAPH_STEPS, 5)
+    sim.prepare()
+    sim.step(case.n_steps)
+    assert np.array_equal(a, sim.read_receivers())
 
 
 def test_tiling_does_not_change_results():
