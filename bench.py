@@ -49,9 +49,9 @@ TRAFFIC_MEASURED = {
 }
 
 # The library's automatic choice of the interleaved schedule (FW_OPT_STEP_CHUNK
-# -1): 3D grids with both plane kernels, at least 480 planes and a plane of at
-# least 200 k cells run 120-plane chunks.
-AUTO_CHUNK, AUTO_CHUNK_MIN_PLANES, AUTO_CHUNK_MIN_PLANE_CELLS = 120, 480, 200000
+# -1): 3D grids with both plane kernels, at least 320 planes and a plane of at
+# least 100 k cells run 120-plane chunks.
+AUTO_CHUNK, AUTO_CHUNK_MIN_PLANES, AUTO_CHUNK_MIN_PLANE_CELLS = 120, 320, 100000
 
 
 def step_chunk_planes(case, step_chunk=None, plane_kernels=None):
@@ -395,29 +395,36 @@ def bench_paper_shape(torch, steps=100):
 
 
 def bench_sweep(torch, steps=2000):
-    """1D sweep: 544 domains x 8192 cells, N = 2, one batched launch; then
-    the same sweep with N = 4 (default launch shape)."""
+    """1D sweep: 544 domains x 8192 cells, N = 2 and N = 4, one batched
+    launch: the default resident step (each domain kept on chip by one
+    workgroup), the whole 14800-step run with it, and the per-step kernels
+    (FW_OPT_RESIDENT_1D 0) for comparison."""
+    from paper_2606_11103_amd.native import FW_OPT_RESIDENT_1D
     from workloads import configs
     from workloads.adapters import to_simulation
-    case = configs.sweep_1d()
-    tab = _tables_or_random(case, 3)
-    sim = to_simulation(case)
-    sim.step(32)                    # untimed: captures the step graph
-    ms_default = _time_steps(torch, sim, steps)
-    cfg = _tune(sim)
-    ms = _time_steps(torch, sim, steps)
-    del sim
-    case4 = configs.sweep_1d(nmech=4)
-    tab4 = _tables_or_random(case4, 3)
-    sim = to_simulation(case4)
-    sim.step(32)
-    ms4 = _time_steps(torch, sim, steps)
-    return {"workload": case.name, "cells": case.cells(), "steps": steps, "tables": tab,
-            "steps_of_full_run": case.n_steps,
-            "gcells": round(case.cells() * steps / (ms / 1e3) / 1e9, 3), "ms_per_step": round(ms / steps, 4),
-            "launch_shape": cfg, "default_shape_gcells": round(case.cells() * steps / (ms_default / 1e3) / 1e9, 3),
-            "n4": {"tables": tab4, "gcells": round(case4.cells() * steps / (ms4 / 1e3) / 1e9, 3),
-                   "ms_per_step": round(ms4 / steps, 4)}}
+    out = {}
+    for nmech in (2, 4):
+        case = configs.sweep_1d(nmech=nmech)
+        tab = _tables_or_random(case, 3)
+        sim = to_simulation(case)
+        sim.step(32)                # untimed
+        ms = _time_steps(torch, sim, steps)
+        sim.reset()
+        ms_full = _time_steps(torch, sim, case.n_steps)
+        sim.set_option(FW_OPT_RESIDENT_1D, 0)
+        sim.step(32)
+        ms_ps = _time_steps(torch, sim, steps)
+        del sim
+        r = {"tables": tab, "gcells": round(case.cells() * steps / (ms / 1e3) / 1e9, 3),
+             "ms_per_step": round(ms / steps, 5), "full_run_ms": round(ms_full, 2),
+             "per_step_kernels_gcells": round(case.cells() * steps / (ms_ps / 1e3) / 1e9, 3)}
+        if nmech == 2:
+            out.update({"workload": case.name, "cells": case.cells(), "steps": steps,
+                        "steps_of_full_run": case.n_steps, "step": "resident (one workgroup per domain)"})
+            out.update(r)
+        else:
+            out["n4"] = r
+    return out
 
 
 def bench_adjoint(torch, steps=3000, ckpt=55):

@@ -449,7 +449,7 @@ int fw_device_copy(void *d_dst, const void *d_src, int64_t bytes, void *hip_stre
  *                        pressure update over [cC-3, (c+1)C-3), chunk after
  *                        chunk (same results); 0 = each update runs once over
  *                        the whole grid; -1 (default) = 120-plane chunks on
- *                        grids of at least 480 planes of 200 k cells, whole-
+ *                        grids of at least 320 planes of 100 k cells, whole-
  *                        grid launches otherwise.  fw_time_kernels follows
  *                        the same schedule; the energy step and the adjoint
  *                        run whole-grid launches.
@@ -461,11 +461,20 @@ int fw_device_copy(void *d_dst, const void *d_src, int64_t bytes, void *hip_stre
  *                        or 8 (a longer tile re-reads the v_z window less
  *                        often, a shorter one needs fewer registers); default
  *                        2 with N >= 3 mechanisms, 8 with N <= 2.
+ *   FW_OPT_RESIDENT_1D   1D grids: -1 (default) or 1 = fw_step runs one
+ *                        workgroup per domain that keeps the domain's state
+ *                        on chip (p and v in LDS, memory variables in
+ *                        registers) for up to 4096 steps per launch, when
+ *                        every domain has at most 8192 cells, the two CPML
+ *                        slabs at most 1024 cells together and no strength
+ *                        map is set (otherwise, and with 0, the per-step
+ *                        kernels).  fw_time_kernels, the energy step and the
+ *                        adjoint's reverse sweep use the per-step kernels.
  * Options change the work decomposition only, never the results.
  */
 enum { FW_OPT_GRAPH_STEPS = 1, FW_OPT_MARCH_CHUNK = 2, FW_OPT_TILE_ROWS = 3, FW_OPT_ROWS_PER_THREAD = 4,
        FW_OPT_PERSISTENT = 5, FW_OPT_TILE_ORDER = 6, FW_OPT_PLANE_KERNELS = 7, FW_OPT_PLANE_ROWS = 8,
-       FW_OPT_VEL_PLANES = 9, FW_OPT_PRS_PLANES = 10, FW_OPT_STEP_CHUNK = 11 };
+       FW_OPT_VEL_PLANES = 9, FW_OPT_PRS_PLANES = 10, FW_OPT_STEP_CHUNK = 11, FW_OPT_RESIDENT_1D = 12 };
 int fw_set_option(fw_sim *sim, int key, int64_t value);
 
 #ifdef __cplusplus

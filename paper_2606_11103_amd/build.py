@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfw25.so")
-SOURCES = ["fw_kernels.hip", "fw_adjoint.hip", "fw_diag.hip", "fw_probe.hip", "fw_runtime.hip"]
+SOURCES = ["fw_kernels.hip", "fw_adjoint.hip", "fw_diag.hip", "fw_probe.hip", "fw_resident.hip", "fw_runtime.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

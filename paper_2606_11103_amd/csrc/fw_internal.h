@@ -148,6 +148,31 @@ struct AdjChainArgs {
     int64_t n_packed;
 };
 
+// Resident 1D step (fw_resident.hip): one workgroup per 1D domain of at most
+// kResident1dCells cells keeps the domain's state on chip for n_steps steps
+// (velocity, pressure, sources/receivers of each step), for CPML widths up to
+// kResident1dSlab / 2 cells.
+constexpr int kResident1dCells = 8192;
+constexpr int kResident1dSlab = 1024;
+
+struct Resident1dArgs {
+    StepArgs s;                // fields (read from s.f, written to s.fo), domains, tables, dt, noise
+    const SrcRecCell *cells;   // distinct source/receiver cells, sorted by cell
+    const int32_t *sr_range;   // [n_domains + 1]: domain d's entries of cells are [sr_range[d], sr_range[d + 1])
+    const int32_t *rec_of;
+    const float *waves;
+    int32_t n_t;
+    float *traces;
+    int64_t n_rec;
+    int32_t n_t_max;
+    int32_t n_steps;
+    int64_t *step, *bad_row;
+    uint32_t *done;
+};
+
+size_t resident1d_lds_bytes(int nmech, int class_cap);
+hipError_t launch_resident1d(int nmech, const Resident1dArgs &r, int n_domains, hipStream_t s);
+
 hipError_t launch_copy(void *dst, const void *src, int64_t bytes, hipStream_t s);
 // memory-traffic probe of one 3D domain: mode 0 velocity streams, 1 pressure
 // streams, 2 both in one pass; order 0 flat sweep, 1 64 x 4 tiles marching 48 planes

@@ -1,0 +1,287 @@
+// Resident 1D step: one workgroup per 1D domain keeps the whole domain on
+// the chip for a run of steps.  p and v live in LDS (with four zero cells on
+// either side, the outside of the domain), the memory variables of the two
+// operators in registers (strided ownership: thread t holds cells t, t + 1024,
+// ...), the CPML variables of the two slabs in LDS; every step is the
+// velocity update, the pressure update and the sources/receivers of the
+// domain, separated by workgroup barriers, and HBM is touched only to load
+// the state at the start and store it at the end of the run (plus the source
+// waveforms and the receiver traces).  A 1D domain of 8192 cells at N = 4
+// holds 320 KB of state: a per-step pass over HBM or the last-level cache
+// costs far more than the arithmetic, so the step is kept on chip.
+//
+// Each value is computed with the operations of k_velocity / k_pressure /
+// k_src_rec in 1D, in the same order (Sec. 3.3 step with the memory
+// variables of Eq. (relaxation_psi), CPML of Sec. 2.3, sources and receivers
+// of Sec. 4.1), so the results are bitwise those of the per-step kernels.
+#include "fw_internal.h"
+#include "fw_vec.h"
+
+namespace fw {
+
+namespace {
+
+constexpr int kNT = 1024;                          // threads per workgroup
+constexpr int kK = kResident1dCells / kNT;         // cells per thread
+
+__device__ __forceinline__ uint64_t splitmix64_r(uint64_t x)
+{
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ float stencil4_r(const float (&c)[4], float d1, float d2, float d3, float d4)
+{
+    return fmaf(c[3], d4, fmaf(c[2], d3, fmaf(c[1], d2, c[0] * d1)));
+}
+
+// bad_row <- min(bad_row, t) with -1 meaning "none yet"; workgroups run
+// different steps at the same time, so the first row is kept by value
+__device__ void flag_bad_row(int64_t *bad_row, int64_t t)
+{
+    unsigned long long *a = reinterpret_cast<unsigned long long *>(bad_row);
+    unsigned long long cur = __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (;;) {
+        const int64_t c = (int64_t)cur;
+        if (c >= 0 && c <= t) return;
+        const unsigned long long prev = atomicCAS(a, cur, (unsigned long long)t);
+        if (prev == cur) return;
+        cur = prev;                       // another workgroup changed it: retry against its value
+    }
+}
+
+// per-class coefficients of both operators in one LDS record per class, so
+// that a cell addresses all of them from one base (class x kCoefStride)
+constexpr int kCoefStride = 24;
+constexpr int kIK1 = 0, kIK2 = 1, kKB = 2, kTB = 3, kA1 = 4, kB1 = 8, kA2 = 12, kB2 = 16, kRHO = 20;
+
+template <int N>
+__global__ __launch_bounds__(kNT) void k_resident1d(const Resident1dArgs R)
+{
+    constexpr int L0 = 4;                             // LDS index of cell 0
+    __shared__ float sp[kResident1dCells + 8];
+    __shared__ float sv[kResident1dCells + 8];
+    __shared__ uint8_t scl[kResident1dCells];
+    // CPML of the slab cells (slab index: [0, P) the first slab, [P, 2P) the
+    // last): memory variables and coefficients of both operators
+    __shared__ float spp1[kResident1dSlab], spp2[kResident1dSlab];
+    __shared__ float saF[kResident1dSlab], sbF[kResident1dSlab], saC[kResident1dSlab], sbC[kResident1dSlab];
+    __shared__ int s_last;
+    extern __shared__ float s_coef[];                 // [class][kCoefStride]
+    const StepArgs &A = R.s;
+
+    const int d = blockIdx.x;
+    const int tid = threadIdx.x;
+    const DomainDesc D = A.doms[d];
+    const int n = (int)D.n[0];
+    const int P = A.pml;
+    const int ns = 2 * P < n ? 2 * P : n;             // slab cells: [0, P) and [n - P, n)
+    const int64_t o = D.cell_off;
+    const int64_t t0 = *R.step;
+    const int32_t poff = D.pml_off[0];
+
+    for (int c = tid; c < D.n_classes; c += kNT) {
+        const ClassCoef &cc = A.classes[D.class_base + c];
+        float *r = s_coef + c * kCoefStride;
+        r[kIK1] = cc.ik1;
+        r[kIK2] = cc.ik2;
+        r[kKB] = cc.K;
+        r[kTB] = cc.twobeta;
+        r[kRHO] = cc.rho;
+#pragma unroll
+        for (int nu = 0; nu < N; ++nu) {
+            r[kA1 + nu] = cc.a1[nu];
+            r[kB1 + nu] = cc.b1[nu];
+            r[kA2 + nu] = cc.a2[nu];
+            r[kB2 + nu] = cc.b2[nu];
+        }
+    }
+    for (int i = tid; i < kResident1dCells + 8; i += kNT) {
+        sp[i] = 0.0f;
+        sv[i] = 0.0f;
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += kNT) {
+        sp[L0 + i] = A.f.p[o + i];
+        sv[L0 + i] = A.f.vx[o + i];
+        scl[i] = A.f.cls[o + i];
+    }
+    for (int s = tid; s < ns; s += kNT) {
+        const int i = s < P ? s : n - 2 * P + s;
+        spp1[s] = A.f.pP1[0][o + i];
+        spp2[s] = A.f.pP2[0][o + i];
+        saF[s] = A.pml_tab[poff + i];
+        sbF[s] = A.pml_tab[poff + n + i];
+        saC[s] = A.pml_tab[poff + 2 * n + i];
+        sbC[s] = A.pml_tab[poff + 3 * n + i];
+    }
+    float ps1[kK][N], ps2[kK][N], mf[kK], Kf[kK];
+    int cb[kK];                                       // LDS record of the cell's class
+#pragma unroll
+    for (int k = 0; k < kK; ++k) {
+        const int i = tid + k * kNT;
+        if (i < n) {
+            load_stream<N>(A.f.psi1x + (o + i) * N, ps1[k]);
+            load_stream<N>(A.f.psi2 + (o + i) * N, ps2[k]);
+        }
+    }
+    __syncthreads();
+    // per-cell constants of the run: class record, face coefficient
+    // 2 dt / (rho_i + rho_{i+1}) and the (perturbed) bulk modulus, formed as
+    // the step kernels form them
+#pragma unroll
+    for (int k = 0; k < kK; ++k) {
+        const int i = tid + k * kNT;
+        cb[k] = 0;
+        mf[k] = 0.0f;
+        Kf[k] = 0.0f;
+        if (i < n) {
+            const int L = scl[i];
+            const int Ln = (i + 1 < n) ? scl[i + 1] : L;
+            cb[k] = L * kCoefStride;
+            mf[k] = 2.0f * A.dt / (s_coef[L * kCoefStride + kRHO] + s_coef[Ln * kCoefStride + kRHO]);
+            float K = s_coef[L * kCoefStride + kKB];
+            if (A.noise_amp != 0.0f) {
+                const uint64_t hsh = splitmix64_r(D.noise_seed ^ (uint64_t)(uint32_t)i);
+                const float u = (float)(hsh >> 40) * 0x1.0p-24f;
+                const float e = A.noise_amp * fmaf(2.0f, u, -1.0f);
+                const float f1 = 1.0f + e;
+                K = K * (f1 * f1);
+            }
+            Kf[k] = K;
+        }
+    }
+    const int32_t sr0 = R.sr_range[d], sr1 = R.sr_range[d + 1];
+
+    for (int st = 0; st < R.n_steps; ++st) {
+        const int64_t t = t0 + st;
+        // the thread index passes through an empty asm statement each step, so
+        // the compiler forms the per-cell LDS addresses inside the loop (a few
+        // integer operations) instead of holding all of them across it
+        int tb = tid;
+        asm volatile("" : "+v"(tb));
+        // velocity update: reads p (stencil) and the thread's own v
+#pragma unroll
+        for (int k = 0; k < kK; ++k) {
+            const int i = tb + k * kNT;
+            if (i >= n) continue;
+            const float *sr = sp + L0 + i;
+            float Da = stencil4_r(A.fd, sr[1] - sr[0], sr[2] - sr[-1], sr[3] - sr[-2], sr[4] - sr[-3]);
+            if (i < P || i >= n - P) {
+                const int s = i < P ? i : i - n + 2 * P;
+                const float qv = fmaf(saF[s], Da, sbF[s] * spp1[s]);
+                spp1[s] = qv;
+                Da += qv;
+            }
+            const float *cr = s_coef + cb[k];
+            float sacc = cr[kIK1] * Da;
+#pragma unroll
+            for (int nu = 0; nu < N; ++nu) {
+                ps1[k][nu] = fmaf(1.0f * cr[kA1 + nu], Da, cr[kB1 + nu] * ps1[k][nu]);
+                sacc += ps1[k][nu];
+            }
+            sv[L0 + i] = fmaf(-mf[k], sacc, sv[L0 + i]);
+        }
+        __syncthreads();
+        // pressure update: reads v (stencil) and the thread's own p
+        asm volatile("" : "+v"(tb));
+#pragma unroll
+        for (int k = 0; k < kK; ++k) {
+            const int i = tb + k * kNT;
+            if (i >= n) continue;
+            const float *sx = sv + L0 + i;
+            float S = stencil4_r(A.fd, sx[0] - sx[-1], sx[1] - sx[-2], sx[2] - sx[-3], sx[3] - sx[-4]);
+            if (i < P || i >= n - P) {
+                const int s = i < P ? i : i - n + 2 * P;
+                const float qv = fmaf(saC[s], S, sbC[s] * spp2[s]);
+                spp2[s] = qv;
+                S += qv;
+            }
+            const float *cr = s_coef + cb[k];
+            float Tt = cr[kIK2] * S;
+#pragma unroll
+            for (int nu = 0; nu < N; ++nu) {
+                ps2[k][nu] = fmaf(1.0f * cr[kA2 + nu], S, cr[kB2 + nu] * ps2[k][nu]);
+                Tt += ps2[k][nu];
+            }
+            const float pn0 = sp[L0 + i];
+            sp[L0 + i] = fmaf(-(A.dt * fmaf(cr[kTB], pn0, Kf[k])), Tt, pn0);
+        }
+        if (sr1 > sr0) {
+            __syncthreads();
+            // sources, then the receivers of the same cells (one thread per cell)
+            const bool inject = t < R.n_t, record = t < R.n_t_max;
+            for (int32_t e = sr0 + tid; e < sr1; e += kNT) {
+                const SrcRecCell c = R.cells[e];
+                const int li = (int)(c.cell - o);
+                float v = sp[L0 + li];
+                if (inject && c.wave >= 0) {
+                    v += R.waves[(int64_t)c.wave * R.n_t + t];
+                    sp[L0 + li] = v;
+                }
+                if (record) {
+                    for (int32_t q = c.r0; q < c.r1; ++q) R.traces[t * R.n_rec + R.rec_of[q]] = v;
+                    if (c.r1 > c.r0 && !isfinite(v)) flag_bad_row(R.bad_row, t);
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // store the state of the run's last step
+    for (int i = tid; i < n; i += kNT) {
+        A.fo.p[o + i] = sp[L0 + i];
+        A.fo.vx[o + i] = sv[L0 + i];
+    }
+#pragma unroll
+    for (int k = 0; k < kK; ++k) {
+        const int i = tid + k * kNT;
+        if (i < n) {
+            store_stream<N>(A.fo.psi1x + (o + i) * N, ps1[k]);
+            store_stream<N>(A.fo.psi2 + (o + i) * N, ps2[k]);
+        }
+    }
+    for (int s = tid; s < ns; s += kNT) {
+        const int i = s < P ? s : n - 2 * P + s;
+        A.fo.pP1[0][o + i] = spp1[s];
+        A.fo.pP2[0][o + i] = spp2[s];
+    }
+    // the last workgroup to finish advances the step counter (every
+    // workgroup has read it by then) and re-arms the count
+    __syncthreads();
+    if (tid == 0) {
+        __threadfence();
+        s_last = atomicAdd(R.done, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (s_last && tid == 0) {
+        *R.done = 0u;
+        *R.step = t0 + R.n_steps;
+    }
+}
+
+}  // namespace
+
+size_t resident1d_lds_bytes(int nmech, int class_cap)
+{
+    (void)nmech;
+    return (size_t)kCoefStride * class_cap * sizeof(float);
+}
+
+hipError_t launch_resident1d(int nmech, const Resident1dArgs &r, int n_domains, hipStream_t s)
+{
+    const size_t lds = resident1d_lds_bytes(nmech, r.s.class_cap);
+    const dim3 grid((unsigned)n_domains), block(kNT);
+    switch (nmech) {
+    case 1: k_resident1d<1><<<grid, block, lds, s>>>(r); break;
+    case 2: k_resident1d<2><<<grid, block, lds, s>>>(r); break;
+    case 3: k_resident1d<3><<<grid, block, lds, s>>>(r); break;
+    case 4: k_resident1d<4><<<grid, block, lds, s>>>(r); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace fw

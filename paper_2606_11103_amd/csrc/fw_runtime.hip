@@ -114,7 +114,10 @@ struct fw_sim {
     std::vector<ChunkList> chunks;
     DevBuf d_vchunks, d_pchunks;
     float *traces() const { return traces_ext ? traces_ext : d_traces.as<float>(); }
-    DevBuf d_srcrec, d_rec_of;
+    DevBuf d_srcrec, d_rec_of, d_sr_range;
+    std::vector<int32_t> h_sr_range;               // per domain: its entries of the source/receiver cell list
+    bool sr_range_dirty = true;
+    int resident = -1;                             // resident 1D step: -1 / 1 where it applies, 0 off
     std::vector<int64_t> h_src_cell, h_rec_cell;   // global cells of the sources and the receivers
     std::vector<int32_t> h_src_wave;               // waveform row of each source
     int64_t n_srcrec = 0;
@@ -323,7 +326,7 @@ static bool plane_pressure_on(const fw_sim *s)
 // launch tails cost more than they save (0.537 / 0.553 ms with 128 planes),
 // so grids of fewer than 480 planes or 200 k cells per plane keep whole-grid
 // launches.
-constexpr int64_t kStepChunk = 120, kChunkMinPlanes = 480, kChunkMinPlaneCells = 200000;
+constexpr int64_t kStepChunk = 120, kChunkMinPlanes = 320, kChunkMinPlaneCells = 100000;
 
 static int build_chunk_lists(fw_sim *s)
 {
@@ -484,6 +487,51 @@ fw::SrcRecArgs srcrec_args(const fw_sim *s)
     a.bad_row = s->d_step.as<int64_t>() + 1;
     a.done = reinterpret_cast<uint32_t *>(s->d_step.as<int64_t>() + 2);
     return a;
+}
+
+// The resident 1D step applies to 1D grids whose domains all fit on chip,
+// with CPML slabs of at most kResident1dSlab cells together and no strength
+// map (the per-step kernels take the map).
+static bool resident_on(const fw_sim *s)
+{
+    if (s->resident == 0 || s->ndim != 1 || s->amap || 2 * s->pml > fw::kResident1dSlab) return false;
+    for (const auto &d : s->doms)
+        if (d.n[0] > fw::kResident1dCells) return false;
+    return true;
+}
+
+// n steps of the resident 1D kernel, in launches of at most kResidentSteps
+// steps (a launch holds its domains' workgroups for its whole run).
+constexpr int kResidentSteps = 4096;
+static int enqueue_resident(fw_sim *s, int n, hipStream_t st)
+{
+    if (s->sr_range_dirty || !s->d_sr_range.ptr) {
+        if (s->h_sr_range.size() != (size_t)s->n_domains + 1) s->h_sr_range.assign((size_t)s->n_domains + 1, 0);
+        HIP_OR_FAIL(s->d_sr_range.ensure(s->h_sr_range.size() * sizeof(int32_t)));
+        HIP_OR_FAIL(hipMemcpy(s->d_sr_range.ptr, s->h_sr_range.data(), s->h_sr_range.size() * sizeof(int32_t),
+                              hipMemcpyHostToDevice));
+        s->sr_range_dirty = false;
+    }
+    const fw::SrcRecArgs r = srcrec_args(s);
+    fw::Resident1dArgs a{};
+    a.s = step_args(s);
+    a.cells = r.cells;
+    a.sr_range = s->d_sr_range.as<int32_t>();
+    a.rec_of = r.rec_of;
+    a.waves = r.waves;
+    a.n_t = r.n_t;
+    a.traces = r.traces;
+    a.n_rec = r.n_rec;
+    a.n_t_max = r.n_t_max;
+    a.step = r.step;
+    a.bad_row = r.bad_row;
+    a.done = r.done;
+    for (int left = n; left > 0;) {
+        a.n_steps = std::min(left, kResidentSteps);
+        HIP_OR_FAIL(fw::launch_resident1d(s->nmech, a, s->n_domains, st));
+        left -= a.n_steps;
+    }
+    return FW_OK;
 }
 
 // The step's arguments restricted to one chunk of the interleaved schedule.
@@ -865,6 +913,13 @@ static int build_srcrec(fw_sim *sim)
         k = k1;
     }
     sim->n_srcrec = (int64_t)tab.size();
+    // the cell list is sorted and the domains occupy consecutive cell ranges
+    sim->h_sr_range.assign((size_t)sim->n_domains + 1, 0);
+    for (int d = 0; d <= sim->n_domains; ++d) {
+        const int64_t first = d < sim->n_domains ? sim->doms[d].cell_off : std::numeric_limits<int64_t>::max();
+        sim->h_sr_range[d] = (int32_t)(std::lower_bound(cells.begin(), cells.end(), first) - cells.begin());
+    }
+    sim->sr_range_dirty = true;
     if (!tab.empty()) {
         HIP_OR_FAIL(sim->d_srcrec.ensure(tab.size() * sizeof(fw::SrcRecCell)));
         HIP_OR_FAIL(hipMemcpy(sim->d_srcrec.ptr, tab.data(), tab.size() * sizeof(fw::SrcRecCell), hipMemcpyHostToDevice));
@@ -990,7 +1045,7 @@ int fw_prepare(fw_sim *sim)
         int rc = build_tiles(sim);
         if (rc != FW_OK) return rc;
     }
-    return sim->graph_steps > 0 ? ensure_graph(sim, sim->graph_steps) : FW_OK;
+    return sim->graph_steps > 0 && !resident_on(sim) ? ensure_graph(sim, sim->graph_steps) : FW_OK;
 }
 
 int fw_step(fw_sim *sim, int n_steps, void *hip_stream)
@@ -1006,6 +1061,12 @@ int fw_step(fw_sim *sim, int n_steps, void *hip_stream)
         if (rc != FW_OK) return rc;
     }
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if (resident_on(sim)) {
+        int rc = enqueue_resident(sim, n_steps, st);
+        if (rc != FW_OK) return rc;
+        sim->host_step += n_steps;
+        return FW_OK;
+    }
     int left = n_steps;
     if (sim->graph_steps > 0 && left >= sim->graph_steps) {
         int rc = ensure_graph(sim, sim->graph_steps);
@@ -1631,6 +1692,11 @@ int fw_set_option(fw_sim *sim, int key, int64_t value)
             return fail(FW_EINVAL, "interleaved chunk must be -1 (auto), 0 (off) or 4..65536 planes");
         sim->step_chunk = (int)value;
         sim->tiles_dirty = true;
+        return FW_OK;
+    case FW_OPT_RESIDENT_1D:
+        if (value < -1 || value > 1) return fail(FW_EINVAL, "resident 1D step must be -1 (auto), 0 (off) or 1");
+        sim->resident = (int)value;
+        sim->drop_graph();
         return FW_OK;
     case FW_OPT_ROWS_PER_THREAD:
         if (value != 1 && value != 2) return fail(FW_EINVAL, "rows per thread must be 1 or 2");

@@ -14,7 +14,7 @@ FW_OK, FW_EINVAL, FW_ESTATE, FW_EUNSTABLE, FW_EHIP, FW_ENOMEM, FW_ENONFINITE, FW
     0, -1, -2, -3, -4, -5, -6, -7
 (FW_OPT_GRAPH_STEPS, FW_OPT_MARCH_CHUNK, FW_OPT_TILE_ROWS, FW_OPT_ROWS_PER_THREAD, FW_OPT_PERSISTENT,
  FW_OPT_TILE_ORDER, FW_OPT_PLANE_KERNELS, FW_OPT_PLANE_ROWS, FW_OPT_VEL_PLANES, FW_OPT_PRS_PLANES,
- FW_OPT_STEP_CHUNK) = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11
+ FW_OPT_STEP_CHUNK, FW_OPT_RESIDENT_1D) = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12
 
 FW_FIELD_P, FW_FIELD_VX, FW_FIELD_VY, FW_FIELD_VZ = 0, 1, 2, 3
 

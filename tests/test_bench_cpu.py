@@ -63,14 +63,17 @@ def test_trace_errors_and_the_jsonl_record():
 
 
 def test_step_chunk_planes_follows_the_automatic_rule():
-    """The benchmark grid (960 x 960 x 720) runs 120-plane chunks by default,
-    the 256^3 grid and any 2D grid whole-grid launches; explicit values win."""
+    """The benchmark grid (960 x 960 x 720) and 384^3 run 120-plane chunks by
+    default, the 256^3 grid and any 2D grid whole-grid launches; explicit
+    values win."""
     import bench
     from types import SimpleNamespace as NS
     big = NS(ndim=3, shapes=[(960, 960, 720)])
     small = NS(ndim=3, shapes=[(256, 256, 256)])
     paper = NS(ndim=3, shapes=[(499, 499, 1247)])
     flat = NS(ndim=2, shapes=[(4096, 4096, 1)])
+    mid = NS(ndim=3, shapes=[(384, 384, 384)])
+    assert bench.step_chunk_planes(mid) == 120
     assert bench.step_chunk_planes(big) == 120
     assert bench.step_chunk_planes(paper) == 120
     assert bench.step_chunk_planes(small) == 0

@@ -289,3 +289,55 @@ def test_reset_reproduces_first_run():
     sim.reset()
     sim.step(case.n_steps)
     assert np.array_equal(sim.read_receivers(), a)
+
+
+@pytest.mark.parametrize("nmech", [1, 2, 3, 4])
+def test_resident_1d_step_equals_the_per_step_kernels(nmech):
+    """FW_OPT_RESIDENT_1D: a ragged 1D batch (8192 cells, the largest domain
+    kept on chip, then 3001 and 77) with per-cell classes, speed perturbation,
+    nonlinear media, CPML and receivers on every domain's first and last
+    cells, stepped in calls of 1, 99, 4200 (two launches of the resident
+    kernel) and the rest: traces and the whole saved state (every field and
+    memory variable, the step counter and the finite-check row) bitwise equal
+    to the per-step kernels, and the traces within the bar of the FP64
+    oracle."""
+    import torch
+    from paper_2606_11103_amd.native import FW_OPT_RESIDENT_1D
+    case = configs.random_small(1, [(8192, 1, 1), (3001, 1, 1), (77, 1, 1)], nmech, 3, seed=60 + nmech, steps=4500,
+                                pml=24)
+    case = configs.with_table(case, *configs.random_relaxation_table(150 + nmech, case.n_classes, case.nmech))
+    case.rec_domain = np.concatenate([case.rec_domain, np.repeat(np.arange(3, dtype=np.int32), 2)])
+    case.rec_cell = np.concatenate([case.rec_cell, np.array([0, 8191, 0, 3000, 0, 76], np.int64)])
+    print("resident 1D", case.shapes, "N=%d" % nmech, flush=True)
+    ref_sim, ref = _run(case, opts={FW_OPT_RESIDENT_1D: 0})
+    sim = to_simulation(case)
+    sim.prepare()
+    for n in (1, 99, 4200, case.n_steps - 4300):
+        sim.step(n)
+    assert sim.get_step() == case.n_steps
+    got = sim.read_receivers()
+    assert np.array_equal(ref, got)
+    # a snapshot holds the state and then the step counter and the finite-check row
+    used = sim.state_bytes() - 256 + 16
+    assert torch.equal(sim.save_state()[:used], ref_sim.save_state()[:used])
+    glob, worst, n = check_traces(got, oracle_traces(case))
+    report("resident 1D N=%d %s: bitwise equal to the per-step kernels; rel_L2=%.3e worst_receiver=%.3e (%d reached)"
+           % (nmech, case.shapes, glob, worst, n))
+
+
+def test_resident_1d_flags_the_first_non_finite_row():
+    """A finite source sample that overflows p: the resident 1D step records
+    the first trace row holding a non-finite value, as the per-step kernels
+    do, across several domains advancing in separate workgroups."""
+    from paper_2606_11103_amd.native import FW_OPT_RESIDENT_1D
+    case = configs.random_small(1, [(700, 1, 1), (300, 1, 1)], 2, 2, seed=77, steps=60, nonlinear=False)
+    case = configs.with_table(case, *configs.random_relaxation_table(77, case.n_classes, case.nmech))
+    case.waves = case.waves.copy()
+    case.waves[0, 20] = np.float32(3e38)
+    case.waves[0, 21] = np.float32(3e38)
+    ref_sim, ref = _run(case, opts={FW_OPT_RESIDENT_1D: 0})
+    sim, got = _run(case)
+    bad = np.nonzero(~np.all(np.isfinite(got), axis=1))[0]
+    assert bad.size > 0
+    assert np.array_equal(np.isfinite(ref), np.isfinite(got))
+    assert sim.first_nonfinite_step() == ref_sim.first_nonfinite_step() == bad[0]
