@@ -52,6 +52,10 @@ __device__ void flag_bad_row(int64_t *bad_row, int64_t t)
     }
 }
 
+template <bool B> struct BoolTag {
+    static constexpr bool value = B;
+};
+
 // per-class coefficients of both operators in one LDS record per class, so
 // that a cell addresses all of them from one base (class x kCoefStride)
 constexpr int kCoefStride = 24;
@@ -68,7 +72,7 @@ __global__ __launch_bounds__(kNT) void k_resident1d(const Resident1dArgs R)
     // last): memory variables and coefficients of both operators
     __shared__ float spp1[kResident1dSlab], spp2[kResident1dSlab];
     __shared__ float saF[kResident1dSlab], sbF[kResident1dSlab], saC[kResident1dSlab], sbC[kResident1dSlab];
-    __shared__ int s_last;
+    __shared__ int s_last, s_mixed;
     extern __shared__ float s_coef[];                 // [class][kCoefStride]
     const StepArgs &A = R.s;
 
@@ -102,6 +106,7 @@ __global__ __launch_bounds__(kNT) void k_resident1d(const Resident1dArgs R)
         sp[i] = 0.0f;
         sv[i] = 0.0f;
     }
+    if (tid == 0) s_mixed = 0;
     __syncthreads();
     for (int i = tid; i < n; i += kNT) {
         sp[L0 + i] = A.f.p[o + i];
@@ -128,6 +133,10 @@ __global__ __launch_bounds__(kNT) void k_resident1d(const Resident1dArgs R)
         }
     }
     __syncthreads();
+    // a domain of one class (a homogeneous medium: every domain of an
+    // attenuation sweep) reads its coefficients once, into scalar registers
+    for (int i = tid; i < n; i += kNT)
+        if (scl[i] != scl[0]) s_mixed = 1;
     // per-cell constants of the run: class record, face coefficient
     // 2 dt / (rho_i + rho_{i+1}) and the (perturbed) bulk modulus, formed as
     // the step kernels form them
@@ -154,7 +163,27 @@ __global__ __launch_bounds__(kNT) void k_resident1d(const Resident1dArgs R)
         }
     }
     const int32_t sr0 = R.sr_range[d], sr1 = R.sr_range[d + 1];
-
+    __syncthreads();
+    const bool uniform = s_mixed == 0;
+    // the run's steps; with UNI every cell's coefficients are those of the
+    // domain's single class (same values as the per-cell path reads)
+    auto run = [&](auto uni_tag) {
+    constexpr bool UNI = decltype(uni_tag)::value;
+    const int Lu = n > 0 ? scl[0] * kCoefStride : 0;
+    auto sgpr = [](float x) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x))); };
+    float u_ik1 = 0.0f, u_ik2 = 0.0f, u_tb = 0.0f, u_a1[N], u_b1[N], u_a2[N], u_b2[N];
+    if constexpr (UNI) {
+        u_ik1 = sgpr(s_coef[Lu + kIK1]);
+        u_ik2 = sgpr(s_coef[Lu + kIK2]);
+        u_tb = sgpr(s_coef[Lu + kTB]);
+#pragma unroll
+        for (int nu = 0; nu < N; ++nu) {
+            u_a1[nu] = sgpr(s_coef[Lu + kA1 + nu]);
+            u_b1[nu] = sgpr(s_coef[Lu + kB1 + nu]);
+            u_a2[nu] = sgpr(s_coef[Lu + kA2 + nu]);
+            u_b2[nu] = sgpr(s_coef[Lu + kB2 + nu]);
+        }
+    }
     for (int st = 0; st < R.n_steps; ++st) {
         const int64_t t = t0 + st;
         // the thread index passes through an empty asm statement each step, so
@@ -176,10 +205,11 @@ __global__ __launch_bounds__(kNT) void k_resident1d(const Resident1dArgs R)
                 Da += qv;
             }
             const float *cr = s_coef + cb[k];
-            float sacc = cr[kIK1] * Da;
+            float sacc = (UNI ? u_ik1 : cr[kIK1]) * Da;
 #pragma unroll
             for (int nu = 0; nu < N; ++nu) {
-                ps1[k][nu] = fmaf(1.0f * cr[kA1 + nu], Da, cr[kB1 + nu] * ps1[k][nu]);
+                const float a = UNI ? u_a1[nu] : cr[kA1 + nu], b = UNI ? u_b1[nu] : cr[kB1 + nu];
+                ps1[k][nu] = fmaf(1.0f * a, Da, b * ps1[k][nu]);
                 sacc += ps1[k][nu];
             }
             sv[L0 + i] = fmaf(-mf[k], sacc, sv[L0 + i]);
@@ -200,14 +230,15 @@ __global__ __launch_bounds__(kNT) void k_resident1d(const Resident1dArgs R)
                 S += qv;
             }
             const float *cr = s_coef + cb[k];
-            float Tt = cr[kIK2] * S;
+            float Tt = (UNI ? u_ik2 : cr[kIK2]) * S;
 #pragma unroll
             for (int nu = 0; nu < N; ++nu) {
-                ps2[k][nu] = fmaf(1.0f * cr[kA2 + nu], S, cr[kB2 + nu] * ps2[k][nu]);
+                const float a = UNI ? u_a2[nu] : cr[kA2 + nu], b = UNI ? u_b2[nu] : cr[kB2 + nu];
+                ps2[k][nu] = fmaf(1.0f * a, S, b * ps2[k][nu]);
                 Tt += ps2[k][nu];
             }
             const float pn0 = sp[L0 + i];
-            sp[L0 + i] = fmaf(-(A.dt * fmaf(cr[kTB], pn0, Kf[k])), Tt, pn0);
+            sp[L0 + i] = fmaf(-(A.dt * fmaf(UNI ? u_tb : cr[kTB], pn0, Kf[k])), Tt, pn0);
         }
         if (sr1 > sr0) {
             __syncthreads();
@@ -229,6 +260,13 @@ __global__ __launch_bounds__(kNT) void k_resident1d(const Resident1dArgs R)
         }
         __syncthreads();
     }
+    };
+    // (at N >= 3 the coefficients held in registers would not fit beside the
+    // memory variables: those domains take the per-cell path)
+    if (N <= 2 && uniform)
+        run(BoolTag<N <= 2>{});
+    else
+        run(BoolTag<false>{});
 
     // store the state of the run's last step
     for (int i = tid; i < n; i += kNT) {

@@ -325,6 +325,24 @@ def test_resident_1d_step_equals_the_per_step_kernels(nmech):
            % (nmech, case.shapes, glob, worst, n))
 
 
+@pytest.mark.parametrize("nmech", [1, 2, 4])
+def test_resident_1d_single_class_domains(nmech):
+    """Domains of one tissue class each (as in the attenuation sweep), which
+    the resident step runs with the class coefficients held in scalar
+    registers at N <= 2: bitwise equal to the per-step kernels over 4200
+    steps (two launches)."""
+    import torch
+    from paper_2606_11103_amd.native import FW_OPT_RESIDENT_1D
+    case = configs.random_small(1, [(8192, 1, 1), (5000, 1, 1), (64, 1, 1)], nmech, 1, seed=90 + nmech, steps=4200,
+                                pml=24)
+    case = configs.with_table(case, *configs.random_relaxation_table(190 + nmech, case.n_classes, case.nmech))
+    ref_sim, ref = _run(case, opts={FW_OPT_RESIDENT_1D: 0})
+    sim, got = _run(case)
+    assert np.array_equal(ref, got)
+    used = sim.state_bytes() - 256 + 16
+    assert torch.equal(sim.save_state()[:used], ref_sim.save_state()[:used])
+
+
 def test_resident_1d_flags_the_first_non_finite_row():
     """A finite source sample that overflows p: the resident 1D step records
     the first trace row holding a non-finite value, as the per-step kernels
