@@ -36,15 +36,12 @@ HBM_PEAK_GBS = 8000.0
 # reports traffic as null.
 TRAFFIC_MEASURED = {
     # velocity plane kernel (64 x 4 tiles, 1 plane) + pressure plane kernel (64 x 4
-    # tiles, 2 planes) + sources/receivers; FETCH_SIZE counts L2 misses sent to
-    # the data fabric, so the z-window reads served by the last-level cache are
-    # included: an upper bound on the HBM bytes
-    ("326671e25f45c411", 0): {"workload": "3d_heterogeneous_960x960x720", "step_bytes": 144.78e9,
-                              "velocity_bytes": 99.25e9,
-                              "profile": "profiles/step_kernels_3d_960x960x720_N4.md"},
-    # the same kernels in the interleaved schedule (6 chunks of 120 planes per step)
-    ("326671e25f45c411", 120): {"workload": "3d_heterogeneous_960x960x720", "step_bytes": 144.83e9,
-                                "velocity_bytes": 99.28e9,
+    # tiles, 2 planes) + sources/receivers, in 6 interleaved chunks of 120 planes
+    # per step; FETCH_SIZE counts L2 misses sent to the data fabric, so the
+    # z-window reads served by the last-level cache are included: an upper bound
+    # on the HBM bytes
+    ("0fc8ad3b904c55ee", 120): {"workload": "3d_heterogeneous_960x960x720", "step_bytes": 144.84e9,
+                                "velocity_bytes": 99.29e9,
                                 "profile": "profiles/step_kernels_3d_960x960x720_N4.md"},
 }
 

@@ -164,15 +164,20 @@ __global__ __launch_bounds__(kNT) void k_resident1d(const Resident1dArgs R)
     }
     const int32_t sr0 = R.sr_range[d], sr1 = R.sr_range[d + 1];
     __syncthreads();
-    const bool uniform = s_mixed == 0;
+    // one class and no speed perturbation: every coefficient of the step,
+    // the face coefficient and the bulk modulus included, is the same in
+    // every cell of the domain
+    const bool uniform = s_mixed == 0 && A.noise_amp == 0.0f;
     // the run's steps; with UNI every cell's coefficients are those of the
     // domain's single class (same values as the per-cell path reads)
     auto run = [&](auto uni_tag) {
     constexpr bool UNI = decltype(uni_tag)::value;
     const int Lu = n > 0 ? scl[0] * kCoefStride : 0;
     auto sgpr = [](float x) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x))); };
-    float u_ik1 = 0.0f, u_ik2 = 0.0f, u_tb = 0.0f, u_a1[N], u_b1[N], u_a2[N], u_b2[N];
+    float u_ik1 = 0.0f, u_ik2 = 0.0f, u_tb = 0.0f, u_mf = 0.0f, u_K = 0.0f, u_a1[N], u_b1[N], u_a2[N], u_b2[N];
     if constexpr (UNI) {
+        u_mf = sgpr(mf[0]);
+        u_K = sgpr(Kf[0]);
         u_ik1 = sgpr(s_coef[Lu + kIK1]);
         u_ik2 = sgpr(s_coef[Lu + kIK2]);
         u_tb = sgpr(s_coef[Lu + kTB]);
@@ -212,7 +217,7 @@ __global__ __launch_bounds__(kNT) void k_resident1d(const Resident1dArgs R)
                 ps1[k][nu] = fmaf(1.0f * a, Da, b * ps1[k][nu]);
                 sacc += ps1[k][nu];
             }
-            sv[L0 + i] = fmaf(-mf[k], sacc, sv[L0 + i]);
+            sv[L0 + i] = fmaf(-(UNI ? u_mf : mf[k]), sacc, sv[L0 + i]);
         }
         __syncthreads();
         // pressure update: reads v (stencil) and the thread's own p
@@ -238,7 +243,7 @@ __global__ __launch_bounds__(kNT) void k_resident1d(const Resident1dArgs R)
                 Tt += ps2[k][nu];
             }
             const float pn0 = sp[L0 + i];
-            sp[L0 + i] = fmaf(-(A.dt * fmaf(UNI ? u_tb : cr[kTB], pn0, Kf[k])), Tt, pn0);
+            sp[L0 + i] = fmaf(-(A.dt * fmaf(UNI ? u_tb : cr[kTB], pn0, UNI ? u_K : Kf[k])), Tt, pn0);
         }
         if (sr1 > sr0) {
             __syncthreads();

@@ -325,16 +325,16 @@ def test_resident_1d_step_equals_the_per_step_kernels(nmech):
            % (nmech, case.shapes, glob, worst, n))
 
 
-@pytest.mark.parametrize("nmech", [1, 2, 4])
-def test_resident_1d_single_class_domains(nmech):
+@pytest.mark.parametrize("nmech,noise", [(1, 0.0), (2, 0.0), (2, 0.01), (4, 0.0)])
+def test_resident_1d_single_class_domains(nmech, noise):
     """Domains of one tissue class each (as in the attenuation sweep), which
-    the resident step runs with the class coefficients held in scalar
-    registers at N <= 2: bitwise equal to the per-step kernels over 4200
-    steps (two launches)."""
+    the resident step runs with every coefficient held in scalar registers
+    at N <= 2 when the speed perturbation is off: bitwise equal to the
+    per-step kernels over 4200 steps (two launches)."""
     import torch
     from paper_2606_11103_amd.native import FW_OPT_RESIDENT_1D
     case = configs.random_small(1, [(8192, 1, 1), (5000, 1, 1), (64, 1, 1)], nmech, 1, seed=90 + nmech, steps=4200,
-                                pml=24)
+                                pml=24, noise=noise)
     case = configs.with_table(case, *configs.random_relaxation_table(190 + nmech, case.n_classes, case.nmech))
     ref_sim, ref = _run(case, opts={FW_OPT_RESIDENT_1D: 0})
     sim, got = _run(case)
