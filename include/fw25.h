@@ -89,16 +89,19 @@ int fw_abi_version(void);
 int fw_create_grid(fw_sim **out, int ndim, int n_domains, const int64_t *shape,
                    double dx, double dt, int n_mech, int pml_cells, const double *pml_params);
 
-/* Release the object and the small tables the library allocated.  The bound
- * workspace is not freed. */
+/* Infrastructure (no operation of the method).  Release the object and the
+ * small tables the library allocated.  The bound workspace is not freed. */
 int fw_destroy(fw_sim *sim);
 
-/* Device bytes the workspace must provide: pressure, velocity, the memory
- * variables (3N face variables and N cell variables summed over axes per
- * cell), CPML memory variables and the uint8 class map.  -1 on a NULL sim. */
+/* The state of Sec. 3.3's scheme: device bytes the workspace must provide:
+ * pressure, velocity, the memory variables of Eq. (relaxation_psi) (3N face
+ * variables and N cell variables summed over axes per cell), CPML memory
+ * variables (the same recursion form, Sec. 2.1) and the uint8 class map.
+ * -1 on a NULL sim. */
 int64_t fw_workspace_bytes(const fw_sim *sim);
 
-/* Bind a caller-owned device buffer of at least fw_workspace_bytes bytes,
+/* Infrastructure (no operation of the method).
+ * Bind a caller-owned device buffer of at least fw_workspace_bytes bytes,
  * 256-byte aligned.  The state is zeroed (synchronously on the default
  * stream) and the step counter reset. */
 int fw_bind_workspace(fw_sim *sim, void *d_ptr, int64_t bytes);
@@ -228,11 +231,14 @@ int fw_step(fw_sim *sim, int n_steps, void *hip_stream);
  */
 int fw_read_receivers(fw_sim *sim, float *dst, int64_t n_elems, int dst_is_device, void *hip_stream);
 
-/* Zero every state field, the traces and the step counter, and clear the
- * finite-check flag (asynchronous). */
+/* The zero initial state of the time iteration (Sec. 3.3; the fields start
+ * at rest before the source of Sec. 4.1 acts).  Zero every state field, the
+ * traces and the step counter, and clear the finite-check flag
+ * (asynchronous). */
 int fw_reset_state(fw_sim *sim, void *hip_stream);
 
-/* Host view of the number of steps enqueued since the last reset. */
+/* Infrastructure: host view of the number of time steps (Sec. 3.3) enqueued
+ * since the last reset. */
 int fw_get_step(const fw_sim *sim, int64_t *step);
 
 /*
@@ -247,12 +253,14 @@ int fw_get_step(const fw_sim *sim, int64_t *step);
  */
 int fw_first_nonfinite_step(fw_sim *sim, int64_t *row, void *hip_stream);
 
-/* Bytes of a full state snapshot (fields, memory variables, CPML variables,
+/* Infrastructure (checkpoints of the time iteration of Sec. 3.3).
+ * Bytes of a full state snapshot (fields, memory variables, CPML variables,
  * the step counter and the first non-finite trace row of
  * fw_first_nonfinite_step); -1 on a NULL sim. */
 int64_t fw_state_bytes(const fw_sim *sim);
 
-/* Copy the full state into / out of a caller-owned device buffer of
+/* Infrastructure (checkpoints of the time iteration of Sec. 3.3).
+ * Copy the full state into / out of a caller-owned device buffer of
  * fw_state_bytes bytes (asynchronous, device-to-device).  Resuming from a
  * saved state reproduces the uninterrupted run bit for bit; loading a state
  * also restores the non-finite row it was saved with, so a row flagged after
@@ -316,8 +324,10 @@ int fw_adjoint(fw_sim *sim, int n_steps, int ckpt_every, void *d_work, int64_t b
                const float *d_adj_src, float *d_grad_c, float *d_grad_alpha0, void *hip_stream);
 
 /*
- * The same reverse sweep as fw_adjoint, returning the gradients before the
- * chain rule (asynchronous): d_grad_K[x] += dJ/dK(x), the cell's bulk
+ * The same reverse sweep as fw_adjoint (the transpose of the step of
+ * Sec. 3.3 applied to Eqs. (wave1)/(wave2); the paper has no adjoint: the
+ * per-voxel parameters of Sec. 4.5 are what it differentiates), returning
+ * the gradients before the chain rule (asynchronous): d_grad_K[x] += dJ/dK(x), the cell's bulk
  * modulus, and d_grad_s[x] += dJ/ds(x), s a scale of every relaxation
  * strength d of the cell (d -> s d, kappa and alpha fixed).  Same workspace,
  * layout and errors as fw_adjoint.
@@ -326,6 +336,8 @@ int fw_adjoint_modulus(fw_sim *sim, int n_steps, int ckpt_every, void *d_work, i
                        const float *d_adj_src, float *d_grad_K, float *d_grad_s, void *hip_stream);
 
 /*
+ * Measurement of the step of Sec. 3.3 (Sec. 5.3 reports the paper's run
+ * times).
  * Advance n_steps steps like fw_step, but launch every kernel eagerly with a
  * HIP event before and after it on hip_stream, wait for completion, and
  * return the average time per step in milliseconds of each kernel kind:
@@ -408,6 +420,7 @@ int fw_read_field(fw_sim *sim, int field, int domain, float *dst, int dst_is_dev
 int fw_stream_probe(fw_sim *sim, int mode, int order, int reps, void *hip_stream, double *avg_ms);
 
 /*
+ * Infrastructure (no operation of the method).
  * Streaming device-to-device copy of bytes bytes on hip_stream (used for
  * state snapshots and checkpoints).  16-byte aligned pointers and sizes use a
  * kernel with one float4 per lane, launched in pieces of at most 16 GiB;

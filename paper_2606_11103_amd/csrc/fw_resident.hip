@@ -12,8 +12,9 @@
 //
 // Each value is computed with the operations of k_velocity / k_pressure /
 // k_src_rec in 1D, in the same order (Sec. 3.3 step with the memory
-// variables of Eq. (relaxation_psi), CPML of Sec. 2.3, sources and receivers
-// of Sec. 4.1), so the results are bitwise those of the per-step kernels.
+// variables of Eq. (relaxation_psi), CPML in the same recursion form as the
+// tissue (Sec. 2.1), sources and receivers of Sec. 4.1), so the results are
+// bitwise those of the per-step kernels.
 #include "fw_internal.h"
 #include "fw_vec.h"
 
