@@ -213,9 +213,8 @@ def test_2d_tile_kernels_on_a_ragged_batch(nmech):
 
 
 def test_default_kernel_choice_with_one_mechanism():
-    """N = 1 in 3D: by default the marching velocity kernel and the plane
-    pressure kernel; bitwise equal to marching both, and to the oracle within
-    the bar."""
+    """N = 1 in 3D: by default both plane kernels (as with option 1);
+    bitwise equal to marching both, and to the oracle within the bar."""
     from paper_2606_11103_amd.native import FW_OPT_PLANE_KERNELS
     case = configs.random_small(3, [(70, 17, 21), (130, 97, 18)], 1, 3, seed=43, steps=90, pml=4)
     case = configs.with_table(case, *configs.random_relaxation_table(143, case.n_classes, case.nmech))
