@@ -162,6 +162,10 @@ def test_sources_and_receivers_validation_without_gpu():
     assert lib.fw_set_option(h, native.FW_OPT_STEP_CHUNK, -2) == native.FW_EINVAL
     for v in (-1, 0, 4, 120):
         assert lib.fw_set_option(h, native.FW_OPT_STEP_CHUNK, v) == 0
+    for v in (-1, 0, 1):
+        assert lib.fw_set_option(h, native.FW_OPT_RESIDENT_1D, v) == 0
+    for v in (-2, 2):
+        assert lib.fw_set_option(h, native.FW_OPT_RESIDENT_1D, v) == native.FW_EINVAL
     assert lib.fw_set_option(h, native.FW_OPT_GRAPH_STEPS, 8) == 0
     lib.fw_destroy(h)
 
