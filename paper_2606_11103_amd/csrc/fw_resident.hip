@@ -163,7 +163,8 @@ __global__ __launch_bounds__(kNT) void k_resident1d(const Resident1dArgs R)
             Kf[k] = K;
         }
     }
-    const int32_t sr0 = R.sr_range[d], sr1 = R.sr_range[d + 1];
+    // no range table: no source or receiver has been set
+    const int32_t sr0 = R.sr_range ? R.sr_range[d] : 0, sr1 = R.sr_range ? R.sr_range[d + 1] : 0;
     __syncthreads();
     // one class and no speed perturbation: every coefficient of the step,
     // the face coefficient and the bulk modulus included, is the same in

@@ -115,8 +115,7 @@ struct fw_sim {
     DevBuf d_vchunks, d_pchunks;
     float *traces() const { return traces_ext ? traces_ext : d_traces.as<float>(); }
     DevBuf d_srcrec, d_rec_of, d_sr_range;
-    std::vector<int32_t> h_sr_range;               // per domain: its entries of the source/receiver cell list
-    bool sr_range_dirty = true;
+    int64_t n_sr_range = 0;                        // entries uploaded to d_sr_range (n_domains + 1, or 0)
     int resident = -1;                             // resident 1D step: -1 / 1 where it applies, 0 off
     std::vector<int64_t> h_src_cell, h_rec_cell;   // global cells of the sources and the receivers
     std::vector<int32_t> h_src_wave;               // waveform row of each source
@@ -505,18 +504,12 @@ static bool resident_on(const fw_sim *s)
 constexpr int kResidentSteps = 4096;
 static int enqueue_resident(fw_sim *s, int n, hipStream_t st)
 {
-    if (s->sr_range_dirty || !s->d_sr_range.ptr) {
-        if (s->h_sr_range.size() != (size_t)s->n_domains + 1) s->h_sr_range.assign((size_t)s->n_domains + 1, 0);
-        HIP_OR_FAIL(s->d_sr_range.ensure(s->h_sr_range.size() * sizeof(int32_t)));
-        HIP_OR_FAIL(hipMemcpy(s->d_sr_range.ptr, s->h_sr_range.data(), s->h_sr_range.size() * sizeof(int32_t),
-                              hipMemcpyHostToDevice));
-        s->sr_range_dirty = false;
-    }
     const fw::SrcRecArgs r = srcrec_args(s);
     fw::Resident1dArgs a{};
     a.s = step_args(s);
     a.cells = r.cells;
-    a.sr_range = s->d_sr_range.as<int32_t>();
+    // no source or receiver set yet: no ranges (the kernel then has none)
+    a.sr_range = s->n_sr_range == s->n_domains + 1 ? s->d_sr_range.as<int32_t>() : nullptr;
     a.rec_of = r.rec_of;
     a.waves = r.waves;
     a.n_t = r.n_t;
@@ -913,13 +906,16 @@ static int build_srcrec(fw_sim *sim)
         k = k1;
     }
     sim->n_srcrec = (int64_t)tab.size();
-    // the cell list is sorted and the domains occupy consecutive cell ranges
-    sim->h_sr_range.assign((size_t)sim->n_domains + 1, 0);
+    // per domain, its entries of the cell list (the list is sorted and the
+    // domains occupy consecutive cell ranges): the resident 1D step's share
+    std::vector<int32_t> range((size_t)sim->n_domains + 1, 0);
     for (int d = 0; d <= sim->n_domains; ++d) {
         const int64_t first = d < sim->n_domains ? sim->doms[d].cell_off : std::numeric_limits<int64_t>::max();
-        sim->h_sr_range[d] = (int32_t)(std::lower_bound(cells.begin(), cells.end(), first) - cells.begin());
+        range[d] = (int32_t)(std::lower_bound(cells.begin(), cells.end(), first) - cells.begin());
     }
-    sim->sr_range_dirty = true;
+    HIP_OR_FAIL(sim->d_sr_range.ensure(range.size() * sizeof(int32_t)));
+    HIP_OR_FAIL(hipMemcpy(sim->d_sr_range.ptr, range.data(), range.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    sim->n_sr_range = (int64_t)range.size();
     if (!tab.empty()) {
         HIP_OR_FAIL(sim->d_srcrec.ensure(tab.size() * sizeof(fw::SrcRecCell)));
         HIP_OR_FAIL(hipMemcpy(sim->d_srcrec.ptr, tab.data(), tab.size() * sizeof(fw::SrcRecCell), hipMemcpyHostToDevice));

@@ -358,3 +358,26 @@ def test_resident_1d_flags_the_first_non_finite_row():
     assert bad.size > 0
     assert np.array_equal(np.isfinite(ref), np.isfinite(got))
     assert sim.first_nonfinite_step() == ref_sim.first_nonfinite_step() == bad[0]
+
+
+def test_resident_1d_before_any_source_or_receiver():
+    """A 1D batch stepped before any source or receiver is set: the resident
+    step runs without a per-domain source/receiver table, the field stays
+    zero, and the state then equals the per-step kernels' bit for bit."""
+    import torch
+    from paper_2606_11103_amd.native import FW_OPT_RESIDENT_1D
+    from paper_2606_11103_amd.sim import Simulation
+    kappa, d, al = configs.random_relaxation_table(5, 2, 2)
+    sims = []
+    for resident in (-1, 0):
+        sim = Simulation(1, [(500, 1, 1), (300, 1, 1)], 1e-4, 2e-8, 2, 10)
+        sim.set_option(FW_OPT_RESIDENT_1D, resident)
+        sim.set_media([np.zeros(500, np.uint8), np.zeros(300, np.uint8)], [0, 1], [1500.0, 1550.0], [1000.0, 1050.0],
+                      [0.0, 0.0])
+        sim.set_relaxation_table(kappa, d, al)
+        sim.step(77)
+        assert sim.get_step() == 77
+        assert np.all(sim.read_field(0, 0) == 0.0) and np.all(sim.read_field(0, 1) == 0.0)
+        sims.append(sim)
+    used = sims[0].state_bytes() - 256 + 16
+    assert torch.equal(sims[0].save_state()[:used], sims[1].save_state()[:used])
