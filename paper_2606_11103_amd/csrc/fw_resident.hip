@@ -3,10 +3,10 @@
 // either side, the outside of the domain), the memory variables of the two
 // operators in registers (strided ownership: thread t holds cells t, t + 1024,
 // ...), the CPML variables of the two slabs in LDS; every step is the
-// velocity update, the pressure update and the sources/receivers of the
-// domain, separated by workgroup barriers, and HBM is touched only to load
-// the state at the start and store it at the end of the run (plus the source
-// waveforms and the receiver traces).  A 1D domain of 8192 cells at N = 4
+// velocity update and the pressure update (with the sources and receivers of
+// the cells it updates), separated by workgroup barriers, and HBM is touched
+// only to load the state at the start and store it at the end of the run
+// (plus the source waveforms and the receiver traces).  A 1D domain of 8192 cells at N = 4
 // holds 320 KB of state: a per-step pass over HBM or the last-level cache
 // costs far more than the arithmetic, so the step is kept on chip.
 //
@@ -73,6 +73,10 @@ __global__ __launch_bounds__(kNT) void k_resident1d(const Resident1dArgs R)
     // last): memory variables and coefficients of both operators
     __shared__ float spp1[kResident1dSlab], spp2[kResident1dSlab];
     __shared__ float saF[kResident1dSlab], sbF[kResident1dSlab], saC[kResident1dSlab], sbC[kResident1dSlab];
+    // per cell: its entry in the domain's source/receiver list (-1: none), so
+    // the thread that updates a cell's pressure also injects its source and
+    // records its receivers, with no separate pass and barrier
+    __shared__ int16_t s_sr[kResident1dCells];
     __shared__ int s_last, s_mixed;
     extern __shared__ float s_coef[];                 // [class][kCoefStride]
     const StepArgs &A = R.s;
@@ -165,6 +169,9 @@ __global__ __launch_bounds__(kNT) void k_resident1d(const Resident1dArgs R)
     }
     // no range table: no source or receiver has been set
     const int32_t sr0 = R.sr_range ? R.sr_range[d] : 0, sr1 = R.sr_range ? R.sr_range[d + 1] : 0;
+    for (int i = tid; i < n; i += kNT) s_sr[i] = -1;
+    __syncthreads();
+    for (int32_t e = sr0 + tid; e < sr1; e += kNT) s_sr[(int)(R.cells[e].cell - o)] = (int16_t)(e - sr0);
     __syncthreads();
     // one class and no speed perturbation: every coefficient of the step,
     // the face coefficient and the bulk modulus included, is the same in
@@ -245,25 +252,18 @@ __global__ __launch_bounds__(kNT) void k_resident1d(const Resident1dArgs R)
                 Tt += ps2[k][nu];
             }
             const float pn0 = sp[L0 + i];
-            sp[L0 + i] = fmaf(-(A.dt * fmaf(UNI ? u_tb : cr[kTB], pn0, UNI ? u_K : Kf[k])), Tt, pn0);
-        }
-        if (sr1 > sr0) {
-            __syncthreads();
-            // sources, then the receivers of the same cells (one thread per cell)
-            const bool inject = t < R.n_t, record = t < R.n_t_max;
-            for (int32_t e = sr0 + tid; e < sr1; e += kNT) {
-                const SrcRecCell c = R.cells[e];
-                const int li = (int)(c.cell - o);
-                float v = sp[L0 + li];
-                if (inject && c.wave >= 0) {
-                    v += R.waves[(int64_t)c.wave * R.n_t + t];
-                    sp[L0 + li] = v;
-                }
-                if (record) {
+            float v = fmaf(-(A.dt * fmaf(UNI ? u_tb : cr[kTB], pn0, UNI ? u_K : Kf[k])), Tt, pn0);
+            const int es = s_sr[i];
+            if (es >= 0) {
+                // the cell's source, then its receivers (after the injection)
+                const SrcRecCell c = R.cells[sr0 + es];
+                if (t < R.n_t && c.wave >= 0) v += R.waves[(int64_t)c.wave * R.n_t + t];
+                if (t < R.n_t_max) {
                     for (int32_t q = c.r0; q < c.r1; ++q) R.traces[t * R.n_rec + R.rec_of[q]] = v;
                     if (c.r1 > c.r0 && !isfinite(v)) flag_bad_row(R.bad_row, t);
                 }
             }
+            sp[L0 + i] = v;
         }
         __syncthreads();
     }
