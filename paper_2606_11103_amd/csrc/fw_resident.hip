@@ -53,6 +53,26 @@ __device__ void flag_bad_row(int64_t *bad_row, int64_t t)
     }
 }
 
+// N consecutive coefficients of a class record as one LDS access (the
+// record's groups of four start on 16-byte boundaries)
+template <int N>
+__device__ __forceinline__ void coef_group(const float *p, float (&v)[N])
+{
+    if constexpr (N >= 3) {
+        const float4 q = *reinterpret_cast<const float4 *>(p);
+        v[0] = q.x;
+        v[1] = q.y;
+        v[2] = q.z;
+        if constexpr (N == 4) v[3] = q.w;
+    } else if constexpr (N == 2) {
+        const float2 q = *reinterpret_cast<const float2 *>(p);
+        v[0] = q.x;
+        v[1] = q.y;
+    } else {
+        v[0] = p[0];
+    }
+}
+
 template <bool B> struct BoolTag {
     static constexpr bool value = B;
 };
@@ -78,7 +98,7 @@ __global__ __launch_bounds__(kNT) void k_resident1d(const Resident1dArgs R)
     // records its receivers, with no separate pass and barrier
     __shared__ int16_t s_sr[kResident1dCells];
     __shared__ int s_last, s_mixed;
-    extern __shared__ float s_coef[];                 // [class][kCoefStride]
+    extern __shared__ __align__(16) float s_coef[];    // [class][kCoefStride], 16-byte aligned records
     const StepArgs &A = R.s;
 
     const int d = blockIdx.x;
@@ -219,10 +239,15 @@ __global__ __launch_bounds__(kNT) void k_resident1d(const Resident1dArgs R)
                 Da += qv;
             }
             const float *cr = s_coef + cb[k];
+            float ca[N], cbv[N];
+            if constexpr (!UNI) {
+                coef_group<N>(cr + kA1, ca);
+                coef_group<N>(cr + kB1, cbv);
+            }
             float sacc = (UNI ? u_ik1 : cr[kIK1]) * Da;
 #pragma unroll
             for (int nu = 0; nu < N; ++nu) {
-                const float a = UNI ? u_a1[nu] : cr[kA1 + nu], b = UNI ? u_b1[nu] : cr[kB1 + nu];
+                const float a = UNI ? u_a1[nu] : ca[nu], b = UNI ? u_b1[nu] : cbv[nu];
                 ps1[k][nu] = fmaf(1.0f * a, Da, b * ps1[k][nu]);
                 sacc += ps1[k][nu];
             }
@@ -244,10 +269,15 @@ __global__ __launch_bounds__(kNT) void k_resident1d(const Resident1dArgs R)
                 S += qv;
             }
             const float *cr = s_coef + cb[k];
+            float ca[N], cbv[N];
+            if constexpr (!UNI) {
+                coef_group<N>(cr + kA2, ca);
+                coef_group<N>(cr + kB2, cbv);
+            }
             float Tt = (UNI ? u_ik2 : cr[kIK2]) * S;
 #pragma unroll
             for (int nu = 0; nu < N; ++nu) {
-                const float a = UNI ? u_a2[nu] : cr[kA2 + nu], b = UNI ? u_b2[nu] : cr[kB2 + nu];
+                const float a = UNI ? u_a2[nu] : ca[nu], b = UNI ? u_b2[nu] : cbv[nu];
                 ps2[k][nu] = fmaf(1.0f * a, S, b * ps2[k][nu]);
                 Tt += ps2[k][nu];
             }
