@@ -36,18 +36,6 @@ namespace fw {
 
 namespace {
 
-__device__ __forceinline__ uint64_t splitmix64_a(uint64_t x)
-{
-    uint64_t z = x + 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-
-__device__ __forceinline__ float st4(const float (&c)[4], float d1, float d2, float d3, float d4)
-{
-    return fmaf(c[3], d4, fmaf(c[2], d3, fmaf(c[1], d2, c[0] * d1)));
-}
 
 struct Geo {
     int n[3];       // nx, ny, nz
@@ -68,7 +56,7 @@ __device__ __forceinline__ float grad_a(const float *__restrict__ f, const Geo &
         const float fm = (i + 1 - m >= 0) ? f[g + (1 - m) * s] : 0.0f;
         d[m - 1] = fp - fm;
     }
-    return st4(fd, d[0], d[1], d[2], d[3]);
+    return stencil4(fd, d[0], d[1], d[2], d[3]);
 }
 
 // staggered divergence term (face field -> cell i of axis a)
@@ -82,7 +70,7 @@ __device__ __forceinline__ float div_a(const float *__restrict__ f, const Geo &G
         const float fm = (i - m >= 0) ? f[g - m * s] : 0.0f;
         d[m - 1] = fp - fm;
     }
-    return st4(fd, d[0], d[1], d[2], d[3]);
+    return stencil4(fd, d[0], d[1], d[2], d[3]);
 }
 
 template <int NDIM>
@@ -159,7 +147,7 @@ struct March {
 
 __device__ __forceinline__ float qdiff(const float (&c)[4], const float (&q)[8])
 {
-    return st4(c, q[4] - q[3], q[5] - q[2], q[6] - q[1], q[7] - q[0]);
+    return stencil4(c, q[4] - q[3], q[5] - q[2], q[6] - q[1], q[7] - q[0]);
 }
 
 // Pointwise parts of the two transposes at one cell, shared by the marching
@@ -247,13 +235,7 @@ __device__ __forceinline__ void adj_pressure_cell(const AdjArgs &A, const Domain
 #pragma unroll
     for (int nu = 0; nu < N; ++nu) Tt += o.psn[nu];
     float K = s_K[L];
-    if (A.s.noise_amp != 0.0f) {
-        const uint64_t h = splitmix64_a(D.noise_seed ^ (uint64_t)(uint32_t)u);
-        const float uu = (float)(h >> 40) * 0x1.0p-24f;
-        const float e = A.s.noise_amp * fmaf(2.0f, uu, -1.0f);
-        const float f1 = 1.0f + e;
-        K = K * (f1 * f1);
-    }
+    if (A.s.noise_amp != 0.0f) K = K * speed_factor_sq(D.noise_seed, (uint32_t)u, A.s.noise_amp);
     const int64_t pk = D.packed_off + u;
     const float gk0 = EARLY ? o.gk0 : A.gK[pk];
     st1<NT>(A.gK + pk, gk0 + lp * (-dt * Tt));
@@ -617,17 +599,17 @@ __global__ __launch_bounds__(64 * TY) void k_adj_pressure_tile2d(const AdjArgs A
     if (fold) {
         const float *l0 = s_l0 + ty * LX + 4 + tx, *l1 = s_l1 + (ty + 4) * BX + tx;
         float acc = 0.0f;
-        acc += st4(A.s.fd, l0[0] - l0[-1], l0[1] - l0[-2], l0[2] - l0[-3], l0[3] - l0[-4]);
-        acc += st4(A.s.fd, l1[0] - l1[-BX], l1[BX] - l1[-2 * BX], l1[2 * BX] - l1[-3 * BX], l1[3 * BX] - l1[-4 * BX]);
+        acc += stencil4(A.s.fd, l0[0] - l0[-1], l0[1] - l0[-2], l0[2] - l0[-3], l0[3] - l0[-4]);
+        acc += stencil4(A.s.fd, l1[0] - l1[-BX], l1[BX] - l1[-2 * BX], l1[2 * BX] - l1[-3 * BX], l1[3 * BX] - l1[-4 * BX]);
         lp -= acc;
         st1<NT>(A.lam.p + gg, lp);
     }
     // forward divergence of v^{n+1/2} (state u^{n+1}) after the CPML stage
     const float *v0 = s_v0 + ty * LX + 4 + tx, *v1 = s_v1 + (ty + 4) * BX + tx;
     float Dd[2];
-    Dd[0] = st4(A.s.fd, v0[0] - v0[-1], v0[1] - v0[-2], v0[2] - v0[-3], v0[3] - v0[-4]);
+    Dd[0] = stencil4(A.s.fd, v0[0] - v0[-1], v0[1] - v0[-2], v0[2] - v0[-3], v0[3] - v0[-4]);
     if (slab(x, nx, P)) Dd[0] += pq[0];
-    Dd[1] = st4(A.s.fd, v1[0] - v1[-BX], v1[BX] - v1[-2 * BX], v1[2 * BX] - v1[-3 * BX], v1[3 * BX] - v1[-4 * BX]);
+    Dd[1] = stencil4(A.s.fd, v1[0] - v1[-BX], v1[BX] - v1[-2 * BX], v1[2 * BX] - v1[-3 * BX], v1[3 * BX] - v1[-4 * BX]);
     if (slab(y, ny, P)) Dd[1] += pq[1];
     float S = Dd[0];
     S += Dd[1];
@@ -719,19 +701,19 @@ __global__ __launch_bounds__(64 * TY) void k_adj_velocity_tile2d(const AdjArgs A
     {   // x: gradient over the row, lamD2_x and p at x - 3 .. x + 4
         const int Ln = (x + 1 < nx) ? s_c[ty * CX + tx + 1] : L;
         const float m = 2.0f * dt / (s_rho[L] + s_rho[Ln]);
-        const float lv = in0.lv0 - st4(A.s.fd, l0[1] - l0[0], l0[2] - l0[-1], l0[3] - l0[-2], l0[4] - l0[-3]);
+        const float lv = in0.lv0 - stencil4(A.s.fd, l0[1] - l0[0], l0[2] - l0[-1], l0[3] - l0[-2], l0[4] - l0[-3]);
         const float r = -m * lv;
-        const float D1 = st4(A.s.fd, sp[1] - sp[0], sp[2] - sp[-1], sp[3] - sp[-2], sp[4] - sp[-3]);
+        const float D1 = stencil4(A.s.fd, sp[1] - sp[0], sp[2] - sp[-1], sp[3] - sp[-2], sp[4] - sp[-3]);
         adj_velocity_axis<N, NT>(A, D, s_tab, C, 0, x, nx, gg, L, lv, r, D1, in0, gsum);
     }
     adj_velocity_load<N, NT>(A, 1, gg, in1);
     {   // y: gradient over the column
         const int Ln = (y + 1 < ny) ? s_c[(ty + 1) * CX + tx] : L;
         const float m = 2.0f * dt / (s_rho[L] + s_rho[Ln]);
-        const float lv = in1.lv0 - st4(A.s.fd, l1[BX] - l1[0], l1[2 * BX] - l1[-BX], l1[3 * BX] - l1[-2 * BX],
+        const float lv = in1.lv0 - stencil4(A.s.fd, l1[BX] - l1[0], l1[2 * BX] - l1[-BX], l1[3 * BX] - l1[-2 * BX],
                                        l1[4 * BX] - l1[-3 * BX]);
         const float r = -m * lv;
-        const float D1 = st4(A.s.fd, sp[LX] - sp[0], sp[2 * LX] - sp[-LX], sp[3 * LX] - sp[-2 * LX],
+        const float D1 = stencil4(A.s.fd, sp[LX] - sp[0], sp[2 * LX] - sp[-LX], sp[3 * LX] - sp[-2 * LX],
                              sp[4 * LX] - sp[-3 * LX]);
         adj_velocity_axis<N, NT>(A, D, s_tab, C, 1, y, ny, gg, L, lv, r, D1, in1, gsum);
     }
@@ -832,14 +814,7 @@ __global__ __launch_bounds__(256) void k_adj_chain(const AdjChainArgs A)
     const int64_t nx = D.n[0];
     const int64_t stored = (g / nx) * D.pitch + g % nx;       // its place in the padded rows
     const float2 ch = A.chain[D.class_base + A.cls[D.cell_off + stored]];
-    float f2 = 1.0f;
-    if (A.noise_amp != 0.0f) {
-        const uint64_t h = splitmix64_a(D.noise_seed ^ (uint64_t)(uint32_t)g);
-        const float u = (float)(h >> 40) * 0x1.0p-24f;
-        const float e = A.noise_amp * fmaf(2.0f, u, -1.0f);
-        const float f1 = 1.0f + e;
-        f2 = f1 * f1;
-    }
+    const float f2 = A.noise_amp != 0.0f ? speed_factor_sq(D.noise_seed, (uint32_t)g, A.noise_amp) : 1.0f;
     A.grad_c[i] = fmaf(ch.x * f2, A.gK[i], A.grad_c[i]);
     if (A.grad_a0) A.grad_a0[i] = fmaf(A.gs[i], ch.y, A.grad_a0[i]);
 }

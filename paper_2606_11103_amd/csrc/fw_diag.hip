@@ -7,18 +7,11 @@
 #include <algorithm>
 
 #include "fw_internal.h"
+#include "fw_vec.h"
 
 namespace fw {
 
 namespace {
-
-__device__ __forceinline__ uint64_t splitmix64_d(uint64_t x)
-{
-    uint64_t z = x + 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
 
 template <int NDIM>
 __global__ __launch_bounds__(1024) void k_energy(const StepArgs A, const float *__restrict__ p_old, double *partial)
@@ -52,13 +45,7 @@ __global__ __launch_bounds__(1024) void k_energy(const StepArgs A, const float *
             const int L = A.f.cls[o + g];
             const ClassCoef &cc = A.classes[D.class_base + L];
             float K = cc.K;
-            if (A.noise_amp != 0.0f) {
-                const uint64_t h = splitmix64_d(D.noise_seed ^ (uint64_t)(uint32_t)u);
-                const float u = (float)(h >> 40) * 0x1.0p-24f;
-                const float ep = A.noise_amp * fmaf(2.0f, u, -1.0f);
-                const float f1 = 1.0f + ep;
-                K = K * (f1 * f1);
-            }
+            if (A.noise_amp != 0.0f) K = K * speed_factor_sq(D.noise_seed, (uint32_t)u, A.noise_amp);
             const float pn = A.f.p[o + g];
             if (!isfinite(pn)) ++nf;
             mx = fmaxf(mx, fabsf(pn));

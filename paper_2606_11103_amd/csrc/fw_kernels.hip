@@ -35,14 +35,6 @@ namespace fw {
 
 namespace {
 
-__device__ __forceinline__ uint64_t splitmix64(uint64_t x)
-{
-    uint64_t z = x + 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-
 // Tile of iteration `it` of this block, or -1.  XCD x (= block % 8, as
 // workgroups are dispatched round-robin over the 8 XCDs) owns the contiguous
 // tile range [x C, (x + 1) C), C = tiles_per_xcd; its blocks interleave over
@@ -64,14 +56,6 @@ __device__ __forceinline__ bool in_slab(int64_t c, int64_t n, int P) { return P 
 __device__ __forceinline__ float strength(const StepArgs &A, const DomainDesc &D, int u)
 {
     return A.amap ? A.amap[D.packed_off + u] : 1.0f;
-}
-
-// sum_m c_m d_m with an explicit fused-multiply-add chain.  The library is
-// compiled without implicit contraction, so every instantiation (tile shape,
-// batching) performs the same rounding sequence.
-__device__ __forceinline__ float stencil4(const float (&c)[4], float d1, float d2, float d3, float d4)
-{
-    return fmaf(c[3], d4, fmaf(c[2], d3, fmaf(c[1], d2, c[0] * d1)));
 }
 
 // Per-domain base pointers (uniform over the block, kept in scalar registers)
@@ -623,13 +607,7 @@ __global__ __launch_bounds__(BX *BY) void k_pressure(const StepArgs A)
             }
             store_stream<N>(Mo.psi2 + (size_t)g * N, psc[r]);
             float K = s_K[L];
-            if (A.noise_amp != 0.0f) {
-                const uint64_t hsh = splitmix64(D.noise_seed ^ (uint64_t)(uint32_t)u);
-                const float u = (float)(hsh >> 40) * 0x1.0p-24f;
-                const float e = A.noise_amp * fmaf(2.0f, u, -1.0f);
-                const float f1 = 1.0f + e;
-                K = K * (f1 * f1);
-            }
+            if (A.noise_amp != 0.0f) K = K * speed_factor_sq(D.noise_seed, (uint32_t)u, A.noise_amp);
             const float pn0 = pc[r];
             store1_stream(Mo.p + g, fmaf(-(A.dt * fmaf(s_tb[L], pn0, K)), Tt, pn0));
         }
@@ -1018,13 +996,7 @@ void k_pressure_planes(const StepArgs A)
             }
             store_stream<N>(Mo.psi2 + (size_t)g * N, psn);
             float K = s_K[L];
-            if (A.noise_amp != 0.0f) {
-                const uint64_t hsh = splitmix64(D.noise_seed ^ (uint64_t)(uint32_t)u);
-                const float u = (float)(hsh >> 40) * 0x1.0p-24f;
-                const float e = A.noise_amp * fmaf(2.0f, u, -1.0f);
-                const float f1 = 1.0f + e;
-                K = K * (f1 * f1);
-            }
+            if (A.noise_amp != 0.0f) K = K * speed_factor_sq(D.noise_seed, (uint32_t)u, A.noise_amp);
             const float pn0 = cur.pc;
             store1_stream(Mo.p + g, fmaf(-(A.dt * fmaf(s_tb[L], pn0, K)), Tt, pn0));
         }
@@ -1296,13 +1268,7 @@ __global__ __launch_bounds__(64 * TY) void k_pressure_tile2d(const StepArgs A)
     }
     store_stream<N>(Mo.psi2 + (size_t)g * N, psc);
     float K = s_K[L];
-    if (A.noise_amp != 0.0f) {
-        const uint64_t hsh = splitmix64(D.noise_seed ^ (uint64_t)(uint32_t)u);
-        const float uu = (float)(hsh >> 40) * 0x1.0p-24f;
-        const float e = A.noise_amp * fmaf(2.0f, uu, -1.0f);
-        const float f1 = 1.0f + e;
-        K = K * (f1 * f1);
-    }
+    if (A.noise_amp != 0.0f) K = K * speed_factor_sq(D.noise_seed, (uint32_t)u, A.noise_amp);
     store1_stream(Mo.p + g, fmaf(-(A.dt * fmaf(s_tb[L], pc, K)), Tt, pc));
 }
 

@@ -25,19 +25,6 @@ namespace {
 constexpr int kNT = 1024;                          // threads per workgroup
 constexpr int kK = kResident1dCells / kNT;         // cells per thread
 
-__device__ __forceinline__ uint64_t splitmix64_r(uint64_t x)
-{
-    uint64_t z = x + 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-
-__device__ __forceinline__ float stencil4_r(const float (&c)[4], float d1, float d2, float d3, float d4)
-{
-    return fmaf(c[3], d4, fmaf(c[2], d3, fmaf(c[1], d2, c[0] * d1)));
-}
-
 // bad_row <- min(bad_row, t) with -1 meaning "none yet"; workgroups run
 // different steps at the same time, so the first row is kept by value
 __device__ void flag_bad_row(int64_t *bad_row, int64_t t)
@@ -177,13 +164,7 @@ __global__ __launch_bounds__(kNT) void k_resident1d(const Resident1dArgs R)
             cb[k] = L * kCoefStride;
             mf[k] = 2.0f * A.dt / (s_coef[L * kCoefStride + kRHO] + s_coef[Ln * kCoefStride + kRHO]);
             float K = s_coef[L * kCoefStride + kKB];
-            if (A.noise_amp != 0.0f) {
-                const uint64_t hsh = splitmix64_r(D.noise_seed ^ (uint64_t)(uint32_t)i);
-                const float u = (float)(hsh >> 40) * 0x1.0p-24f;
-                const float e = A.noise_amp * fmaf(2.0f, u, -1.0f);
-                const float f1 = 1.0f + e;
-                K = K * (f1 * f1);
-            }
+            if (A.noise_amp != 0.0f) K = K * speed_factor_sq(D.noise_seed, (uint32_t)i, A.noise_amp);
             Kf[k] = K;
         }
     }
@@ -231,7 +212,7 @@ __global__ __launch_bounds__(kNT) void k_resident1d(const Resident1dArgs R)
             const int i = tb + k * kNT;
             if (i >= n) continue;
             const float *sr = sp + L0 + i;
-            float Da = stencil4_r(A.fd, sr[1] - sr[0], sr[2] - sr[-1], sr[3] - sr[-2], sr[4] - sr[-3]);
+            float Da = stencil4(A.fd, sr[1] - sr[0], sr[2] - sr[-1], sr[3] - sr[-2], sr[4] - sr[-3]);
             if (i < P || i >= n - P) {
                 const int s = i < P ? i : i - n + 2 * P;
                 const float qv = fmaf(saF[s], Da, sbF[s] * spp1[s]);
@@ -261,7 +242,7 @@ __global__ __launch_bounds__(kNT) void k_resident1d(const Resident1dArgs R)
             const int i = tb + k * kNT;
             if (i >= n) continue;
             const float *sx = sv + L0 + i;
-            float S = stencil4_r(A.fd, sx[0] - sx[-1], sx[1] - sx[-2], sx[2] - sx[-3], sx[3] - sx[-4]);
+            float S = stencil4(A.fd, sx[0] - sx[-1], sx[1] - sx[-2], sx[2] - sx[-3], sx[3] - sx[-4]);
             if (i < P || i >= n - P) {
                 const int s = i < P ? i : i - n + 2 * P;
                 const float qv = fmaf(saC[s], S, sbC[s] * spp2[s]);

@@ -1,11 +1,45 @@
-// Device helpers shared by the step and adjoint kernels: vector loads and
-// stores of a cell's N memory variables (stored contiguously, N * 4 bytes,
-// aligned to N * 4 bytes for N = 2, 4), and their non-temporal forms.
+// Device helpers shared by the step, adjoint, diagnostic and resident
+// kernels: the staggered stencil sum, the per-voxel speed perturbation, and
+// vector loads and stores of a cell's N memory variables (stored
+// contiguously, N * 4 bytes, aligned to N * 4 bytes for N = 2, 4), with their
+// non-temporal forms.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
+
 namespace fw {
+
+// sum_m c_m d_m with an explicit fused-multiply-add chain.  The library is
+// compiled without implicit contraction, so every kernel and every
+// instantiation (tile shape, batching) performs the same rounding sequence.
+__device__ __forceinline__ float stencil4(const float (&c)[4], float d1, float d2, float d3, float d4)
+{
+    return fmaf(c[3], d4, fmaf(c[2], d3, fmaf(c[1], d2, c[0] * d1)));
+}
+
+// SplitMix64 (Steele, Lea and Flood, 2014): the hash behind the per-voxel
+// speed perturbation.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x)
+{
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// (1 + eps)^2, the factor of the bulk modulus rho c^2 (1 + eps)^2 of the cell
+// with unpadded index `index`: eps = amp (2 u - 1), u from the top 24 bits of
+// SplitMix64(seed ^ index).
+__device__ __forceinline__ float speed_factor_sq(uint64_t seed, uint32_t index, float amp)
+{
+    const uint64_t h = splitmix64(seed ^ (uint64_t)index);
+    const float u = (float)(h >> 40) * 0x1.0p-24f;
+    const float e = amp * fmaf(2.0f, u, -1.0f);
+    const float f1 = 1.0f + e;
+    return f1 * f1;
+}
 
 template <int N>
 __device__ __forceinline__ void load_vec(const float *__restrict__ src, float (&v)[N])
