@@ -40,7 +40,7 @@ TRAFFIC_MEASURED = {
     # per step; FETCH_SIZE counts L2 misses sent to the data fabric, so the
     # z-window reads served by the last-level cache are included: an upper bound
     # on the HBM bytes
-    ("0fc8ad3b904c55ee", 120): {"workload": "3d_heterogeneous_960x960x720", "step_bytes": 144.84e9,
+    ("e1266490f05a6ee7", 120): {"workload": "3d_heterogeneous_960x960x720", "step_bytes": 144.84e9,
                                 "velocity_bytes": 99.29e9,
                                 "profile": "profiles/step_kernels_3d_960x960x720_N4.md"},
 }
