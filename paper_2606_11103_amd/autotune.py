@@ -1,7 +1,8 @@
 """Launch-shape autotuner for a Simulation.
 
-Every option it touches (3D plane kernels and 2D tile kernels and their tile rows, tile rows, rows per thread,
-marching chunk, persistent grid) changes only the work decomposition -- results are bitwise
+Every option it touches (3D plane kernels and 2D tile kernels and their tile rows, tile depths,
+the interleaved chunk schedule, tile rows, rows per thread, marching chunk, persistent grid)
+changes only the work decomposition -- results are bitwise
 identical -- so candidates are timed on the live state: the state is saved,
 each candidate runs a few steps with per-kernel HIP events, and the state is
 restored.  The winner is applied and stored in a JSON cache keyed by the
@@ -13,14 +14,16 @@ import math
 import os
 
 from .native import (FW_OPT_MARCH_CHUNK, FW_OPT_PERSISTENT, FW_OPT_PLANE_KERNELS, FW_OPT_PLANE_ROWS,
-                     FW_OPT_PRS_PLANES, FW_OPT_ROWS_PER_THREAD, FW_OPT_TILE_ROWS, FW_OPT_VEL_PLANES)
+                     FW_OPT_PRS_PLANES, FW_OPT_ROWS_PER_THREAD, FW_OPT_STEP_CHUNK, FW_OPT_TILE_ROWS,
+                     FW_OPT_VEL_PLANES)
 
 CACHE_PATH = os.path.join(os.path.expanduser("~"), ".cache", "fw25_autotune.json")
 
 # the library's defaults (3D with N >= 3; 2D grids default to 8-row tile
 # kernels, 3D grids with N <= 2 to 8-row tiles of 2 velocity planes)
 DEFAULT = {"plane_kernels": -1, "plane_rows": 4, "tile_rows": 4, "rows_per_thread": 1, "march_chunk": 0,
-           "persistent": 0, "vel_planes": 1, "prs_planes": 0}    # prs_planes 0: the library's default for N
+           "persistent": 0, "vel_planes": 1, "prs_planes": 0,    # prs_planes 0: the library's default for N
+           "step_chunk": -1}
 
 
 def candidates(ndim):
@@ -31,9 +34,11 @@ def candidates(ndim):
             for prow in (4, 8):
                 for vp in (1, 2, 4):
                     for pp in (2, 4, 8):
-                        out.append({"plane_kernels": plane, "plane_rows": prow, "tile_rows": 4,
-                                    "rows_per_thread": 1, "march_chunk": 0, "persistent": 0,
-                                    "vel_planes": vp, "prs_planes": pp})
+                        # interleaved chunks: the library's choice for the grid, or whole-grid launches
+                        for sc in (-1, 0):
+                            out.append({"plane_kernels": plane, "plane_rows": prow, "tile_rows": 4,
+                                        "rows_per_thread": 1, "march_chunk": 0, "persistent": 0,
+                                        "vel_planes": vp, "prs_planes": pp, "step_chunk": sc})
         for rows, rpt in ((4, 1), (8, 1), (16, 1), (16, 2), (8, 2)):
             for persistent in (0, 4):
                 for chunk in (0, 24, 96):
@@ -66,6 +71,7 @@ def apply(sim, cfg):
     sim.set_option(FW_OPT_VEL_PLANES, cfg.get("vel_planes", vp))
     pp = cfg.get("prs_planes", 0)
     sim.set_option(FW_OPT_PRS_PLANES, pp if pp else (2 if sim.n_mech >= 3 else 8))
+    sim.set_option(FW_OPT_STEP_CHUNK, cfg.get("step_chunk", -1))
     # rows per thread first when shrinking to 4-row tiles is requested
     sim.set_option(FW_OPT_ROWS_PER_THREAD, 1)
     sim.set_option(FW_OPT_TILE_ROWS, cfg["tile_rows"])
