@@ -6,9 +6,10 @@
 // velocity update and the pressure update (with the sources and receivers of
 // the cells it updates), separated by workgroup barriers, and HBM is touched
 // only to load the state at the start and store it at the end of the run
-// (plus the source waveforms and the receiver traces).  A 1D domain of 8192 cells at N = 4
-// holds 320 KB of state: a per-step pass over HBM or the last-level cache
-// costs far more than the arithmetic, so the step is kept on chip.
+// (plus the source waveforms and the receiver traces).  A 1D domain of 8192
+// cells at N = 4 holds 320 KB of state: a per-step pass over HBM or the
+// last-level cache costs far more than the arithmetic, so the step is kept on
+// chip.
 //
 // Each value is computed with the operations of k_velocity / k_pressure /
 // k_src_rec in 1D, in the same order (Sec. 3.3 step with the memory
@@ -180,6 +181,8 @@ __global__ __launch_bounds__(kNT) void k_resident1d(const Resident1dArgs R)
     const bool uniform = s_mixed == 0 && A.noise_amp == 0.0f;
     // the run's steps; with UNI every cell's coefficients are those of the
     // domain's single class (same values as the per-cell path reads)
+    // (readfirstlane takes lane 0's value: a wave with work always has cell
+    // tid < n in lane 0, so its per-cell constants are set)
     auto run = [&](auto uni_tag) {
     constexpr bool UNI = decltype(uni_tag)::value;
     const int Lu = n > 0 ? scl[0] * kCoefStride : 0;
