@@ -2,6 +2,7 @@
 (relative L2 over [steps x receivers], FP64 sums, bar 1e-4), plus the
 bitwise invariances of the HIP path itself (launch path, tiling, batching,
 resume)."""
+import time
 import zlib
 
 import numpy as np
@@ -340,6 +341,67 @@ def test_resident_1d_single_class_domains(nmech, noise):
     assert np.array_equal(ref, got)
     used = sim.state_bytes() - 256 + 16
     assert torch.equal(sim.save_state()[:used], ref_sim.save_state()[:used])
+
+
+def test_resident_1d_path_is_the_one_taken():
+    """The resident comparisons above only mean something if the default
+    really runs the resident kernel: on 256 domains of 8192 cells it is
+    several times faster than the per-step kernels (about 9x measured), which
+    no other path reaches."""
+    import torch
+    from paper_2606_11103_amd.native import FW_OPT_RESIDENT_1D
+    case = configs.random_small(1, [(8192, 1, 1)] * 256, 2, 1, seed=5, steps=2000, pml=24, noise=0.0)
+    case = configs.with_table(case, *configs.random_relaxation_table(5, case.n_classes, case.nmech))
+    ms = {}
+    for resident in (0, -1):
+        sim = to_simulation(case)
+        sim.set_option(FW_OPT_RESIDENT_1D, resident)
+        sim.prepare()
+        sim.step(10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(case.n_steps - 10)
+        torch.cuda.synchronize()
+        ms[resident] = 1e3 * (time.perf_counter() - t0)
+    report("resident 1D, 256 x 8192 cells, N=2, %d steps: %.1f ms resident, %.1f ms per-step kernels"
+           % (case.n_steps - 10, ms[-1], ms[0]))
+    assert 3.0 * ms[-1] < ms[0]
+
+
+def test_resident_1d_mixed_with_energy_steps_and_rewind():
+    """Resident launches interleaved with energy steps (which take the
+    per-step kernels), an odd number of steps between them, and a rewind to a
+    saved state: traces, energies and the final state bitwise equal to the
+    same sequence run with the per-step kernels only."""
+    import torch
+    from paper_2606_11103_amd.native import FW_OPT_RESIDENT_1D
+    case = configs.random_small(1, [(4096, 1, 1), (999, 1, 1)], 3, 3, seed=311, steps=900, pml=16)
+    case = configs.with_table(case, *configs.random_relaxation_table(311, case.n_classes, case.nmech))
+    out = []
+    for resident in (0, -1):
+        sim = to_simulation(case)
+        sim.set_option(FW_OPT_RESIDENT_1D, resident)
+        energies = []
+        sim.step(101)
+        energies.append(sim.energy_step())
+        sim.step(250)
+        snap = sim.save_state()
+        sim.step(33)
+        energies.append(sim.energy_step())
+        sim.load_state(snap)
+        assert sim.get_step() == 352
+        energies.append(sim.energy_step())
+        sim.step(case.n_steps - 353)
+        assert sim.get_step() == case.n_steps
+        used = sim.state_bytes() - 256 + 16
+        out.append((sim.read_receivers(), np.stack(energies), sim.save_state()[:used]))
+    (ref, e_ref, s_ref), (got, e_got, s_got) = out
+    assert np.array_equal(ref, got)
+    assert np.array_equal(e_ref, e_got)
+    assert torch.equal(s_ref, s_got)
+    glob, worst, n = check_traces(got, oracle_traces(case))
+    report("resident 1D mixed with energy steps and a rewind: bitwise equal; rel_L2=%.3e worst_receiver=%.3e "
+           "(%d reached)" % (glob, worst, n))
 
 
 def test_resident_1d_flags_the_first_non_finite_row():
