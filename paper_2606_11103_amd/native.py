@@ -72,6 +72,13 @@ class FWError(RuntimeError):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libfw25.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    # torch ships its own HIP runtime.  Loaded first, it is the one the
+    # library's libamdhip64 dependency binds to, so the library and torch
+    # share one runtime (torch's device memory and streams are valid in the
+    # library's calls).  Loading the library first would bring in the
+    # system's runtime beside torch's, and the library's calls would then
+    # fail to find the device.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)

@@ -177,3 +177,18 @@ def test_python_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     with pytest.raises(ImportError):
         nat._load()
     importlib.reload(nat)
+
+
+def test_binding_shares_the_hip_runtime_torch_loads():
+    """Importing the binding before torch still loads a single HIP runtime
+    (torch's): a second one beside it would not know torch's device memory
+    and would report no device from the library's calls."""
+    import subprocess
+    import sys
+    code = ("import paper_2606_11103_amd.native\n"
+            "libs = sorted({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l})\n"
+            "print(len(libs), libs)\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.split()[0] == "1", out.stdout
