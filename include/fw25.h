@@ -147,6 +147,29 @@ int fw_set_media(fw_sim *sim, const uint8_t *h_class, const int32_t *class_base,
 int fw_set_strength_map(fw_sim *sim, const float *d_scale, void *hip_stream);
 
 /*
+ * Staggered first-derivative coefficients c_1..c_4 of every update (Sec. 3.3:
+ * an operator of order 2M in space, M = 4, with fourth order in time).  The
+ * default is the Taylor set (1225/1024, -245/3072, 49/5120, -5/7168), with
+ * which the leapfrog step is of second order in time.  c_ref > 0 selects the
+ * time-space-domain set for the Courant number r = c_ref dt / dx: the c_m
+ * solving sum_m c_m (2m - 1)^(2k - 1) = r^(2k - 2), k = 1..4 (Liu and Sen
+ * 2011), which makes the 1D step of order 8 in both time and space for waves
+ * at speed c_ref (the relation sin(w dt / 2) = r sum_m c_m sin((2m - 1) k dx
+ * / 2) then agrees with w = c_ref k through (k dx)^7).  Along each axis of a
+ * 2D or 3D grid the same holds; oblique directions keep a second-order time
+ * error, since that needs the off-axis stencil points of Tan and Huang (2014),
+ * which this operator does not have.  c_ref = 0 restores the Taylor set.
+ * FW_EINVAL if c_ref < 0, not finite or r >= 1; FW_EUNSTABLE (the previous
+ * set kept) if media are set and the stability bound of the new set fails.
+ * May come before or after fw_set_media; drops a captured step graph.  The
+ * adjoint uses the same coefficients, so it stays the exact transpose.
+ */
+int fw_set_time_space_stencil(fw_sim *sim, double c_ref);
+
+/* The four coefficients in use (c_m, dimensionless, FP64) into coef4[4]. */
+int fw_get_stencil(const fw_sim *sim, double *coef4);
+
+/*
  * Relaxation parameters per class (Sec. 2.1, Table 2 variables), FP64 in:
  *   kappa [n_classes][2], d [n_classes][2][N], alpha [n_classes][2][N]
  *   (index 0: gradient operator nabla_1, index 1: divergence nabla_2).

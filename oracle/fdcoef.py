@@ -16,15 +16,28 @@ is exact for every odd monomial x^(2k-1), k = 1..M, which gives the linear
 system  sum_m c_m (2m-1)^(2k-1) = delta_{k,1}.  Even monomials cancel by
 symmetry, so the operator is exact for all polynomials of degree <= 2M-1.
 The system is solved here in exact rational arithmetic.
+
+Time order (Sec. 3.3 asks for an operator of order 2M in space and fourth
+order in time, after Tan & Huang 2014).  With the Taylor coefficients the
+leapfrog step is of second order in time.  The time-space-domain staggered
+coefficients (Liu & Sen 2011, after Finkelstein & Kastner 2007) instead match
+the scheme's own 1D dispersion relation
+
+    sin(w dt / 2) = r * sum_m c_m sin((2m-1) k h / 2),   r = c dt / h,
+
+to the exact w = c k term by term in k h: the powers (kh)^(2k-1),
+k = 1..M, agree when  sum_m c_m (2m-1)^(2k-1) = r^(2k-2).  At the reference
+speed the 1D step is then of order 2M in space and in time together (the
+leading error is (kh)^(2M+1)).  r = 0 gives back the Taylor set.
 """
 from fractions import Fraction
 
 
-def staggered_coefficients_exact(M=4):
-    """Return [c_1..c_M] as Fractions solving sum_m c_m (2m-1)^(2k-1) = [k==1]."""
+def _solve_odd_moments(M, rhs):
+    """[c_1..c_M] as Fractions solving sum_m c_m (2m-1)^(2k-1) = rhs[k-1]."""
     A = [[Fraction((2 * m - 1) ** (2 * k - 1)) for m in range(1, M + 1)]
          for k in range(1, M + 1)]
-    rhs = [Fraction(1 if k == 1 else 0) for k in range(1, M + 1)]
+    rhs = list(rhs)
     # Gauss-Jordan elimination with exact rationals.
     n = M
     for col in range(n):
@@ -42,6 +55,24 @@ def staggered_coefficients_exact(M=4):
     return rhs
 
 
+def staggered_coefficients_exact(M=4):
+    """Return [c_1..c_M] as Fractions solving sum_m c_m (2m-1)^(2k-1) = [k==1]."""
+    return _solve_odd_moments(M, [Fraction(1 if k == 1 else 0) for k in range(1, M + 1)])
+
+
 def staggered_coefficients(M=4):
     """FP64 values of the exact coefficients."""
     return [float(c) for c in staggered_coefficients_exact(M)]
+
+
+def time_space_coefficients_exact(r, M=4):
+    """Time-space-domain coefficients for the Courant number r = c dt / h:
+    Fractions solving sum_m c_m (2m-1)^(2k-1) = r^(2k-2), k = 1..M, with r
+    taken as the exact rational value of the FP64 number given."""
+    rr = Fraction(r) ** 2
+    return _solve_odd_moments(M, [rr ** (k - 1) for k in range(1, M + 1)])
+
+
+def time_space_coefficients(r, M=4):
+    """FP64 values of time_space_coefficients_exact(r, M)."""
+    return [float(c) for c in time_space_coefficients_exact(r, M)]

@@ -146,13 +146,15 @@ class OracleSim:
     d and alpha [C][2][N] (index 0 for the gradient operator, 1 for the
     divergence operator).  a_scale (per voxel, optional) multiplies both
     operators' recursion coefficients a of the voxel (its relaxation
-    strength; b, the relaxation times, unchanged).
+    strength; b, the relaxation times, unchanged).  fd_c_ref (optional, a
+    speed) selects the time-space-domain staggered coefficients for the
+    Courant number fd_c_ref dt / dx instead of the Taylor ones.
     """
 
     def __init__(self, ndim, shape, dx, dt, nmech, class_map, c, rho, beta,
                  kappa, d, alpha, pml_cells=0, pml_R0=1e-4, pml_f_alpha=1e6, pml_c_ref=None,
                  noise_amp=0.0, noise_seed=0, d_scale=None, noise_index=None, axis_full=None,
-                 engine=None, a_scale=None):
+                 engine=None, a_scale=None, fd_c_ref=None):
         self.engine = engine
         self.ndim = int(ndim)
         nx, ny, nz = (list(shape) + [1, 1, 1])[:3]
@@ -198,7 +200,12 @@ class OracleSim:
             self.coef["b" + nm] = np.ascontiguousarray(b_)
             self.coef["as" + nm] = np.ascontiguousarray(as_ / s[None, :])
             self.coef["bs" + nm] = np.ascontiguousarray(bs_ / s[None, :])
-        self.fd = fdcoef.staggered_coefficients(4)
+        # staggered coefficients: the Taylor set, or the time-space set for
+        # the Courant number of the speed fd_c_ref (fdcoef)
+        if fd_c_ref:
+            self.fd = fdcoef.time_space_coefficients(float(fd_c_ref) * self.dt / self.dx, 4)
+        else:
+            self.fd = fdcoef.staggered_coefficients(4)
         cref = float(np.max(c)) if pml_c_ref is None else float(pml_c_ref)
         self.nmax = max(self.shape)
         pm = {k: np.zeros((3, self.nmax)) for k in ("aF", "bF", "aC", "bC")}

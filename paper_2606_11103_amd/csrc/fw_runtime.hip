@@ -42,7 +42,36 @@ int fail(int code, const char *fmt, ...)
 // exact for odd monomials up to x^7 on the half-integer stencil).
 constexpr double kFD[4] = {1225.0 / 1024.0, -245.0 / 3072.0, 49.0 / 5120.0, -5.0 / 7168.0};
 
-double fd_abs_sum() { return std::fabs(kFD[0]) + std::fabs(kFD[1]) + std::fabs(kFD[2]) + std::fabs(kFD[3]); }
+// Time-space-domain staggered coefficients for the Courant number r: the
+// solution of sum_m c_m (2m - 1)^(2k - 1) = r^(2k - 2), k = 1..4, which makes
+// the 1D leapfrog dispersion relation sin(w dt / 2) = r sum_m c_m sin((2m - 1)
+// k dx / 2) agree with w = c k through (k dx)^7 at the speed r dx / dt, so the
+// step is of order 8 in time as well as in space there (Liu and Sen 2011).
+// r = 0 gives the Taylor set.  Gaussian elimination with partial pivoting
+// in FP64 on the 4 x 4 system of odd moments.
+static void time_space_coefficients(double r, double out[4])
+{
+    double A[4][5];
+    for (int k = 0; k < 4; ++k) {
+        for (int m = 0; m < 4; ++m) A[k][m] = std::pow(2.0 * m + 1.0, 2.0 * k + 1.0);
+        A[k][4] = std::pow(r * r, (double)k);
+    }
+    for (int col = 0; col < 4; ++col) {
+        int piv = col;
+        for (int rr = col + 1; rr < 4; ++rr)
+            if (std::fabs(A[rr][col]) > std::fabs(A[piv][col])) piv = rr;
+        for (int j = 0; j < 5; ++j) std::swap(A[col][j], A[piv][j]);
+        for (int rr = col + 1; rr < 4; ++rr) {
+            const double f = A[rr][col] / A[col][col];
+            for (int j = col; j < 5; ++j) A[rr][j] -= f * A[col][j];
+        }
+    }
+    for (int m = 3; m >= 0; --m) {
+        double acc = A[m][4];
+        for (int j = m + 1; j < 4; ++j) acc -= A[m][j] * out[j];
+        out[m] = acc / A[m][m];
+    }
+}
 
 constexpr int64_t kAlignCells = 64;
 constexpr int64_t kRowCells = 32;        // row pitch granule of 2D/3D domains: one 128-byte line
@@ -101,6 +130,11 @@ struct fw_sim {
     uint64_t noise_seed = 0;
     std::vector<double> kappa, dcoef, alpha;
     std::vector<double> alpha0;          // power-law coefficient per class (fw_set_class_alpha0)
+    // staggered first-derivative coefficients (Taylor, or the time-space set of
+    // fw_set_time_space_stencil) and the smallest kappa1 kappa2 of the table
+    double fd[4] = {kFD[0], kFD[1], kFD[2], kFD[3]};
+    double fd_cref = 0.0, min_kk = 1.0;
+    double fd_abs_sum() const { return std::fabs(fd[0]) + std::fabs(fd[1]) + std::fabs(fd[2]) + std::fabs(fd[3]); }
     // device tables
     DevBuf d_doms, d_classes, d_pml, d_tiles, d_vtiles, d_ptiles, d_waves, d_traces, d_step;
     float *traces_ext = nullptr;         // caller-owned trace buffer (fw_set_receivers_into), borrowed
@@ -232,7 +266,7 @@ int stability_check(const fw_sim *s, double min_kappa_prod)
 {
     double cmax = 0;
     for (double v : s->c) cmax = std::max(cmax, v);
-    const double courant = cmax * (1.0 + s->noise_amp) * s->dt / s->dx * std::sqrt((double)s->ndim) * fd_abs_sum() /
+    const double courant = cmax * (1.0 + s->noise_amp) * s->dt / s->dx * std::sqrt((double)s->ndim) * s->fd_abs_sum() /
                            std::sqrt(min_kappa_prod);
     if (!(courant < 1.0))
         return fail(FW_EUNSTABLE, "time step too large: c_max dt/dx sqrt(ndim) sum|c_m| / sqrt(kappa1 kappa2) = %.6f >= 1",
@@ -463,7 +497,7 @@ fw::StepArgs step_args(const fw_sim *s)
     a.ptiles = s->d_ptiles.as<fw::Tile>();
     a.n_ptiles = s->n_ptiles;
     a.ptiles_per_xcd = s->ptiles_per_xcd;
-    for (int m = 0; m < 4; ++m) a.fd[m] = (float)(kFD[m] / s->dx);
+    for (int m = 0; m < 4; ++m) a.fd[m] = (float)(s->fd[m] / s->dx);
     a.dt = (float)s->dt;
     a.noise_amp = (float)s->noise_amp;
     a.amap = s->amap;
@@ -849,6 +883,7 @@ int fw_set_relaxation_table(fw_sim *sim, int n_classes, const double *kappa, con
     }
     int rc = stability_check(sim, min_kk);
     if (rc != FW_OK) return rc;
+    sim->min_kk = min_kk;
     sim->kappa.assign(kappa, kappa + 2 * n_classes);
     sim->dcoef.assign(d, d + 2 * N * n_classes);
     sim->alpha.assign(alpha, alpha + 2 * N * n_classes);
@@ -1468,6 +1503,42 @@ extern "C" int fw_adjoint_modulus(fw_sim *sim, int n_steps, int ckpt_every, void
     g_err.clear();
     if (!sim || !d_work || !d_adj_src || !d_grad_K || !d_grad_s) return fail(FW_EINVAL, "NULL argument");
     return adjoint_sweep(sim, n_steps, ckpt_every, d_work, bytes, d_adj_src, d_grad_K, d_grad_s, hip_stream);
+}
+
+extern "C" int fw_set_time_space_stencil(fw_sim *sim, double c_ref)
+{
+    g_err.clear();
+    if (!sim) return fail(FW_EINVAL, "sim is NULL");
+    if (!(c_ref >= 0.0) || !std::isfinite(c_ref)) return fail(FW_EINVAL, "c_ref must be finite and >= 0 (got %g)", c_ref);
+    const double r = c_ref * sim->dt / sim->dx;
+    if (!(r < 1.0)) return fail(FW_EINVAL, "c_ref dt / dx = %g: the time-space coefficients need a Courant number < 1", r);
+    double prev[4];
+    std::copy(sim->fd, sim->fd + 4, prev);
+    const double prev_cref = sim->fd_cref;
+    if (c_ref > 0.0) {
+        time_space_coefficients(r, sim->fd);
+    } else {
+        std::copy(kFD, kFD + 4, sim->fd);
+    }
+    sim->fd_cref = c_ref;
+    if (sim->media_set) {
+        const int rc = stability_check(sim, sim->table_set ? sim->min_kk : 1.0);
+        if (rc != FW_OK) {
+            std::copy(prev, prev + 4, sim->fd);
+            sim->fd_cref = prev_cref;
+            return rc;
+        }
+    }
+    sim->drop_graph();            // captured steps hold the previous coefficients
+    return FW_OK;
+}
+
+extern "C" int fw_get_stencil(const fw_sim *sim, double *coef4)
+{
+    g_err.clear();
+    if (!sim || !coef4) return fail(FW_EINVAL, "NULL argument");
+    std::copy(sim->fd, sim->fd + 4, coef4);
+    return FW_OK;
 }
 
 extern "C" int fw_set_class_alpha0(fw_sim *sim, int n_classes, const double *alpha0)

@@ -221,6 +221,17 @@ class Simulation:
             raise ValueError("adj_src needs [n_steps][n_rec] values")
         return adj_src
 
+    def set_time_space_stencil(self, c_ref):
+        """Staggered coefficients tuned to the speed c_ref (time-space-domain
+        set of fw_set_time_space_stencil); 0 restores the Taylor set."""
+        check(lib.fw_set_time_space_stencil(self._h, float(c_ref)))
+
+    def stencil(self):
+        """The four staggered coefficients in use (FP64)."""
+        out = (ctypes.c_double * 4)()
+        check(lib.fw_get_stencil(self._h, out))
+        return list(out)
+
     def set_strength_map(self, scale, stream=None):
         """Per-voxel relaxation strength scale s(x) in [0, 1] (a device float
         tensor over all cells, unpadded layout), or None to clear it.  The

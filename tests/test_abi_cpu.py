@@ -192,3 +192,34 @@ def test_binding_shares_the_hip_runtime_torch_loads():
     out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.split()[0] == "1", out.stdout
+
+
+def test_time_space_stencil_host_setup():
+    """fw_set_time_space_stencil computes the time-space set on the host: the
+    same coefficients as the oracle's exact rational solution, the Taylor set
+    back with c_ref = 0, and documented errors for invalid speeds."""
+    from oracle import fdcoef
+    from paper_2606_11103_amd import native
+    lib = native.lib
+    dx, dt = 1e-4, 2e-8
+    rc, h = _create(dx=dx, dt=dt)
+    assert rc == 0
+    out = np.zeros(4)
+    p = ctypes.c_void_p(out.ctypes.data)
+    assert lib.fw_get_stencil(h, p) == 0
+    assert np.array_equal(out, np.array(fdcoef.staggered_coefficients(4)))
+    for c_ref in (800.0, 1540.0, 3000.0, 4900.0):
+        assert lib.fw_set_time_space_stencil(h, c_ref) == 0
+        assert lib.fw_get_stencil(h, p) == 0
+        ref = np.array(fdcoef.time_space_coefficients(c_ref * dt / dx, 4))
+        assert np.max(np.abs(out - ref) / np.abs(ref)) < 1e-13, (c_ref, out, ref)
+    assert lib.fw_set_time_space_stencil(h, -1.0) == native.FW_EINVAL
+    assert lib.fw_set_time_space_stencil(h, float("nan")) == native.FW_EINVAL
+    assert lib.fw_set_time_space_stencil(h, dx / dt) == native.FW_EINVAL      # r = 1
+    assert lib.fw_get_stencil(h, p) == 0                                       # unchanged by the failures
+    assert np.max(np.abs(out - ref) / np.abs(ref)) < 1e-13
+    assert lib.fw_set_time_space_stencil(h, 0.0) == 0
+    assert lib.fw_get_stencil(h, p) == 0
+    assert np.array_equal(out, np.array(fdcoef.staggered_coefficients(4)))
+    assert lib.fw_set_time_space_stencil(None, 1500.0) == native.FW_EINVAL
+    assert lib.fw_destroy(h) == 0

@@ -47,6 +47,7 @@ class Case:
     d: Optional[np.ndarray] = None      # [C][2][N]
     alpha: Optional[np.ndarray] = None  # [C][2][N]
     strength: Optional[List[np.ndarray]] = None   # per-voxel strength scale in [0, 1] per domain (float32)
+    fd_c_ref: float = 0.0               # > 0: staggered coefficients of the time-space set for this speed
 
     @property
     def n_classes(self):
