@@ -29,6 +29,17 @@ to the exact w = c k term by term in k h: the powers (kh)^(2k-1),
 k = 1..M, agree when  sum_m c_m (2m-1)^(2k-1) = r^(2k-2).  At the reference
 speed the 1D step is then of order 2M in space and in time together (the
 leading error is (kh)^(2M+1)).  r = 0 gives back the Taylor set.
+
+In 2D and 3D an on-axis stencil cannot reach fourth order in time for oblique
+waves: the leapfrog relation sin^2(w dt/2) = r^2 sum_a A_a^2 has mixed terms
+(k_a k_b)^2 at fourth order that no sum of squares of on-axis symbols
+produces.  Tan & Huang widen each difference by the two-point difference
+along its axis in the neighbouring rows of every other axis, with weight b:
+A_x = sum_m c_m sin((2m-1) k_x h/2) + 2 b sin(k_x h/2) sum_{o != x} cos(k_o h).
+Expanding to fourth order gives b = r^2/24 for the mixed terms, and along each
+axis the moments  sum_m c_m (2m-1)^(2k-1) = r^(2k-2) - 2 (d-1) b,  k = 1..M,
+in d dimensions.  The divergence takes the same widened stencil, so it stays
+the negative transpose of the gradient.
 """
 from fractions import Fraction
 
@@ -76,3 +87,17 @@ def time_space_coefficients_exact(r, M=4):
 def time_space_coefficients(r, M=4):
     """FP64 values of time_space_coefficients_exact(r, M)."""
     return [float(c) for c in time_space_coefficients_exact(r, M)]
+
+
+def isotropic_time_space_coefficients_exact(r, ndim, M=4):
+    """(c_1..c_M, b) as Fractions for the widened stencil in ndim dimensions:
+    b = r^2 / 24 and sum_m c_m (2m-1)^(2k-1) = r^(2k-2) - 2 (ndim-1) b."""
+    rr = Fraction(r) ** 2
+    b = rr / 24
+    return _solve_odd_moments(M, [rr ** (k - 1) - 2 * (ndim - 1) * b for k in range(1, M + 1)]), b
+
+
+def isotropic_time_space_coefficients(r, ndim, M=4):
+    """FP64 values of isotropic_time_space_coefficients_exact: ([c_m], b)."""
+    c, b = isotropic_time_space_coefficients_exact(r, ndim, M)
+    return [float(x) for x in c], float(b)

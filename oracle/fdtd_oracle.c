@@ -36,6 +36,7 @@ typedef struct {
     int64_t n[3];
     double dx, dt;
     double fd[4];                      /* staggered coefficients c_1..c_4 */
+    double fd_b;                       /* off-axis weight (0: on-axis stencil only) */
     /* per-cell material arrays [cells] */
     const double *rho, *K, *beta, *ik1, *ik2;
     /* per-cell recursion coefficients [nmech][cells] */
@@ -65,6 +66,31 @@ static int64_t coord_of(const ora_sim *s, int64_t idx, int a)
     return idx / (s->n[0] * s->n[1]);
 }
 
+/* Off-axis part of the axis-a difference (the widened stencil of Tan and
+ * Huang): the two-point difference f[ia + hi] - f[ia + lo] along axis a taken
+ * in the rows one cell away along every other axis o, both sides, summed;
+ * zero outside the grid.  The gradient at face i+1/2 uses (hi, lo) = (1, 0),
+ * the divergence at cell i uses (0, -1). */
+static double off_axis(const ora_sim *s, const double *f, int64_t idx, int a, int hi, int lo)
+{
+    if (s->fd_b == 0.0) return 0.0;
+    const int64_t st = stride_of(s, a), ia = coord_of(s, idx, a), na = s->n[a];
+    double acc = 0.0;
+    for (int o = 0; o < s->ndim; ++o) {
+        if (o == a) continue;
+        const int64_t so = stride_of(s, o), io = coord_of(s, idx, o), no = s->n[o];
+        for (int sg = -1; sg <= 1; sg += 2) {
+            const int64_t jo = io + sg;
+            if (jo < 0 || jo >= no) continue;
+            const int64_t row = idx + sg * so;
+            const double fh = (ia + hi >= 0 && ia + hi < na) ? f[row + hi * st] : 0.0;
+            const double fl = (ia + lo >= 0 && ia + lo < na) ? f[row + lo * st] : 0.0;
+            acc += fh - fl;
+        }
+    }
+    return acc;
+}
+
 /* Staggered gradient of a cell field f at face i+1/2 of axis a:
  * (1/dx) sum_m c_m (f[i+m] - f[i+1-m]), zero outside the grid. */
 static double grad_face(const ora_sim *s, const double *f, int64_t idx, int a)
@@ -77,6 +103,7 @@ static double grad_face(const ora_sim *s, const double *f, int64_t idx, int a)
         const double fm = (jm >= 0 && jm < na) ? f[idx + (jm - ia) * st] : 0.0;
         D += s->fd[m - 1] * (fp - fm);
     }
+    D += s->fd_b * off_axis(s, f, idx, a, 1, 0);
     return D / s->dx;
 }
 
@@ -92,6 +119,7 @@ static double div_cell(const ora_sim *s, const double *g, int64_t idx, int a)
         const double gm = (jm >= 0 && jm < na) ? g[idx + (jm - ia) * st] : 0.0;
         D += s->fd[m - 1] * (gp - gm);
     }
+    D += s->fd_b * off_axis(s, g, idx, a, 0, -1);
     return D / s->dx;
 }
 

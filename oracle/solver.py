@@ -67,7 +67,7 @@ def _load(path=None):
 class _Sim(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int32), ("nmech", ctypes.c_int32),
                 ("n", ctypes.c_int64 * 3), ("dx", ctypes.c_double), ("dt", ctypes.c_double),
-                ("fd", ctypes.c_double * 4)] + \
+                ("fd", ctypes.c_double * 4), ("fd_b", ctypes.c_double)] + \
                [(nm, ctypes.c_void_p) for nm in ("rho", "K", "beta", "ik1", "ik2",
                                                   "a1", "b1", "a2", "b2",
                                                   "pml_aF", "pml_bF", "pml_aC", "pml_bC")] + \
@@ -148,13 +148,14 @@ class OracleSim:
     operators' recursion coefficients a of the voxel (its relaxation
     strength; b, the relaxation times, unchanged).  fd_c_ref (optional, a
     speed) selects the time-space-domain staggered coefficients for the
-    Courant number fd_c_ref dt / dx instead of the Taylor ones.
+    Courant number fd_c_ref dt / dx instead of the Taylor ones; with
+    off_axis (2D/3D) the widened stencil of fdcoef.isotropic_time_space_coefficients.
     """
 
     def __init__(self, ndim, shape, dx, dt, nmech, class_map, c, rho, beta,
                  kappa, d, alpha, pml_cells=0, pml_R0=1e-4, pml_f_alpha=1e6, pml_c_ref=None,
                  noise_amp=0.0, noise_seed=0, d_scale=None, noise_index=None, axis_full=None,
-                 engine=None, a_scale=None, fd_c_ref=None):
+                 engine=None, a_scale=None, fd_c_ref=None, off_axis=False):
         self.engine = engine
         self.ndim = int(ndim)
         nx, ny, nz = (list(shape) + [1, 1, 1])[:3]
@@ -202,7 +203,13 @@ class OracleSim:
             self.coef["bs" + nm] = np.ascontiguousarray(bs_ / s[None, :])
         # staggered coefficients: the Taylor set, or the time-space set for
         # the Courant number of the speed fd_c_ref (fdcoef)
-        if fd_c_ref:
+        # off_axis: the widened stencil of fdcoef.isotropic_time_space_coefficients
+        # (fourth order in time in every direction of a 2D/3D grid)
+        self.fd_b = 0.0
+        if fd_c_ref and off_axis and self.ndim > 1:
+            self.fd, self.fd_b = fdcoef.isotropic_time_space_coefficients(
+                float(fd_c_ref) * self.dt / self.dx, self.ndim, 4)
+        elif fd_c_ref:
             self.fd = fdcoef.time_space_coefficients(float(fd_c_ref) * self.dt / self.dx, 4)
         else:
             self.fd = fdcoef.staggered_coefficients(4)
@@ -249,6 +256,7 @@ class OracleSim:
         st.dx, st.dt = self.dx, self.dt
         for i in range(4):
             st.fd[i] = self.fd[i]
+        st.fd_b = self.fd_b
         ptr = lambda arr: arr.ctypes.data
         st.rho, st.K, st.beta = ptr(self.rho), ptr(self.K), ptr(self.beta)
         st.ik1, st.ik2 = ptr(self.ik1), ptr(self.ik2)

@@ -125,3 +125,88 @@ def test_energy_conserved_with_time_space_set(ndim, shape):
     e = en[nsrc:]
     assert e[0] > 0
     assert np.max(np.abs(e - e[0])) / e[0] < 1e-12
+
+
+def _exact_2d(n, h, c, rho, sigma, t_p, t_v):
+    """Continuous solution of p_t = -rho c^2 div v, rho v_t = -grad p on the
+    plane, from p(x, 0) = Gaussian, v(x, 0) = 0 (spectral, on a grid large
+    enough that the field stays clear of its edges): p at cells at time t_p,
+    v at the faces (x + h/2, y) and (x, y + h/2) at time t_v."""
+    k = 2 * np.pi * np.fft.fftfreq(n, h)
+    KX, KY = np.meshgrid(k, k, indexing="xy")
+    kk = np.sqrt(KX ** 2 + KY ** 2)
+    x = (np.arange(n) - n / 2) * h
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    G = np.fft.fft2(np.exp(-(X ** 2 + Y ** 2) / (2 * sigma ** 2)))
+    w = c * kk
+    p = np.real(np.fft.ifft2(G * np.cos(w * t_p)))
+    s = np.where(kk > 0, np.sin(w * t_v) / np.where(kk > 0, w, 1.0), t_v)
+    vx = np.real(np.fft.ifft2(-1j * KX / rho * G * s * np.exp(1j * KX * h / 2)))
+    vy = np.real(np.fft.ifft2(-1j * KY / rho * G * s * np.exp(1j * KY * h / 2)))
+    return p, vx, vy
+
+
+def _pulse_error_2d(n, r, fd_c_ref=None, off_axis=False, L=0.0128, c=1500.0, rho=1000.0):
+    h = L / n
+    dt = r * h / c
+    sigma = L / 24
+    steps = int(round(0.2 * L / c / dt))
+    sim = OracleSim(2, (n, n, 1), h, dt, 1, np.zeros((1, n, n), np.uint8), [c], [rho], [0.0],
+                    [[1.0, 1.0]], np.zeros((1, 2, 1)), np.ones((1, 2, 1)), fd_c_ref=fd_c_ref, off_axis=off_axis)
+    p0, vx, vy = _exact_2d(n, h, c, rho, sigma, 0.0, -dt / 2)
+    sim.p[:] = p0.reshape(-1)
+    sim.v[0, :] = vx.reshape(-1)
+    sim.v[1, :] = vy.reshape(-1)
+    sim.run(steps)
+    pe, _, _ = _exact_2d(n, h, c, rho, sigma, steps * dt, 0.0)
+    return np.linalg.norm(sim.p - pe.reshape(-1)) / np.linalg.norm(pe)
+
+
+def test_widened_stencil_coefficients_closed_forms():
+    # b = r^2 / 24; the on-axis moments shift by 2 (d - 1) b, which moves c_1
+    # alone (the shift solves the moment system with (1, 0, 0, 0)); no shift
+    # and no b at r = 0 (the Taylor set)
+    for ndim in (2, 3):
+        c, b = fdcoef.isotropic_time_space_coefficients_exact(0.45, ndim, 4)
+        ts = fdcoef.time_space_coefficients_exact(0.45, 4)
+        assert b == Fraction(0.45) ** 2 / 24
+        assert c[0] == ts[0] - 2 * (ndim - 1) * b and c[1:] == ts[1:]
+        c0, b0 = fdcoef.isotropic_time_space_coefficients_exact(0.0, ndim, 4)
+        assert b0 == 0 and c0 == fdcoef.staggered_coefficients_exact(4)
+
+
+def test_widened_stencil_is_fourth_order_in_time_for_a_2d_pulse():
+    # a Gaussian pulse (every propagation direction) against the continuous
+    # solution, refined at fixed r = 0.5: the error falls 4x per halving with
+    # the Taylor and the on-axis time-space sets (second order: their mixed
+    # (k_x k_y)^2 terms), 16x with the widened stencil (fourth order)
+    r = 0.5
+    ty = [_pulse_error_2d(n, r) for n in (96, 192)]
+    ts = [_pulse_error_2d(n, r, fd_c_ref=1500.0) for n in (96, 192)]
+    iso = [_pulse_error_2d(n, r, fd_c_ref=1500.0, off_axis=True) for n in (96, 192)]
+    assert 3.5 < ty[0] / ty[1] < 4.6
+    assert 3.5 < ts[0] / ts[1] < 4.6
+    assert iso[0] / iso[1] > 13.0
+    assert iso[1] < ts[1] / 50
+
+
+def test_energy_conserved_with_widened_stencil():
+    # the divergence takes the same widened stencil, so it stays the negative
+    # transpose of the gradient and a closed lossless heterogeneous box keeps
+    # its discrete energy (2D and 3D)
+    for ndim, shape in ((2, (48, 40, 1)), (3, (20, 18, 16))):
+        rng = np.random.default_rng(9)
+        nx, ny, nz = shape
+        cls = rng.integers(0, 3, (nz, ny, nx)).astype(np.uint8)
+        dx, cmax = 1e-4, 1600.0
+        dt = 0.35 * dx / cmax
+        sim = OracleSim(ndim, shape, dx, dt, 1, cls, [1400, 1500, 1600], [900, 1000, 1100], [0.0] * 3,
+                        np.ones((3, 2)), np.zeros((3, 2, 1)), np.ones((3, 2, 1)), fd_c_ref=1500.0, off_axis=True)
+        assert sim.fd_b > 0
+        nsrc = 80
+        w = W.tone_burst(nsrc, dt, 1.5e6, 1, amplitude=1e3).astype(np.float64)
+        nc = nx * ny * nz
+        _, en = sim.run(500, [nc // 2 + 3], w[None, :], [0], energy=True)
+        e = en[nsrc:]
+        assert e[0] > 0
+        assert np.max(np.abs(e - e[0])) / e[0] < 1e-12
