@@ -166,8 +166,28 @@ int fw_set_strength_map(fw_sim *sim, const float *d_scale, void *hip_stream);
  */
 int fw_set_time_space_stencil(fw_sim *sim, double c_ref);
 
-/* The four coefficients in use (c_m, dimensionless, FP64) into coef4[4]. */
-int fw_get_stencil(const fw_sim *sim, double *coef4);
+/*
+ * Widened staggered stencil for fourth order in time in every direction of a
+ * 2D grid (Sec. 3.3; the off-axis construction of Tan and Huang 2014).  Each
+ * axis's difference gains b times the two-point differences along that axis
+ * in the two rows (columns) one cell away on the other axis; with
+ * r = c_ref dt / dx, b = r^2 / 24 and the on-axis c_m solving
+ * sum_m c_m (2m - 1)^(2k - 1) = r^(2k - 2) - 2 b, k = 1..4, the leapfrog
+ * relation sin^2(w dt / 2) = r^2 (A_x^2 + A_y^2) matches w = c_ref |k|
+ * through fourth order in k dx for every direction (the mixed terms
+ * included), and through eighth order along the axes.  The divergence takes
+ * the same widened stencil, so it stays the negative transpose of the
+ * gradient.  c_ref = 0 restores the Taylor set (b = 0).  Only the 2D tile
+ * kernels implement it: fw_step returns FW_EUNSUPPORTED on other 2D paths
+ * (FW_OPT_PLANE_KERNELS 0, a persistent grid), and so does the adjoint.
+ * FW_EUNSUPPORTED unless ndim = 2; otherwise the errors of
+ * fw_set_time_space_stencil.  Drops a captured step graph.
+ */
+int fw_set_widened_stencil(fw_sim *sim, double c_ref);
+
+/* The coefficients in use into coef5[5]: c_1..c_4 and the off-axis weight b
+ * (0 unless fw_set_widened_stencil set it); dimensionless, FP64. */
+int fw_get_stencil(const fw_sim *sim, double *coef5);
 
 /*
  * Relaxation parameters per class (Sec. 2.1, Table 2 variables), FP64 in:

@@ -73,6 +73,7 @@ struct StepArgs {
     int32_t n_ptiles;
     int32_t ptiles_per_xcd;
     float fd[4];               // staggered coefficients c_m / dx
+    float fd_b;                // off-axis weight b / dx of the widened 2D stencil (0: on-axis only)
     float dt;
     float noise_amp;
     // optional per-voxel relaxation strength scale s(x) in [0, 1] (NULL: 1

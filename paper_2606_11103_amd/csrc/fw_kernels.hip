@@ -1017,15 +1017,21 @@ void k_pressure_planes(const StepArgs A)
 // marching kernels.  The halo rows are rows of the neighbouring tiles of the
 // same band, read again from L2.  Same operations in the same order as
 // k_velocity / k_pressure in 2D, so the results are identical.
+// WIDE: the widened stencil of the fourth-order-in-time set, which adds to
+// each axis's difference b times the two-point differences along that axis
+// in the rows one cell away on the other axis (both sides); its extra
+// operands come from the same LDS tiles, enlarged by one row or column.
 // ---------------------------------------------------------------------------
-template <int N, int TY, bool SMAP>
+template <int N, int TY, bool SMAP, bool WIDE>
 __global__ __launch_bounds__(64 * TY) void k_velocity_tile2d(const StepArgs A)
 {
     constexpr int BX = 64, LX = BX + 8, LY = TY + 8, NT = BX * TY, CX = BX + 1;
     // p halo the stencils read: 3 rows above and 4 below the tile over its
     // columns, 3 columns left and 4 right over its rows (LDS row hy holds
-    // y0 - 4 + hy, column hx holds x0 - 4 + hx; corners never read)
-    constexpr int NHALO = 7 * BX + 7 * TY;
+    // y0 - 4 + hy, column hx holds x0 - 4 + hx); WIDE also reads the corner
+    // cells (x0 + 64, y0 - 1), (x0 + 64, y0 + TY) and (x0 - 1, y0 + TY)
+    constexpr int NCORE = 7 * BX + 7 * TY;
+    constexpr int NHALO = NCORE + (WIDE ? 3 : 0);
     constexpr int HS = (NHALO + NT - 1) / NT;
     constexpr int NCH = TY + BX;
     __shared__ float sp[LY * LX];
@@ -1070,11 +1076,15 @@ __global__ __launch_bounds__(64 * TY) void k_velocity_tile2d(const StepArgs A)
             const int rr = h / BX;
             hy = rr < 3 ? rr + 1 : TY + 1 + rr;
             hx = 4 + h - rr * BX;
-        } else {
+        } else if (h < NCORE) {
             const int hh = h - 7 * BX;
             hy = 4 + hh / 7;
             const int k = hh - (hh / 7) * 7;
             hx = k < 3 ? k + 1 : BX + 1 + k;
+        } else {
+            const int k = h - NCORE;       // WIDE corners (h < NHALO is checked below)
+            hx = k == 2 ? 3 : BX + 4;
+            hy = k == 0 ? 3 : TY + 4;
         }
         const int gx = T.x0 - 4 + hx, gy = T.y0 - 4 + hy;
         const bool inside = h < NHALO && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
@@ -1124,6 +1134,11 @@ __global__ __launch_bounds__(64 * TY) void k_velocity_tile2d(const StepArgs A)
     Ln[0] = (x + 1 < nx) ? scl[ty * CX + tx + 1] : L;
     Dv[1] = stencil4(A.fd, sr[LX] - sr[0], sr[2 * LX] - sr[-LX], sr[3 * LX] - sr[-2 * LX], sr[4 * LX] - sr[-3 * LX]);
     Ln[1] = (y + 1 < ny) ? scl[(ty + 1) * CX + tx] : L;
+    if constexpr (WIDE) {
+        // face (x + 1/2, y): rows y + 1 and y - 1; face (x, y + 1/2): columns x + 1 and x - 1
+        Dv[0] = fmaf(A.fd_b, (sr[LX + 1] - sr[LX]) + (sr[1 - LX] - sr[-LX]), Dv[0]);
+        Dv[1] = fmaf(A.fd_b, (sr[LX + 1] - sr[1]) + (sr[LX - 1] - sr[-1]), Dv[1]);
+    }
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
         float Da = Dv[a];
@@ -1148,16 +1163,23 @@ __global__ __launch_bounds__(64 * TY) void k_velocity_tile2d(const StepArgs A)
     }
 }
 
-template <int N, int TY, bool SMAP>
+template <int N, int TY, bool SMAP, bool WIDE>
 __global__ __launch_bounds__(64 * TY) void k_pressure_tile2d(const StepArgs A)
 {
     constexpr int BX = 64, LX = BX + 8, LY = TY + 8, NT = BX * TY;
     // halo cells the stencils read: x-4 .. x-1 and x+64 .. x+66 of v_x over
-    // the tile's rows, y-4 .. y-1 and y+TY .. y+TY+2 of v_y over its columns
-    constexpr int NHALO = 7 * TY + 7 * BX;
+    // the tile's rows, y-4 .. y-1 and y+TY .. y+TY+2 of v_y over its columns;
+    // WIDE also reads v_x in rows y0-1 and y0+TY over columns x0-1 .. x0+63
+    // (svx gets a row above and below) and v_y in columns x0-1 and x0+64 over
+    // rows y0-1 .. y0+TY-1 (svy gets a column on each side)
+    constexpr int RX0 = WIDE ? 1 : 0, SXR = TY + 2 * RX0;     // svx: first tile row, rows
+    constexpr int CY0 = WIDE ? 1 : 0, SYC = BX + 2 * CY0;     // svy: first tile column, row pitch
+    constexpr int NCORE = 7 * TY + 7 * BX;
+    constexpr int NXR = 2 * (BX + 1), NYC = 2 * (TY + 1);     // WIDE extra v_x and v_y cells
+    constexpr int NHALO = NCORE + (WIDE ? NXR + NYC : 0);
     constexpr int HS = (NHALO + NT - 1) / NT;
-    __shared__ float svx[TY * LX];
-    __shared__ float svy[LY * BX];
+    __shared__ float svx[SXR * LX];
+    __shared__ float svy[LY * SYC];
     extern __shared__ float s_dyn[];
     const int C = A.class_cap;
     float *s_ik = s_dyn, *s_K = s_dyn + C, *s_tb = s_dyn + 2 * C, *s_a = s_dyn + 3 * C, *s_b = s_dyn + (3 + N) * C;
@@ -1202,15 +1224,28 @@ __global__ __launch_bounds__(64 * TY) void k_pressure_tile2d(const StepArgs A)
             const int hx = k < 4 ? k : BX + k;
             gx = T.x0 - 4 + hx;
             gy = T.y0 + row;
-            li = row * LX + hx;
-        } else {
+            li = (row + RX0) * LX + hx;
+        } else if (h < NCORE) {
             const int hh = h - 7 * TY;
             const int rr = hh / BX;
             const int hy = rr < 4 ? rr : TY + rr;
             const int hx = hh - rr * BX;
             gx = T.x0 + hx;
             gy = T.y0 - 4 + hy;
-            li = -(hy * BX + hx) - 2;
+            li = -(hy * SYC + CY0 + hx) - 2;
+        } else if (h < NCORE + NXR) {
+            // WIDE: v_x of row y0 - 1 (svx row 0) or y0 + TY (svx row TY + 1)
+            const int e = h - NCORE, side = e / (BX + 1), hx = 3 + e - side * (BX + 1);
+            gx = T.x0 - 4 + hx;
+            gy = side == 0 ? T.y0 - 1 : T.y0 + TY;
+            li = (side == 0 ? 0 : TY + 1) * LX + hx;
+        } else {
+            // WIDE: v_y of column x0 - 1 (svy column 0) or x0 + 64 (column BX + 1)
+            // (h < NHALO is checked below)
+            const int e = h - NCORE - NXR, side = e / (TY + 1), hy = 3 + e - side * (TY + 1);
+            gx = side == 0 ? T.x0 - 1 : T.x0 + BX;
+            gy = T.y0 - 4 + hy;
+            li = -(hy * SYC + (side == 0 ? 0 : BX + 1)) - 2;
         }
         const bool inside = h < NHALO && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
         hli[s] = h < NHALO ? li : -1;
@@ -1229,8 +1264,8 @@ __global__ __launch_bounds__(64 * TY) void k_pressure_tile2d(const StepArgs A)
             ppc[a] = in_slab(c, n, P) ? M.pP2[a][g] : 0.0f;
         }
     }
-    svx[ty * LX + 4 + tx] = ox;
-    svy[(ty + 4) * BX + tx] = oy;
+    svx[(ty + RX0) * LX + 4 + tx] = ox;
+    svy[(ty + 4) * SYC + CY0 + tx] = oy;
 #pragma unroll
     for (int s = 0; s < HS; ++s) {
         if (hli[s] >= 0)
@@ -1240,11 +1275,17 @@ __global__ __launch_bounds__(64 * TY) void k_pressure_tile2d(const StepArgs A)
     }
     __syncthreads();
     if (!ok) return;
-    const float *sx = svx + ty * LX + 4 + tx;
-    const float *sy = svy + (ty + 4) * BX + tx;
+    const float *sx = svx + (ty + RX0) * LX + 4 + tx;
+    const float *sy = svy + (ty + 4) * SYC + CY0 + tx;
     float Dd[2];
     Dd[0] = stencil4(A.fd, sx[0] - sx[-1], sx[1] - sx[-2], sx[2] - sx[-3], sx[3] - sx[-4]);
-    Dd[1] = stencil4(A.fd, sy[0] - sy[-BX], sy[BX] - sy[-2 * BX], sy[2 * BX] - sy[-3 * BX], sy[3 * BX] - sy[-4 * BX]);
+    Dd[1] = stencil4(A.fd, sy[0] - sy[-SYC], sy[SYC] - sy[-2 * SYC], sy[2 * SYC] - sy[-3 * SYC],
+                     sy[3 * SYC] - sy[-4 * SYC]);
+    if constexpr (WIDE) {
+        // cell (x, y): v_x differences in rows y + 1 and y - 1, v_y differences in columns x + 1 and x - 1
+        Dd[0] = fmaf(A.fd_b, (sx[LX] - sx[LX - 1]) + (sx[-LX] - sx[-LX - 1]), Dd[0]);
+        Dd[1] = fmaf(A.fd_b, (sy[1] - sy[1 - SYC]) + (sy[-1] - sy[-1 - SYC]), Dd[1]);
+    }
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
         const int c = a == 0 ? x : y, n = a == 0 ? nx : ny;
@@ -1370,26 +1411,26 @@ hipError_t launch_pressure_planes(const StepArgs &a, size_t lds, hipStream_t s)
 }
 
 // 2D tile kernels: 64 x plane_rows tiles (4, 8 or 16 rows), one per block
-template <int N, bool SMAP>
+template <int N, bool SMAP, bool WIDE>
 hipError_t launch_tile2d(bool velocity, const StepArgs &a, size_t lds, hipStream_t s)
 {
     const dim3 grid(8 * (velocity ? a.vtiles_per_xcd : a.ptiles_per_xcd));
     const dim3 block(64, a.plane_rows);
     if (a.plane_rows == 16) {
         if (velocity)
-            k_velocity_tile2d<N, 16, SMAP><<<grid, block, lds, s>>>(a);
+            k_velocity_tile2d<N, 16, SMAP, WIDE><<<grid, block, lds, s>>>(a);
         else
-            k_pressure_tile2d<N, 16, SMAP><<<grid, block, lds, s>>>(a);
+            k_pressure_tile2d<N, 16, SMAP, WIDE><<<grid, block, lds, s>>>(a);
     } else if (a.plane_rows == 8) {
         if (velocity)
-            k_velocity_tile2d<N, 8, SMAP><<<grid, block, lds, s>>>(a);
+            k_velocity_tile2d<N, 8, SMAP, WIDE><<<grid, block, lds, s>>>(a);
         else
-            k_pressure_tile2d<N, 8, SMAP><<<grid, block, lds, s>>>(a);
+            k_pressure_tile2d<N, 8, SMAP, WIDE><<<grid, block, lds, s>>>(a);
     } else {
         if (velocity)
-            k_velocity_tile2d<N, 4, SMAP><<<grid, dim3(64, 4), lds, s>>>(a);
+            k_velocity_tile2d<N, 4, SMAP, WIDE><<<grid, dim3(64, 4), lds, s>>>(a);
         else
-            k_pressure_tile2d<N, 4, SMAP><<<grid, dim3(64, 4), lds, s>>>(a);
+            k_pressure_tile2d<N, 4, SMAP, WIDE><<<grid, dim3(64, 4), lds, s>>>(a);
     }
     return hipGetLastError();
 }
@@ -1398,6 +1439,7 @@ hipError_t launch_tile2d(bool velocity, const StepArgs &a, size_t lds, hipStream
 template <int NDIM, int N>
 hipError_t launch_nd(bool velocity, int tile_rows, int rpt, const StepArgs &a, hipStream_t s)
 {
+    if (NDIM != 2 && a.fd_b != 0.0f) return hipErrorNotSupported;
     if constexpr (NDIM == 3) {
         if (velocity && a.plane) {
             const size_t lds = (size_t)a.class_cap * (2 + 2 * N) * sizeof(float);
@@ -1415,8 +1457,13 @@ hipError_t launch_nd(bool velocity, int tile_rows, int rpt, const StepArgs &a, h
     } else if constexpr (NDIM == 2) {
         if ((velocity && a.plane) || (!velocity && a.plane_p)) {
             const size_t lds = (size_t)a.class_cap * (velocity ? 2 + 2 * N : 3 + 2 * N) * sizeof(float);
-            return a.amap ? launch_tile2d<N, true>(velocity, a, lds, s) : launch_tile2d<N, false>(velocity, a, lds, s);
+            if (a.fd_b != 0.0f)
+                return a.amap ? launch_tile2d<N, true, true>(velocity, a, lds, s)
+                              : launch_tile2d<N, false, true>(velocity, a, lds, s);
+            return a.amap ? launch_tile2d<N, true, false>(velocity, a, lds, s)
+                          : launch_tile2d<N, false, false>(velocity, a, lds, s);
         }
+        if (a.fd_b != 0.0f) return hipErrorNotSupported;     // the widened stencil runs on the tile kernels only
         return launch_pair<2, N, 64, 1, 1>(velocity, a, s);
     } else {
         return launch_pair<1, N, 256, 1, 1>(velocity, a, s);

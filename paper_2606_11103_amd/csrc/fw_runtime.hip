@@ -49,12 +49,13 @@ constexpr double kFD[4] = {1225.0 / 1024.0, -245.0 / 3072.0, 49.0 / 5120.0, -5.0
 // step is of order 8 in time as well as in space there (Liu and Sen 2011).
 // r = 0 gives the Taylor set.  Gaussian elimination with partial pivoting
 // in FP64 on the 4 x 4 system of odd moments.
-static void time_space_coefficients(double r, double out[4])
+// shift: the widened 2D stencil's moments r^(2k - 2) - shift, shift = 2 b.
+static void time_space_coefficients(double r, double out[4], double shift = 0.0)
 {
     double A[4][5];
     for (int k = 0; k < 4; ++k) {
         for (int m = 0; m < 4; ++m) A[k][m] = std::pow(2.0 * m + 1.0, 2.0 * k + 1.0);
-        A[k][4] = std::pow(r * r, (double)k);
+        A[k][4] = std::pow(r * r, (double)k) - shift;
     }
     for (int col = 0; col < 4; ++col) {
         int piv = col;
@@ -132,9 +133,15 @@ struct fw_sim {
     std::vector<double> alpha0;          // power-law coefficient per class (fw_set_class_alpha0)
     // staggered first-derivative coefficients (Taylor, or the time-space set of
     // fw_set_time_space_stencil) and the smallest kappa1 kappa2 of the table
+    // and the off-axis weight b of the widened 2D stencil (fw_set_widened_stencil)
     double fd[4] = {kFD[0], kFD[1], kFD[2], kFD[3]};
-    double fd_cref = 0.0, min_kk = 1.0;
-    double fd_abs_sum() const { return std::fabs(fd[0]) + std::fabs(fd[1]) + std::fabs(fd[2]) + std::fabs(fd[3]); }
+    double fd_b = 0.0, fd_cref = 0.0, min_kk = 1.0;
+    // bound of one axis's difference symbol: sum |c_m| + 2 (ndim - 1) |b|
+    double fd_abs_sum() const
+    {
+        return std::fabs(fd[0]) + std::fabs(fd[1]) + std::fabs(fd[2]) + std::fabs(fd[3]) +
+               2.0 * (ndim - 1) * std::fabs(fd_b);
+    }
     // device tables
     DevBuf d_doms, d_classes, d_pml, d_tiles, d_vtiles, d_ptiles, d_waves, d_traces, d_step;
     float *traces_ext = nullptr;         // caller-owned trace buffer (fw_set_receivers_into), borrowed
@@ -498,6 +505,7 @@ fw::StepArgs step_args(const fw_sim *s)
     a.n_ptiles = s->n_ptiles;
     a.ptiles_per_xcd = s->ptiles_per_xcd;
     for (int m = 0; m < 4; ++m) a.fd[m] = (float)(s->fd[m] / s->dx);
+    a.fd_b = (float)(s->fd_b / s->dx);
     a.dt = (float)s->dt;
     a.noise_amp = (float)s->noise_amp;
     a.amap = s->amap;
@@ -582,6 +590,9 @@ static bool interleaved_on(const fw_sim *s, const fw::StepArgs &a)
 int enqueue_steps(fw_sim *s, int n, hipStream_t st)
 {
     const fw::StepArgs a = step_args(s);
+    if (s->fd_b != 0.0 && !(a.plane && a.plane_p))
+        return fail(FW_EUNSUPPORTED, "the widened stencil runs on the 2D tile kernels only (FW_OPT_PLANE_KERNELS "
+                                     "off or a persistent grid selected)");
     const fw::SrcRecArgs r = srcrec_args(s);
     const bool interleaved = interleaved_on(s, a);
     for (int i = 0; i < n; ++i) {
@@ -1429,6 +1440,7 @@ static int adjoint_sweep(fw_sim *sim, int n_steps, int ckpt_every, void *d_work,
     for (double b : sim->beta)
         if (b != 0.0) return fail(FW_EUNSUPPORTED, "the adjoint supports linear media only (beta = 0 in every class)");
     if (sim->amap) return fail(FW_EUNSUPPORTED, "the adjoint does not support a relaxation strength map");
+    if (sim->fd_b != 0.0) return fail(FW_EUNSUPPORTED, "the adjoint does not support the widened stencil");
     if (sim->tiles_dirty) {
         rc = build_tiles(sim);
         if (rc != FW_OK) return rc;
@@ -1505,20 +1517,21 @@ extern "C" int fw_adjoint_modulus(fw_sim *sim, int n_steps, int ckpt_every, void
     return adjoint_sweep(sim, n_steps, ckpt_every, d_work, bytes, d_adj_src, d_grad_K, d_grad_s, hip_stream);
 }
 
-extern "C" int fw_set_time_space_stencil(fw_sim *sim, double c_ref)
+// Time-space coefficients for c_ref (Taylor at 0), with the widened 2D
+// stencil's off-axis weight b = r^2 / 24 when `wide`; restores the previous
+// set when the stability bound fails.
+static int set_stencil(fw_sim *sim, double c_ref, bool wide)
 {
-    g_err.clear();
-    if (!sim) return fail(FW_EINVAL, "sim is NULL");
-    if (!(c_ref >= 0.0) || !std::isfinite(c_ref)) return fail(FW_EINVAL, "c_ref must be finite and >= 0 (got %g)", c_ref);
     const double r = c_ref * sim->dt / sim->dx;
-    if (!(r < 1.0)) return fail(FW_EINVAL, "c_ref dt / dx = %g: the time-space coefficients need a Courant number < 1", r);
     double prev[4];
     std::copy(sim->fd, sim->fd + 4, prev);
-    const double prev_cref = sim->fd_cref;
+    const double prev_cref = sim->fd_cref, prev_b = sim->fd_b;
     if (c_ref > 0.0) {
-        time_space_coefficients(r, sim->fd);
+        sim->fd_b = wide ? r * r / 24.0 : 0.0;
+        time_space_coefficients(r, sim->fd, 2.0 * (sim->ndim - 1) * sim->fd_b);
     } else {
         std::copy(kFD, kFD + 4, sim->fd);
+        sim->fd_b = 0.0;
     }
     sim->fd_cref = c_ref;
     if (sim->media_set) {
@@ -1526,6 +1539,7 @@ extern "C" int fw_set_time_space_stencil(fw_sim *sim, double c_ref)
         if (rc != FW_OK) {
             std::copy(prev, prev + 4, sim->fd);
             sim->fd_cref = prev_cref;
+            sim->fd_b = prev_b;
             return rc;
         }
     }
@@ -1533,11 +1547,33 @@ extern "C" int fw_set_time_space_stencil(fw_sim *sim, double c_ref)
     return FW_OK;
 }
 
-extern "C" int fw_get_stencil(const fw_sim *sim, double *coef4)
+extern "C" int fw_set_time_space_stencil(fw_sim *sim, double c_ref)
 {
     g_err.clear();
-    if (!sim || !coef4) return fail(FW_EINVAL, "NULL argument");
-    std::copy(sim->fd, sim->fd + 4, coef4);
+    if (!sim) return fail(FW_EINVAL, "sim is NULL");
+    if (!(c_ref >= 0.0) || !std::isfinite(c_ref)) return fail(FW_EINVAL, "c_ref must be finite and >= 0 (got %g)", c_ref);
+    const double r = c_ref * sim->dt / sim->dx;
+    if (!(r < 1.0)) return fail(FW_EINVAL, "c_ref dt / dx = %g: the time-space coefficients need a Courant number < 1", r);
+    return set_stencil(sim, c_ref, false);
+}
+
+extern "C" int fw_set_widened_stencil(fw_sim *sim, double c_ref)
+{
+    g_err.clear();
+    if (!sim) return fail(FW_EINVAL, "sim is NULL");
+    if (sim->ndim != 2) return fail(FW_EUNSUPPORTED, "the widened stencil is built for 2D grids");
+    if (!(c_ref >= 0.0) || !std::isfinite(c_ref)) return fail(FW_EINVAL, "c_ref must be finite and >= 0 (got %g)", c_ref);
+    const double r = c_ref * sim->dt / sim->dx;
+    if (!(r < 1.0)) return fail(FW_EINVAL, "c_ref dt / dx = %g: the time-space coefficients need a Courant number < 1", r);
+    return set_stencil(sim, c_ref, true);
+}
+
+extern "C" int fw_get_stencil(const fw_sim *sim, double *coef5)
+{
+    g_err.clear();
+    if (!sim || !coef5) return fail(FW_EINVAL, "NULL argument");
+    std::copy(sim->fd, sim->fd + 4, coef5);
+    coef5[4] = sim->fd_b;
     return FW_OK;
 }
 

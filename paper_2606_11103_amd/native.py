@@ -60,6 +60,7 @@ SIGNATURES = {
     "fw_set_class_alpha0": (_I, [_P, _I, _P]),
     "fw_set_strength_map": (_I, [_P, _P, _P]),
     "fw_set_time_space_stencil": (_I, [_P, _D]),
+    "fw_set_widened_stencil": (_I, [_P, _D]),
     "fw_get_stencil": (_I, [_P, _P]),
     "fw_stream_probe": (_I, [_P, _I, _I, _I, _P, _P]),
 }

@@ -226,11 +226,16 @@ class Simulation:
         set of fw_set_time_space_stencil); 0 restores the Taylor set."""
         check(lib.fw_set_time_space_stencil(self._h, float(c_ref)))
 
+    def set_widened_stencil(self, c_ref):
+        """2D only: the widened stencil (fourth order in time in every
+        direction) tuned to the speed c_ref; 0 restores the Taylor set."""
+        check(lib.fw_set_widened_stencil(self._h, float(c_ref)))
+
     def stencil(self):
-        """The four staggered coefficients in use (FP64)."""
-        out = (ctypes.c_double * 4)()
+        """The staggered coefficients in use (FP64): ([c_1..c_4], b)."""
+        out = (ctypes.c_double * 5)()
         check(lib.fw_get_stencil(self._h, out))
-        return list(out)
+        return list(out)[:4], out[4]
 
     def set_strength_map(self, scale, stream=None):
         """Per-voxel relaxation strength scale s(x) in [0, 1] (a device float

@@ -204,10 +204,11 @@ def test_time_space_stencil_host_setup():
     dx, dt = 1e-4, 2e-8
     rc, h = _create(dx=dx, dt=dt)
     assert rc == 0
-    out = np.zeros(4)
-    p = ctypes.c_void_p(out.ctypes.data)
+    buf = np.zeros(5)
+    out = buf[:4]
+    p = ctypes.c_void_p(buf.ctypes.data)
     assert lib.fw_get_stencil(h, p) == 0
-    assert np.array_equal(out, np.array(fdcoef.staggered_coefficients(4)))
+    assert np.array_equal(out, np.array(fdcoef.staggered_coefficients(4))) and buf[4] == 0.0
     for c_ref in (800.0, 1540.0, 3000.0, 4900.0):
         assert lib.fw_set_time_space_stencil(h, c_ref) == 0
         assert lib.fw_get_stencil(h, p) == 0
@@ -222,4 +223,37 @@ def test_time_space_stencil_host_setup():
     assert lib.fw_get_stencil(h, p) == 0
     assert np.array_equal(out, np.array(fdcoef.staggered_coefficients(4)))
     assert lib.fw_set_time_space_stencil(None, 1500.0) == native.FW_EINVAL
+    assert lib.fw_destroy(h) == 0
+
+
+def test_widened_stencil_host_setup():
+    """fw_set_widened_stencil: 2D only; c_1..c_4 and b equal the oracle's exact
+    rationals; fw_set_time_space_stencil and c_ref = 0 clear b."""
+    from oracle import fdcoef
+    from paper_2606_11103_amd import native
+    lib = native.lib
+    dx, dt = 1e-4, 2e-8
+    buf = np.zeros(5)
+    p = ctypes.c_void_p(buf.ctypes.data)
+    rc, h3 = _create(ndim=3, shapes=((40, 36, 30),), dx=dx, dt=dt)
+    assert rc == 0
+    assert lib.fw_set_widened_stencil(h3, 1500.0) == native.FW_EUNSUPPORTED
+    assert lib.fw_destroy(h3) == 0
+    rc, h = _create(dx=dx, dt=dt)
+    assert rc == 0
+    for c_ref in (900.0, 1540.0, 3500.0):
+        assert lib.fw_set_widened_stencil(h, c_ref) == 0
+        assert lib.fw_get_stencil(h, p) == 0
+        c, b = fdcoef.isotropic_time_space_coefficients(c_ref * dt / dx, 2, 4)
+        assert np.max(np.abs(buf[:4] - c) / np.abs(c)) < 1e-13
+        assert abs(buf[4] - b) <= 1e-15 * b
+    assert lib.fw_set_widened_stencil(h, -5.0) == native.FW_EINVAL
+    assert lib.fw_set_widened_stencil(h, dx / dt) == native.FW_EINVAL
+    assert lib.fw_set_time_space_stencil(h, 1540.0) == 0
+    assert lib.fw_get_stencil(h, p) == 0
+    assert buf[4] == 0.0
+    assert lib.fw_set_widened_stencil(h, 1540.0) == 0
+    assert lib.fw_set_widened_stencil(h, 0.0) == 0
+    assert lib.fw_get_stencil(h, p) == 0
+    assert np.array_equal(buf[:4], np.array(fdcoef.staggered_coefficients(4))) and buf[4] == 0.0
     assert lib.fw_destroy(h) == 0

@@ -44,7 +44,8 @@ def test_time_space_set_matches_oracle(name):
     sim = to_simulation(case)
     from oracle import fdcoef
     ref_coef = fdcoef.time_space_coefficients(case.fd_c_ref * case.dt / case.dx, 4)
-    assert np.max(np.abs(np.array(sim.stencil()) - ref_coef) / np.abs(ref_coef)) < 1e-13
+    coef, b = sim.stencil()
+    assert np.max(np.abs(np.array(coef) - ref_coef) / np.abs(ref_coef)) < 1e-13 and b == 0.0
     sim.step(case.n_steps)
     got = sim.read_receivers()
     del sim
@@ -88,3 +89,77 @@ def test_time_space_set_adjoint_matches_fp64_adjoint():
     report("time-space stencil adjoint 2D N=4 rel_L2 gK=%.3e gs=%.3e" % (rK, rs))
     assert np.abs(oK).max() > 0 and np.abs(os_).max() > 0
     assert rK <= 1e-4 and rs <= 1e-4
+
+
+def _widened(case):
+    return dataclasses.replace(case, fd_c_ref=float(np.mean(case.c)), fd_widened=True)
+
+
+def _run(case, opts=None, steps=None):
+    sim = to_simulation(case)
+    for k, v in (opts or {}).items():
+        sim.set_option(k, v)
+    sim.step(case.n_steps if steps is None else steps)
+    tr = sim.read_receivers()
+    del sim
+    return tr
+
+
+@pytest.mark.parametrize("nmech", [1, 4])
+def test_widened_stencil_2d_tiles_match_oracle(nmech):
+    """The widened 2D stencil (fourth order in time in every direction) on the
+    2D tile kernels with 4-, 8- and 16-row tiles, over a ragged batch of five
+    domains (partial tiles on both axes, CPML, noise, nonlinearity), against
+    the FP64 oracle with the same stencil; with a strength map too (N = 4)."""
+    from paper_2606_11103_amd.native import FW_OPT_PLANE_ROWS
+    from oracle import fdcoef
+    shapes = [(70, 21, 1), (33, 38, 1), (130, 97, 1), (64, 61, 1), (65, 19, 1)]
+    c = configs.random_small(2, shapes, nmech, 3, seed=80 + nmech, steps=200, pml=5)
+    base = configs.with_table(c, *configs.random_relaxation_table(180 + nmech, c.n_classes, c.nmech))
+    case = _widened(base)
+    print("widened stencil, ragged 2D batch, N=%d" % nmech, flush=True)
+    sim = to_simulation(case)
+    coef, b = sim.stencil()
+    rc, rb = fdcoef.isotropic_time_space_coefficients(case.fd_c_ref * case.dt / case.dx, 2, 4)
+    assert np.max(np.abs(np.array(coef) - rc) / np.abs(rc)) < 1e-13 and abs(b - rb) <= 1e-15 * rb
+    del sim
+    runs = {rows: _run(case, {FW_OPT_PLANE_ROWS: rows}) for rows in (4, 8, 16)}
+    assert np.array_equal(runs[4], runs[8]) and np.array_equal(runs[4], runs[16])
+    ref = oracle_traces(case)
+    glob, worst, n = check_traces(runs[8], ref)
+    sep = float(np.linalg.norm(oracle_traces(_with_ts(base)) - ref) / np.linalg.norm(ref))
+    report("widened stencil 2D ragged batch N=%d: rel_L2=%.3e worst_receiver=%.3e (%d reached); on-axis set "
+           "differs by %.3e" % (nmech, glob, worst, n, sep))
+    assert sep > 100 * max(glob, 1e-6)
+    if nmech == 4:
+        smap = configs.with_strength(case, 9, 0.2, 1.0)
+        got = _run(smap, {FW_OPT_PLANE_ROWS: 8})
+        glob_s, worst_s, n_s = check_traces(got, oracle_traces(smap))
+        report("widened stencil 2D ragged batch N=4 with a strength map: rel_L2=%.3e worst_receiver=%.3e"
+               % (glob_s, worst_s))
+
+
+def test_widened_stencil_rejects_paths_without_it():
+    """Marching 2D kernels and the adjoint do not implement the widened
+    stencil: stepping on them and the adjoint fail with FW_EUNSUPPORTED
+    instead of running another scheme; restoring the Taylor set lifts it."""
+    import torch
+    from paper_2606_11103_amd.native import FW_EUNSUPPORTED, FW_OPT_PLANE_KERNELS, FWError
+    c = configs.random_small(2, [(64, 64, 1)], 2, 3, seed=86, steps=40, pml=6, nonlinear=False)
+    case = _widened(configs.with_table(c, *configs.random_relaxation_table(186, c.n_classes, c.nmech)))
+    sim = to_simulation(case)
+    sim.set_option(FW_OPT_PLANE_KERNELS, 0)
+    with pytest.raises(FWError) as e:
+        sim.step(1)
+    assert e.value.code == FW_EUNSUPPORTED
+    sim.set_option(FW_OPT_PLANE_KERNELS, 1)
+    work = sim.adjoint_workspace(case.n_steps, 10)
+    sim.forward_checkpointed(case.n_steps, 10, work)        # a forward run on the tile kernels
+    res = torch.zeros((case.n_steps, len(case.rec_cell)), dtype=torch.float32, device=sim.device)
+    with pytest.raises(FWError) as e:
+        sim.adjoint_modulus(case.n_steps, 10, work, res)
+    assert e.value.code == FW_EUNSUPPORTED
+    sim.set_widened_stencil(0.0)
+    sim.set_option(FW_OPT_PLANE_KERNELS, 0)
+    sim.reset()
+    sim.step(5)

@@ -13,7 +13,9 @@ def to_simulation(case, **kw):
     from paper_2606_11103_amd.sim import Simulation, beta_from_b_over_a
     sim = Simulation(case.ndim, case.shapes, case.dx, case.dt, case.nmech, case.pml_cells,
                      pml_params=case.pml_params, **kw)
-    if case.fd_c_ref > 0:
+    if case.fd_c_ref > 0 and case.fd_widened:
+        sim.set_widened_stencil(case.fd_c_ref)
+    elif case.fd_c_ref > 0:
         sim.set_time_space_stencil(case.fd_c_ref)
     beta = beta_from_b_over_a(case.b_over_a) if case.nonlinear else np.zeros(case.n_classes)
     sim.set_media(case.class_maps, case.class_base, case.c, case.rho, beta, case.noise_amp, case.noise_seed)
@@ -42,6 +44,7 @@ def to_oracle(case, domain=0, **kw):
         kw["a_scale"] = np.asarray(case.strength[domain], np.float64).reshape(-1)
     if case.fd_c_ref > 0 and "fd_c_ref" not in kw:
         kw["fd_c_ref"] = case.fd_c_ref
+        kw["off_axis"] = case.fd_widened
     return OracleSim(case.ndim, case.shapes[domain], case.dx, case.dt, case.nmech, case.class_maps[domain],
                      case.c[sl], case.rho[sl], beta, case.kappa[sl], case.d[sl], case.alpha[sl],
                      pml_cells=case.pml_cells, pml_R0=pp[0], pml_f_alpha=pp[1], pml_c_ref=cref,

@@ -48,6 +48,7 @@ class Case:
     alpha: Optional[np.ndarray] = None  # [C][2][N]
     strength: Optional[List[np.ndarray]] = None   # per-voxel strength scale in [0, 1] per domain (float32)
     fd_c_ref: float = 0.0               # > 0: staggered coefficients of the time-space set for this speed
+    fd_widened: bool = False            # with fd_c_ref, 2D: the widened (off-axis) stencil
 
     @property
     def n_classes(self):
