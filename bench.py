@@ -40,8 +40,8 @@ TRAFFIC_MEASURED = {
     # per step; FETCH_SIZE counts L2 misses sent to the data fabric, so the
     # z-window reads served by the last-level cache are included: an upper bound
     # on the HBM bytes
-    ("e1266490f05a6ee7", 120): {"workload": "3d_heterogeneous_960x960x720", "step_bytes": 144.84e9,
-                                "velocity_bytes": 99.29e9,
+    ("567f6cbf917326a1", 120): {"workload": "3d_heterogeneous_960x960x720", "step_bytes": 144.85e9,
+                                "velocity_bytes": 99.30e9,
                                 "profile": "profiles/step_kernels_3d_960x960x720_N4.md"},
 }
 
