@@ -75,6 +75,7 @@ def test_oracle_pins_under_sanitizers(sanitized_engine):
                            os.path.join(HERE, "test_oracle_solver.py"),
                            os.path.join(HERE, "test_oracle_crop.py"),
                            os.path.join(HERE, "test_oracle_interface.py"),
+                           os.path.join(HERE, "test_oracle_time_order.py"),
                            "-k", "not 3d_interface_normal_to_z and not planted"],
                           cwd=ROOT, env=sanitized_engine, capture_output=True, text=True, timeout=900)
     _check(proc)
