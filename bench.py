@@ -367,9 +367,18 @@ def bench_two_layer(torch, steps=400):
     sim = to_simulation(case)
     sim.step(32)                    # untimed: captures the step graph
     ms = _time_steps(torch, sim, steps)
+    # the same steps with the widened stencil (fourth order in time in every
+    # direction): the 2D tile kernels' WIDE variants, tuned to the mean speed
+    c_ref = float(np.mean(case.c))
+    sim.set_widened_stencil(c_ref)
+    sim.reset()
+    sim.step(32)                    # untimed: re-captures the step graph
+    ms_w = _time_steps(torch, sim, steps)
     return {"workload": case.name, "cells": case.cells(), "steps": steps, "tables": tab,
             "gcells": round(case.cells() * steps / (ms / 1e3) / 1e9, 3), "ms_per_step": round(ms / steps, 4),
-            "step_frac": _step_frac(case, ms / steps)}
+            "step_frac": _step_frac(case, ms / steps),
+            "widened_stencil": {"c_ref": round(c_ref, 1), "gcells": round(case.cells() * steps / (ms_w / 1e3) / 1e9, 3),
+                                "ms_per_step": round(ms_w / steps, 4), "vs_taylor": round(ms_w / ms, 4)}}
 
 
 def bench_paper_shape(torch, steps=100):
