@@ -163,3 +163,17 @@ def test_widened_stencil_rejects_paths_without_it():
     sim.set_option(FW_OPT_PLANE_KERNELS, 0)
     sim.reset()
     sim.step(5)
+
+
+def test_widened_stencil_long_horizon_512():
+    """The widened 2D stencil over 2000 steps on 512 x 512 cells (N = 4, 24-cell
+    CPML, noise, nonlinear, 24 receivers) against the live FP64 oracle: the
+    global and the worst reached receiver's relative L2 within the bar."""
+    c = configs.random_small(2, [(512, 512, 1)], 4, 3, seed=88, steps=2000, pml=24, n_rec=24)
+    case = _widened(configs.with_table(c, *configs.random_relaxation_table(188, c.n_classes, c.nmech)))
+    print("widened stencil, 512^2, 2000 steps", flush=True)
+    got = _run(case)
+    ref = oracle_traces(case)
+    glob, worst, n = check_traces(got, ref)
+    report("widened stencil 2D 512x512 N=4, 2000 steps: rel_L2=%.3e worst_receiver=%.3e (%d of %d reached)"
+           % (glob, worst, n, len(case.rec_cell)))
