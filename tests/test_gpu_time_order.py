@@ -177,3 +177,31 @@ def test_widened_stencil_long_horizon_512():
     glob, worst, n = check_traces(got, ref)
     report("widened stencil 2D 512x512 N=4, 2000 steps: rel_L2=%.3e worst_receiver=%.3e (%d of %d reached)"
            % (glob, worst, n, len(case.rec_cell)))
+
+
+def test_widened_stencil_graph_eager_resume_and_switch_are_bitwise():
+    """With the widened stencil: eager launches, graph replays of 16 and 7
+    steps, and a save / advance / reload / resume give the same bits; setting
+    the stencil drops the captured graph, so switching back to the Taylor set
+    mid-life reproduces a plain Taylor run from a reset."""
+    from paper_2606_11103_amd.native import FW_OPT_GRAPH_STEPS
+    c = configs.random_small(2, [(150, 130, 1), (77, 96, 1)], 4, 3, seed=89, steps=240, pml=6)
+    base = configs.with_table(c, *configs.random_relaxation_table(189, c.n_classes, c.nmech))
+    case = _widened(base)
+    a = _run(case, {FW_OPT_GRAPH_STEPS: 0})
+    assert np.array_equal(a, _run(case, {FW_OPT_GRAPH_STEPS: 16}))
+    assert np.array_equal(a, _run(case, {FW_OPT_GRAPH_STEPS: 7}))
+    n = case.n_steps
+    sim = to_simulation(case)
+    sim.step(n // 2)
+    buf = sim.save_state()
+    sim.step(17)
+    sim.load_state(buf)
+    sim.step(n - n // 2)
+    assert np.array_equal(sim.read_receivers(), a)
+    # back to the Taylor set on the same Simulation (the widened graph is dropped)
+    sim.set_widened_stencil(0.0)
+    sim.reset()
+    sim.step(n)
+    assert np.array_equal(sim.read_receivers(), _run(base))
+    assert not np.array_equal(a, _run(base))
